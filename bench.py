@@ -1,0 +1,199 @@
+"""Throughput of the batched navigation step on one MI355X.
+
+Workload (default): 4096 envs over 16 seeded 128x128 maps at 0.05 m (rectangles
+and rasterised discs, ~15 % occupancy), disc robot r = 0.18 m, 360 beams over
+360 deg pooled to 30 sectors, r_max 6 m, dt 0.1 s, uniform random actions,
+auto-reset.  Inputs are resident in HBM before the timed region.
+
+One step = one launch of the fused step kernel over all envs (action ->
+pose -> collision -> 360-beam scan -> pooling -> reward/flags -> masked
+reset).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
+KERNEL_SRC = os.path.join(ROOT, "paper_2606_15846_amd", "csrc", "navsim_kernels.hip")
+PMC_FILE = os.path.join(ROOT, "profiles", "fused_step_c2_hbm_traffic.txt")
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def hbm_traffic_from_profile():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when absent or taken on a different kernel source."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    vals = {}
+    for line in open(PMC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, acts, target_s: float = 10.0) -> dict:
+    import oracle
+    threads = min(len(os.sched_getaffinity(0)), 16)
+    ref = oracle.OracleSim(w["cfg"], w["maps"], w["res"], w["env_map"])
+    ref.reset(threads=threads)
+    N, K = ref.N, ref.K
+    t0 = time.perf_counter()
+    ref.step(acts[0], debug=False, threads=threads)
+    one = time.perf_counter() - t0
+    steps = int(max(1, min(acts.shape[0] - 1, target_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    for t in range(1, 1 + steps):
+        ref.step(acts[t], debug=False, threads=threads)
+    dt = time.perf_counter() - t0
+    rate = N * steps / dt
+    return {"value": rate, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+            "rays_per_s": rate * K,
+            "sample": f"{steps} steps x {N} envs of the same workload (scalar FP64 C oracle, "
+                      f"{threads} threads over env slices), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--plain-steps", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run 5 device-to-device copies of 256 MiB (HBM counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the step shards by env with no exchange, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": a.numel() * 4,
+                          "copy_bytes_written_per_launch": b.numel() * 4, "launches": 5}))
+        return
+
+    from paper_2606_15846_amd.navsim import NAVSIM_KERNEL_FUSED, NavSim
+    from workloads import configs
+
+    dev = torch.device("cuda", 0)
+    w = configs.build_workload(args.workload)
+    cfg = w["cfg"]
+    N, K, m = cfg["num_envs"], cfg["num_beams"], cfg["num_sectors"]
+    total = args.warmup + args.steps
+    acts_np = configs.uniform_actions(total, N, seed=42)
+    acts = torch.from_numpy(acts_np).to(dev)
+    sim = NavSim(cfg, w["maps"], w["res"], w["env_map"], device=0)
+    sim.reset()
+    for t in range(args.warmup):
+        sim.step(acts[t])
+    torch.cuda.synchronize()
+    start_state = sim.get_state()
+    stream = torch.cuda.current_stream(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    resets = torch.zeros((), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    for t in range(args.steps):
+        ev[t][0].record(stream)
+        sim.step(acts[args.warmup + t])
+        ev[t][1].record(stream)
+    torch.cuda.synchronize()
+    per_launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    total_ms = ev[0][0].elapsed_time(ev[-1][1])
+    ms_per_step = total_ms / args.steps
+    value = N * args.steps / (total_ms / 1e3)
+
+    # algorithmic work of the timed steps: replay them with the per-ray visit
+    # counts switched on (same state, same actions, results are bitwise equal)
+    sim.set_state(start_state)
+    visits = 0
+    for t in range(args.steps):
+        dbg = sim.step_debug(acts[args.warmup + t], kernel=NAVSIM_KERNEL_FUSED)
+        visits += int(dbg["visits"].sum().item())
+        resets += dbg["reset"].sum()
+    reset_rate = float(resets.item()) / (N * args.steps)
+    lds_bytes_per_launch = 4.0 * visits / args.steps
+    avg_launch_s = float(per_launch_ms.mean()) / 1e3
+    achieved = lds_bytes_per_launch / avg_launch_s / 1e9
+    traffic = hbm_traffic_from_profile()
+
+    plain = None
+    if not args.no_plain:
+        sim.set_state(start_state)
+        torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record(stream)
+        for t in range(args.plain_steps):
+            sim.step(acts[args.warmup + t], plain=True)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        pms = p0.elapsed_time(p1)
+        prate = N * args.plain_steps / (pms / 1e3)
+        plain = {"value": prate, "rays_per_s": prate * K, "steps": args.plain_steps,
+                 "ms_per_step": pms / args.plain_steps,
+                 "mapping": "one thread per env, beams in sequence, bitmap in HBM"}
+    sim.close()
+
+    cpu = None if args.no_cpu else cpu_baseline(w, acts_np[args.warmup:])
+    out = {
+        "metric": "env-steps/s + rays/s on 1 MI355X, fused-batched vs plain step; % LDS roofline",
+        "value": value,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32+f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "envs": N, "beams": K, "sectors": m,
+                   "maps": len(w["maps"]), "map_cells": f"{w['maps'][0].shape[1]}x{w['maps'][0].shape[0]}",
+                   "res_m": w["res"][0], "max_range_m": cfg["max_range_m"],
+                   "footprint": "disc" if cfg["footprint"] == 0 else "rect"},
+        "rays_per_s": value * K,
+        "plain": plain,
+        "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "reset_rate_per_step": reset_rate,
+        "cell_visits_per_env_step": visits / (N * args.steps),
+        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": traffic,
+                     "kernel": "fused_step_kernel",
+                     "avg_launch_us": avg_launch_s * 1e6,
+                     "algorithmic_bytes_per_launch": lds_bytes_per_launch},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * navsim: batched bitmap navigation step for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libnavsim.so.  Implements the data-parallel environment step of
+ * FlashNav (arXiv 2606.15846, section 2.2): thousands of independent
+ * goal-conditioned navigation environments on occupancy bitmaps, advanced by
+ * one fused GPU step per call.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every call returns a navsim_status (0 = NAVSIM_OK, < 0 = error).  On error
+ *   navsim_last_error() returns a message for the calling thread.
+ * - Argument errors are reported synchronously, before anything is enqueued;
+ *   output buffers are then untouched.
+ * - "device" pointers are HIP device allocations on the handle's device (for
+ *   example torch tensors' data pointers), contiguous, with the stated layout.
+ *   "host" pointers are ordinary process memory, read during the call only.
+ * - Calls that take `hip_stream` (a hipStream_t; NULL = the null stream)
+ *   enqueue their work on that stream and return without waiting.  The caller
+ *   keeps device buffers alive until the stream has consumed them.  Faults of
+ *   enqueued work surface at the next synchronisation.
+ * - A handle is used by one thread at a time; different handles are
+ *   independent.  Calls on one handle that overlap on different streams race.
+ *
+ * Environment layout (the navigation MDP of section 2.1)
+ * ------------------------------------------------------
+ * Per env the library keeps, in device memory, float32 pose x, y, theta (m,
+ * m, rad in [-pi, pi]), commanded velocity v, w, goal gx, gy, previous goal
+ * distance d_prev, int32 step counter t and uint32 episode counter.
+ * Observation row (eq. 1, raw pooled ranges; the reciprocal transform of
+ * eq. 2 has a trainable parameter and belongs to the policy):
+ *     obs[e] = [ l_1 .. l_m , d_goal , phi_goal , v , w ]   (m + 4 floats)
+ * l_j = min range over sector j (eq. 6): sectors are contiguous blocks of K/m
+ * beams.  Beam k's angle to the heading is -pi + k 2pi/K for a full circle,
+ * -fov/2 + k fov/(K-1) otherwise.  phi_goal is the goal bearing in the robot
+ * frame, in (-pi, pi].
+ */
+#ifndef NAVSIM_H
+#define NAVSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NAVSIM_ABI_VERSION 1u
+
+typedef struct navsim_s *navsim_t;
+
+typedef enum {
+    NAVSIM_OK = 0,
+    NAVSIM_E_INVALID_ARG = -1,    /* bad pointer, size or parameter value          */
+    NAVSIM_E_BAD_HANDLE = -2,     /* NULL or destroyed handle                       */
+    NAVSIM_E_STATE = -3,          /* call order: step before load_maps/reset        */
+    NAVSIM_E_NO_FREE_SPACE = -4,  /* a map used by some env has no collision-free cell */
+    NAVSIM_E_OOM = -5,            /* device or host allocation failed               */
+    NAVSIM_E_HIP = -6,            /* a HIP runtime call failed (message has details) */
+    NAVSIM_E_UNSUPPORTED = -7     /* valid but beyond this build's limits           */
+} navsim_status;
+
+enum { NAVSIM_DISC = 0, NAVSIM_RECT = 1 };
+
+/* Robot preset and episode parameters (section 2.2.1 presets; appendix B,
+ * tables 7-9 for the paper's values). */
+typedef struct {
+    uint32_t abi_version;        /* must equal NAVSIM_ABI_VERSION                        */
+    int32_t num_envs;            /* N >= 1                                                */
+    int32_t num_beams;           /* K, 1..4096                                            */
+    int32_t num_sectors;         /* m, K % m == 0                                         */
+    float fov_rad;               /* >= 2pi - 1e-6 means a full circle                     */
+    float max_range_m;           /* r_max > 0 (eq. 5)                                     */
+    float dt_s;                  /* integration step > 0                                  */
+    int32_t horizon;             /* truncation after this many steps (table 7: 200)       */
+    float goal_radius_m;         /* goal reached when d < this (table 7: 0.2)             */
+    float c_progress;            /* eq. 3 progress coefficient c_1 (table 7: 2)           */
+    float r_success;             /* eq. 3 goal reward (table 7: +10)                      */
+    float r_collision;           /* eq. 3 collision reward (table 7: -10)                 */
+    int32_t footprint;           /* NAVSIM_DISC or NAVSIM_RECT                            */
+    float radius_m;              /* disc radius                                           */
+    float length_m, width_m;     /* rectangle, long side along the heading                */
+    float v_min, v_max;          /* linear velocity for normalised action -1 / +1          */
+    float w_min, w_max;          /* angular velocity for normalised action -1 / +1         */
+    float goal_min_dist_m;       /* reset: minimum start-goal distance                    */
+    int32_t reset_max_tries;     /* reset: rejection attempts before the free-cell list, 1..1024 */
+    uint64_t seed;               /* key of the reset sampler's counter-based generator     */
+} navsim_config;
+
+/* Create a simulator for cfg on HIP device hip_device.  Allocates the env
+ * state on that device (state starts zeroed; call navsim_load_maps and
+ * navsim_reset before stepping).  *out receives the handle. */
+navsim_status navsim_create(const navsim_config *cfg, int hip_device, navsim_t *out);
+
+/* Load the occupancy bitmaps (section 2.2.1) and the env-to-map assignment.
+ * All pointers are host memory, copied during the call (synchronous).
+ *   width, height [num_maps]  cells per row / rows, 1..2048 each
+ *   res_m [num_maps]          cell size in metres (> 0); cell (ix, iy) covers
+ *                             [ix s, (ix+1) s) x [iy s, (iy+1) s)
+ *   occ                       maps concatenated, each row-major [height][width],
+ *                             iy-major, byte 0 = free, nonzero = occupied;
+ *                             everything outside the map counts as occupied
+ *   env_map [num_envs]        map id of each env, 0..num_maps-1
+ * Errors: NAVSIM_E_NO_FREE_SPACE if a used map has no cell where the footprint's
+ * circumscribed disc fits (the reset sampler could not succeed). */
+navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *width,
+                               const int32_t *height, const float *res_m, const uint8_t *occ,
+                               const int32_t *env_map);
+
+/* Sparse reset (section 2.2.3): every env with mask[e] != 0 (mask NULL = all)
+ * gets a new collision-free start pose and goal from its map's free space,
+ * zero velocity, t = 0, and its reset observation written to obs row e.  Rows
+ * of envs not reset are left untouched.  The first reset must use mask NULL.
+ *   mask  device uint8 [N] or NULL
+ *   obs   device float32 [N][m+4] */
+navsim_status navsim_reset(navsim_t h, const uint8_t *mask, float *obs, void *hip_stream);
+
+/* One environment step for all N envs, the step data path of eq. 7:
+ * action -> pose -> ranges -> (collision, reward, termination) -> O_{t+1}
+ * -> reset observation where the episode ended.
+ *   act         device float32 [N][2], normalised (a_v, a_w); clipped to [-1, 1],
+ *               NaN treated as 0; v = v_min + (a_v + 1)/2 (v_max - v_min), w alike
+ *   obs         device float32 [N][m+4]: O_{t+1}, or the reset observation for envs
+ *               whose episode ended in this step
+ *   reward      device float32 [N]   eq. 3 for the transition just taken
+ *   terminated  device uint8 [N]     goal reached or collision
+ *   truncated   device uint8 [N]     t reached the horizon with neither event
+ *   final_obs   device float32 [N][m+4] or NULL: O_{t+1} of envs that ended
+ *               (rows of other envs untouched)
+ * The fused GPU step: one wavefront per env, the env's bitmap staged in LDS. */
+navsim_status navsim_step(navsim_t h, const float *act, float *obs, float *reward,
+                          uint8_t *terminated, uint8_t *truncated, float *final_obs,
+                          void *hip_stream);
+
+/* Same contract and results as navsim_step, computed by the plain mapping: one
+ * GPU thread per env, beams in sequence, bitmap read from device memory.  Kept
+ * as the comparison point for the fused step. */
+navsim_status navsim_step_plain(navsim_t h, const float *act, float *obs, float *reward,
+                                uint8_t *terminated, uint8_t *truncated, float *final_obs,
+                                void *hip_stream);
+
+/* Optional per-step diagnostics.  Every pointer may be NULL (= not written). */
+typedef struct {
+    float *ranges;      /* device float32 [N][K]: range of each beam at the pre-reset pose */
+    int32_t *hits;      /* device int32 [N][K]: hit cell iy*W+ix, -1 none within r_max,
+                           -2 map boundary                                              */
+    int32_t *visits;    /* device int32 [N][K]: cells whose occupancy the ray read      */
+    uint8_t *collision; /* device uint8 [N]                                            */
+    uint8_t *goal;      /* device uint8 [N]                                            */
+    uint8_t *reset;     /* device uint8 [N]: env was reset in this step                */
+    uint8_t *fallback;  /* device uint8 [N]: bit 0 start, bit 1 goal came from the
+                           free-cell list                                              */
+} navsim_debug;
+
+enum { NAVSIM_KERNEL_FUSED = 0, NAVSIM_KERNEL_PLAIN = 1 };
+
+/* navsim_step (kernel = NAVSIM_KERNEL_FUSED) or navsim_step_plain
+ * (NAVSIM_KERNEL_PLAIN) that also writes the diagnostics in *dbg (host struct
+ * of device pointers; NULL = none). */
+navsim_status navsim_step_debug(navsim_t h, const float *act, float *obs, float *reward,
+                                uint8_t *terminated, uint8_t *truncated, float *final_obs,
+                                const navsim_debug *dbg, int32_t kernel, void *hip_stream);
+
+/* Host copy of the env state (checkpoint), SoA, N entries each, in this order:
+ * float32 x, y, theta, v, w, gx, gy, d_prev; int32 t; uint32 episode
+ * (10 * 4 * N bytes).  Waits for hip_stream before copying. */
+#define NAVSIM_STATE_BYTES(n) ((size_t)(n) * 40u)
+navsim_status navsim_get_state(navsim_t h, void *host_soa, size_t bytes, void *hip_stream);
+
+/* Replace the env state from a host blob in the navsim_get_state layout
+ * (restores a checkpoint; also counts as the first reset).  Synchronous. */
+navsim_status navsim_set_state(navsim_t h, const void *host_soa, size_t bytes, void *hip_stream);
+
+/* Free all device and host memory of the handle.  Using h afterwards, or
+ * destroying it twice, is undefined. */
+navsim_status navsim_destroy(navsim_t h);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *navsim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NAVSIM_H */

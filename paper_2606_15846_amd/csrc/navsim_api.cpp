@@ -1,0 +1,495 @@
+// Host side of libnavsim.so: argument checking, map packing, free-cell lists,
+// env grouping, device allocation and kernel launches.  The C ABI is declared
+// and documented in include/navsim.h.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "navsim.h"
+#include "navsim_internal.hpp"
+
+using namespace navsim;
+
+namespace {
+
+thread_local std::string g_err;
+
+navsim_status fail(navsim_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define NS_HIP(call)                                                                        \
+    do {                                                                                    \
+        hipError_t _e = (call);                                                             \
+        if (_e != hipSuccess) return fail(NAVSIM_E_HIP, "%s: %s", #call, hipGetErrorString(_e)); \
+    } while (0)
+
+// Makes the handle's device current for the duration of a call and restores
+// the caller's device afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool finite_pos(float v) { return isfinite(v) && v > 0.0f; }
+
+}  // namespace
+
+struct navsim_s {
+    navsim_config cfg;
+    int device = 0;
+    double rc = 0.0;
+    bool loaded = false;
+    bool initialized = false;
+    // device memory
+    void *state_buf = nullptr;
+    DevState st{};
+    double2 *beams = nullptr;
+    uint32_t *bits = nullptr;
+    MapDesc *maps = nullptr;
+    int32_t *free_cells = nullptr;
+    int32_t *env_map = nullptr;
+    int32_t *perm = nullptr;
+    Tile *tiles = nullptr;
+    int num_maps = 0, num_tiles = 0, max_words = 0;
+};
+
+namespace {
+
+navsim_status check_config(const navsim_config *c) {
+    if (!c) return fail(NAVSIM_E_INVALID_ARG, "cfg is NULL");
+    if (c->abi_version != NAVSIM_ABI_VERSION)
+        return fail(NAVSIM_E_INVALID_ARG, "abi_version %u, library has %u", c->abi_version,
+                    NAVSIM_ABI_VERSION);
+    if (c->num_envs < 1) return fail(NAVSIM_E_INVALID_ARG, "num_envs must be >= 1");
+    if (c->num_beams < 1 || c->num_beams > kMaxBeams)
+        return fail(NAVSIM_E_INVALID_ARG, "num_beams must be in 1..%d", kMaxBeams);
+    if (c->num_sectors < 1 || c->num_beams % c->num_sectors != 0)
+        return fail(NAVSIM_E_INVALID_ARG, "num_sectors must divide num_beams");
+    if (!finite_pos(c->fov_rad)) return fail(NAVSIM_E_INVALID_ARG, "fov_rad must be > 0");
+    if (!finite_pos(c->max_range_m) || c->max_range_m > 1.0e4f)
+        return fail(NAVSIM_E_INVALID_ARG, "max_range_m must be in (0, 1e4]");
+    if (!finite_pos(c->dt_s)) return fail(NAVSIM_E_INVALID_ARG, "dt_s must be > 0");
+    if (c->horizon < 1) return fail(NAVSIM_E_INVALID_ARG, "horizon must be >= 1");
+    if (!isfinite(c->goal_radius_m) || c->goal_radius_m < 0.0f)
+        return fail(NAVSIM_E_INVALID_ARG, "goal_radius_m must be >= 0");
+    if (!isfinite(c->c_progress) || !isfinite(c->r_success) || !isfinite(c->r_collision))
+        return fail(NAVSIM_E_INVALID_ARG, "reward parameters must be finite");
+    if (c->footprint == NAVSIM_DISC) {
+        if (!finite_pos(c->radius_m)) return fail(NAVSIM_E_INVALID_ARG, "radius_m must be > 0");
+    } else if (c->footprint == NAVSIM_RECT) {
+        if (!finite_pos(c->length_m) || !finite_pos(c->width_m))
+            return fail(NAVSIM_E_INVALID_ARG, "length_m and width_m must be > 0");
+    } else {
+        return fail(NAVSIM_E_INVALID_ARG, "footprint must be NAVSIM_DISC or NAVSIM_RECT");
+    }
+    if (!isfinite(c->v_min) || !isfinite(c->v_max) || c->v_min > c->v_max)
+        return fail(NAVSIM_E_INVALID_ARG, "need finite v_min <= v_max");
+    if (!isfinite(c->w_min) || !isfinite(c->w_max) || c->w_min > c->w_max)
+        return fail(NAVSIM_E_INVALID_ARG, "need finite w_min <= w_max");
+    if (!isfinite(c->goal_min_dist_m) || c->goal_min_dist_m < 0.0f)
+        return fail(NAVSIM_E_INVALID_ARG, "goal_min_dist_m must be >= 0");
+    if (c->reset_max_tries < 1 || c->reset_max_tries > 1024)
+        return fail(NAVSIM_E_INVALID_ARG, "reset_max_tries must be in 1..1024");
+    return NAVSIM_OK;
+}
+
+// Angle of beam k to the heading: K equal steps from -pi over a full circle,
+// K points spanning [-fov/2, fov/2] otherwise.
+double beam_angle(const navsim_config &c, int k) {
+    const double pi = 3.14159265358979323846;
+    const double fov = (double)c.fov_rad;
+    const int K = c.num_beams;
+    if (fov >= 2.0 * pi - 1e-6) return -pi + (double)k * (2.0 * pi / (double)K);
+    if (K == 1) return 0.0;
+    return -0.5 * fov + (double)k * (fov / (double)(K - 1));
+}
+
+double circumradius(const navsim_config &c) {
+    if (c.footprint == NAVSIM_DISC) return (double)c.radius_m;
+    const double hl = 0.5 * (double)c.length_m, hb = 0.5 * (double)c.width_m;
+    return sqrt(hl * hl + hb * hb);
+}
+
+// Host copy of the disc predicate used for the free-cell lists (same closed-box
+// rule as the kernels: strictly closer than r, out of bounds occupied).
+bool disc_clear_host(const uint8_t *occ, int W, int H, double s, double x, double y, double r) {
+    const long i0 = (long)floor((x - r) / s), i1 = (long)floor((x + r) / s);
+    const long j0 = (long)floor((y - r) / s), j1 = (long)floor((y + r) / s);
+    const double r2 = r * r;
+    for (long j = j0; j <= j1; ++j)
+        for (long i = i0; i <= i1; ++i) {
+            const bool filled = i < 0 || j < 0 || i >= W || j >= H || occ[(size_t)j * W + i] != 0;
+            if (!filled) continue;
+            const double bx0 = (double)i * s, bx1 = (double)(i + 1) * s;
+            const double by0 = (double)j * s, by1 = (double)(j + 1) * s;
+            const double cx = x < bx0 ? bx0 : (x > bx1 ? bx1 : x);
+            const double cy = y < by0 ? by0 : (y > by1 ? by1 : y);
+            const double ex = x - cx, ey = y - cy;
+            if (ex * ex + ey * ey < r2) return false;
+        }
+    return true;
+}
+
+void free_device(navsim_s *h) {
+    void *ptrs[] = {h->bits, h->maps, h->free_cells, h->env_map, h->perm, h->tiles};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    h->bits = nullptr;
+    h->maps = nullptr;
+    h->free_cells = nullptr;
+    h->env_map = nullptr;
+    h->perm = nullptr;
+    h->tiles = nullptr;
+}
+
+template <typename T>
+navsim_status upload(T **dst, const std::vector<T> &src) {
+    const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+    if (hipMalloc((void **)dst, bytes) != hipSuccess)
+        return fail(NAVSIM_E_OOM, "hipMalloc of %zu bytes failed", bytes);
+    if (!src.empty()) NS_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return NAVSIM_OK;
+}
+
+StepParams make_params(const navsim_s *h) {
+    const navsim_config &c = h->cfg;
+    StepParams p;
+    memset(&p, 0, sizeof p);
+    p.N = c.num_envs;
+    p.K = c.num_beams;
+    p.m = c.num_sectors;
+    p.horizon = c.horizon;
+    p.footprint = c.footprint;
+    p.tries = c.reset_max_tries;
+    p.rmax = c.max_range_m;
+    p.dt = c.dt_s;
+    p.goal_r = c.goal_radius_m;
+    p.c1 = c.c_progress;
+    p.r_succ = c.r_success;
+    p.r_coll = c.r_collision;
+    p.radius = c.radius_m;
+    p.len = c.length_m;
+    p.wid = c.width_m;
+    p.vlo = c.v_min;
+    p.vhi = c.v_max;
+    p.wlo = c.w_min;
+    p.whi = c.w_max;
+    p.gmd = c.goal_min_dist_m;
+    p.key0 = (uint32_t)(c.seed & 0xffffffffu);
+    p.key1 = (uint32_t)(c.seed >> 32);
+    p.rc = h->rc;
+    p.st = h->st;
+    p.env_map = h->env_map;
+    p.maps = h->maps;
+    p.bits = h->bits;
+    p.free_cells = h->free_cells;
+    p.beams = h->beams;
+    p.perm = h->perm;
+    p.tiles = h->tiles;
+    p.num_tiles = h->num_tiles;
+    p.max_words = h->max_words;
+    return p;
+}
+
+navsim_status run(navsim_t h, const StepParams &p, int kernel, hipStream_t s) {
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
+    const hipError_t e = kernel == NAVSIM_KERNEL_PLAIN ? launch_plain(p, s) : launch_fused(p, s);
+    if (e != hipSuccess) return fail(NAVSIM_E_HIP, "kernel launch: %s", hipGetErrorString(e));
+    return NAVSIM_OK;
+}
+
+navsim_status step_common(navsim_t h, const float *act, float *obs, float *reward,
+                          uint8_t *terminated, uint8_t *truncated, float *final_obs,
+                          const navsim_debug *dbg, int32_t kernel, void *stream) {
+    if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
+    if (!h->loaded) return fail(NAVSIM_E_STATE, "navsim_load_maps has not been called");
+    if (!h->initialized) return fail(NAVSIM_E_STATE, "navsim_reset (mask NULL) must come first");
+    if (!act || !obs || !reward || !terminated || !truncated)
+        return fail(NAVSIM_E_INVALID_ARG, "act, obs, reward, terminated, truncated are required");
+    if (kernel != NAVSIM_KERNEL_FUSED && kernel != NAVSIM_KERNEL_PLAIN)
+        return fail(NAVSIM_E_INVALID_ARG, "unknown kernel %d", kernel);
+    StepParams p = make_params(h);
+    p.mode = 0;
+    p.act = act;
+    p.obs = obs;
+    p.reward = reward;
+    p.term = terminated;
+    p.trunc = truncated;
+    p.final_obs = final_obs;
+    if (dbg) {
+        p.d_ranges = dbg->ranges;
+        p.d_hits = dbg->hits;
+        p.d_visits = dbg->visits;
+        p.d_coll = dbg->collision;
+        p.d_goal = dbg->goal;
+        p.d_reset = dbg->reset;
+        p.d_fb = dbg->fallback;
+    }
+    return run(h, p, kernel, (hipStream_t)stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *navsim_last_error(void) { return g_err.c_str(); }
+
+navsim_status navsim_create(const navsim_config *cfg, int hip_device, navsim_t *out) {
+    if (!out) return fail(NAVSIM_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    navsim_status s = check_config(cfg);
+    if (s != NAVSIM_OK) return s;
+    int ndev = 0;
+    NS_HIP(hipGetDeviceCount(&ndev));
+    if (hip_device < 0 || hip_device >= ndev)
+        return fail(NAVSIM_E_INVALID_ARG, "hip_device %d not in 0..%d", hip_device, ndev - 1);
+    DeviceGuard g(hip_device);
+    if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
+    navsim_s *h = new (std::nothrow) navsim_s();
+    if (!h) return fail(NAVSIM_E_OOM, "host allocation failed");
+    h->cfg = *cfg;
+    h->device = hip_device;
+    h->rc = circumradius(*cfg);
+    const size_t N = (size_t)cfg->num_envs;
+    if (hipMalloc(&h->state_buf, 40 * N) != hipSuccess) {
+        delete h;
+        return fail(NAVSIM_E_OOM, "hipMalloc of the env state failed");
+    }
+    if (hipMemset(h->state_buf, 0, 40 * N) != hipSuccess) {
+        (void)hipFree(h->state_buf);
+        delete h;
+        return fail(NAVSIM_E_HIP, "hipMemset of the env state failed");
+    }
+    float *f = (float *)h->state_buf;
+    h->st.x = f;
+    h->st.y = f + N;
+    h->st.th = f + 2 * N;
+    h->st.v = f + 3 * N;
+    h->st.w = f + 4 * N;
+    h->st.gx = f + 5 * N;
+    h->st.gy = f + 6 * N;
+    h->st.dprev = f + 7 * N;
+    h->st.t = (int32_t *)(f + 8 * N);
+    h->st.ep = (uint32_t *)(f + 9 * N);
+    std::vector<double2> beams((size_t)cfg->num_beams);
+    for (int k = 0; k < cfg->num_beams; ++k) {
+        const double a = beam_angle(*cfg, k);
+        beams[k] = make_double2(cos(a), sin(a));
+    }
+    s = upload(&h->beams, beams);
+    if (s != NAVSIM_OK) {
+        (void)hipFree(h->state_buf);
+        delete h;
+        return s;
+    }
+    *out = h;
+    return NAVSIM_OK;
+}
+
+navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *width,
+                               const int32_t *height, const float *res_m, const uint8_t *occ,
+                               const int32_t *env_map) {
+    if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
+    if (num_maps < 1 || !width || !height || !res_m || !occ || !env_map)
+        return fail(NAVSIM_E_INVALID_ARG, "num_maps >= 1 and all arrays are required");
+    const int N = h->cfg.num_envs;
+    std::vector<int64_t> occ_off(num_maps + 1, 0);
+    for (int k = 0; k < num_maps; ++k) {
+        if (width[k] < 1 || height[k] < 1 || width[k] > 4096 || height[k] > 4096)
+            return fail(NAVSIM_E_INVALID_ARG, "map %d: size %dx%d out of range", k, width[k],
+                        height[k]);
+        if (!finite_pos(res_m[k])) return fail(NAVSIM_E_INVALID_ARG, "map %d: res must be > 0", k);
+        const int64_t wpr = (width[k] + 2 + 31) / 32;
+        if (wpr * (int64_t)(height[k] + 2) > kMaxMapWords)
+            return fail(NAVSIM_E_UNSUPPORTED,
+                        "map %d: padded bitmap of %lld words exceeds the %d-word LDS budget", k,
+                        (long long)(wpr * (height[k] + 2)), kMaxMapWords);
+        occ_off[k + 1] = occ_off[k] + (int64_t)width[k] * height[k];
+    }
+    std::vector<int> used(num_maps, 0);
+    for (int e = 0; e < N; ++e) {
+        if (env_map[e] < 0 || env_map[e] >= num_maps)
+            return fail(NAVSIM_E_INVALID_ARG, "env_map[%d] = %d not in 0..%d", e, env_map[e],
+                        num_maps - 1);
+        used[env_map[e]] = 1;
+    }
+
+    // padded bitmaps, free-cell lists
+    std::vector<MapDesc> descs(num_maps);
+    std::vector<uint32_t> bits;
+    std::vector<int32_t> free_cells;
+    int max_words = 4;
+    for (int k = 0; k < num_maps; ++k) {
+        const int W = width[k], H = height[k];
+        const uint8_t *m = occ + occ_off[k];
+        MapDesc &d = descs[k];
+        d.w = W;
+        d.h = H;
+        d.wpr = (W + 2 + 31) / 32;
+        d.words = ((d.wpr * (H + 2)) + 3) & ~3;
+        d.word_off = (int64_t)bits.size();
+        d.res = res_m[k];
+        bits.resize(bits.size() + d.words, 0xffffffffu);
+        uint32_t *b = bits.data() + d.word_off;
+        for (int iy = 0; iy < H; ++iy) {
+            uint32_t *row = b + (size_t)(iy + 1) * d.wpr;
+            for (int wd = 0; wd < d.wpr; ++wd) row[wd] = 0u;
+            for (int c = 0; c < d.wpr * 32; ++c) {
+                const int ix = c - 1;
+                const bool filled = ix < 0 || ix >= W || m[(size_t)iy * W + ix] != 0;
+                if (filled) row[c >> 5] |= 1u << (c & 31);
+            }
+        }
+        max_words = std::max(max_words, d.words);
+        d.free_off = (int64_t)free_cells.size();
+        const double s = (double)res_m[k];
+        for (int iy = 0; iy < H; ++iy)
+            for (int ix = 0; ix < W; ++ix) {
+                const float cx = (float)(((double)ix + 0.5) * s);
+                const float cy = (float)(((double)iy + 0.5) * s);
+                if (disc_clear_host(m, W, H, s, (double)cx, (double)cy, h->rc))
+                    free_cells.push_back(iy * W + ix);
+            }
+        d.free_cnt = (int32_t)((int64_t)free_cells.size() - d.free_off);
+        if (used[k] && d.free_cnt == 0)
+            return fail(NAVSIM_E_NO_FREE_SPACE, "map %d has no cell where the footprint fits", k);
+    }
+
+    const size_t lds = 4 * ((size_t)max_words + (size_t)kWavesPerGroup * h->cfg.num_beams);
+    if (lds > 65536)
+        return fail(NAVSIM_E_UNSUPPORTED,
+                    "largest map plus %d beams need %zu bytes of LDS per workgroup (max 65536)",
+                    h->cfg.num_beams, lds);
+
+    // group envs by map into tiles of up to kWavesPerGroup envs
+    std::vector<int32_t> perm(N);
+    for (int e = 0; e < N; ++e) perm[e] = e;
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&](int32_t a, int32_t b) { return env_map[a] < env_map[b]; });
+    std::vector<Tile> tiles;
+    for (int i = 0; i < N;) {
+        const int map = env_map[perm[i]];
+        int j = i;
+        while (j < N && env_map[perm[j]] == map && j - i < kWavesPerGroup) ++j;
+        tiles.push_back(Tile{map, i, j - i, 0});
+        i = j;
+    }
+
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
+    free_device(h);
+    h->loaded = false;
+    h->initialized = false;
+    navsim_status s;
+    std::vector<int32_t> em(env_map, env_map + N);
+    if ((s = upload(&h->bits, bits)) != NAVSIM_OK) return s;
+    if ((s = upload(&h->maps, descs)) != NAVSIM_OK) return s;
+    if ((s = upload(&h->free_cells, free_cells)) != NAVSIM_OK) return s;
+    if ((s = upload(&h->env_map, em)) != NAVSIM_OK) return s;
+    if ((s = upload(&h->perm, perm)) != NAVSIM_OK) return s;
+    if ((s = upload(&h->tiles, tiles)) != NAVSIM_OK) return s;
+    h->num_maps = num_maps;
+    h->num_tiles = (int)tiles.size();
+    h->max_words = max_words;
+    h->loaded = true;
+    return NAVSIM_OK;
+}
+
+navsim_status navsim_reset(navsim_t h, const uint8_t *mask, float *obs, void *hip_stream) {
+    if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
+    if (!h->loaded) return fail(NAVSIM_E_STATE, "navsim_load_maps has not been called");
+    if (!obs) return fail(NAVSIM_E_INVALID_ARG, "obs is required");
+    if (mask && !h->initialized)
+        return fail(NAVSIM_E_STATE, "the first reset must cover all envs (mask NULL)");
+    StepParams p = make_params(h);
+    p.mode = 1;
+    p.mask = mask;
+    p.obs = obs;
+    const navsim_status s = run(h, p, NAVSIM_KERNEL_FUSED, (hipStream_t)hip_stream);
+    if (s == NAVSIM_OK) h->initialized = true;
+    return s;
+}
+
+navsim_status navsim_step(navsim_t h, const float *act, float *obs, float *reward,
+                          uint8_t *terminated, uint8_t *truncated, float *final_obs,
+                          void *hip_stream) {
+    return step_common(h, act, obs, reward, terminated, truncated, final_obs, nullptr,
+                       NAVSIM_KERNEL_FUSED, hip_stream);
+}
+
+navsim_status navsim_step_plain(navsim_t h, const float *act, float *obs, float *reward,
+                                uint8_t *terminated, uint8_t *truncated, float *final_obs,
+                                void *hip_stream) {
+    return step_common(h, act, obs, reward, terminated, truncated, final_obs, nullptr,
+                       NAVSIM_KERNEL_PLAIN, hip_stream);
+}
+
+navsim_status navsim_step_debug(navsim_t h, const float *act, float *obs, float *reward,
+                                uint8_t *terminated, uint8_t *truncated, float *final_obs,
+                                const navsim_debug *dbg, int32_t kernel, void *hip_stream) {
+    return step_common(h, act, obs, reward, terminated, truncated, final_obs, dbg, kernel,
+                       hip_stream);
+}
+
+navsim_status navsim_get_state(navsim_t h, void *host_soa, size_t bytes, void *hip_stream) {
+    if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
+    if (!host_soa || bytes != NAVSIM_STATE_BYTES(h->cfg.num_envs))
+        return fail(NAVSIM_E_INVALID_ARG, "need a host buffer of exactly %zu bytes",
+                    NAVSIM_STATE_BYTES(h->cfg.num_envs));
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
+    NS_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+    NS_HIP(hipMemcpy(host_soa, h->state_buf, bytes, hipMemcpyDeviceToHost));
+    return NAVSIM_OK;
+}
+
+navsim_status navsim_set_state(navsim_t h, const void *host_soa, size_t bytes, void *hip_stream) {
+    if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
+    if (!host_soa || bytes != NAVSIM_STATE_BYTES(h->cfg.num_envs))
+        return fail(NAVSIM_E_INVALID_ARG, "need a host buffer of exactly %zu bytes",
+                    NAVSIM_STATE_BYTES(h->cfg.num_envs));
+    if (!h->loaded) return fail(NAVSIM_E_STATE, "navsim_load_maps has not been called");
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
+    NS_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
+    NS_HIP(hipMemcpy(h->state_buf, host_soa, bytes, hipMemcpyHostToDevice));
+    h->initialized = true;
+    return NAVSIM_OK;
+}
+
+navsim_status navsim_destroy(navsim_t h) {
+    if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
+    {
+        DeviceGuard g(h->device);
+        free_device(h);
+        if (h->beams) (void)hipFree(h->beams);
+        if (h->state_buf) (void)hipFree(h->state_buf);
+    }
+    delete h;
+    return NAVSIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,268 @@
+"""Python binding of libnavsim.so (the C ABI in include/navsim.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+library.  Device buffers are torch tensors on the simulator's device; the
+calls enqueue on the current torch stream of that device unless a stream is
+given.  If the library is not built, loading fails loudly: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnavsim.so")
+
+NAVSIM_ABI_VERSION = 1
+NAVSIM_DISC, NAVSIM_RECT = 0, 1
+NAVSIM_KERNEL_FUSED, NAVSIM_KERNEL_PLAIN = 0, 1
+STATUS = {0: "NAVSIM_OK", -1: "NAVSIM_E_INVALID_ARG", -2: "NAVSIM_E_BAD_HANDLE",
+          -3: "NAVSIM_E_STATE", -4: "NAVSIM_E_NO_FREE_SPACE", -5: "NAVSIM_E_OOM",
+          -6: "NAVSIM_E_HIP", -7: "NAVSIM_E_UNSUPPORTED"}
+EXPORTS = ("navsim_create", "navsim_load_maps", "navsim_reset", "navsim_step",
+           "navsim_step_plain", "navsim_step_debug", "navsim_get_state", "navsim_set_state",
+           "navsim_destroy", "navsim_last_error")
+STATE_KEYS = ("x", "y", "th", "v", "w", "gx", "gy", "dprev", "t", "ep")
+_STATE_DT = (np.float32,) * 8 + (np.int32, np.uint32)
+
+
+class NavsimConfig(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("num_envs", C.c_int32), ("num_beams", C.c_int32),
+        ("num_sectors", C.c_int32), ("fov_rad", C.c_float), ("max_range_m", C.c_float),
+        ("dt_s", C.c_float), ("horizon", C.c_int32), ("goal_radius_m", C.c_float),
+        ("c_progress", C.c_float), ("r_success", C.c_float), ("r_collision", C.c_float),
+        ("footprint", C.c_int32), ("radius_m", C.c_float), ("length_m", C.c_float),
+        ("width_m", C.c_float), ("v_min", C.c_float), ("v_max", C.c_float),
+        ("w_min", C.c_float), ("w_max", C.c_float), ("goal_min_dist_m", C.c_float),
+        ("reset_max_tries", C.c_int32), ("seed", C.c_uint64),
+    ]
+
+
+class NavsimDebug(C.Structure):
+    _fields_ = [("ranges", C.c_void_p), ("hits", C.c_void_p), ("visits", C.c_void_p),
+                ("collision", C.c_void_p), ("goal", C.c_void_p), ("reset", C.c_void_p),
+                ("fallback", C.c_void_p)]
+
+
+class NavsimError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libnavsim.so (built in-tree by __graft_entry__.build())."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(path)
+    vp, i32 = C.c_void_p, C.c_int32
+    L.navsim_create.argtypes = [C.POINTER(NavsimConfig), C.c_int, C.POINTER(vp)]
+    L.navsim_load_maps.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.navsim_reset.argtypes = [vp, vp, vp, vp]
+    L.navsim_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.navsim_step_plain.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.navsim_step_debug.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(NavsimDebug), i32, vp]
+    L.navsim_get_state.argtypes = [vp, vp, C.c_size_t, vp]
+    L.navsim_set_state.argtypes = [vp, vp, C.c_size_t, vp]
+    L.navsim_destroy.argtypes = [vp]
+    L.navsim_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name != "navsim_last_error":
+            getattr(L, name).restype = C.c_int
+    _LIB = L
+    return L
+
+
+def navsim_last_error() -> str:
+    return load_library().navsim_last_error().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise NavsimError(status, navsim_last_error())
+
+
+def make_config(cfg: dict) -> NavsimConfig:
+    c = NavsimConfig()
+    c.abi_version = NAVSIM_ABI_VERSION
+    for name, _ in NavsimConfig._fields_[1:]:
+        setattr(c, name, cfg[name])
+    return c
+
+
+def _dev_ptr(t, dtype, shape, device, name, optional=False):
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or t.device != device:
+        raise ValueError(f"{name} must be a tensor on {device}")
+    if t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream, device):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return C.c_void_p(s.cuda_stream)
+
+
+def navsim_create(cfg: dict, hip_device: int = 0):
+    h = C.c_void_p()
+    c = make_config(cfg)
+    _check(load_library().navsim_create(C.byref(c), int(hip_device), C.byref(h)))
+    return h
+
+
+def navsim_load_maps(h, maps, res, env_map):
+    maps = [np.ascontiguousarray(m, dtype=np.uint8) for m in maps]
+    w = np.array([m.shape[1] for m in maps], np.int32)
+    hh = np.array([m.shape[0] for m in maps], np.int32)
+    r = np.asarray(res, np.float32)
+    occ = np.ascontiguousarray(np.concatenate([m.ravel() for m in maps]))
+    em = np.ascontiguousarray(env_map, dtype=np.int32)
+    _check(load_library().navsim_load_maps(h, len(maps), w.ctypes.data, hh.ctypes.data,
+                                           r.ctypes.data, occ.ctypes.data, em.ctypes.data))
+
+
+def navsim_reset(h, mask, obs, stream=None):
+    dev = obs.device
+    _check(load_library().navsim_reset(
+        h, None if mask is None else C.c_void_p(mask.data_ptr()), C.c_void_p(obs.data_ptr()),
+        _stream_ptr(stream, dev)))
+
+
+def navsim_step(h, act, obs, reward, terminated, truncated, final_obs=None, stream=None):
+    _check(load_library().navsim_step(
+        h, C.c_void_p(act.data_ptr()), C.c_void_p(obs.data_ptr()), C.c_void_p(reward.data_ptr()),
+        C.c_void_p(terminated.data_ptr()), C.c_void_p(truncated.data_ptr()),
+        None if final_obs is None else C.c_void_p(final_obs.data_ptr()),
+        _stream_ptr(stream, obs.device)))
+
+
+def navsim_step_plain(h, act, obs, reward, terminated, truncated, final_obs=None, stream=None):
+    _check(load_library().navsim_step_plain(
+        h, C.c_void_p(act.data_ptr()), C.c_void_p(obs.data_ptr()), C.c_void_p(reward.data_ptr()),
+        C.c_void_p(terminated.data_ptr()), C.c_void_p(truncated.data_ptr()),
+        None if final_obs is None else C.c_void_p(final_obs.data_ptr()),
+        _stream_ptr(stream, obs.device)))
+
+
+def navsim_step_debug(h, act, obs, reward, terminated, truncated, final_obs, dbg: dict,
+                      kernel: int = NAVSIM_KERNEL_FUSED, stream=None):
+    d = NavsimDebug()
+    for name, _ in NavsimDebug._fields_:
+        t = dbg.get(name)
+        setattr(d, name, None if t is None else t.data_ptr())
+    _check(load_library().navsim_step_debug(
+        h, C.c_void_p(act.data_ptr()), C.c_void_p(obs.data_ptr()), C.c_void_p(reward.data_ptr()),
+        C.c_void_p(terminated.data_ptr()), C.c_void_p(truncated.data_ptr()),
+        None if final_obs is None else C.c_void_p(final_obs.data_ptr()), C.byref(d), int(kernel),
+        _stream_ptr(stream, obs.device)))
+
+
+def navsim_get_state(h, num_envs: int, stream=None, device=None) -> dict:
+    buf = np.zeros(10 * num_envs, np.uint32)
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    _check(load_library().navsim_get_state(h, buf.ctypes.data, buf.nbytes,
+                                           _stream_ptr(stream, dev)))
+    out = {}
+    for i, (k, dt) in enumerate(zip(STATE_KEYS, _STATE_DT)):
+        out[k] = buf[i * num_envs:(i + 1) * num_envs].view(dt).copy()
+    return out
+
+
+def navsim_set_state(h, state: dict, num_envs: int, stream=None, device=None):
+    buf = np.zeros(10 * num_envs, np.uint32)
+    for i, (k, dt) in enumerate(zip(STATE_KEYS, _STATE_DT)):
+        buf[i * num_envs:(i + 1) * num_envs] = np.asarray(state[k]).astype(dt).view(np.uint32)
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    _check(load_library().navsim_set_state(h, buf.ctypes.data, buf.nbytes,
+                                           _stream_ptr(stream, dev)))
+
+
+def navsim_destroy(h):
+    _check(load_library().navsim_destroy(h))
+
+
+class NavSim:
+    """Gymnasium-style vector environment over one navsim handle (section
+    2.2.4): step() returns obs, reward, terminated, truncated and the final
+    observation of the envs that ended."""
+
+    def __init__(self, cfg: dict, maps, res, env_map, device: int | str = 0):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        self.cfg = dict(cfg)
+        self.N, self.K, self.m = int(cfg["num_envs"]), int(cfg["num_beams"]), int(cfg["num_sectors"])
+        self.h = None
+        self.h = navsim_create(cfg, self.device.index or 0)
+        try:
+            navsim_load_maps(self.h, maps, res, env_map)
+        except Exception:
+            h, self.h = self.h, None
+            navsim_destroy(h)
+            raise
+        z = dict(device=self.device)
+        self.obs = torch.zeros(self.N, self.m + 4, dtype=torch.float32, **z)
+        self.final_obs = torch.zeros(self.N, self.m + 4, dtype=torch.float32, **z)
+        self.reward = torch.zeros(self.N, dtype=torch.float32, **z)
+        self.terminated = torch.zeros(self.N, dtype=torch.uint8, **z)
+        self.truncated = torch.zeros(self.N, dtype=torch.uint8, **z)
+
+    def close(self):
+        h, self.h = getattr(self, "h", None), None
+        if h is not None:
+            navsim_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_act(self, act):
+        _dev_ptr(act, torch.float32, (self.N, 2), self.device, "act")
+
+    def reset(self, mask=None):
+        if mask is not None:
+            _dev_ptr(mask, torch.uint8, (self.N,), self.device, "mask")
+        navsim_reset(self.h, mask, self.obs)
+        return self.obs
+
+    def step(self, act, plain: bool = False):
+        self._check_act(act)
+        fn = navsim_step_plain if plain else navsim_step
+        fn(self.h, act, self.obs, self.reward, self.terminated, self.truncated, self.final_obs)
+        return self.obs, self.reward, self.terminated, self.truncated, {"final_obs": self.final_obs}
+
+    def step_debug(self, act, kernel=NAVSIM_KERNEL_FUSED):
+        self._check_act(act)
+        z = dict(device=self.device)
+        dbg = dict(ranges=torch.zeros(self.N, self.K, dtype=torch.float32, **z),
+                   hits=torch.zeros(self.N, self.K, dtype=torch.int32, **z),
+                   visits=torch.zeros(self.N, self.K, dtype=torch.int32, **z),
+                   collision=torch.zeros(self.N, dtype=torch.uint8, **z),
+                   goal=torch.zeros(self.N, dtype=torch.uint8, **z),
+                   reset=torch.zeros(self.N, dtype=torch.uint8, **z),
+                   fallback=torch.zeros(self.N, dtype=torch.uint8, **z))
+        navsim_step_debug(self.h, act, self.obs, self.reward, self.terminated, self.truncated,
+                          self.final_obs, dbg, kernel)
+        return dbg
+
+    def get_state(self) -> dict:
+        return navsim_get_state(self.h, self.N, device=self.device)
+
+    def set_state(self, state: dict):
+        navsim_set_state(self.h, state, self.N, device=self.device)

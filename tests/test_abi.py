@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI (no GPU compute): the library loads, exports
+every entry point declared in include/navsim.h, the Python binding's struct
+layout matches the C header, and argument validation that happens before any
+HIP call reports the documented errors."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2606_15846_amd import navsim
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "navsim.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:navsim_status|const char \*)\s*(navsim_\w+)\s*\(", text,
+                                 re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = navsim.load_library()
+    names = declared_functions()
+    assert len(names) == 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(navsim.EXPORTS) == names
+
+
+def test_struct_layout_matches_header(tmp_path):
+    # compile a probe against the header with the host C compiler
+    fields = [f for f, _ in navsim.NavsimConfig._fields_]
+    dfields = [f for f, _ in navsim.NavsimDebug._fields_]
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "navsim.h"', "int main(void){",
+           'printf("%zu\\n", sizeof(navsim_config));',
+           'printf("%zu\\n", sizeof(navsim_debug));']
+    src += [f'printf("%zu\\n", offsetof(navsim_config, {f}));' for f in fields]
+    src += [f'printf("%zu\\n", offsetof(navsim_debug, {f}));' for f in dfields]
+    src += ["return 0;}"]
+    c = tmp_path / "probe.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == C.sizeof(navsim.NavsimConfig)
+    assert vals[1] == C.sizeof(navsim.NavsimDebug)
+    offs = [getattr(navsim.NavsimConfig, f).offset for f in fields]
+    doffs = [getattr(navsim.NavsimDebug, f).offset for f in dfields]
+    assert vals[2:2 + len(fields)] == offs
+    assert vals[2 + len(fields):] == doffs
+
+
+def _cfg(**kw):
+    from workloads import configs
+    c = configs.make_config(num_envs=8, num_beams=36, num_sectors=6, fov_rad=6.2832,
+                            max_range_m=3.0, dt_s=0.1, footprint=0, radius_m=0.18,
+                            v_min=0.0, v_max=0.5, w_min=-1.0, w_max=1.0)
+    c.update(kw)
+    return c
+
+
+@pytest.mark.parametrize("bad", [
+    dict(num_envs=0), dict(num_beams=0), dict(num_beams=5000), dict(num_sectors=7),
+    dict(max_range_m=0.0), dict(max_range_m=float("nan")), dict(dt_s=-1.0), dict(horizon=0),
+    dict(footprint=2), dict(radius_m=0.0), dict(footprint=1, length_m=0.0, width_m=0.3),
+    dict(v_min=1.0, v_max=0.0), dict(reset_max_tries=0), dict(goal_min_dist_m=-1.0),
+])
+def test_config_validation_before_any_device_call(bad):
+    lib = navsim.load_library()
+    c = navsim.make_config(_cfg(**bad))
+    h = C.c_void_p(1234)
+    st = lib.navsim_create(C.byref(c), 0, C.byref(h))
+    assert st == -1
+    assert h.value is None
+    assert navsim.navsim_last_error() != ""
+
+
+def test_abi_version_and_null_arguments():
+    lib = navsim.load_library()
+    c = navsim.make_config(_cfg())
+    c.abi_version = 99
+    h = C.c_void_p()
+    assert lib.navsim_create(C.byref(c), 0, C.byref(h)) == -1
+    assert "abi_version" in navsim.navsim_last_error()
+    assert lib.navsim_create(None, 0, C.byref(h)) == -1
+    assert lib.navsim_create(C.byref(c), 0, None) == -1
+    for fn, args in [("navsim_step", (None,) * 8), ("navsim_step_plain", (None,) * 8),
+                     ("navsim_reset", (None,) * 4), ("navsim_destroy", (None,)),
+                     ("navsim_get_state", (None, None, 0, None)),
+                     ("navsim_set_state", (None, None, 0, None)),
+                     ("navsim_load_maps", (None, 1, None, None, None, None, None))]:
+        assert getattr(lib, fn)(*args) == -2, fn

@@ -1,0 +1,242 @@
+"""GPU parity: the HIP step (fused and plain mappings, through the C ABI)
+against the CPU oracle, teacher-forced from identical states each step."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2606_15846_amd import navsim
+from paper_2606_15846_amd.navsim import NAVSIM_KERNEL_FUSED, NAVSIM_KERNEL_PLAIN, NavSim
+from tests.parity import compare_step, gpu_step
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+KERNELS = {"fused": NAVSIM_KERNEL_FUSED, "plain": NAVSIM_KERNEL_PLAIN}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_pair(cfg, maps, res, env_map):
+    sim = NavSim(cfg, maps, res, env_map, device=0)
+    ref = oracle.OracleSim(cfg, maps, res, env_map)
+    return sim, ref
+
+
+def run_teacher_forced(sim, ref, steps, kernel, seed=42, threads=16, label=""):
+    obs = sim.reset()
+    ref_obs, _ = ref.reset(threads=threads)
+    torch.cuda.synchronize()
+    st = sim.get_state()
+    for k in oracle.STATE_KEYS:
+        assert np.array_equal(st[k], ref.state[k]), f"{label}: reset state {k} differs"
+    acts = configs.uniform_actions(steps, ref.N, seed=seed)
+    totals = dict(rays=0, grazing=0, grazing_mismatch=0, resets=0, visits=0)
+    for t in range(steps):
+        ref.set_state(sim.get_state())
+        g, gst = gpu_step(sim, acts[t], kernel)
+        r = ref.step(acts[t], threads=threads)
+        c = compare_step(g, r, gst, ref, label=f"{label} step {t}")
+        for k in totals:
+            totals[k] += c[k]
+    say(f"{label}: {totals}")
+    return totals
+
+
+@pytest.mark.parametrize("kname", ["fused", "plain"])
+def test_c1_full_rollout(kname):
+    say(f"c1 rollout 16 envs x 200 steps, kernel={kname}")
+    w = configs.build_workload("c1")
+    sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
+    tot = run_teacher_forced(sim, ref, 200, KERNELS[kname], label=f"c1/{kname}")
+    assert tot["resets"] > 0
+    sim.close()
+
+
+def test_c2_full_size_fused():
+    say("c2 4096 envs x 360 beams, 16 maps 128^2, fused, 4 steps")
+    w = configs.build_workload("c2")
+    sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
+    tot = run_teacher_forced(sim, ref, 4, NAVSIM_KERNEL_FUSED, label="c2/fused")
+    assert tot["grazing"] < 0.01 * tot["rays"]
+    sim.close()
+
+
+def test_c2_plain_subset():
+    say("c2 maps, 256 envs, plain, 3 steps")
+    w = configs.build_workload("c2", num_envs=256)
+    sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
+    run_teacher_forced(sim, ref, 3, NAVSIM_KERNEL_PLAIN, label="c2/plain")
+    sim.close()
+
+
+def test_c3_rect_reverse_fused():
+    say("c3 maps 256^2, rectangle footprint, 720 beams, 2048 envs, fused, 3 steps")
+    w = configs.build_workload("c3", num_envs=2048)
+    sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
+    run_teacher_forced(sim, ref, 3, NAVSIM_KERNEL_FUSED, label="c3/fused")
+    sim.close()
+
+
+def _small_cfg(**kw):
+    c = configs.make_config(num_envs=13, num_beams=100, num_sectors=10, fov_rad=2 * math.pi,
+                            max_range_m=2.5, dt_s=0.1, footprint=0, radius_m=0.18,
+                            v_min=-0.5, v_max=0.5, w_min=-1.0, w_max=1.0)
+    c.update(kw)
+    return c
+
+
+@pytest.mark.parametrize("case", ["ragged", "many_sectors", "fov270", "rect_noborder",
+                                  "single_env", "long_range"])
+@pytest.mark.parametrize("kname", ["fused", "plain"])
+def test_edge_configs(case, kname):
+    say(f"edge config {case}, kernel={kname}")
+    from workloads import maps as gm
+    occ = gm.gen_rect_disc_map(7, w=90, h=70, res=0.05)
+    cfg = _small_cfg()
+    if case == "many_sectors":
+        cfg.update(num_beams=130, num_sectors=130)
+    elif case == "fov270":
+        cfg.update(fov_rad=math.radians(270.0), num_beams=1080, num_sectors=30, max_range_m=20.0)
+    elif case == "rect_noborder":
+        occ = (np.random.default_rng(3).random((60, 75)) < 0.003).astype(np.uint8)
+        cfg.update(footprint=1, length_m=0.8, width_m=0.41)
+    elif case == "single_env":
+        cfg.update(num_envs=1)
+    elif case == "long_range":
+        cfg.update(max_range_m=50.0, num_beams=64, num_sectors=8)
+    maps = [occ, occ[::-1].copy()]
+    env_map = (np.arange(cfg["num_envs"]) % 2).astype(np.int32)
+    sim, ref = make_pair(cfg, maps, [0.05, 0.05], env_map)
+    run_teacher_forced(sim, ref, 25, KERNELS[kname], seed=5, label=f"{case}/{kname}")
+    sim.close()
+
+
+def test_pose_outside_map_and_inside_obstacle():
+    say("poses outside the map / inside an obstacle")
+    occ = np.zeros((40, 40), np.uint8)
+    occ[20:25, 20:25] = 1
+    cfg = _small_cfg(num_envs=4, num_beams=64, num_sectors=8)
+    sim, ref = make_pair(cfg, [occ], [0.05], np.zeros(4, np.int32))
+    sim.reset()
+    ref.reset()
+    torch.cuda.synchronize()
+    st = sim.get_state()
+    st["x"][:] = [-0.3, 1.1, 2.5, 1.0]
+    st["y"][:] = [0.5, 1.1, 0.5, 1.0]
+    st["v"][:] = 0.0
+    sim.set_state(st)
+    ref.set_state(st)
+    act = np.zeros((4, 2), np.float32)
+    act[:, 0] = 0.0   # v = 0 (bounds -0.5..0.5)
+    g, gst = gpu_step(sim, act, NAVSIM_KERNEL_FUSED)
+    r = ref.step(act)
+    compare_step(g, r, gst, ref, label="outside/inside")
+    assert r["collision"][0] and r["collision"][1] and r["collision"][2]
+    assert np.all(g["hits"][0] == -2) and np.all(g["ranges"][0] == 0)
+    assert np.all(g["ranges"][1] == 0)
+    sim.close()
+
+
+def test_fused_equals_plain_bitwise():
+    say("fused vs plain bitwise, c2 maps, 512 envs, 5 steps")
+    w = configs.build_workload("c2", num_envs=512)
+    a = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
+    b = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
+    a.reset()
+    b.reset()
+    acts = configs.uniform_actions(5, 512, seed=9)
+    for t in range(5):
+        ga, sa = gpu_step(a, acts[t], NAVSIM_KERNEL_FUSED)
+        gb, sb = gpu_step(b, acts[t], NAVSIM_KERNEL_PLAIN)
+        for k in ga:
+            assert np.array_equal(ga[k], gb[k]) or k == "final_obs", k
+        for k in oracle.STATE_KEYS:
+            assert np.array_equal(sa[k], sb[k]), k
+    a.close()
+    b.close()
+
+
+def test_determinism_and_checkpoint():
+    say("determinism + checkpoint/resume, c2 maps, 256 envs")
+    w = configs.build_workload("c2", num_envs=256)
+    acts = torch.from_numpy(configs.uniform_actions(100, 256, seed=11)).cuda()
+
+    def run(sim, t0, t1):
+        for t in range(t0, t1):
+            sim.step(acts[t])
+        torch.cuda.synchronize()
+        return sim.obs.cpu().numpy().copy(), sim.get_state()
+
+    a = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
+    a.reset()
+    oa, sa = run(a, 0, 100)
+    b = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
+    b.reset()
+    _, mid = run(b, 0, 50)
+    b.close()
+    c = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
+    c.set_state(mid)
+    oc, sc = run(c, 50, 100)
+    assert np.array_equal(oa, oc)
+    for k in oracle.STATE_KEYS:
+        assert np.array_equal(sa[k], sc[k]), k
+    a.close()
+    c.close()
+
+
+def test_reset_mask_leaves_other_rows():
+    say("masked reset")
+    w = configs.build_workload("c2", num_envs=64)
+    sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
+    sim.reset()
+    ref.reset()
+    torch.cuda.synchronize()
+    before = sim.obs.cpu().numpy().copy()
+    mask = np.zeros(64, np.uint8)
+    mask[[0, 5, 63]] = 1
+    sim.reset(torch.from_numpy(mask).cuda())
+    ro, _ = ref.reset(mask)
+    torch.cuda.synchronize()
+    after = sim.obs.cpu().numpy()
+    keep = mask == 0
+    assert np.array_equal(before[keep], after[keep])
+    st = sim.get_state()
+    for k in oracle.STATE_KEYS:
+        assert np.array_equal(st[k], ref.state[k]), k
+    assert np.abs(after[mask == 1] - ro[mask == 1]).max() <= 1e-4
+    sim.close()
+
+
+def test_api_errors_on_device():
+    say("API error paths on the device")
+    w = configs.build_workload("c1")
+    cfg = w["cfg"]
+    h = navsim.navsim_create(cfg, 0)
+    obs = torch.zeros(16, cfg["num_sectors"] + 4, device="cuda")
+    act = torch.zeros(16, 2, device="cuda")
+    r = torch.zeros(16, device="cuda")
+    u8 = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(navsim.NavsimError) as ei:
+        navsim.navsim_step(h, act, obs, r, u8, u8)
+    assert ei.value.status == -3
+    with pytest.raises(navsim.NavsimError) as ei:
+        navsim.navsim_load_maps(h, w["maps"], w["res"], np.full(16, 3, np.int32))
+    assert ei.value.status == -1
+    full = np.ones((20, 20), np.uint8)
+    with pytest.raises(navsim.NavsimError) as ei:
+        navsim.navsim_load_maps(h, [full], [0.1], np.zeros(16, np.int32))
+    assert ei.value.status == -4
+    navsim.navsim_load_maps(h, w["maps"], w["res"], w["env_map"])
+    with pytest.raises(navsim.NavsimError) as ei:
+        navsim.navsim_reset(h, u8, obs)
+    assert ei.value.status == -3
+    navsim.navsim_reset(h, None, obs)
+    navsim.navsim_step(h, act, obs, r, u8, u8)
+    torch.cuda.synchronize()
+    navsim.navsim_destroy(h)
