@@ -5,9 +5,10 @@ and rasterised discs, ~15 % occupancy), disc robot r = 0.18 m, 360 beams over
 360 deg pooled to 30 sectors, r_max 6 m, dt 0.1 s, uniform random actions,
 auto-reset.  Inputs are resident in HBM before the timed region.
 
-One step = one launch of the fused step kernel over all envs (action ->
-pose -> collision -> 360-beam scan -> pooling -> reward/flags -> masked
-reset).  Prints one JSON line.
+One step = one navsim_step call over all envs = one launch of the fused step
+kernel (action -> pose -> collision -> reward/flags -> reset draws -> 360-beam
+scan of every new pose and every reset pose -> sector pooling -> observation
+rows).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -80,6 +81,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--tile-envs", type=int, default=None)
+    ap.add_argument("--refill-at", type=int, default=None)
+    ap.add_argument("--groups", type=int, default=None)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 device-to-device copies of 256 MiB (HBM counter scale)")
     args = ap.parse_args()
@@ -111,6 +115,14 @@ def main():
     acts_np = configs.uniform_actions(total, N, seed=42)
     acts = torch.from_numpy(acts_np).to(dev)
     sim = NavSim(cfg, w["maps"], w["res"], w["env_map"], device=0)
+    # launch shape: the autotuned one for this workload (paper_2606_15846_amd/
+    # tuning.json) unless given on the command line; results do not depend on it
+    from paper_2606_15846_amd import autotune
+    tuning = autotune.best_for(autotune.workload_key(cfg, w["maps"]))
+    for k in ("tile_envs", "refill_at", "groups"):
+        if getattr(args, k) is not None:
+            tuning[k] = getattr(args, k)
+    sim.set_tuning(**tuning)
     sim.reset()
     for t in range(args.warmup):
         sim.step(acts[t])
@@ -160,6 +172,7 @@ def main():
         plain = {"value": prate, "rays_per_s": prate * K, "steps": args.plain_steps,
                  "ms_per_step": pms / args.plain_steps,
                  "mapping": "one thread per env, beams in sequence, bitmap in HBM"}
+    sim_tuning = sim.get_tuning()
     sim.close()
 
     cpu = None if args.no_cpu else cpu_baseline(w, acts_np[args.warmup:])
@@ -183,13 +196,15 @@ def main():
         "rays_per_s": value * K,
         "plain": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "tuning": sim_tuning,
         "reset_rate_per_step": reset_rate,
         "cell_visits_per_env_step": visits / (N * args.steps),
         "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / LDS_PEAK_GBS, "traffic": traffic,
                      "kernel": "fused_step_kernel",
                      "avg_launch_us": avg_launch_s * 1e6,
-                     "algorithmic_bytes_per_launch": lds_bytes_per_launch},
+                     "algorithmic_bytes_per_launch": lds_bytes_per_launch,
+                     "bytes_per_unit": "4 B of bitmap word per DDA cell visit of the step's pre-reset scan"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

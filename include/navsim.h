@@ -3,8 +3,8 @@
  *
  * C ABI of libnavsim.so.  Implements the data-parallel environment step of
  * FlashNav (arXiv 2606.15846, section 2.2): thousands of independent
- * goal-conditioned navigation environments on occupancy bitmaps, advanced by
- * one fused GPU step per call.
+ * goal-conditioned navigation environments on occupancy bitmaps, advanced
+ * together by one step call.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -94,7 +94,11 @@ navsim_status navsim_create(const navsim_config *cfg, int hip_device, navsim_t *
 
 /* Load the occupancy bitmaps (section 2.2.1) and the env-to-map assignment.
  * All pointers are host memory, copied during the call (synchronous).
- *   width, height [num_maps]  cells per row / rows, 1..2048 each
+ *   width, height [num_maps]  cells per row / rows, >= 1; the map with its
+ *                             4-cell padding ring, (height + 8) * ceil((width + 8)
+ *                             / 32) 32-bit words, must fit 48 KiB of LDS (for
+ *                             example 512 x 700 cells); larger maps give
+ *                             NAVSIM_E_UNSUPPORTED
  *   res_m [num_maps]          cell size in metres (> 0); cell (ix, iy) covers
  *                             [ix s, (ix+1) s) x [iy s, (iy+1) s)
  *   occ                       maps concatenated, each row-major [height][width],
@@ -127,7 +131,11 @@ navsim_status navsim_reset(navsim_t h, const uint8_t *mask, float *obs, void *hi
  *   truncated   device uint8 [N]     t reached the horizon with neither event
  *   final_obs   device float32 [N][m+4] or NULL: O_{t+1} of envs that ended
  *               (rows of other envs untouched)
- * The fused GPU step: one wavefront per env, the env's bitmap staged in LDS. */
+ * One launch on hip_stream: a workgroup per tile of envs that share a map
+ * stages the map's bitmap in LDS, steps each env on a group of 16 lanes
+ * (ballots for collision and reset attempts), walks all of the tile's rays
+ * (new poses and reset poses) with every lane, pools sectors in LDS and writes
+ * the observation rows. */
 navsim_status navsim_step(navsim_t h, const float *act, float *obs, float *reward,
                           uint8_t *terminated, uint8_t *truncated, float *final_obs,
                           void *hip_stream);
@@ -160,6 +168,23 @@ enum { NAVSIM_KERNEL_FUSED = 0, NAVSIM_KERNEL_PLAIN = 1 };
 navsim_status navsim_step_debug(navsim_t h, const float *act, float *obs, float *reward,
                                 uint8_t *terminated, uint8_t *truncated, float *final_obs,
                                 const navsim_debug *dbg, int32_t kernel, void *hip_stream);
+
+/* Launch shape of the fused step.  Results never depend on it (bitwise); it
+ * only moves work between lanes, wavefronts and workgroups. */
+typedef struct {
+    int32_t tile_envs;  /* envs per workgroup (they share one staged map): 4, 8 or 16     */
+    int32_t refill_at;  /* a wavefront hands new rays to its idle lanes once at most this
+                           many of its 64 lanes are still walking, 0..63                  */
+    int32_t groups;     /* 4-cell groups a lane walks between refill checks, 1..64        */
+} navsim_tuning;
+
+/* Set the fused step's launch shape (defaults: 4, 48, 4).  Changing tile_envs
+ * after navsim_load_maps waits for the device and re-groups the envs; returns
+ * NAVSIM_E_UNSUPPORTED if the larger tile would not fit LDS. */
+navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t);
+
+/* Current launch shape. */
+navsim_status navsim_get_tuning(navsim_t h, navsim_tuning *t);
 
 /* Host copy of the env state (checkpoint), SoA, N entries each, in this order:
  * float32 x, y, theta, v, w, gx, gy, d_prev; int32 t; uint32 episode

@@ -1,0 +1,116 @@
+"""Launch-shape autotuner for the fused step.
+
+The fused step's results do not depend on its launch shape (tile_envs,
+refill_at, groups; see navsim_set_tuning in include/navsim.h), only its speed
+does.  The tuner replays the same seeded steps from the same saved state under
+every candidate shape, times them with HIP events on the simulator's stream,
+and keeps the fastest.  Results are stored per workload key in tuning.json
+next to this file; bench.py and NavSim users can load them with best_for().
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TUNING_FILE = os.path.join(HERE, "tuning.json")
+DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4}
+SPACE = {"tile_envs": (4, 8, 16), "refill_at": (32, 40, 48, 56), "groups": (2, 4, 8)}
+
+
+def workload_key(cfg: dict, maps) -> str:
+    w = max(m.shape[1] for m in maps)
+    h = max(m.shape[0] for m in maps)
+    return (f"N{cfg['num_envs']}_K{cfg['num_beams']}_m{cfg['num_sectors']}_map{w}x{h}"
+            f"_fp{cfg['footprint']}_r{cfg['max_range_m']:g}")
+
+
+def load_all() -> dict:
+    if not os.path.exists(TUNING_FILE):
+        return {}
+    with open(TUNING_FILE) as f:
+        return json.load(f)
+
+
+def best_for(key: str) -> dict:
+    entry = load_all().get(key)
+    return dict(entry["best"]) if entry else dict(DEFAULT)
+
+
+def save(key: str, best: dict, table: list, device_name: str):
+    allt = load_all()
+    allt[key] = {"best": best, "device": device_name, "table": table}
+    with open(TUNING_FILE, "w") as f:
+        json.dump(allt, f, indent=1, sort_keys=True)
+
+
+def time_steps(sim, acts, start_state, steps: int) -> float:
+    """Mean milliseconds per step over `steps` steps from start_state."""
+    sim.set_state(start_state)
+    stream = torch.cuda.current_stream(sim.device)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(sim.device)
+    a.record(stream)
+    for t in range(steps):
+        sim.step(acts[t])
+    b.record(stream)
+    torch.cuda.synchronize(sim.device)
+    return a.elapsed_time(b) / steps
+
+
+def tune(sim, acts, steps: int = 50, space: dict | None = None, verbose: bool = False):
+    space = space or SPACE
+    start = sim.get_state()
+    table = []
+    for te, ra, gr in itertools.product(space["tile_envs"], space["refill_at"], space["groups"]):
+        try:
+            sim.set_tuning(te, ra, gr)
+        except Exception as exc:  # a shape the map does not fit (LDS)
+            table.append({"tile_envs": te, "refill_at": ra, "groups": gr, "error": str(exc)})
+            continue
+        time_steps(sim, acts, start, min(5, steps))  # settle
+        ms = time_steps(sim, acts, start, steps)
+        table.append({"tile_envs": te, "refill_at": ra, "groups": gr, "ms_per_step": ms})
+        if verbose:
+            print(f"tile_envs={te:2d} refill_at={ra:2d} groups={gr} -> {ms * 1e3:8.1f} us/step",
+                  flush=True)
+    ok = [r for r in table if "ms_per_step" in r]
+    best = min(ok, key=lambda r: r["ms_per_step"])
+    best = {k: best[k] for k in ("tile_envs", "refill_at", "groups")}
+    sim.set_tuning(**best)
+    sim.set_state(start)
+    return best, table
+
+
+def main():
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_2606_15846_amd.navsim import NavSim
+    from workloads import configs
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--steps", type=int, default=50)
+    args = ap.parse_args()
+    w = configs.build_workload(args.workload)
+    cfg = w["cfg"]
+    dev = torch.device("cuda", 0)
+    sim = NavSim(cfg, w["maps"], w["res"], w["env_map"], device=0)
+    sim.reset()
+    acts = torch.from_numpy(configs.uniform_actions(args.steps + 20, cfg["num_envs"], seed=7)).to(dev)
+    for t in range(20):
+        sim.step(acts[t])
+    best, table = tune(sim, acts[20:], steps=args.steps, verbose=True)
+    key = workload_key(cfg, w["maps"])
+    save(key, best, table, torch.cuda.get_device_name(0))
+    print(json.dumps({"key": key, "best": best}))
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -73,6 +73,8 @@ struct navsim_s {
     int32_t *perm = nullptr;
     Tile *tiles = nullptr;
     int num_maps = 0, num_tiles = 0, max_words = 0;
+    int tile_envs = kDefaultTileEnvs, refill_at = kDefaultRefillAt, groups = kDefaultGroups;
+    std::vector<int32_t> host_env_map;  // kept to rebuild the tiles when tile_envs changes
 };
 
 namespace {
@@ -209,14 +211,37 @@ StepParams make_params(const navsim_s *h) {
     p.perm = h->perm;
     p.tiles = h->tiles;
     p.num_tiles = h->num_tiles;
+    p.num_maps = h->num_maps;
     p.max_words = h->max_words;
+    p.refill_at = h->refill_at;
+    p.groups = h->groups;
     return p;
+}
+
+// Envs grouped by map (stable in env order) into tiles of up to tile_envs envs,
+// one fused workgroup each.
+void build_tiles(const std::vector<int32_t> &env_map, int tile_envs, std::vector<int32_t> &perm,
+                 std::vector<Tile> &tiles) {
+    const int N = (int)env_map.size();
+    perm.resize(N);
+    for (int e = 0; e < N; ++e) perm[e] = e;
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&](int32_t a, int32_t b) { return env_map[a] < env_map[b]; });
+    tiles.clear();
+    for (int i = 0; i < N;) {
+        const int map = env_map[perm[i]];
+        int j = i;
+        while (j < N && env_map[perm[j]] == map && j - i < tile_envs) ++j;
+        tiles.push_back(Tile{map, i, j - i, 0});
+        i = j;
+    }
 }
 
 navsim_status run(navsim_t h, const StepParams &p, int kernel, hipStream_t s) {
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
-    const hipError_t e = kernel == NAVSIM_KERNEL_PLAIN ? launch_plain(p, s) : launch_fused(p, s);
+    const hipError_t e =
+        kernel == NAVSIM_KERNEL_PLAIN ? launch_plain(p, s) : launch_fused(p, h->tile_envs, s);
     if (e != hipSuccess) return fail(NAVSIM_E_HIP, "kernel launch: %s", hipGetErrorString(e));
     return NAVSIM_OK;
 }
@@ -322,11 +347,11 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
             return fail(NAVSIM_E_INVALID_ARG, "map %d: size %dx%d out of range", k, width[k],
                         height[k]);
         if (!finite_pos(res_m[k])) return fail(NAVSIM_E_INVALID_ARG, "map %d: res must be > 0", k);
-        const int64_t wpr = (width[k] + 2 + 31) / 32;
-        if (wpr * (int64_t)(height[k] + 2) > kMaxMapWords)
+        const int64_t wpr = (width[k] + 2 * kPad + 31) / 32;
+        if (wpr * (int64_t)(height[k] + 2 * kPad) > kMaxMapWords)
             return fail(NAVSIM_E_UNSUPPORTED,
                         "map %d: padded bitmap of %lld words exceeds the %d-word LDS budget", k,
-                        (long long)(wpr * (height[k] + 2)), kMaxMapWords);
+                        (long long)(wpr * (height[k] + 2 * kPad)), kMaxMapWords);
         occ_off[k + 1] = occ_off[k] + (int64_t)width[k] * height[k];
     }
     std::vector<int> used(num_maps, 0);
@@ -348,17 +373,17 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
         MapDesc &d = descs[k];
         d.w = W;
         d.h = H;
-        d.wpr = (W + 2 + 31) / 32;
-        d.words = ((d.wpr * (H + 2)) + 3) & ~3;
+        d.wpr = (W + 2 * kPad + 31) / 32;
+        d.words = ((d.wpr * (H + 2 * kPad)) + 3) & ~3;
         d.word_off = (int64_t)bits.size();
         d.res = res_m[k];
         bits.resize(bits.size() + d.words, 0xffffffffu);
         uint32_t *b = bits.data() + d.word_off;
         for (int iy = 0; iy < H; ++iy) {
-            uint32_t *row = b + (size_t)(iy + 1) * d.wpr;
+            uint32_t *row = b + (size_t)(iy + kPad) * d.wpr;
             for (int wd = 0; wd < d.wpr; ++wd) row[wd] = 0u;
             for (int c = 0; c < d.wpr * 32; ++c) {
-                const int ix = c - 1;
+                const int ix = c - kPad;
                 const bool filled = ix < 0 || ix >= W || m[(size_t)iy * W + ix] != 0;
                 if (filled) row[c >> 5] |= 1u << (c & 31);
             }
@@ -378,25 +403,17 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
             return fail(NAVSIM_E_NO_FREE_SPACE, "map %d has no cell where the footprint fits", k);
     }
 
-    const size_t lds = 4 * ((size_t)max_words + (size_t)kWavesPerGroup * h->cfg.num_beams);
+    const size_t lds =
+        fused_lds_bytes(max_words, h->cfg.num_sectors, h->tile_envs, h->cfg.num_beams);
     if (lds > 65536)
         return fail(NAVSIM_E_UNSUPPORTED,
-                    "largest map plus %d beams need %zu bytes of LDS per workgroup (max 65536)",
-                    h->cfg.num_beams, lds);
-
-    // group envs by map into tiles of up to kWavesPerGroup envs
-    std::vector<int32_t> perm(N);
-    for (int e = 0; e < N; ++e) perm[e] = e;
-    std::stable_sort(perm.begin(), perm.end(),
-                     [&](int32_t a, int32_t b) { return env_map[a] < env_map[b]; });
+                    "largest map, %d beams and %d sectors need %zu bytes of LDS per workgroup "
+                    "(max 65536)",
+                    h->cfg.num_beams, h->cfg.num_sectors, lds);
+    std::vector<int32_t> host_env_map(env_map, env_map + N);
+    std::vector<int32_t> perm;
     std::vector<Tile> tiles;
-    for (int i = 0; i < N;) {
-        const int map = env_map[perm[i]];
-        int j = i;
-        while (j < N && env_map[perm[j]] == map && j - i < kWavesPerGroup) ++j;
-        tiles.push_back(Tile{map, i, j - i, 0});
-        i = j;
-    }
+    build_tiles(host_env_map, h->tile_envs, perm, tiles);
 
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
@@ -414,6 +431,7 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
     h->num_maps = num_maps;
     h->num_tiles = (int)tiles.size();
     h->max_words = max_words;
+    h->host_env_map.swap(host_env_map);
     h->loaded = true;
     return NAVSIM_OK;
 }
@@ -477,6 +495,49 @@ navsim_status navsim_set_state(navsim_t h, const void *host_soa, size_t bytes, v
     NS_HIP(hipStreamSynchronize((hipStream_t)hip_stream));
     NS_HIP(hipMemcpy(h->state_buf, host_soa, bytes, hipMemcpyHostToDevice));
     h->initialized = true;
+    return NAVSIM_OK;
+}
+
+navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
+    if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
+    if (!t) return fail(NAVSIM_E_INVALID_ARG, "tuning is NULL");
+    if (!fused_tile_envs_supported(t->tile_envs))
+        return fail(NAVSIM_E_INVALID_ARG, "tile_envs must be 4, 8 or 16");
+    if (t->refill_at < 0 || t->refill_at > 63)
+        return fail(NAVSIM_E_INVALID_ARG, "refill_at must be in 0..63");
+    if (t->groups < 1 || t->groups > 64) return fail(NAVSIM_E_INVALID_ARG, "groups must be in 1..64");
+    if (h->loaded && t->tile_envs != h->tile_envs) {
+        const size_t lds =
+            fused_lds_bytes(h->max_words, h->cfg.num_sectors, t->tile_envs, h->cfg.num_beams);
+        if (lds > 65536)
+            return fail(NAVSIM_E_UNSUPPORTED, "tile_envs %d needs %zu bytes of LDS", t->tile_envs, lds);
+        std::vector<int32_t> perm;
+        std::vector<Tile> tiles;
+        build_tiles(h->host_env_map, t->tile_envs, perm, tiles);
+        DeviceGuard g(h->device);
+        if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
+        NS_HIP(hipDeviceSynchronize());
+        (void)hipFree(h->perm);
+        (void)hipFree(h->tiles);
+        h->perm = nullptr;
+        h->tiles = nullptr;
+        navsim_status s;
+        if ((s = upload(&h->perm, perm)) != NAVSIM_OK) return s;
+        if ((s = upload(&h->tiles, tiles)) != NAVSIM_OK) return s;
+        h->num_tiles = (int)tiles.size();
+    }
+    h->tile_envs = t->tile_envs;
+    h->refill_at = t->refill_at;
+    h->groups = t->groups;
+    return NAVSIM_OK;
+}
+
+navsim_status navsim_get_tuning(navsim_t h, navsim_tuning *t) {
+    if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
+    if (!t) return fail(NAVSIM_E_INVALID_ARG, "tuning is NULL");
+    t->tile_envs = h->tile_envs;
+    t->refill_at = h->refill_at;
+    t->groups = h->groups;
     return NAVSIM_OK;
 }
 

@@ -9,26 +9,30 @@
 
 namespace navsim {
 
-// Largest padded bitmap (in 32-bit words) the fused step stages in LDS.
-constexpr int kMaxMapWords = 12288;  // 48 KiB
+// Padded bitmap layout.  A map of W x H cells is stored with a ring of kPad
+// occupied cells on every side: row r = iy + kPad in 0..H + 2 kPad - 1,
+// column c = ix + kPad, bit c & 31 of word r * wpr + (c >> 5), with
+// 32 * wpr >= W + 2 kPad; every bit at c >= W + kPad is set.  Leaving the map
+// reads as occupied, and a walk that starts inside the map can look up to kPad
+// cells ahead without leaving the stored rows.
+constexpr int kPad = 4;
+constexpr int kMaxMapWords = 12288;  // largest padded bitmap staged in LDS (48 KiB)
 constexpr int kMaxBeams = 4096;
-constexpr int kWavesPerGroup = 4;    // envs per workgroup in the fused step
+constexpr int kDefaultTileEnvs = 4;  // envs per fused workgroup (4, 8 or 16)
+constexpr int kDefaultRefillAt = 48;  // refill idle lanes once at most this many are busy
+constexpr int kDefaultGroups = 4;     // 4-cell groups walked between refill checks
 
-// Per-map table entry in device memory.  A map of W x H cells is stored with a
-// one-cell ring of occupied padding: row r = iy + 1 in 0..H+1, column
-// c = ix + 1 in 0..W+1, bit c & 31 of word r * wpr + (c >> 5); every bit at
-// c >= W + 1 is set, so leaving the map reads as occupied.
 struct MapDesc {
     int32_t w, h;
-    int32_t wpr;       // words per padded row, 32 * wpr >= W + 2
-    int32_t words;     // padded words, rounded up to a multiple of 4
-    int64_t word_off;  // start in the bit pool (multiple of 4 words)
-    int64_t free_off;  // start of this map's free-cell list
+    int32_t wpr;        // words per padded row
+    int32_t words;      // padded words, rounded up to a multiple of 4
+    int64_t word_off;   // start in the bit pool (multiple of 4 words)
+    int64_t free_off;   // start of this map's free-cell list
     int32_t free_cnt;
     float res;
 };
 
-// A group of up to kWavesPerGroup envs that share one map (fused step).
+// A group of up to tile_envs envs that share one map (one fused workgroup).
 struct Tile {
     int32_t map, first, count, pad;
 };
@@ -41,7 +45,8 @@ struct DevState {
 
 // Everything a step or reset launch needs, passed by value.
 struct StepParams {
-    int32_t N, K, m, horizon, footprint, tries, full_circle, mode;  // mode 0 step, 1 reset
+    int32_t N, K, m, horizon, footprint, tries, mode;  // mode 0 step, 1 reset
+    int32_t refill_at, groups;  // fused walk: refill threshold, 4-cell groups per check
     float rmax, dt, goal_r, c1, r_succ, r_coll, radius, len, wid;
     float vlo, vhi, wlo, whi, gmd;
     uint32_t key0, key1;
@@ -54,7 +59,7 @@ struct StepParams {
     const double2 *beams;  // (cos, sin) of each beam's angle to the heading
     const int32_t *perm;   // env ids grouped by map
     const Tile *tiles;
-    int32_t num_tiles, max_words;
+    int32_t num_tiles, num_maps, max_words;
     // inputs / outputs
     const float *act;
     const uint8_t *mask;
@@ -66,7 +71,9 @@ struct StepParams {
     uint8_t *d_coll, *d_goal, *d_reset, *d_fb;
 };
 
-hipError_t launch_fused(const StepParams &p, hipStream_t s);
+size_t fused_lds_bytes(int max_words, int m, int tile_envs, int K);
+bool fused_tile_envs_supported(int tile_envs);
+hipError_t launch_fused(const StepParams &p, int tile_envs, hipStream_t s);
 hipError_t launch_plain(const StepParams &p, hipStream_t s);
 
 }  // namespace navsim

@@ -1,14 +1,13 @@
 // HIP kernels of the batched bitmap navigation step (FlashNav, arXiv
 // 2606.15846, section 2.2) for gfx950.
 //
-// Two mappings of the same step, with identical results:
-//   fused_step_kernel  one workgroup per tile of envs sharing a map; the map's
-//                      padded bitmap is staged once into LDS; one wavefront per
-//                      env; lanes take beams (range scan), footprint cells
-//                      (collision, ballot) and reset attempts (ballot, lowest
-//                      successful attempt wins).
-//   plain_step_kernel  one thread per env, everything sequential, bitmap read
-//                      from device memory.  The comparison point.
+// Two mappings of the same step (step data path of eq. 7), identical results:
+//   fused_step_kernel  one workgroup per tile of envs sharing a map: the map's
+//                      padded bitmap staged in LDS, per-env work on 16-lane
+//                      groups, the tile's rays (new poses and reset poses)
+//                      walked by all lanes with refill, sector pooling in LDS.
+//   plain_step_kernel  one thread per env, everything in sequence, bitmap read
+//                      from device memory (the comparison point).
 //
 // Numerics.  Per-env scalars (action map, kinematics, collision geometry, goal
 // features, reward, reset draws) are evaluated in double precision in a fixed
@@ -57,18 +56,33 @@ __device__ __forceinline__ void draw4(const StepParams &p, uint32_t env, uint32_
 }
 
 // ---------------------------------------------------------------------------
-// Occupancy access.  `bits` points at the map's padded bitmap (LDS in the fused
-// step, device memory in the plain one); pitch = 32 * words per row.
+// Occupancy access.  `bits` points at the map's padded bitmap (LDS in the scan
+// kernel, device memory elsewhere); pitch = 32 * wpr bits per padded row.
 struct MapView {
     const uint32_t *bits;
-    int w, h, pitch;
+    int w, h, wpr, pitch;
     double s;
 };
 
+__device__ __forceinline__ MapView map_view(const uint32_t *bits, const MapDesc &md) {
+    return MapView{bits, md.w, md.h, md.wpr, md.wpr * 32, (double)md.res};
+}
+
 __device__ __forceinline__ bool cell_filled(const MapView &M, int i, int j) {
     if ((unsigned)i >= (unsigned)M.w || (unsigned)j >= (unsigned)M.h) return true;
-    const int b = (j + 1) * M.pitch + (i + 1);
+    const int b = (j + kPad) * M.pitch + (i + kPad);
     return (M.bits[b >> 5] >> (b & 31)) & 1u;
+}
+
+// len (1..32) bits of padded row r starting at padded column c0, as the low
+// bits of the result.
+__device__ __forceinline__ uint32_t row_bits(const MapView &M, int r, int c0, int len) {
+    const uint32_t *row = M.bits + r * M.wpr;
+    const int w = c0 >> 5, sh = c0 & 31;
+    uint64_t v = row[w];
+    if (sh + len > 32) v |= (uint64_t)row[w + 1] << 32;
+    const uint32_t bits = (uint32_t)(v >> sh);
+    return len >= 32 ? bits : bits & ((1u << len) - 1u);
 }
 
 // Disc of squared radius r2 at (x, y) against cell (i, j)'s closed box: the
@@ -136,58 +150,53 @@ __device__ __forceinline__ CellRange cells_around(double x, double y, double ex,
     return r;
 }
 
-// One lane tests a whole footprint (reset attempts, plain kernel).
-__device__ bool disc_hits_serial(const MapView &M, double x, double y, double r) {
-    const CellRange cr = cells_around(x, y, r, r, M.s);
-    const double r2 = r * r;
+// Does any occupied candidate cell satisfy the exact predicate F(i, j)?  When
+// the window lies inside the stored rows, whole rows are tested with one mask
+// and F runs only on occupied cells; otherwise every cell is checked.
+template <typename F>
+__device__ __forceinline__ bool any_filled_cell(const MapView &M, const CellRange &cr, F f) {
+    const bool inside = cr.i0 >= -kPad && cr.j0 >= -kPad && cr.i0 + cr.nx <= M.w + kPad &&
+                        cr.j0 + cr.ny <= M.h + kPad;
+    if (inside) {
+        for (int dj = 0; dj < cr.ny; ++dj) {
+            const int r = cr.j0 + dj + kPad;
+            for (int c = 0; c < cr.nx; c += 32) {
+                uint32_t m = row_bits(M, r, cr.i0 + kPad + c, min(32, cr.nx - c));
+                while (m) {
+                    const int b = __ffs(m) - 1;
+                    m &= m - 1u;
+                    if (f(cr.i0 + c + b, cr.j0 + dj)) return true;
+                }
+            }
+        }
+        return false;
+    }
     for (int dj = 0; dj < cr.ny; ++dj)
         for (int di = 0; di < cr.nx; ++di) {
             const int i = cr.i0 + di, j = cr.j0 + dj;
-            if (cell_filled(M, i, j) && disc_cell(x, y, r2, i, j, M.s)) return true;
+            if (cell_filled(M, i, j) && f(i, j)) return true;
         }
     return false;
 }
 
-__device__ bool footprint_hits_serial(const MapView &M, const StepParams &p, double x, double y,
-                                      double th) {
-    if (p.footprint == NAVSIM_DISC) return disc_hits_serial(M, x, y, (double)p.radius);
+__device__ bool disc_hits(const MapView &M, double x, double y, double r) {
+    const CellRange cr = cells_around(x, y, r, r, M.s);
+    const double r2 = r * r, s = M.s;
+    return any_filled_cell(M, cr, [&](int i, int j) { return disc_cell(x, y, r2, i, j, s); });
+}
+
+__device__ bool footprint_hits(const MapView &M, const StepParams &p, double x, double y,
+                               double th) {
+    if (p.footprint == NAVSIM_DISC) return disc_hits(M, x, y, (double)p.radius);
     const RectGeom g = rect_geom(th, (double)p.len, (double)p.wid, M.s);
     const CellRange cr = cells_around(x, y, g.ex, g.ey, M.s);
-    for (int dj = 0; dj < cr.ny; ++dj)
-        for (int di = 0; di < cr.nx; ++di) {
-            const int i = cr.i0 + di, j = cr.j0 + dj;
-            if (cell_filled(M, i, j) && rect_cell(g, x, y, i, j, M.s)) return true;
-        }
-    return false;
-}
-
-// A wavefront tests one footprint: candidate cells spread over lanes, ballot.
-__device__ bool footprint_hits_wave(const MapView &M, const StepParams &p, double x, double y,
-                                    double th, int lane) {
-    bool hit = false;
-    if (p.footprint == NAVSIM_DISC) {
-        const double r = (double)p.radius, r2 = r * r;
-        const CellRange cr = cells_around(x, y, r, r, M.s);
-        const int total = cr.nx * cr.ny;
-        for (int c = lane; c < total; c += 64) {
-            const int i = cr.i0 + c % cr.nx, j = cr.j0 + c / cr.nx;
-            if (cell_filled(M, i, j) && disc_cell(x, y, r2, i, j, M.s)) hit = true;
-        }
-    } else {
-        const RectGeom g = rect_geom(th, (double)p.len, (double)p.wid, M.s);
-        const CellRange cr = cells_around(x, y, g.ex, g.ey, M.s);
-        const int total = cr.nx * cr.ny;
-        for (int c = lane; c < total; c += 64) {
-            const int i = cr.i0 + c % cr.nx, j = cr.j0 + c / cr.nx;
-            if (cell_filled(M, i, j) && rect_cell(g, x, y, i, j, M.s)) hit = true;
-        }
-    }
-    return __ballot(hit) != 0ull;
+    const double s = M.s;
+    return any_filled_cell(M, cr, [&](int i, int j) { return rect_cell(g, x, y, i, j, s); });
 }
 
 // ---------------------------------------------------------------------------
-// Range scan (eq. 4-5).  Per pose: the origin in cells, split into a 32.32
-// fixed-point value; per ray: the walk over the cells the ray enters, in order,
+// Range scan (eq. 4-5).  Per pose: the origin in cells and its 32.32
+// fixed-point value; per ray: a walk over the cells the ray enters, in order,
 // until an occupied (or padding = out-of-bounds) cell or the cell holding the
 // r_max end point.
 struct RayOrigin {
@@ -227,17 +236,18 @@ __device__ __forceinline__ RayOrigin ray_origin(const MapView &M, double x, doub
     return o;
 }
 
-// Walk one ray from a free origin cell.  With g = distance to the next grid
-// line in the direction of travel (2^-32 cells) and D = quantised |direction|,
+// Integer walk state of one ray.  With g = distance to the next grid line in
+// the direction of travel (2^-32 cells) and D = quantised |direction|,
 // E = gx DY - gy DX compares the two next crossing distances; an x crossing
 // adds 2^32 DY, a y crossing subtracts 2^32 DX.  The low word of E never
-// changes, so only the high word is carried; a tie (E == 0) crosses x first.
-// The walk is bounded by the number of cells to the r_max end point; the hit
-// range is recomputed once in double from the crossed grid line.
-template <typename Bits>
-__device__ __forceinline__ void cast_ray(Bits bits, int pitch, int W, int H, const RayOrigin &o,
-                                         double dx, double dy, double rmax, double rmax_c,
-                                         float &range, int &hit, int &visits) {
+// changes, so only the high word Eh is carried; a tie (E == 0) crosses x
+// first.  n bounds the walk: cells between the origin and the r_max end point.
+struct Walk {
+    int B, Eh, thr, incx, incy, dEx, dEy, n;
+};
+
+__device__ __forceinline__ Walk walk_setup(int pitch, const RayOrigin &o, double dx, double dy,
+                                           double rmax_c) {
     const uint32_t DX = (uint32_t)rint(fabs(dx) * kTwoPow30);
     const uint32_t DY = (uint32_t)rint(fabs(dy) * kTwoPow30);
     const bool px = dx > 0.0, py = dy > 0.0;
@@ -245,37 +255,57 @@ __device__ __forceinline__ void cast_ray(Bits bits, int pitch, int W, int H, con
     const uint64_t gx = px ? (4294967296ull - fx) : (uint64_t)fx;
     const uint64_t gy = py ? (4294967296ull - fy) : (uint64_t)fy;
     const int64_t E = (int64_t)(gx * (uint64_t)DY) - (int64_t)(gy * (uint64_t)DX);
-    int Eh = (int)(E >> 32);
-    const int thr = ((uint32_t)(uint64_t)E == 0u) ? 1 : 0;
+    Walk w;
+    w.Eh = (int)(E >> 32);
+    w.thr = ((uint32_t)(uint64_t)E == 0u) ? 1 : 0;
     const double exc = fmin(fmax(o.xc + rmax_c * dx, -1048576.0), 1048576.0);
     const double eyc = fmin(fmax(o.yc + rmax_c * dy, -1048576.0), 1048576.0);
-    const int n = abs((int)floor(exc) - o.i0) + abs((int)floor(eyc) - o.j0);
-    int B = (o.j0 + 1) * pitch + (o.i0 + 1);
-    const int incx = px ? 1 : -1, incy = py ? pitch : -pitch;
-    const int dEx = (int)DY, dEy = -(int)DX;
+    w.n = abs((int)floor(exc) - o.i0) + abs((int)floor(eyc) - o.j0);
+    w.B = (o.j0 + kPad) * pitch + (o.i0 + kPad);
+    w.incx = px ? 1 : -1;
+    w.incy = py ? pitch : -pitch;
+    w.dEx = (int)DY;
+    w.dEy = -(int)DX;
+    return w;
+}
+
+// Range and hit id of a walk that stopped in cell B (entered by an x crossing
+// when lastx): the crossing distance recomputed once in double.
+__device__ __forceinline__ void walk_result(const RayOrigin &o, int pitch, int W, int H, int B,
+                                            bool lastx, double dx, double dy, double rmax,
+                                            float &range, int &hit) {
+    const int row = B / pitch, col = B - row * pitch;
+    const int ix = col - kPad, iy = row - kPad;
+    double t = lastx ? (((double)(dx > 0.0 ? ix : ix + 1)) * o.s - o.x) / dx
+                     : (((double)(dy > 0.0 ? iy : iy + 1)) * o.s - o.y) / dy;
+    t = t > 0.0 ? t : 0.0;  // also maps -0 and NaN to +0
+    t = t < rmax ? t : rmax;
+    range = (float)t;
+    hit = ((unsigned)ix < (unsigned)W && (unsigned)iy < (unsigned)H) ? iy * W + ix : -2;
+}
+
+// Sequential walk of one ray (plain kernel).
+__device__ __forceinline__ void cast_ray(const MapView &M, const RayOrigin &o, double dx,
+                                         double dy, double rmax, double rmax_c, float &range,
+                                         int &hit, int &visits) {
+    Walk w = walk_setup(M.pitch, o, dx, dy, rmax_c);
     int k = 0;
     bool found = false, lastx = false;
-    for (; k < n; ++k) {
-        const bool xs = Eh < thr;
-        B += xs ? incx : incy;
-        Eh += xs ? dEx : dEy;
-        if ((bits[B >> 5] >> (B & 31)) & 1u) {
+    while (k < w.n) {
+        const bool xs = w.Eh < w.thr;
+        w.B += xs ? w.incx : w.incy;
+        w.Eh += xs ? w.dEx : w.dEy;
+        ++k;
+        if ((M.bits[w.B >> 5] >> (w.B & 31)) & 1u) {
             found = true;
             lastx = xs;
             break;
         }
     }
+    visits = k + 1;
     if (found) {
-        visits = k + 2;
-        const int row = B / pitch, col = B - row * pitch;
-        const int ix = col - 1, iy = row - 1;
-        double t = lastx ? (((double)(px ? ix : ix + 1)) * o.s - o.x) / dx
-                         : (((double)(py ? iy : iy + 1)) * o.s - o.y) / dy;
-        t = fmin(fmax(t, 0.0), rmax);
-        range = (float)t;
-        hit = ((unsigned)ix < (unsigned)W && (unsigned)iy < (unsigned)H) ? iy * W + ix : -2;
+        walk_result(o, M.pitch, M.w, M.h, w.B, lastx, dx, dy, rmax, range, hit);
     } else {
-        visits = n + 1;
         range = (float)rmax;
         hit = -1;
     }
@@ -324,10 +354,6 @@ __device__ __forceinline__ void goal_features(double x, double y, double c, doub
     phi32 = (float)phi;
 }
 
-__device__ __forceinline__ float uniform_pos(double u, double extent) {
-    return (float)(u * extent);
-}
-
 __device__ __forceinline__ float uniform_heading(double u) {
     return (float)((2.0 * u - 1.0) * kPi);
 }
@@ -341,242 +367,528 @@ __device__ __forceinline__ void free_cell_centre(const StepParams &p, const MapD
     y = (float)(((double)iy + 0.5) * (double)md.res);
 }
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Reset draws of env e (section 2.2.3): attempt a of the start pose uses
+// counter (e, episode, a, 0), x = u0 W s, y = u1 H s, th = (2 u2 - 1) pi; the
+// first pose whose footprint is clear wins.  Goal attempt b uses (e, episode,
+// b, 1); the first goal whose circumscribed disc is clear and which is at
+// least goal_min_dist from the start wins.  When all attempts fail, a cell of
+// the free-cell list is used (stream 2 start, 3 goal).
+struct ResetPose {
+    float x, y, th, gx, gy;
+    uint32_t fb;
+};
+
+__device__ ResetPose sample_reset(const StepParams &p, const MapView &M, const MapDesc &md,
+                                  int e, uint32_t ep) {
+    const double s = M.s, Ws = (double)md.w * s, Hs = (double)md.h * s;
+    ResetPose r{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
+    bool found = false;
+    for (int a = 0; a < p.tries && !found; ++a) {
+        double u[4];
+        draw4(p, (uint32_t)e, ep, (uint32_t)a, 0u, u);
+        r.x = (float)(u[0] * Ws);
+        r.y = (float)(u[1] * Hs);
+        r.th = uniform_heading(u[2]);
+        found = !footprint_hits(M, p, (double)r.x, (double)r.y, (double)r.th);
+    }
+    if (!found) {
+        double u[4];
+        draw4(p, (uint32_t)e, ep, 0u, 2u, u);
+        free_cell_centre(p, md, u[0], r.x, r.y);
+        r.th = uniform_heading(u[2]);
+        r.fb |= 1u;
+    }
+    found = false;
+    for (int b = 0; b < p.tries && !found; ++b) {
+        double u[4];
+        draw4(p, (uint32_t)e, ep, (uint32_t)b, 1u, u);
+        r.gx = (float)(u[0] * Ws);
+        r.gy = (float)(u[1] * Hs);
+        if (disc_hits(M, (double)r.gx, (double)r.gy, p.rc)) continue;
+        const double ddx = (double)r.gx - (double)r.x, ddy = (double)r.gy - (double)r.y;
+        found = sqrt(ddx * ddx + ddy * ddy) >= (double)p.gmd;
+    }
+    if (!found) {
+        double u[4];
+        draw4(p, (uint32_t)e, ep, 0u, 3u, u);
+        free_cell_centre(p, md, u[0], r.gx, r.gy);
+        r.fb |= 2u;
+    }
+    return r;
+}
+
+// Store a reset: new state and the reset observation's scalar part (d, phi,
+// v = w = 0); c, sn receive the new heading's cosine and sine for its scan.
+__device__ void store_reset(const StepParams &p, int e, uint32_t ep, const ResetPose &r,
+                            double &c, double &sn) {
+    sincos((double)r.th, &sn, &c);
+    double d64;
+    float d32, phi;
+    goal_features((double)r.x, (double)r.y, c, sn, r.gx, r.gy, d64, d32, phi);
+    float *row = p.obs + (int64_t)e * (p.m + 4);
+    row[p.m] = d32;
+    row[p.m + 1] = phi;
+    row[p.m + 2] = 0.0f;
+    row[p.m + 3] = 0.0f;
+    p.st.x[e] = r.x;
+    p.st.y[e] = r.y;
+    p.st.th[e] = r.th;
+    p.st.v[e] = 0.0f;
+    p.st.w[e] = 0.0f;
+    p.st.gx[e] = r.gx;
+    p.st.gy[e] = r.gy;
+    p.st.dprev[e] = d32;
+    p.st.t[e] = 0;
+    p.st.ep[e] = ep + 1u;
+    if (p.d_fb) p.d_fb[e] = (uint8_t)r.fb;
 }
 
 // ---------------------------------------------------------------------------
-// Fused mapping: one wavefront per env.
+// Fused step: one workgroup per tile of up to E envs that share a map.
+//
+//   1. stage the map's padded bitmap in LDS;
+//   2. motion: a group of 16 lanes per env (action, kinematics, collision with
+//      the footprint's candidate rows spread over the group, goal features,
+//      reward, flags; for envs that ended, 16 reset attempts at a time);
+//   3. scan: the tile's pool of rays -- K per new pose and K per reset pose --
+//      is walked by all lanes; a lane that finishes takes the next ray from an
+//      LDS counter, refilled whenever at most refill_at lanes are busy, so the
+//      lanes stay busy whatever the ray lengths;
+//   4. sector minima (eq. 6) folded with LDS atomics, written as observation
+//      rows.
 
-// Scan all K beams of a pose into s_rng (lane-strided beams).
-__device__ void scan_wave(const StepParams &p, const MapView &M, const RayOrigin &o, double c,
-                          double sn, int lane, float *s_rng, int64_t dbg_row) {
-    const double rmax = (double)p.rmax, rmax_c = rmax / M.s;
-    for (int kb = 0; kb < p.K; kb += 64) {
-        const int k = kb + lane;
-        if (k >= p.K) break;
-        float rg;
-        int hit, vis;
-        if (o.blocked) {
-            rg = 0.0f;
-            hit = o.block_hit;
-            vis = 1;
+struct TileJob {
+    double c, s, x, y, xc, yc;
+    int64_t OX, OY;
+    int i0, j0, blocked, block_hit, env, dst;  // dst 0 obs row, 1 final_obs row, 2 none
+};
+
+constexpr int kFusedThreads = 256;
+constexpr int kGroupLanes = 16;
+
+size_t fused_lds_bytes(int max_words, int m, int E, int K) {
+    return (size_t)max_words * 4u + 2u * (size_t)E * sizeof(TileJob) +
+           2u * (size_t)E * (size_t)m * 4u + (4u * (size_t)E + 8u) * 4u + 16u * (size_t)K;
+}
+
+__device__ __forceinline__ void make_tile_job(TileJob &j, const MapView &M, float x, float y,
+                                              double c, double s, int env, int dst) {
+    const RayOrigin o = ray_origin(M, (double)x, (double)y);
+    j.c = c;
+    j.s = s;
+    j.x = o.x;
+    j.y = o.y;
+    j.xc = o.xc;
+    j.yc = o.yc;
+    j.OX = o.OX;
+    j.OY = o.OY;
+    j.i0 = o.i0;
+    j.j0 = o.j0;
+    j.blocked = o.blocked;
+    j.block_hit = o.block_hit;
+    j.env = env;
+    j.dst = dst;
+}
+
+__device__ __forceinline__ RayOrigin tile_origin(const TileJob &j, double s) {
+    RayOrigin o;
+    o.x = j.x;
+    o.y = j.y;
+    o.s = s;
+    o.xc = j.xc;
+    o.yc = j.yc;
+    o.OX = j.OX;
+    o.OY = j.OY;
+    o.i0 = j.i0;
+    o.j0 = j.j0;
+    o.blocked = j.blocked;
+    o.block_hit = j.block_hit;
+    return o;
+}
+
+// q = floor(a / b) for 0 <= a < 2^24, 1 <= b < 2^24 (float estimate, then fixed).
+__device__ __forceinline__ int small_div(int a, int b, float inv_b) {
+    int q = (int)((float)a * inv_b);
+    if (q * b > a) --q;
+    if ((q + 1) * b <= a) ++q;
+    return q;
+}
+
+// The 16 ballot bits of this lane's group of 16.
+__device__ __forceinline__ uint32_t group_ballot(bool pred) {
+    const uint64_t b = __ballot(pred);
+    return (uint32_t)(b >> (threadIdx.x & 48)) & 0xFFFFu;
+}
+
+// Footprint test by a group of 16: lane li takes candidate rows li, li+16, ...
+template <typename F>
+__device__ __forceinline__ bool group_any_filled(const MapView &M, const CellRange &cr, int li,
+                                                 F f) {
+    const bool inside = cr.i0 >= -kPad && cr.j0 >= -kPad && cr.i0 + cr.nx <= M.w + kPad &&
+                        cr.j0 + cr.ny <= M.h + kPad;
+    bool hit = false;
+    for (int dj = li; dj < cr.ny && !hit; dj += kGroupLanes) {
+        if (inside) {
+            const int r = cr.j0 + dj + kPad;
+            for (int c = 0; c < cr.nx && !hit; c += 32) {
+                uint32_t m = row_bits(M, r, cr.i0 + kPad + c, min(32, cr.nx - c));
+                while (m) {
+                    const int b = __ffs(m) - 1;
+                    m &= m - 1u;
+                    if (f(cr.i0 + c + b, cr.j0 + dj)) {
+                        hit = true;
+                        break;
+                    }
+                }
+            }
         } else {
-            const double2 cs = p.beams[k];
-            const double dx = c * cs.x - sn * cs.y;
-            const double dy = sn * cs.x + c * cs.y;
-            cast_ray(M.bits, M.pitch, M.w, M.h, o, dx, dy, rmax, rmax_c, rg, hit, vis);
-        }
-        s_rng[k] = rg;
-        if (dbg_row >= 0) {
-            if (p.d_ranges) p.d_ranges[dbg_row * p.K + k] = rg;
-            if (p.d_hits) p.d_hits[dbg_row * p.K + k] = hit;
-            if (p.d_visits) p.d_visits[dbg_row * p.K + k] = vis;
+            for (int di = 0; di < cr.nx; ++di) {
+                const int i = cr.i0 + di, j = cr.j0 + dj;
+                if (cell_filled(M, i, j) && f(i, j)) {
+                    hit = true;
+                    break;
+                }
+            }
         }
     }
-    wave_sync();
+    return group_ballot(hit) != 0u;
 }
 
-// Pooled sector j (eq. 6): min over its K/m contiguous beams.
-__device__ __forceinline__ float pooled(const StepParams &p, const float *s_rng, int j) {
-    const int per = p.K / p.m;
-    float l = s_rng[j * per];
-    for (int q = 1; q < per; ++q) l = fminf(l, s_rng[j * per + q]);
-    return l;
+__device__ bool group_footprint_hits(const MapView &M, const StepParams &p, double x, double y,
+                                     double th, int li) {
+    if (p.footprint == NAVSIM_DISC) {
+        const double r = (double)p.radius, r2 = r * r, s = M.s;
+        const CellRange cr = cells_around(x, y, r, r, s);
+        return group_any_filled(M, cr, li, [&](int i, int j) { return disc_cell(x, y, r2, i, j, s); });
+    }
+    const RectGeom g = rect_geom(th, (double)p.len, (double)p.wid, M.s);
+    const CellRange cr = cells_around(x, y, g.ex, g.ey, M.s);
+    const double s = M.s;
+    return group_any_filled(M, cr, li, [&](int i, int j) { return rect_cell(g, x, y, i, j, s); });
 }
 
-// Sparse reset of env e (section 2.2.3): lane a tries attempt a; the lowest
-// successful attempt wins, which is the first success of the sequential
-// sampler.  Writes the new state and the reset observation row.
-__device__ void reset_env_wave(const StepParams &p, const MapView &M, const MapDesc &md, int e,
-                               int lane, float *s_rng, float *obs_row) {
-    const uint32_t ep = p.st.ep[e];
+// Reset draws of one env by its group: 16 attempts at a time, each lane
+// testing one whole candidate; the lowest successful attempt wins, which is
+// the first success of the sequential sampler.
+__device__ ResetPose group_sample_reset(const StepParams &p, const MapView &M, const MapDesc &md,
+                                        int e, uint32_t ep, int li) {
     const double s = M.s, Ws = (double)md.w * s, Hs = (double)md.h * s;
-    float xs = 0.0f, ys = 0.0f, ths = 0.0f, gx = 0.0f, gy = 0.0f;
-    uint32_t fb = 0;
+    const int gbase = threadIdx.x & 48;
+    ResetPose r{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
     bool found = false;
-    for (int a0 = 0; a0 < p.tries && !found; a0 += 64) {
-        const int a = a0 + lane;
+    for (int a0 = 0; a0 < p.tries; a0 += kGroupLanes) {
+        const int a = a0 + li;
         bool ok = false;
         float cx = 0.0f, cy = 0.0f, ct = 0.0f;
         if (a < p.tries) {
             double u[4];
             draw4(p, (uint32_t)e, ep, (uint32_t)a, 0u, u);
-            cx = uniform_pos(u[0], Ws);
-            cy = uniform_pos(u[1], Hs);
+            cx = (float)(u[0] * Ws);
+            cy = (float)(u[1] * Hs);
             ct = uniform_heading(u[2]);
-            ok = !footprint_hits_serial(M, p, (double)cx, (double)cy, (double)ct);
+            ok = !footprint_hits(M, p, (double)cx, (double)cy, (double)ct);
         }
-        const uint64_t b = __ballot(ok);
-        if (b) {
-            const int win = __ffsll((unsigned long long)b) - 1;
-            xs = __shfl(cx, win);
-            ys = __shfl(cy, win);
-            ths = __shfl(ct, win);
+        const uint32_t gm = group_ballot(ok);
+        if (gm) {
+            const int src = gbase + __ffs(gm) - 1;
+            r.x = __shfl(cx, src);
+            r.y = __shfl(cy, src);
+            r.th = __shfl(ct, src);
             found = true;
+            break;
         }
     }
     if (!found) {
         double u[4];
         draw4(p, (uint32_t)e, ep, 0u, 2u, u);
-        free_cell_centre(p, md, u[0], xs, ys);
-        ths = uniform_heading(u[2]);
-        fb |= 1u;
+        free_cell_centre(p, md, u[0], r.x, r.y);
+        r.th = uniform_heading(u[2]);
+        r.fb |= 1u;
     }
     found = false;
-    const double gmd = (double)p.gmd;
-    for (int b0 = 0; b0 < p.tries && !found; b0 += 64) {
-        const int bq = b0 + lane;
+    for (int b0 = 0; b0 < p.tries; b0 += kGroupLanes) {
+        const int b = b0 + li;
         bool ok = false;
         float cx = 0.0f, cy = 0.0f;
-        if (bq < p.tries) {
+        if (b < p.tries) {
             double u[4];
-            draw4(p, (uint32_t)e, ep, (uint32_t)bq, 1u, u);
-            cx = uniform_pos(u[0], Ws);
-            cy = uniform_pos(u[1], Hs);
-            if (!disc_hits_serial(M, (double)cx, (double)cy, p.rc)) {
-                const double ddx = (double)cx - (double)xs, ddy = (double)cy - (double)ys;
-                ok = sqrt(ddx * ddx + ddy * ddy) >= gmd;
+            draw4(p, (uint32_t)e, ep, (uint32_t)b, 1u, u);
+            cx = (float)(u[0] * Ws);
+            cy = (float)(u[1] * Hs);
+            if (!disc_hits(M, (double)cx, (double)cy, p.rc)) {
+                const double ddx = (double)cx - (double)r.x, ddy = (double)cy - (double)r.y;
+                ok = sqrt(ddx * ddx + ddy * ddy) >= (double)p.gmd;
             }
         }
-        const uint64_t b = __ballot(ok);
-        if (b) {
-            const int win = __ffsll((unsigned long long)b) - 1;
-            gx = __shfl(cx, win);
-            gy = __shfl(cy, win);
+        const uint32_t gm = group_ballot(ok);
+        if (gm) {
+            const int src = gbase + __ffs(gm) - 1;
+            r.gx = __shfl(cx, src);
+            r.gy = __shfl(cy, src);
             found = true;
+            break;
         }
     }
     if (!found) {
         double u[4];
         draw4(p, (uint32_t)e, ep, 0u, 3u, u);
-        free_cell_centre(p, md, u[0], gx, gy);
-        fb |= 2u;
+        free_cell_centre(p, md, u[0], r.gx, r.gy);
+        r.fb |= 2u;
     }
-    // observation of the new pose
-    double sn, c;
-    sincos((double)ths, &sn, &c);
-    const RayOrigin o = ray_origin(M, (double)xs, (double)ys);
-    scan_wave(p, M, o, c, sn, lane, s_rng, -1);
-    double d64;
-    float d32, phi;
-    goal_features((double)xs, (double)ys, c, sn, gx, gy, d64, d32, phi);
-    for (int j = lane; j < p.m + 4; j += 64) {
-        float val;
-        if (j < p.m)
-            val = pooled(p, s_rng, j);
-        else if (j == p.m)
-            val = d32;
-        else if (j == p.m + 1)
-            val = phi;
-        else
-            val = 0.0f;
-        obs_row[j] = val;
-    }
-    if (lane == 0) {
-        p.st.x[e] = xs;
-        p.st.y[e] = ys;
-        p.st.th[e] = ths;
-        p.st.v[e] = 0.0f;
-        p.st.w[e] = 0.0f;
-        p.st.gx[e] = gx;
-        p.st.gy[e] = gy;
-        p.st.dprev[e] = d32;
-        p.st.t[e] = 0;
-        p.st.ep[e] = ep + 1u;
-        if (p.d_fb) p.d_fb[e] = (uint8_t)fb;
-    }
-    wave_sync();
+    return r;
 }
 
-__device__ void env_step_wave(const StepParams &p, const MapView &M, const MapDesc &md, int e,
-                              int lane, float *s_rng) {
-    const int row = p.m + 4;
-    float *obs_row = p.obs + (int64_t)e * row;
-    if (p.mode == 1) {
-        if (p.mask && !p.mask[e]) return;
-        reset_env_wave(p, M, md, e, lane, s_rng, obs_row);
-        return;
-    }
-    const Motion mo = apply_action(p, p.act[2 * (int64_t)e], p.act[2 * (int64_t)e + 1], p.st.x[e],
-                                   p.st.y[e], p.st.th[e]);
-    const double x1 = (double)mo.x1, y1 = (double)mo.y1, th1 = (double)mo.th1;
-    const bool coll = footprint_hits_wave(M, p, x1, y1, th1, lane);
-    double sn, c;
-    sincos(th1, &sn, &c);
-    const RayOrigin o = ray_origin(M, x1, y1);
-    scan_wave(p, M, o, c, sn, lane, s_rng, e);
-    double d64;
-    float d32, phi;
-    goal_features(x1, y1, c, sn, p.st.gx[e], p.st.gy[e], d64, d32, phi);
-    const bool goal = d64 < (double)p.goal_r;
-    const int t = p.st.t[e] + 1;
-    const bool term = goal || coll;
-    const bool trunc = (t >= p.horizon) && !term;
-    const bool done = term || trunc;
-    const float rew = goal ? p.r_succ
-                           : (coll ? p.r_coll
-                                   : (float)((double)p.c1 * ((double)p.st.dprev[e] - (double)d32)));
-    float *fin = (done && p.final_obs) ? p.final_obs + (int64_t)e * row : nullptr;
-    for (int j = lane; j < row; j += 64) {
-        float val;
-        if (j < p.m)
-            val = pooled(p, s_rng, j);
-        else if (j == p.m)
-            val = d32;
-        else if (j == p.m + 1)
-            val = phi;
-        else if (j == p.m + 2)
-            val = mo.v;
-        else
-            val = mo.w;
-        obs_row[j] = val;
-        if (fin) fin[j] = val;
-    }
-    if (lane == 0) {
-        p.reward[e] = rew;
-        p.term[e] = (uint8_t)term;
-        p.trunc[e] = (uint8_t)trunc;
-        if (p.d_coll) p.d_coll[e] = (uint8_t)coll;
-        if (p.d_goal) p.d_goal[e] = (uint8_t)goal;
-        if (p.d_reset) p.d_reset[e] = (uint8_t)done;
-        if (p.d_fb) p.d_fb[e] = 0;
-        if (!done) {
-            p.st.x[e] = mo.x1;
-            p.st.y[e] = mo.y1;
-            p.st.th[e] = mo.th1;
-            p.st.v[e] = mo.v;
-            p.st.w[e] = mo.w;
-            p.st.dprev[e] = d32;
-            p.st.t[e] = t;
+// Range, hit and visits of the ray a lane holds, folded into the pool.
+__device__ __forceinline__ void finish_ray(const StepParams &p, const MapView &M, const TileJob &j,
+                                           const double2 *s_beam, int job, int beam, bool found,
+                                           bool lastx, int B, int k, uint32_t *s_pool, int per,
+                                           float inv_per, int E) {
+    float rg;
+    int hit, vis;
+    if (j.blocked) {
+        rg = 0.0f;
+        hit = j.block_hit;
+        vis = 1;
+    } else {
+        vis = k + 1;
+        if (found) {
+            const double2 cs = s_beam[beam];
+            const double dx = j.c * cs.x - j.s * cs.y;
+            const double dy = j.s * cs.x + j.c * cs.y;
+            walk_result(tile_origin(j, M.s), M.pitch, M.w, M.h, B, lastx, dx, dy, (double)p.rmax,
+                        rg, hit);
+        } else {
+            rg = p.rmax;
+            hit = -1;
         }
     }
-    wave_sync();
-    if (done) reset_env_wave(p, M, md, e, lane, s_rng, obs_row);
+    atomicMin(&s_pool[job * p.m + small_div(beam, per, inv_per)], __float_as_uint(rg));
+    if (job < E) {
+        const int64_t o = (int64_t)j.env * p.K + beam;
+        if (p.d_ranges) p.d_ranges[o] = rg;
+        if (p.d_hits) p.d_hits[o] = hit;
+        if (p.d_visits) p.d_visits[o] = vis;
+    }
 }
 
-template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void fused_step_kernel(StepParams p) {
+template <int E>
+__global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p) {
     extern __shared__ uint4 smem4[];
-    uint32_t *smem = reinterpret_cast<uint32_t *>(smem4);
+    uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem4);
+    TileJob *s_jobs = reinterpret_cast<TileJob *>(s_bits + p.max_words);  // [2E]: main, reset
+    uint32_t *s_pool = reinterpret_cast<uint32_t *>(s_jobs + 2 * E);      // [2E][m]
+    int *s_list = reinterpret_cast<int *>(s_pool + 2 * E * p.m);          // [2E] active jobs
+    int *s_misc = s_list + 2 * E;  // [0] active jobs, [1] next ray, [2..] done flags
+    double2 *s_beam = reinterpret_cast<double2 *>(s_misc + 2 * E + 8);  // [K] beam (cos, sin)
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int K = p.K, m = p.m, per = K / m;
     const Tile tile = p.tiles[blockIdx.x];
     const MapDesc md = p.maps[tile.map];
-    const uint4 *src = reinterpret_cast<const uint4 *>(p.bits + md.word_off);
-    for (int q = threadIdx.x; q < md.words / 4; q += WAVES * 64) smem4[q] = src[q];
+    {
+        const uint4 *g = reinterpret_cast<const uint4 *>(p.bits + md.word_off);
+        for (int q = tid; q < md.words / 4; q += kFusedThreads) smem4[q] = g[q];
+        for (int q = tid; q < K; q += kFusedThreads) s_beam[q] = p.beams[q];
+    }
     __syncthreads();
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (wave >= tile.count) return;
-    const int e = p.perm[tile.first + wave];
-    float *s_rng = reinterpret_cast<float *>(smem + p.max_words) + wave * p.K;
-    const MapView M{smem, md.w, md.h, md.wpr * 32, (double)md.res};
-    env_step_wave(p, M, md, e, lane, s_rng);
+    const MapView M = map_view(s_bits, md);
+    const bool want_debug = p.d_ranges || p.d_hits || p.d_visits;
+
+    // ---- motion: one group of 16 lanes per env ----
+    const int grp = tid >> 4, li = tid & 15;
+    if (grp < E) {
+        bool active = false, done = false;
+        if (grp < tile.count) {
+            const int e = p.perm[tile.first + grp];
+            active = true;
+            if (p.mode == 1) {
+                done = !p.mask || p.mask[e];
+                if (li == 0) s_jobs[grp].dst = 3;
+            } else {
+                const Motion mo = apply_action(p, p.act[2 * (int64_t)e], p.act[2 * (int64_t)e + 1],
+                                               p.st.x[e], p.st.y[e], p.st.th[e]);
+                const double x1 = (double)mo.x1, y1 = (double)mo.y1, th1 = (double)mo.th1;
+                const bool coll = group_footprint_hits(M, p, x1, y1, th1, li);
+                double sn, c;
+                sincos(th1, &sn, &c);
+                double d64;
+                float d32, phi;
+                goal_features(x1, y1, c, sn, p.st.gx[e], p.st.gy[e], d64, d32, phi);
+                const bool goal = d64 < (double)p.goal_r;
+                const int t = p.st.t[e] + 1;
+                const bool term = goal || coll;
+                const bool trunc = (t >= p.horizon) && !term;
+                done = term || trunc;
+                if (li == 0) {
+                    const float rew =
+                        goal ? p.r_succ
+                             : (coll ? p.r_coll
+                                     : (float)((double)p.c1 * ((double)p.st.dprev[e] - (double)d32)));
+                    p.reward[e] = rew;
+                    p.term[e] = (uint8_t)term;
+                    p.trunc[e] = (uint8_t)trunc;
+                    if (p.d_coll) p.d_coll[e] = (uint8_t)coll;
+                    if (p.d_goal) p.d_goal[e] = (uint8_t)goal;
+                    if (p.d_reset) p.d_reset[e] = (uint8_t)done;
+                    if (p.d_fb) p.d_fb[e] = 0;
+                    float *row = done ? p.final_obs : p.obs;
+                    if (row) {
+                        row += (int64_t)e * (m + 4);
+                        row[m] = d32;
+                        row[m + 1] = phi;
+                        row[m + 2] = mo.v;
+                        row[m + 3] = mo.w;
+                    }
+                    int dst = done ? (p.final_obs ? 1 : 2) : 0;
+                    if (dst == 2 && !want_debug) dst = 3;
+                    make_tile_job(s_jobs[grp], M, mo.x1, mo.y1, c, sn, e, dst);
+                    if (!done) {
+                        p.st.x[e] = mo.x1;
+                        p.st.y[e] = mo.y1;
+                        p.st.th[e] = mo.th1;
+                        p.st.v[e] = mo.v;
+                        p.st.w[e] = mo.w;
+                        p.st.dprev[e] = d32;
+                        p.st.t[e] = t;
+                    }
+                }
+            }
+            if (done) {
+                const uint32_t ep = p.st.ep[e];
+                const ResetPose r = group_sample_reset(p, M, md, e, ep, li);
+                if (li == 0) {
+                    double c, sn;
+                    store_reset(p, e, ep, r, c, sn);
+                    make_tile_job(s_jobs[E + grp], M, r.x, r.y, c, sn, e, 0);
+                }
+            }
+        }
+        if (li == 0) {
+            if (!active) s_jobs[grp].dst = 3;
+            s_misc[2 + grp] = (active && done) ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int nj = 0;
+        for (int j = 0; j < E; ++j)
+            if (s_jobs[j].dst != 3) s_list[nj++] = j;
+        for (int j = 0; j < E; ++j)
+            if (s_misc[2 + j]) s_list[nj++] = E + j;
+        s_misc[0] = nj;
+        s_misc[1] = 0;
+    }
+    for (int q = tid; q < 2 * E * m; q += kFusedThreads) s_pool[q] = 0x7f800000u;  // +inf
+    __syncthreads();
+
+    // ---- scan: lanes walk the tile's rays, refilling from s_misc[1] ----
+    const int nj = s_misc[0];
+    const int R = nj * K;
+    const float inv_K = 1.0f / (float)K, inv_per = 1.0f / (float)per;
+    const double rmax_c = (double)p.rmax / M.s;
+    int job = -1, beam = 0;  // ray held by this lane (finished rays are folded at the next refill)
+    bool act = false, found = false, lastx = false, exhausted = false;
+    Walk w{};
+    int k = 0;
+    for (;;) {
+        uint64_t am = __ballot(act);
+        if (!exhausted && __popcll(am) <= p.refill_at) {
+            if (!act && job >= 0) {
+                finish_ray(p, M, s_jobs[job], s_beam, job, beam, found, lastx, w.B, k, s_pool, per,
+                           inv_per, E);
+                job = -1;
+            }
+            const uint64_t idle = ~am;
+            const int nidle = 64 - __popcll(am);
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
+            base = __shfl(base, 0);
+            const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
+            if (!act && my < R) {
+                const int jl = small_div(my, K, inv_K);
+                job = s_list[jl];
+                beam = my - jl * K;
+                const TileJob &j = s_jobs[job];
+                k = 0;
+                found = false;
+                lastx = false;
+                act = false;
+                if (!j.blocked) {
+                    const double2 cs = s_beam[beam];
+                    const double dx = j.c * cs.x - j.s * cs.y;
+                    const double dy = j.s * cs.x + j.c * cs.y;
+                    w = walk_setup(M.pitch, tile_origin(j, M.s), dx, dy, rmax_c);
+                    act = w.n > 0;
+                }
+            }
+            exhausted = base + nidle >= R;
+            am = __ballot(act);
+        }
+        if (am == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+        if (act) {
+            // up to `groups` groups of 4 cells; the 4 cells of a group are read
+            // before any is tested (the padding ring keeps them in the bitmap)
+#pragma unroll 1
+            for (int gi = 0; gi < p.groups; ++gi) {
+                const bool x0 = w.Eh < w.thr;
+                const int B0 = w.B + (x0 ? w.incx : w.incy);
+                const int E1 = w.Eh + (x0 ? w.dEx : w.dEy);
+                const bool x1 = E1 < w.thr;
+                const int B1 = B0 + (x1 ? w.incx : w.incy);
+                const int E2 = E1 + (x1 ? w.dEx : w.dEy);
+                const bool x2 = E2 < w.thr;
+                const int B2 = B1 + (x2 ? w.incx : w.incy);
+                const int E3 = E2 + (x2 ? w.dEx : w.dEy);
+                const bool x3 = E3 < w.thr;
+                const int B3 = B2 + (x3 ? w.incx : w.incy);
+                const int E4 = E3 + (x3 ? w.dEx : w.dEy);
+                const uint32_t w0 = s_bits[B0 >> 5], w1 = s_bits[B1 >> 5];
+                const uint32_t w2 = s_bits[B2 >> 5], w3 = s_bits[B3 >> 5];
+                const uint32_t h = __builtin_amdgcn_ubfe(w0, (uint32_t)B0, 1u) |
+                                   (__builtin_amdgcn_ubfe(w1, (uint32_t)B1, 1u) << 1) |
+                                   (__builtin_amdgcn_ubfe(w2, (uint32_t)B2, 1u) << 2) |
+                                   (__builtin_amdgcn_ubfe(w3, (uint32_t)B3, 1u) << 3);
+                // first occupied cell of the group (32 when none); cells past the
+                // r_max budget do not count
+                const int rem = w.n - k;
+                const int f = (int)__builtin_ctz(h | 16u);
+                if (f < rem && f < 4) {
+                    w.B = f == 0 ? B0 : (f == 1 ? B1 : (f == 2 ? B2 : B3));
+                    lastx = f == 0 ? x0 : (f == 1 ? x1 : (f == 2 ? x2 : x3));
+                    k += f + 1;
+                    found = true;
+                    act = false;
+                    break;
+                }
+                if (rem <= 4) {
+                    k = w.n;
+                    act = false;
+                    break;
+                }
+                w.B = B3;
+                w.Eh = E4;
+                k += 4;
+            }
+        }
+    }
+    if (job >= 0)
+        finish_ray(p, M, s_jobs[job], s_beam, job, beam, found, lastx, w.B, k, s_pool, per, inv_per,
+                   E);
+    __syncthreads();
+
+    // ---- pooled sector minima -> observation rows ----
+    for (int q = tid; q < nj * m; q += kFusedThreads) {
+        const int jl = q / m, sec = q - jl * m;
+        const TileJob &j = s_jobs[s_list[jl]];
+        float *dst = j.dst == 0 ? p.obs : (j.dst == 1 ? p.final_obs : nullptr);
+        if (dst) dst[(int64_t)j.env * (m + 4) + sec] = __uint_as_float(s_pool[s_list[jl] * m + sec]);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Plain mapping: one thread per env, the same arithmetic in sequence.
+// Plain mapping: one thread per env, the whole step in sequence.
 
 __device__ void observe_serial(const StepParams &p, const MapView &M, double x, double y, double c,
                                double sn, float *obs_row, int64_t dbg_row) {
@@ -597,7 +909,7 @@ __device__ void observe_serial(const StepParams &p, const MapView &M, double x, 
                 const double2 cs = p.beams[k];
                 const double dx = c * cs.x - sn * cs.y;
                 const double dy = sn * cs.x + c * cs.y;
-                cast_ray(M.bits, M.pitch, M.w, M.h, o, dx, dy, rmax, rmax_c, rg, hit, vis);
+                cast_ray(M, o, dx, dy, rmax, rmax_c, rg, hit, vis);
             }
             l = q == 0 ? rg : fminf(l, rg);
             if (dbg_row >= 0) {
@@ -606,135 +918,89 @@ __device__ void observe_serial(const StepParams &p, const MapView &M, double x, 
                 if (p.d_visits) p.d_visits[dbg_row * p.K + k] = vis;
             }
         }
-        obs_row[j] = l;
+        if (obs_row) obs_row[j] = l;
     }
-}
-
-__device__ void reset_env_serial(const StepParams &p, const MapView &M, const MapDesc &md, int e,
-                                 float *obs_row) {
-    const uint32_t ep = p.st.ep[e];
-    const double s = M.s, Ws = (double)md.w * s, Hs = (double)md.h * s;
-    float xs = 0.0f, ys = 0.0f, ths = 0.0f, gx = 0.0f, gy = 0.0f;
-    uint32_t fb = 0;
-    bool found = false;
-    for (int a = 0; a < p.tries && !found; ++a) {
-        double u[4];
-        draw4(p, (uint32_t)e, ep, (uint32_t)a, 0u, u);
-        xs = uniform_pos(u[0], Ws);
-        ys = uniform_pos(u[1], Hs);
-        ths = uniform_heading(u[2]);
-        found = !footprint_hits_serial(M, p, (double)xs, (double)ys, (double)ths);
-    }
-    if (!found) {
-        double u[4];
-        draw4(p, (uint32_t)e, ep, 0u, 2u, u);
-        free_cell_centre(p, md, u[0], xs, ys);
-        ths = uniform_heading(u[2]);
-        fb |= 1u;
-    }
-    found = false;
-    for (int b = 0; b < p.tries && !found; ++b) {
-        double u[4];
-        draw4(p, (uint32_t)e, ep, (uint32_t)b, 1u, u);
-        gx = uniform_pos(u[0], Ws);
-        gy = uniform_pos(u[1], Hs);
-        if (disc_hits_serial(M, (double)gx, (double)gy, p.rc)) continue;
-        const double ddx = (double)gx - (double)xs, ddy = (double)gy - (double)ys;
-        found = sqrt(ddx * ddx + ddy * ddy) >= (double)p.gmd;
-    }
-    if (!found) {
-        double u[4];
-        draw4(p, (uint32_t)e, ep, 0u, 3u, u);
-        free_cell_centre(p, md, u[0], gx, gy);
-        fb |= 2u;
-    }
-    double sn, c;
-    sincos((double)ths, &sn, &c);
-    observe_serial(p, M, (double)xs, (double)ys, c, sn, obs_row, -1);
-    double d64;
-    float d32, phi;
-    goal_features((double)xs, (double)ys, c, sn, gx, gy, d64, d32, phi);
-    obs_row[p.m] = d32;
-    obs_row[p.m + 1] = phi;
-    obs_row[p.m + 2] = 0.0f;
-    obs_row[p.m + 3] = 0.0f;
-    p.st.x[e] = xs;
-    p.st.y[e] = ys;
-    p.st.th[e] = ths;
-    p.st.v[e] = 0.0f;
-    p.st.w[e] = 0.0f;
-    p.st.gx[e] = gx;
-    p.st.gy[e] = gy;
-    p.st.dprev[e] = d32;
-    p.st.t[e] = 0;
-    p.st.ep[e] = ep + 1u;
-    if (p.d_fb) p.d_fb[e] = (uint8_t)fb;
 }
 
 __global__ __launch_bounds__(64) void plain_step_kernel(StepParams p) {
     const int e = blockIdx.x * 64 + threadIdx.x;
     if (e >= p.N) return;
     const MapDesc md = p.maps[p.env_map[e]];
-    const MapView M{p.bits + md.word_off, md.w, md.h, md.wpr * 32, (double)md.res};
+    const MapView M = map_view(p.bits + md.word_off, md);
     const int row = p.m + 4;
     float *obs_row = p.obs + (int64_t)e * row;
+    bool do_reset;
     if (p.mode == 1) {
-        if (p.mask && !p.mask[e]) return;
-        reset_env_serial(p, M, md, e, obs_row);
-        return;
-    }
-    const Motion mo = apply_action(p, p.act[2 * (int64_t)e], p.act[2 * (int64_t)e + 1], p.st.x[e],
-                                   p.st.y[e], p.st.th[e]);
-    const double x1 = (double)mo.x1, y1 = (double)mo.y1, th1 = (double)mo.th1;
-    const bool coll = footprint_hits_serial(M, p, x1, y1, th1);
-    double sn, c;
-    sincos(th1, &sn, &c);
-    observe_serial(p, M, x1, y1, c, sn, obs_row, e);
-    double d64;
-    float d32, phi;
-    goal_features(x1, y1, c, sn, p.st.gx[e], p.st.gy[e], d64, d32, phi);
-    const bool goal = d64 < (double)p.goal_r;
-    const int t = p.st.t[e] + 1;
-    const bool term = goal || coll;
-    const bool trunc = (t >= p.horizon) && !term;
-    const bool done = term || trunc;
-    const float rew = goal ? p.r_succ
-                           : (coll ? p.r_coll
-                                   : (float)((double)p.c1 * ((double)p.st.dprev[e] - (double)d32)));
-    obs_row[p.m] = d32;
-    obs_row[p.m + 1] = phi;
-    obs_row[p.m + 2] = mo.v;
-    obs_row[p.m + 3] = mo.w;
-    if (done && p.final_obs) {
-        float *fin = p.final_obs + (int64_t)e * row;
-        for (int j = 0; j < row; ++j) fin[j] = obs_row[j];
-    }
-    p.reward[e] = rew;
-    p.term[e] = (uint8_t)term;
-    p.trunc[e] = (uint8_t)trunc;
-    if (p.d_coll) p.d_coll[e] = (uint8_t)coll;
-    if (p.d_goal) p.d_goal[e] = (uint8_t)goal;
-    if (p.d_reset) p.d_reset[e] = (uint8_t)done;
-    if (p.d_fb) p.d_fb[e] = 0;
-    if (done) {
-        reset_env_serial(p, M, md, e, obs_row);
+        do_reset = !p.mask || p.mask[e];
     } else {
-        p.st.x[e] = mo.x1;
-        p.st.y[e] = mo.y1;
-        p.st.th[e] = mo.th1;
-        p.st.v[e] = mo.v;
-        p.st.w[e] = mo.w;
-        p.st.dprev[e] = d32;
-        p.st.t[e] = t;
+        const Motion mo = apply_action(p, p.act[2 * (int64_t)e], p.act[2 * (int64_t)e + 1],
+                                       p.st.x[e], p.st.y[e], p.st.th[e]);
+        const double x1 = (double)mo.x1, y1 = (double)mo.y1, th1 = (double)mo.th1;
+        const bool coll = footprint_hits(M, p, x1, y1, th1);
+        double sn, c;
+        sincos(th1, &sn, &c);
+        double d64;
+        float d32, phi;
+        goal_features(x1, y1, c, sn, p.st.gx[e], p.st.gy[e], d64, d32, phi);
+        const bool goal = d64 < (double)p.goal_r;
+        const int t = p.st.t[e] + 1;
+        const bool term = goal || coll;
+        const bool trunc = (t >= p.horizon) && !term;
+        do_reset = term || trunc;
+        const float rew =
+            goal ? p.r_succ
+                 : (coll ? p.r_coll : (float)((double)p.c1 * ((double)p.st.dprev[e] - (double)d32)));
+        float *pre = do_reset ? (p.final_obs ? p.final_obs + (int64_t)e * row : nullptr) : obs_row;
+        observe_serial(p, M, x1, y1, c, sn, pre, e);
+        if (pre) {
+            pre[p.m] = d32;
+            pre[p.m + 1] = phi;
+            pre[p.m + 2] = mo.v;
+            pre[p.m + 3] = mo.w;
+        }
+        p.reward[e] = rew;
+        p.term[e] = (uint8_t)term;
+        p.trunc[e] = (uint8_t)trunc;
+        if (p.d_coll) p.d_coll[e] = (uint8_t)coll;
+        if (p.d_goal) p.d_goal[e] = (uint8_t)goal;
+        if (p.d_reset) p.d_reset[e] = (uint8_t)do_reset;
+        if (p.d_fb) p.d_fb[e] = 0;
+        if (!do_reset) {
+            p.st.x[e] = mo.x1;
+            p.st.y[e] = mo.y1;
+            p.st.th[e] = mo.th1;
+            p.st.v[e] = mo.v;
+            p.st.w[e] = mo.w;
+            p.st.dprev[e] = d32;
+            p.st.t[e] = t;
+        }
     }
+    if (!do_reset) return;
+    const uint32_t ep = p.st.ep[e];
+    const ResetPose r = sample_reset(p, M, md, e, ep);
+    double c, sn;
+    store_reset(p, e, ep, r, c, sn);
+    observe_serial(p, M, (double)r.x, (double)r.y, c, sn, obs_row, -1);
 }
 
 // ---------------------------------------------------------------------------
-hipError_t launch_fused(const StepParams &p, hipStream_t s) {
-    const size_t lds = (size_t)p.max_words * 4u + (size_t)kWavesPerGroup * (size_t)p.K * 4u;
-    hipLaunchKernelGGL(fused_step_kernel<kWavesPerGroup>, dim3((unsigned)p.num_tiles),
-                       dim3(kWavesPerGroup * 64), lds, s, p);
+template <int E>
+static hipError_t launch_fused_e(const StepParams &p, hipStream_t s) {
+    hipLaunchKernelGGL(fused_step_kernel<E>, dim3((unsigned)p.num_tiles), dim3(kFusedThreads),
+                       fused_lds_bytes(p.max_words, p.m, E, p.K), s, p);
     return hipGetLastError();
+}
+
+bool fused_tile_envs_supported(int E) { return E == 4 || E == 8 || E == 16; }
+
+hipError_t launch_fused(const StepParams &p, int tile_envs, hipStream_t s) {
+    if (p.num_tiles == 0) return hipSuccess;
+    switch (tile_envs) {
+        case 4: return launch_fused_e<4>(p, s);
+        case 8: return launch_fused_e<8>(p, s);
+        case 16: return launch_fused_e<16>(p, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_plain(const StepParams &p, hipStream_t s) {

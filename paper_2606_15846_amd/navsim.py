@@ -24,8 +24,8 @@ STATUS = {0: "NAVSIM_OK", -1: "NAVSIM_E_INVALID_ARG", -2: "NAVSIM_E_BAD_HANDLE",
           -3: "NAVSIM_E_STATE", -4: "NAVSIM_E_NO_FREE_SPACE", -5: "NAVSIM_E_OOM",
           -6: "NAVSIM_E_HIP", -7: "NAVSIM_E_UNSUPPORTED"}
 EXPORTS = ("navsim_create", "navsim_load_maps", "navsim_reset", "navsim_step",
-           "navsim_step_plain", "navsim_step_debug", "navsim_get_state", "navsim_set_state",
-           "navsim_destroy", "navsim_last_error")
+           "navsim_step_plain", "navsim_step_debug", "navsim_set_tuning", "navsim_get_tuning",
+           "navsim_get_state", "navsim_set_state", "navsim_destroy", "navsim_last_error")
 STATE_KEYS = ("x", "y", "th", "v", "w", "gx", "gy", "dprev", "t", "ep")
 _STATE_DT = (np.float32,) * 8 + (np.int32, np.uint32)
 
@@ -47,6 +47,10 @@ class NavsimDebug(C.Structure):
     _fields_ = [("ranges", C.c_void_p), ("hits", C.c_void_p), ("visits", C.c_void_p),
                 ("collision", C.c_void_p), ("goal", C.c_void_p), ("reset", C.c_void_p),
                 ("fallback", C.c_void_p)]
+
+
+class NavsimTuning(C.Structure):
+    _fields_ = [("tile_envs", C.c_int32), ("refill_at", C.c_int32), ("groups", C.c_int32)]
 
 
 class NavsimError(RuntimeError):
@@ -73,6 +77,8 @@ def load_library(path: str = LIB_PATH):
     L.navsim_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.navsim_step_plain.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.navsim_step_debug.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(NavsimDebug), i32, vp]
+    L.navsim_set_tuning.argtypes = [vp, C.POINTER(NavsimTuning)]
+    L.navsim_get_tuning.argtypes = [vp, C.POINTER(NavsimTuning)]
     L.navsim_get_state.argtypes = [vp, vp, C.c_size_t, vp]
     L.navsim_set_state.argtypes = [vp, vp, C.c_size_t, vp]
     L.navsim_destroy.argtypes = [vp]
@@ -173,6 +179,17 @@ def navsim_step_debug(h, act, obs, reward, terminated, truncated, final_obs, dbg
         _stream_ptr(stream, obs.device)))
 
 
+def navsim_set_tuning(h, tile_envs: int, refill_at: int, groups: int):
+    t = NavsimTuning(int(tile_envs), int(refill_at), int(groups))
+    _check(load_library().navsim_set_tuning(h, C.byref(t)))
+
+
+def navsim_get_tuning(h) -> dict:
+    t = NavsimTuning()
+    _check(load_library().navsim_get_tuning(h, C.byref(t)))
+    return {"tile_envs": t.tile_envs, "refill_at": t.refill_at, "groups": t.groups}
+
+
 def navsim_get_state(h, num_envs: int, stream=None, device=None) -> dict:
     buf = np.zeros(10 * num_envs, np.uint32)
     dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -260,6 +277,12 @@ class NavSim:
         navsim_step_debug(self.h, act, self.obs, self.reward, self.terminated, self.truncated,
                           self.final_obs, dbg, kernel)
         return dbg
+
+    def set_tuning(self, tile_envs: int, refill_at: int, groups: int):
+        navsim_set_tuning(self.h, tile_envs, refill_at, groups)
+
+    def get_tuning(self) -> dict:
+        return navsim_get_tuning(self.h)
 
     def get_state(self) -> dict:
         return navsim_get_state(self.h, self.N, device=self.device)

@@ -24,7 +24,7 @@ def declared_functions():
 def test_library_exports_every_declared_function():
     lib = navsim.load_library()
     names = declared_functions()
-    assert len(names) == 10
+    assert len(names) == 12
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(navsim.EXPORTS) == names
@@ -90,6 +90,7 @@ def test_abi_version_and_null_arguments():
     assert lib.navsim_create(C.byref(c), 0, None) == -1
     for fn, args in [("navsim_step", (None,) * 8), ("navsim_step_plain", (None,) * 8),
                      ("navsim_reset", (None,) * 4), ("navsim_destroy", (None,)),
+                     ("navsim_set_tuning", (None, None)), ("navsim_get_tuning", (None, None)),
                      ("navsim_get_state", (None, None, 0, None)),
                      ("navsim_set_state", (None, None, 0, None)),
                      ("navsim_load_maps", (None, 1, None, None, None, None, None))]:

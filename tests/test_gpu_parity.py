@@ -240,3 +240,28 @@ def test_api_errors_on_device():
     navsim.navsim_step(h, act, obs, r, u8, u8)
     torch.cuda.synchronize()
     navsim.navsim_destroy(h)
+
+
+def test_launch_shape_does_not_change_results():
+    say("tuning invariance: tile_envs x refill_at x groups, c2 maps, 600 envs, 3 steps")
+    w = configs.build_workload("c2", num_envs=600)
+    acts = configs.uniform_actions(3, 600, seed=21)
+    ref_out = None
+    for te, ra, gr in [(4, 48, 4), (8, 32, 2), (16, 56, 8), (4, 0, 1), (8, 63, 64)]:
+        sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
+        sim.set_tuning(te, ra, gr)
+        assert sim.get_tuning() == {"tile_envs": te, "refill_at": ra, "groups": gr}
+        sim.reset()
+        outs = []
+        for t in range(3):
+            g, st = gpu_step(sim, acts[t], NAVSIM_KERNEL_FUSED)
+            outs.append((g, st))
+        if ref_out is None:
+            ref_out = outs
+        else:
+            for (ga, sa), (gb, sb) in zip(ref_out, outs):
+                for k in ga:
+                    assert np.array_equal(ga[k], gb[k]) or k == "final_obs", (te, ra, gr, k)
+                for k in oracle.STATE_KEYS:
+                    assert np.array_equal(sa[k], sb[k]), (te, ra, gr, k)
+        sim.close()
