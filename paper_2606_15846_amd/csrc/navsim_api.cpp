@@ -74,6 +74,7 @@ struct navsim_s {
     Tile *tiles = nullptr;
     int num_maps = 0, num_tiles = 0, max_words = 0;
     int tile_envs = kDefaultTileEnvs, refill_at = kDefaultRefillAt, groups = kDefaultGroups;
+    int ray_cap = 0;
     std::vector<int32_t> host_env_map;  // kept to rebuild the tiles when tile_envs changes
 };
 
@@ -215,6 +216,7 @@ StepParams make_params(const navsim_s *h) {
     p.max_words = h->max_words;
     p.refill_at = h->refill_at;
     p.groups = h->groups;
+    p.ray_cap = h->ray_cap;
     return p;
 }
 
@@ -352,6 +354,9 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
             return fail(NAVSIM_E_UNSUPPORTED,
                         "map %d: padded bitmap of %lld words exceeds the %d-word LDS budget", k,
                         (long long)(wpr * (height[k] + 2 * kPad)), kMaxMapWords);
+        if (width[k] + height[k] + 2 * kPad > 8191)
+            return fail(NAVSIM_E_UNSUPPORTED, "map %d: width + height must be at most %d", k,
+                        8191 - 2 * kPad);
         occ_off[k + 1] = occ_off[k] + (int64_t)width[k] * height[k];
     }
     std::vector<int> used(num_maps, 0);
@@ -403,13 +408,12 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
             return fail(NAVSIM_E_NO_FREE_SPACE, "map %d has no cell where the footprint fits", k);
     }
 
-    const size_t lds =
-        fused_lds_bytes(max_words, h->cfg.num_sectors, h->tile_envs, h->cfg.num_beams);
-    if (lds > 65536)
+    const int ray_cap =
+        fused_ray_cap(max_words, h->cfg.num_sectors, h->tile_envs, h->cfg.num_beams);
+    if (ray_cap == 0)
         return fail(NAVSIM_E_UNSUPPORTED,
-                    "largest map, %d beams and %d sectors need %zu bytes of LDS per workgroup "
-                    "(max 65536)",
-                    h->cfg.num_beams, h->cfg.num_sectors, lds);
+                    "largest map, %d beams and %d sectors do not fit 64 KiB of LDS per workgroup",
+                    h->cfg.num_beams, h->cfg.num_sectors);
     std::vector<int32_t> host_env_map(env_map, env_map + N);
     std::vector<int32_t> perm;
     std::vector<Tile> tiles;
@@ -431,6 +435,7 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
     h->num_maps = num_maps;
     h->num_tiles = (int)tiles.size();
     h->max_words = max_words;
+    h->ray_cap = ray_cap;
     h->host_env_map.swap(host_env_map);
     h->loaded = true;
     return NAVSIM_OK;
@@ -506,11 +511,11 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     if (t->refill_at < 0 || t->refill_at > 63)
         return fail(NAVSIM_E_INVALID_ARG, "refill_at must be in 0..63");
     if (t->groups < 1 || t->groups > 64) return fail(NAVSIM_E_INVALID_ARG, "groups must be in 1..64");
+    int ray_cap = h->ray_cap;
     if (h->loaded && t->tile_envs != h->tile_envs) {
-        const size_t lds =
-            fused_lds_bytes(h->max_words, h->cfg.num_sectors, t->tile_envs, h->cfg.num_beams);
-        if (lds > 65536)
-            return fail(NAVSIM_E_UNSUPPORTED, "tile_envs %d needs %zu bytes of LDS", t->tile_envs, lds);
+        ray_cap = fused_ray_cap(h->max_words, h->cfg.num_sectors, t->tile_envs, h->cfg.num_beams);
+        if (ray_cap == 0)
+            return fail(NAVSIM_E_UNSUPPORTED, "tile_envs %d does not fit LDS", t->tile_envs);
         std::vector<int32_t> perm;
         std::vector<Tile> tiles;
         build_tiles(h->host_env_map, t->tile_envs, perm, tiles);
@@ -529,6 +534,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     h->tile_envs = t->tile_envs;
     h->refill_at = t->refill_at;
     h->groups = t->groups;
+    h->ray_cap = ray_cap;
     return NAVSIM_OK;
 }
 

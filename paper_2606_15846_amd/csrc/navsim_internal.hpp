@@ -47,6 +47,7 @@ struct DevState {
 struct StepParams {
     int32_t N, K, m, horizon, footprint, tries, mode;  // mode 0 step, 1 reset
     int32_t refill_at, groups;  // fused walk: refill threshold, 4-cell groups per check
+    int32_t ray_cap;            // rays walked per chunk (LDS slots)
     float rmax, dt, goal_r, c1, r_succ, r_coll, radius, len, wid;
     float vlo, vhi, wlo, whi, gmd;
     uint32_t key0, key1;
@@ -71,7 +72,8 @@ struct StepParams {
     uint8_t *d_coll, *d_goal, *d_reset, *d_fb;
 };
 
-size_t fused_lds_bytes(int max_words, int m, int tile_envs, int K);
+size_t fused_lds_bytes(int max_words, int m, int tile_envs, int K, int ray_cap);
+int fused_ray_cap(int max_words, int m, int tile_envs, int K);
 bool fused_tile_envs_supported(int tile_envs);
 hipError_t launch_fused(const StepParams &p, int tile_envs, hipStream_t s);
 hipError_t launch_plain(const StepParams &p, hipStream_t s);

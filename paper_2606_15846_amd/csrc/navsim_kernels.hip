@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "navsim_internal.hpp"
 
 namespace navsim {
@@ -269,15 +271,19 @@ __device__ __forceinline__ Walk walk_setup(int pitch, const RayOrigin &o, double
     return w;
 }
 
-// Range and hit id of a walk that stopped in cell B (entered by an x crossing
-// when lastx): the crossing distance recomputed once in double.
+// Range and hit id of a walk that stopped in cell B.  The ray enters a cell
+// when it has crossed both the cell's x line and its y line facing it, so the
+// range is the later of the two crossing distances (a line behind the origin,
+// or parallel to the ray, gives -inf); recomputed once in double.
 __device__ __forceinline__ void walk_result(const RayOrigin &o, int pitch, int W, int H, int B,
-                                            bool lastx, double dx, double dy, double rmax,
-                                            float &range, int &hit) {
+                                            double dx, double dy, double rmax, float &range,
+                                            int &hit) {
     const int row = B / pitch, col = B - row * pitch;
     const int ix = col - kPad, iy = row - kPad;
-    double t = lastx ? (((double)(dx > 0.0 ? ix : ix + 1)) * o.s - o.x) / dx
-                     : (((double)(dy > 0.0 ? iy : iy + 1)) * o.s - o.y) / dy;
+    const double ninf = -__builtin_huge_val();
+    const double tx = dx != 0.0 ? (((double)(dx > 0.0 ? ix : ix + 1)) * o.s - o.x) / dx : ninf;
+    const double ty = dy != 0.0 ? (((double)(dy > 0.0 ? iy : iy + 1)) * o.s - o.y) / dy : ninf;
+    double t = tx > ty ? tx : ty;
     t = t > 0.0 ? t : 0.0;  // also maps -0 and NaN to +0
     t = t < rmax ? t : rmax;
     range = (float)t;
@@ -290,7 +296,7 @@ __device__ __forceinline__ void cast_ray(const MapView &M, const RayOrigin &o, d
                                          int &hit, int &visits) {
     Walk w = walk_setup(M.pitch, o, dx, dy, rmax_c);
     int k = 0;
-    bool found = false, lastx = false;
+    bool found = false;
     while (k < w.n) {
         const bool xs = w.Eh < w.thr;
         w.B += xs ? w.incx : w.incy;
@@ -298,13 +304,12 @@ __device__ __forceinline__ void cast_ray(const MapView &M, const RayOrigin &o, d
         ++k;
         if ((M.bits[w.B >> 5] >> (w.B & 31)) & 1u) {
             found = true;
-            lastx = xs;
             break;
         }
     }
     visits = k + 1;
     if (found) {
-        walk_result(o, M.pitch, M.w, M.h, w.B, lastx, dx, dy, rmax, range, hit);
+        walk_result(o, M.pitch, M.w, M.h, w.B, dx, dy, rmax, range, hit);
     } else {
         range = (float)rmax;
         hit = -1;
@@ -466,9 +471,10 @@ struct TileJob {
 constexpr int kFusedThreads = 256;
 constexpr int kGroupLanes = 16;
 
-size_t fused_lds_bytes(int max_words, int m, int E, int K) {
+size_t fused_lds_bytes(int max_words, int m, int E, int K, int ray_cap) {
     return (size_t)max_words * 4u + 2u * (size_t)E * sizeof(TileJob) +
-           2u * (size_t)E * (size_t)m * 4u + (4u * (size_t)E + 8u) * 4u + 16u * (size_t)K;
+           2u * (size_t)E * (size_t)m * 4u + (4u * (size_t)E + 8u) * 4u + 16u * (size_t)K +
+           16u * (size_t)ray_cap;
 }
 
 __device__ __forceinline__ void make_tile_job(TileJob &j, const MapView &M, float x, float y,
@@ -638,11 +644,27 @@ __device__ ResetPose group_sample_reset(const StepParams &p, const MapView &M, c
     return r;
 }
 
-// Range, hit and visits of the ray a lane holds, folded into the pool.
+// Packed walk of one ray in LDS (16 bytes).  Written by the bulk setup:
+//   x = B | n << 19        bit address of the origin cell, cells to walk
+//   y = Eh - thr           the next crossing is an x crossing iff negative
+//   z = DX | (dx > 0) << 31
+//   w = DY | (dy > 0) << 31
+// and, once walked, x = B | k << 19 (cell where the walk stopped, cells
+// walked) and y = 1 if that cell is occupied.
+__device__ __forceinline__ uint4 pack_walk(const Walk &w, int max_n) {
+    const int n = min(w.n, max_n);
+    uint4 r;
+    r.x = (uint32_t)w.B | ((uint32_t)n << 19);
+    r.y = (uint32_t)(w.Eh - w.thr);
+    r.z = (uint32_t)(-w.dEy) | (w.incx > 0 ? 0x80000000u : 0u);
+    r.w = (uint32_t)w.dEx | (w.incy > 0 ? 0x80000000u : 0u);
+    return r;
+}
+
+// Range, hit and visits of a walked ray, folded into the sector pool.
 __device__ __forceinline__ void finish_ray(const StepParams &p, const MapView &M, const TileJob &j,
-                                           const double2 *s_beam, int job, int beam, bool found,
-                                           bool lastx, int B, int k, uint32_t *s_pool, int per,
-                                           float inv_per, int E) {
+                                           const double2 *s_beam, int job, int beam, uint2 res,
+                                           uint32_t *s_pool, int per, float inv_per, int E) {
     float rg;
     int hit, vis;
     if (j.blocked) {
@@ -650,13 +672,14 @@ __device__ __forceinline__ void finish_ray(const StepParams &p, const MapView &M
         hit = j.block_hit;
         vis = 1;
     } else {
+        const int B = (int)(res.x & 0x7FFFFu), k = (int)(res.x >> 19);
         vis = k + 1;
-        if (found) {
+        if (res.y & 1u) {
             const double2 cs = s_beam[beam];
             const double dx = j.c * cs.x - j.s * cs.y;
             const double dy = j.s * cs.x + j.c * cs.y;
-            walk_result(tile_origin(j, M.s), M.pitch, M.w, M.h, B, lastx, dx, dy, (double)p.rmax,
-                        rg, hit);
+            walk_result(tile_origin(j, M.s), M.pitch, M.w, M.h, B, dx, dy, (double)p.rmax, rg,
+                        hit);
         } else {
             rg = p.rmax;
             hit = -1;
@@ -680,6 +703,7 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
     int *s_list = reinterpret_cast<int *>(s_pool + 2 * E * p.m);          // [2E] active jobs
     int *s_misc = s_list + 2 * E;  // [0] active jobs, [1] next ray, [2..] done flags
     double2 *s_beam = reinterpret_cast<double2 *>(s_misc + 2 * E + 8);  // [K] beam (cos, sin)
+    uint4 *s_ray = reinterpret_cast<uint4 *>(s_beam + p.K);               // [ray_cap] walks
     const int tid = threadIdx.x, lane = tid & 63;
     const int K = p.K, m = p.m, per = K / m;
     const Tile tile = p.tiles[blockIdx.x];
@@ -696,6 +720,9 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
     // ---- motion: one group of 16 lanes per env ----
     const int grp = tid >> 4, li = tid & 15;
     if (grp < E) {
+        // the rest of the workgroup waits for this: let it win issue slots from
+        // other workgroups' walks on the same SIMD
+        __builtin_amdgcn_s_setprio(3);
         bool active = false, done = false;
         if (grp < tile.count) {
             const int e = p.perm[tile.first + grp];
@@ -766,6 +793,7 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
             if (!active) s_jobs[grp].dst = 3;
             s_misc[2 + grp] = (active && done) ? 1 : 0;
         }
+        __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
     if (tid == 0) {
@@ -780,103 +808,130 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
     for (int q = tid; q < 2 * E * m; q += kFusedThreads) s_pool[q] = 0x7f800000u;  // +inf
     __syncthreads();
 
-    // ---- scan: lanes walk the tile's rays, refilling from s_misc[1] ----
+    // ---- scan, in chunks of at most ray_cap rays ----
     const int nj = s_misc[0];
     const int R = nj * K;
     const float inv_K = 1.0f / (float)K, inv_per = 1.0f / (float)per;
     const double rmax_c = (double)p.rmax / M.s;
-    int job = -1, beam = 0;  // ray held by this lane (finished rays are folded at the next refill)
-    bool act = false, found = false, lastx = false, exhausted = false;
-    Walk w{};
-    int k = 0;
-    for (;;) {
-        uint64_t am = __ballot(act);
-        if (!exhausted && __popcll(am) <= p.refill_at) {
-            if (!act && job >= 0) {
-                finish_ray(p, M, s_jobs[job], s_beam, job, beam, found, lastx, w.B, k, s_pool, per,
-                           inv_per, E);
-                job = -1;
+    const int max_n = M.w + M.h + 2 * kPad;  // a walk meets the padding ring before this
+    for (int c0 = 0; c0 < R; c0 += p.ray_cap) {
+        const int Rc = min(p.ray_cap, R - c0);
+        // (1) every ray's walk start, all lanes busy
+        for (int r = tid; r < Rc; r += kFusedThreads) {
+            const int g = c0 + r, jl = small_div(g, K, inv_K), beam = g - jl * K;
+            const TileJob &j = s_jobs[s_list[jl]];
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (!j.blocked) {
+                const double2 cs = s_beam[beam];
+                const double dx = j.c * cs.x - j.s * cs.y;
+                const double dy = j.s * cs.x + j.c * cs.y;
+                v = pack_walk(walk_setup(M.pitch, tile_origin(j, M.s), dx, dy, rmax_c), max_n);
             }
-            const uint64_t idle = ~am;
-            const int nidle = 64 - __popcll(am);
-            int base = 0;
-            if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
-            base = __shfl(base, 0);
-            const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
-            if (!act && my < R) {
-                const int jl = small_div(my, K, inv_K);
-                job = s_list[jl];
-                beam = my - jl * K;
-                const TileJob &j = s_jobs[job];
-                k = 0;
-                found = false;
-                lastx = false;
-                act = false;
-                if (!j.blocked) {
-                    const double2 cs = s_beam[beam];
-                    const double dx = j.c * cs.x - j.s * cs.y;
-                    const double dy = j.s * cs.x + j.c * cs.y;
-                    w = walk_setup(M.pitch, tile_origin(j, M.s), dx, dy, rmax_c);
-                    act = w.n > 0;
+            s_ray[r] = v;
+        }
+        if (tid == 0) s_misc[1] = 0;
+        __syncthreads();
+        // (2) walk: lanes take rays from s_misc[1]; a lane whose ray is done
+        // writes its result back and takes a new one once at most refill_at
+        // lanes of its wavefront are still walking
+        int r = -1;
+        bool act = false, exhausted = false;
+        int B = 0, Eh = 0, incx = 0, incy = 0, dEx = 0, dEy = 0, n = 0, k = 0;
+        uint32_t flags = 0u;
+        for (;;) {
+            uint64_t am = __ballot(act);
+            if (!exhausted && __popcll(am) <= p.refill_at) {
+                if (!act && r >= 0) {
+                    reinterpret_cast<uint2 *>(s_ray)[2 * r] =
+                        make_uint2((uint32_t)B | ((uint32_t)k << 19), flags);
+                    r = -1;
                 }
+                const uint64_t idle = ~am;
+                const int nidle = 64 - __popcll(am);
+                int base = 0;
+                if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
+                base = __shfl(base, 0);
+                const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
+                if (!act && my < Rc) {
+                    const uint4 v = s_ray[my];
+                    r = my;
+                    B = (int)(v.x & 0x7FFFFu);
+                    n = (int)(v.x >> 19);
+                    Eh = (int)v.y;
+                    dEy = -(int)(v.z & 0x7FFFFFFFu);
+                    dEx = (int)(v.w & 0x7FFFFFFFu);
+                    incx = (v.z >> 31) ? 1 : -1;
+                    incy = (v.w >> 31) ? M.pitch : -M.pitch;
+                    k = 0;
+                    flags = 0u;
+                    act = n > 0;
+                }
+                exhausted = base + nidle >= Rc;
+                am = __ballot(act);
             }
-            exhausted = base + nidle >= R;
-            am = __ballot(act);
-        }
-        if (am == 0ull) {
-            if (exhausted) break;
-            continue;
-        }
-        if (act) {
-            // up to `groups` groups of 4 cells; the 4 cells of a group are read
-            // before any is tested (the padding ring keeps them in the bitmap)
+            if (am == 0ull) {
+                if (exhausted) break;
+                continue;
+            }
+            if (act) {
+                // up to `groups` groups of 4 cells; the 4 cells of a group are
+                // read before any is tested (the padding ring keeps them in the
+                // stored bitmap)
 #pragma unroll 1
-            for (int gi = 0; gi < p.groups; ++gi) {
-                const bool x0 = w.Eh < w.thr;
-                const int B0 = w.B + (x0 ? w.incx : w.incy);
-                const int E1 = w.Eh + (x0 ? w.dEx : w.dEy);
-                const bool x1 = E1 < w.thr;
-                const int B1 = B0 + (x1 ? w.incx : w.incy);
-                const int E2 = E1 + (x1 ? w.dEx : w.dEy);
-                const bool x2 = E2 < w.thr;
-                const int B2 = B1 + (x2 ? w.incx : w.incy);
-                const int E3 = E2 + (x2 ? w.dEx : w.dEy);
-                const bool x3 = E3 < w.thr;
-                const int B3 = B2 + (x3 ? w.incx : w.incy);
-                const int E4 = E3 + (x3 ? w.dEx : w.dEy);
-                const uint32_t w0 = s_bits[B0 >> 5], w1 = s_bits[B1 >> 5];
-                const uint32_t w2 = s_bits[B2 >> 5], w3 = s_bits[B3 >> 5];
-                const uint32_t h = __builtin_amdgcn_ubfe(w0, (uint32_t)B0, 1u) |
-                                   (__builtin_amdgcn_ubfe(w1, (uint32_t)B1, 1u) << 1) |
-                                   (__builtin_amdgcn_ubfe(w2, (uint32_t)B2, 1u) << 2) |
-                                   (__builtin_amdgcn_ubfe(w3, (uint32_t)B3, 1u) << 3);
-                // first occupied cell of the group (32 when none); cells past the
-                // r_max budget do not count
-                const int rem = w.n - k;
-                const int f = (int)__builtin_ctz(h | 16u);
-                if (f < rem && f < 4) {
-                    w.B = f == 0 ? B0 : (f == 1 ? B1 : (f == 2 ? B2 : B3));
-                    lastx = f == 0 ? x0 : (f == 1 ? x1 : (f == 2 ? x2 : x3));
-                    k += f + 1;
-                    found = true;
-                    act = false;
-                    break;
+                for (int gi = 0; gi < p.groups; ++gi) {
+                    const bool x0 = Eh < 0;
+                    const int B0 = B + (x0 ? incx : incy);
+                    const int E1 = Eh + (x0 ? dEx : dEy);
+                    const bool x1 = E1 < 0;
+                    const int B1 = B0 + (x1 ? incx : incy);
+                    const int E2 = E1 + (x1 ? dEx : dEy);
+                    const bool x2 = E2 < 0;
+                    const int B2 = B1 + (x2 ? incx : incy);
+                    const int E3 = E2 + (x2 ? dEx : dEy);
+                    const bool x3 = E3 < 0;
+                    const int B3 = B2 + (x3 ? incx : incy);
+                    const int E4 = E3 + (x3 ? dEx : dEy);
+                    const uint32_t w0 = s_bits[B0 >> 5], w1 = s_bits[B1 >> 5];
+                    const uint32_t w2 = s_bits[B2 >> 5], w3 = s_bits[B3 >> 5];
+                    const uint32_t h = __builtin_amdgcn_ubfe(w0, (uint32_t)B0, 1u) |
+                                       (__builtin_amdgcn_ubfe(w1, (uint32_t)B1, 1u) << 1) |
+                                       (__builtin_amdgcn_ubfe(w2, (uint32_t)B2, 1u) << 2) |
+                                       (__builtin_amdgcn_ubfe(w3, (uint32_t)B3, 1u) << 3);
+                    // first occupied cell of the group (4 when none); cells past
+                    // the r_max budget do not count
+                    const int rem = n - k;
+                    const int f = (int)__builtin_ctz(h | 16u);
+                    if (f < rem && f < 4) {
+                        B = f == 0 ? B0 : (f == 1 ? B1 : (f == 2 ? B2 : B3));
+                        flags = 1u;
+                        k += f + 1;
+                        act = false;
+                        break;
+                    }
+                    if (rem <= 4) {
+                        k = n;
+                        act = false;
+                        break;
+                    }
+                    B = B3;
+                    Eh = E4;
+                    k += 4;
                 }
-                if (rem <= 4) {
-                    k = w.n;
-                    act = false;
-                    break;
-                }
-                w.B = B3;
-                w.Eh = E4;
-                k += 4;
             }
         }
+        if (r >= 0)
+            reinterpret_cast<uint2 *>(s_ray)[2 * r] = make_uint2((uint32_t)B | ((uint32_t)k << 19), flags);
+        __syncthreads();
+        // (3) ranges, hits, pooling, all lanes busy
+        for (int q = tid; q < Rc; q += kFusedThreads) {
+            const int g = c0 + q, jl = small_div(g, K, inv_K), beam = g - jl * K;
+            const int job = s_list[jl];
+            const uint4 v = s_ray[q];
+            finish_ray(p, M, s_jobs[job], s_beam, job, beam, make_uint2(v.x, v.y), s_pool, per,
+                       inv_per, E);
+        }
+        __syncthreads();
     }
-    if (job >= 0)
-        finish_ray(p, M, s_jobs[job], s_beam, job, beam, found, lastx, w.B, k, s_pool, per, inv_per,
-                   E);
-    __syncthreads();
 
     // ---- pooled sector minima -> observation rows ----
     for (int q = tid; q < nj * m; q += kFusedThreads) {
@@ -987,11 +1042,21 @@ __global__ __launch_bounds__(64) void plain_step_kernel(StepParams p) {
 template <int E>
 static hipError_t launch_fused_e(const StepParams &p, hipStream_t s) {
     hipLaunchKernelGGL(fused_step_kernel<E>, dim3((unsigned)p.num_tiles), dim3(kFusedThreads),
-                       fused_lds_bytes(p.max_words, p.m, E, p.K), s, p);
+                       fused_lds_bytes(p.max_words, p.m, E, p.K, p.ray_cap), s, p);
     return hipGetLastError();
 }
 
 bool fused_tile_envs_supported(int E) { return E == 4 || E == 8 || E == 16; }
+
+// LDS walk slots per chunk: the rays of a full tile plus one reset pose
+// ((E + 1) K, rounded up to a wavefront), so a tile walks a second chunk only
+// when two or more of its envs reset; fewer if that does not fit 64 KiB.
+int fused_ray_cap(int max_words, int m, int E, int K) {
+    const size_t base = fused_lds_bytes(max_words, m, E, K, 0);
+    if (base + 16u * 256u > 65536u) return 0;
+    const int fit = (int)((65536u - base) / 16u) & ~63;
+    return std::max(std::min(((E + 1) * K + 63) & ~63, fit), 256);
+}
 
 hipError_t launch_fused(const StepParams &p, int tile_envs, hipStream_t s) {
     if (p.num_tiles == 0) return hipSuccess;
