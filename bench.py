@@ -51,12 +51,12 @@ def hbm_traffic_from_profile():
         return None
 
 
-def cpu_baseline(w, acts, target_s: float = 10.0) -> dict:
+def cpu_baseline(w, acts, rays_per_env_step: float, target_s: float = 10.0) -> dict:
     import oracle
     threads = min(len(os.sched_getaffinity(0)), 16)
-    ref = oracle.OracleSim(w["cfg"], w["maps"], w["res"], w["env_map"])
+    ref = oracle.OracleSim(w["cfg"], w["maps"], w["res"], w["env_map"], profiles=w["profiles"])
     ref.reset(threads=threads)
-    N, K = ref.N, ref.K
+    N = ref.N
     t0 = time.perf_counter()
     ref.step(acts[0], debug=False, threads=threads)
     one = time.perf_counter() - t0
@@ -67,7 +67,7 @@ def cpu_baseline(w, acts, target_s: float = 10.0) -> dict:
     dt = time.perf_counter() - t0
     rate = N * steps / dt
     return {"value": rate, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
-            "rays_per_s": rate * K,
+            "rays_per_s": rate * rays_per_env_step,
             "sample": f"{steps} steps x {N} envs of the same workload (scalar FP64 C oracle, "
                       f"{threads} threads over env slices), {dt:.1f} s"}
 
@@ -88,8 +88,9 @@ def main():
                     help="only run 5 device-to-device copies of 256 MiB (HBM counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the step shards by env with no exchange, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}): the step shards by "
+              "env with no exchange between GPUs, so N GPUs run N independent shares",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -111,14 +112,20 @@ def main():
     w = configs.build_workload(args.workload)
     cfg = w["cfg"]
     N, K, m = cfg["num_envs"], cfg["num_beams"], cfg["num_sectors"]
+    # beams cast per step (per-map beam counts when the workload has profiles)
+    if w["profiles"] is None:
+        rays_per_step = N * K
+    else:
+        kmap = np.array([q["num_beams"] for q in w["profiles"]], dtype=np.int64)
+        rays_per_step = int(kmap[np.asarray(w["env_map"])].sum())
     total = args.warmup + args.steps
     acts_np = configs.uniform_actions(total, N, seed=42)
     acts = torch.from_numpy(acts_np).to(dev)
-    sim = NavSim(cfg, w["maps"], w["res"], w["env_map"], device=0)
+    sim = NavSim(cfg, w["maps"], w["res"], w["env_map"], device=0, profiles=w["profiles"])
     # launch shape: the autotuned one for this workload (paper_2606_15846_amd/
     # tuning.json) unless given on the command line; results do not depend on it
     from paper_2606_15846_amd import autotune
-    tuning = autotune.best_for(autotune.workload_key(cfg, w["maps"]))
+    tuning = autotune.best_for(autotune.workload_key(cfg, w["maps"], w["profiles"]))
     for k in ("tile_envs", "refill_at", "groups"):
         if getattr(args, k) is not None:
             tuning[k] = getattr(args, k)
@@ -169,13 +176,13 @@ def main():
         torch.cuda.synchronize()
         pms = p0.elapsed_time(p1)
         prate = N * args.plain_steps / (pms / 1e3)
-        plain = {"value": prate, "rays_per_s": prate * K, "steps": args.plain_steps,
+        plain = {"value": prate, "rays_per_s": prate * rays_per_step / N, "steps": args.plain_steps,
                  "ms_per_step": pms / args.plain_steps,
                  "mapping": "one thread per env, beams in sequence, bitmap in HBM"}
     sim_tuning = sim.get_tuning()
     sim.close()
 
-    cpu = None if args.no_cpu else cpu_baseline(w, acts_np[args.warmup:])
+    cpu = None if args.no_cpu else cpu_baseline(w, acts_np[args.warmup:], rays_per_step / N)
     out = {
         "metric": "env-steps/s + rays/s on 1 MI355X, fused-batched vs plain step; % LDS roofline",
         "value": value,
@@ -189,11 +196,15 @@ def main():
         "vs_baseline": None,
         "dtype": "int32+f64",
         "data": "synthetic",
-        "config": {"workload": w["name"], "envs": N, "beams": K, "sectors": m,
-                   "maps": len(w["maps"]), "map_cells": f"{w['maps'][0].shape[1]}x{w['maps'][0].shape[0]}",
+        "config": {"workload": w["name"], "envs": N, "sectors": m, "maps": len(w["maps"]),
+                   "beams": K if w["profiles"] is None else "per map",
+                   "beams_per_env_step": rays_per_step / N,
+                   "map_cells": (f"{w['maps'][0].shape[1]}x{w['maps'][0].shape[0]}"
+                                 if w["profiles"] is None else "per map"),
                    "res_m": w["res"][0], "max_range_m": cfg["max_range_m"],
-                   "footprint": "disc" if cfg["footprint"] == 0 else "rect"},
-        "rays_per_s": value * K,
+                   "footprint": ("per map" if w["profiles"] is not None
+                                 else "disc" if cfg["footprint"] == 0 else "rect")},
+        "rays_per_s": value * rays_per_step / N,
         "plain": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "tuning": sim_tuning,

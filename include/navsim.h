@@ -111,6 +111,21 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
                                const int32_t *height, const float *res_m, const uint8_t *occ,
                                const int32_t *env_map);
 
+/* Robot and sensor of the envs on one map: lets maps of different beam counts
+ * and footprints run in the same step (the configuration's beam count is then
+ * the largest, and the stride of per-ray diagnostics). */
+typedef struct {
+    int32_t num_beams;        /* K for this map: 1..cfg.num_beams, multiple of num_sectors */
+    int32_t footprint;        /* NAVSIM_DISC or NAVSIM_RECT                                */
+    float radius_m, length_m, width_m;
+} navsim_map_profile;
+
+/* navsim_load_maps with one profile per map (host array [num_maps]; NULL = the
+ * configuration's beam count and footprint for every map). */
+navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *width,
+                                  const int32_t *height, const float *res_m, const uint8_t *occ,
+                                  const int32_t *env_map, const navsim_map_profile *profiles);
+
 /* Sparse reset (section 2.2.3): every env with mask[e] != 0 (mask NULL = all)
  * gets a new collision-free start pose and goal from its map's free space,
  * zero velocity, t = 0, and its reset observation written to obs row e.  Rows

@@ -49,6 +49,9 @@ class OrcMaps(C.Structure):
         ("off", C.POINTER(C.c_int64)), ("occ", C.POINTER(C.c_uint8)),
         ("free_off", C.POINTER(C.c_int64)), ("free_cnt", C.POINTER(C.c_int32)),
         ("free_cells", C.POINTER(C.c_int32)),
+        ("prof_beams", C.POINTER(C.c_int32)), ("prof_footprint", C.POINTER(C.c_int32)),
+        ("prof_radius", C.POINTER(C.c_float)), ("prof_length", C.POINTER(C.c_float)),
+        ("prof_width", C.POINTER(C.c_float)),
     ]
 
 
@@ -104,6 +107,7 @@ def lib():
                            C.c_double, C.c_double, P(OrcRay)]
     L.orc_march.argtypes = [P(OrcMaps), C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                             C.c_double, C.c_double, P(C.c_double), P(C.c_int32)]
+    L.orc_cfg_for_map.argtypes = [P(OrcCfg), P(OrcMaps), C.c_int, P(OrcCfg)]
     L.orc_beam_angle.argtypes = [P(OrcCfg), C.c_int]
     L.orc_beam_angle.restype = C.c_double
     L.orc_scan.argtypes = [P(OrcMaps), C.c_int, P(OrcCfg), C.c_double, C.c_double, C.c_double,
@@ -138,9 +142,11 @@ def make_cfg(cfg: dict) -> OrcCfg:
 
 
 class OracleMaps:
-    """Maps concatenated for the oracle, with the free-cell lists it builds."""
+    """Maps concatenated for the oracle, with the free-cell lists it builds and
+    optional per-map robot/sensor profiles (dicts with num_beams, footprint,
+    radius_m, length_m, width_m)."""
 
-    def __init__(self, maps, res, circumradius: float | None = None):
+    def __init__(self, maps, res, circumradius: float | None = None, profiles=None):
         self.maps = [np.ascontiguousarray(m, dtype=np.uint8) for m in maps]
         n = len(self.maps)
         self.w = np.array([m.shape[1] for m in self.maps], dtype=np.int32)
@@ -152,23 +158,36 @@ class OracleMaps:
         self.free_off = np.zeros(n, dtype=np.int64)
         self.free_cnt = np.zeros(n, dtype=np.int32)
         self.free_cells = np.zeros(1, dtype=np.int32)
+        self.profiles = profiles
+        if profiles is not None:
+            self.p_beams = np.array([q["num_beams"] for q in profiles], np.int32)
+            self.p_fp = np.array([q["footprint"] for q in profiles], np.int32)
+            self.p_rad = np.array([q.get("radius_m", 0.0) for q in profiles], np.float32)
+            self.p_len = np.array([q.get("length_m", 0.0) for q in profiles], np.float32)
+            self.p_wid = np.array([q.get("width_m", 0.0) for q in profiles], np.float32)
         self._mk()
         if circumradius is not None:
             self.build_free_lists(circumradius)
 
     def _mk(self):
+        pr = self.profiles is not None
         self.struct = OrcMaps(
             int(len(self.maps)), _ptr(self.w, C.c_int32), _ptr(self.h, C.c_int32),
             _ptr(self.res, C.c_float), _ptr(self.off, C.c_int64), _ptr(self.occ, C.c_uint8),
             _ptr(self.free_off, C.c_int64), _ptr(self.free_cnt, C.c_int32),
-            _ptr(self.free_cells, C.c_int32))
+            _ptr(self.free_cells, C.c_int32),
+            _ptr(self.p_beams, C.c_int32) if pr else None, _ptr(self.p_fp, C.c_int32) if pr else None,
+            _ptr(self.p_rad, C.c_float) if pr else None, _ptr(self.p_len, C.c_float) if pr else None,
+            _ptr(self.p_wid, C.c_float) if pr else None)
 
-    def build_free_lists(self, rc: float):
+    def build_free_lists(self, rc):
+        """rc: one circumradius for every map, or a list with one per map."""
         L = lib()
         lists = []
+        rcs = list(rc) if np.ndim(rc) else [rc] * len(self.maps)
         for k in range(len(self.maps)):
             buf = np.zeros(int(self.w[k]) * int(self.h[k]), dtype=np.int32)
-            cnt = L.orc_free_list(C.byref(self.struct), k, float(rc), _ptr(buf, C.c_int32))
+            cnt = L.orc_free_list(C.byref(self.struct), k, float(rcs[k]), _ptr(buf, C.c_int32))
             lists.append(buf[:cnt])
         self.free_cnt = np.array([len(x) for x in lists], dtype=np.int32)
         self.free_off = np.concatenate([[0], np.cumsum(self.free_cnt)[:-1]]).astype(np.int64)
@@ -205,15 +224,20 @@ class OracleMaps:
 class OracleSim:
     """Batched simulator state on the CPU, stepped by the C oracle."""
 
-    def __init__(self, cfg: dict, maps, res, env_map):
+    def __init__(self, cfg: dict, maps, res, env_map, profiles=None):
         self.cfg_dict = dict(cfg)
         self.cfg = make_cfg(cfg)
         self.N = int(cfg["num_envs"])
-        self.K = int(cfg["num_beams"])
+        self.K = int(cfg["num_beams"])  # largest beam count: stride of per-ray outputs
         self.m = int(cfg["num_sectors"])
         L = lib()
-        self.maps = OracleMaps(maps, res)
-        self.maps.build_free_lists(L.orc_circumradius(C.byref(self.cfg)))
+        self.maps = OracleMaps(maps, res, profiles=profiles)
+        rcs = []
+        for k in range(len(maps)):
+            mc = OrcCfg()
+            L.orc_cfg_for_map(C.byref(self.cfg), C.byref(self.maps.struct), k, C.byref(mc))
+            rcs.append(L.orc_circumradius(C.byref(mc)))
+        self.maps.build_free_lists(rcs)
         self.env_map = np.ascontiguousarray(env_map, dtype=np.int32)
         self.state = {k: np.zeros(self.N, dtype=_STATE_DTYPES[k]) for k in STATE_KEYS}
         self._mk_state()
@@ -284,13 +308,20 @@ class OracleSim:
         self._run(run, threads)
         return o
 
+    def map_cfg(self, map_id) -> OrcCfg:
+        mc = OrcCfg()
+        lib().orc_cfg_for_map(C.byref(self.cfg), C.byref(self.maps.struct), int(map_id),
+                              C.byref(mc))
+        return mc
+
     def scan(self, map_id, x, y, th):
-        K = self.K
+        mc = self.map_cfg(map_id)
+        K = int(mc.num_beams)
         rg = np.zeros(K, np.float32)
         hit = np.zeros(K, np.int32)
         gr = np.zeros(K, np.uint8)
         vis = np.zeros(K, np.int32)
-        lib().orc_scan(C.byref(self.maps.struct), int(map_id), C.byref(self.cfg), float(x),
+        lib().orc_scan(C.byref(self.maps.struct), int(map_id), C.byref(mc), float(x),
                        float(y), float(th), _ptr(rg, C.c_float), _ptr(hit, C.c_int32),
                        _ptr(gr, C.c_uint8), _ptr(vis, C.c_int32))
         return rg, hit, gr, vis
@@ -299,5 +330,6 @@ class OracleSim:
         return lib().orc_beam_angle(C.byref(self.cfg), int(k))
 
     def collides(self, map_id, x, y, th) -> bool:
+        mc = self.map_cfg(map_id)
         return bool(lib().orc_footprint_hits(C.byref(self.maps.struct), int(map_id),
-                                             C.byref(self.cfg), float(x), float(y), float(th)))
+                                             C.byref(mc), float(x), float(y), float(th)))

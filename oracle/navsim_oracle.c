@@ -54,6 +54,9 @@ typedef struct {
     const int64_t *free_off;   /* start of map k's free-cell list */
     const int32_t *free_cnt;
     const int32_t *free_cells; /* iy*w + ix */
+    /* optional per-map robot/sensor profile (NULL: the config's values) */
+    const int32_t *prof_beams, *prof_footprint;
+    const float *prof_radius, *prof_length, *prof_width;
 } orc_maps;
 
 typedef struct {
@@ -78,6 +81,20 @@ typedef struct {
     double range, perp, t_end;
     int32_t hit, visits, grazing, pad;
 } orc_ray;
+
+/* The configuration that applies to envs on map `map`: the global one with
+ * the map's beam count and footprint when a per-map profile is given. */
+void orc_cfg_for_map(const orc_cfg *cfg, const orc_maps *M, int map, orc_cfg *out)
+{
+    *out = *cfg;
+    if (M->prof_beams) out->num_beams = M->prof_beams[map];
+    if (M->prof_footprint) {
+        out->footprint = M->prof_footprint[map];
+        out->radius_m = M->prof_radius[map];
+        out->length_m = M->prof_length[map];
+        out->width_m = M->prof_width[map];
+    }
+}
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): a counter-based        */
@@ -399,10 +416,13 @@ static float orc_observe(const orc_maps *M, int map, const orc_cfg *cfg, double 
  * goal_min_dist from the start wins.  When every attempt fails, a cell of the
  * free-cell list is taken instead (index floor(u0 n_free), counter stream 2
  * for the start, 3 for the goal; the goal fallback ignores the distance). */
-static void orc_reset_env(const orc_cfg *cfg, const orc_maps *M, orc_state *st, int64_t e,
+static void orc_reset_env(const orc_cfg *gcfg, const orc_maps *M, orc_state *st, int64_t e,
                           float *obs, uint8_t *fallback)
 {
     int map = st->map[e];
+    orc_cfg mcfg;
+    orc_cfg_for_map(gcfg, M, map, &mcfg);
+    const orc_cfg *cfg = &mcfg;
     uint32_t ep = st->ep[e];
     double s = (double)M->res[map];
     double Ws = (double)M->w[map] * s, Hs = (double)M->h[map] * s;
@@ -477,13 +497,16 @@ void orc_reset(const orc_cfg *cfg, const orc_maps *M, orc_state *st, const uint8
 }
 
 /* One step of envs [e0, e1), in the order of the step data path (eq. 7). */
-void orc_step(const orc_cfg *cfg, const orc_maps *M, orc_state *st, const float *act,
+void orc_step(const orc_cfg *gcfg, const orc_maps *M, orc_state *st, const float *act,
               const orc_out *out, int64_t e0, int64_t e1)
 {
-    int K = cfg->num_beams, m = cfg->num_sectors;
-    double dt = (double)cfg->dt_s;
+    int K = gcfg->num_beams, m = gcfg->num_sectors; /* output strides: the largest K */
+    double dt = (double)gcfg->dt_s;
     for (int64_t e = e0; e < e1; ++e) {
         int map = st->map[e];
+        orc_cfg mcfg;
+        orc_cfg_for_map(gcfg, M, map, &mcfg);
+        const orc_cfg *cfg = &mcfg;
         /* action map (section 2.2.3, table 7): clip to [-1, 1], NaN -> 0 */
         double a0 = (double)act[2 * e], a1 = (double)act[2 * e + 1];
         if (a0 != a0) a0 = 0.0;
@@ -547,7 +570,7 @@ void orc_step(const orc_cfg *cfg, const orc_maps *M, orc_state *st, const float 
         if (term || trunc) {
             if (out->final_obs)
                 memcpy(out->final_obs + e * (m + 4), obs_row, sizeof(float) * (size_t)(m + 4));
-            orc_reset_env(cfg, M, st, e, out->obs, out->fallback);
+            orc_reset_env(gcfg, M, st, e, out->obs, out->fallback);
         }
     }
 }

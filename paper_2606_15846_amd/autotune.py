@@ -24,11 +24,14 @@ DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4}
 SPACE = {"tile_envs": (4, 8, 16), "refill_at": (32, 40, 48, 56), "groups": (2, 4, 8)}
 
 
-def workload_key(cfg: dict, maps) -> str:
+def workload_key(cfg: dict, maps, profiles=None) -> str:
     w = max(m.shape[1] for m in maps)
     h = max(m.shape[0] for m in maps)
-    return (f"N{cfg['num_envs']}_K{cfg['num_beams']}_m{cfg['num_sectors']}_map{w}x{h}"
-            f"_fp{cfg['footprint']}_r{cfg['max_range_m']:g}")
+    key = (f"N{cfg['num_envs']}_K{cfg['num_beams']}_m{cfg['num_sectors']}_map{w}x{h}"
+           f"_fp{cfg['footprint']}_r{cfg['max_range_m']:g}")
+    if profiles is not None:
+        key += f"_maps{len(maps)}_mixed{sum(q['num_beams'] for q in profiles)}"
+    return key
 
 
 def load_all() -> dict:
@@ -100,13 +103,13 @@ def main():
     w = configs.build_workload(args.workload)
     cfg = w["cfg"]
     dev = torch.device("cuda", 0)
-    sim = NavSim(cfg, w["maps"], w["res"], w["env_map"], device=0)
+    sim = NavSim(cfg, w["maps"], w["res"], w["env_map"], device=0, profiles=w["profiles"])
     sim.reset()
     acts = torch.from_numpy(configs.uniform_actions(args.steps + 20, cfg["num_envs"], seed=7)).to(dev)
     for t in range(20):
         sim.step(acts[t])
     best, table = tune(sim, acts[20:], steps=args.steps, verbose=True)
-    key = workload_key(cfg, w["maps"])
+    key = workload_key(cfg, w["maps"], w["profiles"])
     save(key, best, table, torch.cuda.get_device_name(0))
     print(json.dumps({"key": key, "best": best}))
     sim.close()

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -59,7 +60,6 @@ bool finite_pos(float v) { return isfinite(v) && v > 0.0f; }
 struct navsim_s {
     navsim_config cfg;
     int device = 0;
-    double rc = 0.0;
     bool loaded = false;
     bool initialized = false;
     // device memory
@@ -75,6 +75,7 @@ struct navsim_s {
     int num_maps = 0, num_tiles = 0, max_words = 0;
     int tile_envs = kDefaultTileEnvs, refill_at = kDefaultRefillAt, groups = kDefaultGroups;
     int ray_cap = 0;
+    bool beams_lds = true;
     std::vector<int32_t> host_env_map;  // kept to rebuild the tiles when tile_envs changes
 };
 
@@ -118,20 +119,19 @@ navsim_status check_config(const navsim_config *c) {
     return NAVSIM_OK;
 }
 
-// Angle of beam k to the heading: K equal steps from -pi over a full circle,
-// K points spanning [-fov/2, fov/2] otherwise.
-double beam_angle(const navsim_config &c, int k) {
+// Angle of beam k of K to the heading: K equal steps from -pi over a full
+// circle, K points spanning [-fov/2, fov/2] otherwise.
+double beam_angle(float fov_rad, int K, int k) {
     const double pi = 3.14159265358979323846;
-    const double fov = (double)c.fov_rad;
-    const int K = c.num_beams;
+    const double fov = (double)fov_rad;
     if (fov >= 2.0 * pi - 1e-6) return -pi + (double)k * (2.0 * pi / (double)K);
     if (K == 1) return 0.0;
     return -0.5 * fov + (double)k * (fov / (double)(K - 1));
 }
 
-double circumradius(const navsim_config &c) {
-    if (c.footprint == NAVSIM_DISC) return (double)c.radius_m;
-    const double hl = 0.5 * (double)c.length_m, hb = 0.5 * (double)c.width_m;
+double circumradius(int footprint, float radius, float length, float width) {
+    if (footprint == NAVSIM_DISC) return (double)radius;
+    const double hl = 0.5 * (double)length, hb = 0.5 * (double)width;
     return sqrt(hl * hl + hb * hb);
 }
 
@@ -181,10 +181,9 @@ StepParams make_params(const navsim_s *h) {
     StepParams p;
     memset(&p, 0, sizeof p);
     p.N = c.num_envs;
-    p.K = c.num_beams;
+    p.K = c.num_beams;  // the largest per-map beam count
     p.m = c.num_sectors;
     p.horizon = c.horizon;
-    p.footprint = c.footprint;
     p.tries = c.reset_max_tries;
     p.rmax = c.max_range_m;
     p.dt = c.dt_s;
@@ -192,9 +191,6 @@ StepParams make_params(const navsim_s *h) {
     p.c1 = c.c_progress;
     p.r_succ = c.r_success;
     p.r_coll = c.r_collision;
-    p.radius = c.radius_m;
-    p.len = c.length_m;
-    p.wid = c.width_m;
     p.vlo = c.v_min;
     p.vhi = c.v_max;
     p.wlo = c.w_min;
@@ -202,7 +198,6 @@ StepParams make_params(const navsim_s *h) {
     p.gmd = c.goal_min_dist_m;
     p.key0 = (uint32_t)(c.seed & 0xffffffffu);
     p.key1 = (uint32_t)(c.seed >> 32);
-    p.rc = h->rc;
     p.st = h->st;
     p.env_map = h->env_map;
     p.maps = h->maps;
@@ -217,7 +212,21 @@ StepParams make_params(const navsim_s *h) {
     p.refill_at = h->refill_at;
     p.groups = h->groups;
     p.ray_cap = h->ray_cap;
+    p.beams_lds = h->beams_lds ? 1 : 0;
     return p;
+}
+
+// LDS walk slots per chunk, keeping the beam table in LDS when a full tile's
+// rays still fit next to it, else reading it from device memory.
+int choose_ray_cap(int max_words, const navsim_config &c, int tile_envs, bool &beams_lds) {
+    const int with = fused_ray_cap(max_words, c.num_sectors, tile_envs, c.num_beams, true);
+    if (with >= tile_envs * c.num_beams) {
+        beams_lds = true;
+        return with;
+    }
+    const int without = fused_ray_cap(max_words, c.num_sectors, tile_envs, c.num_beams, false);
+    beams_lds = without <= with;
+    return beams_lds ? with : without;
 }
 
 // Envs grouped by map (stable in env order) into tiles of up to tile_envs envs,
@@ -287,7 +296,7 @@ const char *navsim_last_error(void) { return g_err.c_str(); }
 navsim_status navsim_create(const navsim_config *cfg, int hip_device, navsim_t *out) {
     if (!out) return fail(NAVSIM_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    navsim_status s = check_config(cfg);
+    const navsim_status s = check_config(cfg);
     if (s != NAVSIM_OK) return s;
     int ndev = 0;
     NS_HIP(hipGetDeviceCount(&ndev));
@@ -299,7 +308,6 @@ navsim_status navsim_create(const navsim_config *cfg, int hip_device, navsim_t *
     if (!h) return fail(NAVSIM_E_OOM, "host allocation failed");
     h->cfg = *cfg;
     h->device = hip_device;
-    h->rc = circumradius(*cfg);
     const size_t N = (size_t)cfg->num_envs;
     if (hipMalloc(&h->state_buf, 40 * N) != hipSuccess) {
         delete h;
@@ -321,17 +329,6 @@ navsim_status navsim_create(const navsim_config *cfg, int hip_device, navsim_t *
     h->st.dprev = f + 7 * N;
     h->st.t = (int32_t *)(f + 8 * N);
     h->st.ep = (uint32_t *)(f + 9 * N);
-    std::vector<double2> beams((size_t)cfg->num_beams);
-    for (int k = 0; k < cfg->num_beams; ++k) {
-        const double a = beam_angle(*cfg, k);
-        beams[k] = make_double2(cos(a), sin(a));
-    }
-    s = upload(&h->beams, beams);
-    if (s != NAVSIM_OK) {
-        (void)hipFree(h->state_buf);
-        delete h;
-        return s;
-    }
     *out = h;
     return NAVSIM_OK;
 }
@@ -339,10 +336,42 @@ navsim_status navsim_create(const navsim_config *cfg, int hip_device, navsim_t *
 navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *width,
                                const int32_t *height, const float *res_m, const uint8_t *occ,
                                const int32_t *env_map) {
+    return navsim_load_maps_ex(h, num_maps, width, height, res_m, occ, env_map, nullptr);
+}
+
+navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *width,
+                                  const int32_t *height, const float *res_m, const uint8_t *occ,
+                                  const int32_t *env_map, const navsim_map_profile *profiles) {
     if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
     if (num_maps < 1 || !width || !height || !res_m || !occ || !env_map)
         return fail(NAVSIM_E_INVALID_ARG, "num_maps >= 1 and all arrays are required");
     const int N = h->cfg.num_envs;
+    const navsim_config &cfg = h->cfg;
+    std::vector<navsim_map_profile> prof((size_t)num_maps);
+    for (int k = 0; k < num_maps; ++k) {
+        if (profiles) {
+            prof[k] = profiles[k];
+        } else {
+            prof[k].num_beams = cfg.num_beams;
+            prof[k].footprint = cfg.footprint;
+            prof[k].radius_m = cfg.radius_m;
+            prof[k].length_m = cfg.length_m;
+            prof[k].width_m = cfg.width_m;
+        }
+        const navsim_map_profile &q = prof[k];
+        if (q.num_beams < 1 || q.num_beams > cfg.num_beams || q.num_beams % cfg.num_sectors != 0)
+            return fail(NAVSIM_E_INVALID_ARG,
+                        "map %d: num_beams %d must be in 1..%d and a multiple of num_sectors", k,
+                        q.num_beams, cfg.num_beams);
+        if (q.footprint == NAVSIM_DISC) {
+            if (!finite_pos(q.radius_m)) return fail(NAVSIM_E_INVALID_ARG, "map %d: radius_m", k);
+        } else if (q.footprint == NAVSIM_RECT) {
+            if (!finite_pos(q.length_m) || !finite_pos(q.width_m))
+                return fail(NAVSIM_E_INVALID_ARG, "map %d: length_m and width_m", k);
+        } else {
+            return fail(NAVSIM_E_INVALID_ARG, "map %d: footprint", k);
+        }
+    }
     std::vector<int64_t> occ_off(num_maps + 1, 0);
     for (int k = 0; k < num_maps; ++k) {
         if (width[k] < 1 || height[k] < 1 || width[k] > 4096 || height[k] > 4096)
@@ -367,8 +396,10 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
         used[env_map[e]] = 1;
     }
 
-    // padded bitmaps, free-cell lists
+    // padded bitmaps, beam tables (one per distinct beam count), free-cell lists
     std::vector<MapDesc> descs(num_maps);
+    std::vector<double2> beams;
+    std::map<int, int32_t> beam_off;
     std::vector<uint32_t> bits;
     std::vector<int32_t> free_cells;
     int max_words = 4;
@@ -382,6 +413,21 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
         d.words = ((d.wpr * (H + 2 * kPad)) + 3) & ~3;
         d.word_off = (int64_t)bits.size();
         d.res = res_m[k];
+        d.K = prof[k].num_beams;
+        d.footprint = prof[k].footprint;
+        d.radius = prof[k].radius_m;
+        d.len = prof[k].length_m;
+        d.wid = prof[k].width_m;
+        d.rc = circumradius(d.footprint, d.radius, d.len, d.wid);
+        auto it = beam_off.find(d.K);
+        if (it == beam_off.end()) {
+            it = beam_off.emplace(d.K, (int32_t)beams.size()).first;
+            for (int b = 0; b < d.K; ++b) {
+                const double a = beam_angle(cfg.fov_rad, d.K, b);
+                beams.push_back(make_double2(cos(a), sin(a)));
+            }
+        }
+        d.beam_off = it->second;
         bits.resize(bits.size() + d.words, 0xffffffffu);
         uint32_t *b = bits.data() + d.word_off;
         for (int iy = 0; iy < H; ++iy) {
@@ -400,7 +446,7 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
             for (int ix = 0; ix < W; ++ix) {
                 const float cx = (float)(((double)ix + 0.5) * s);
                 const float cy = (float)(((double)iy + 0.5) * s);
-                if (disc_clear_host(m, W, H, s, (double)cx, (double)cy, h->rc))
+                if (disc_clear_host(m, W, H, s, (double)cx, (double)cy, d.rc))
                     free_cells.push_back(iy * W + ix);
             }
         d.free_cnt = (int32_t)((int64_t)free_cells.size() - d.free_off);
@@ -408,12 +454,12 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
             return fail(NAVSIM_E_NO_FREE_SPACE, "map %d has no cell where the footprint fits", k);
     }
 
-    const int ray_cap =
-        fused_ray_cap(max_words, h->cfg.num_sectors, h->tile_envs, h->cfg.num_beams);
+    bool beams_lds = true;
+    const int ray_cap = choose_ray_cap(max_words, cfg, h->tile_envs, beams_lds);
     if (ray_cap == 0)
         return fail(NAVSIM_E_UNSUPPORTED,
                     "largest map, %d beams and %d sectors do not fit 64 KiB of LDS per workgroup",
-                    h->cfg.num_beams, h->cfg.num_sectors);
+                    cfg.num_beams, cfg.num_sectors);
     std::vector<int32_t> host_env_map(env_map, env_map + N);
     std::vector<int32_t> perm;
     std::vector<Tile> tiles;
@@ -422,9 +468,12 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
     free_device(h);
+    if (h->beams) (void)hipFree(h->beams);
+    h->beams = nullptr;
     h->loaded = false;
     h->initialized = false;
     navsim_status s;
+    if ((s = upload(&h->beams, beams)) != NAVSIM_OK) return s;
     std::vector<int32_t> em(env_map, env_map + N);
     if ((s = upload(&h->bits, bits)) != NAVSIM_OK) return s;
     if ((s = upload(&h->maps, descs)) != NAVSIM_OK) return s;
@@ -436,6 +485,7 @@ navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *widt
     h->num_tiles = (int)tiles.size();
     h->max_words = max_words;
     h->ray_cap = ray_cap;
+    h->beams_lds = beams_lds;
     h->host_env_map.swap(host_env_map);
     h->loaded = true;
     return NAVSIM_OK;
@@ -512,8 +562,9 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
         return fail(NAVSIM_E_INVALID_ARG, "refill_at must be in 0..63");
     if (t->groups < 1 || t->groups > 64) return fail(NAVSIM_E_INVALID_ARG, "groups must be in 1..64");
     int ray_cap = h->ray_cap;
+    bool beams_lds = h->beams_lds;
     if (h->loaded && t->tile_envs != h->tile_envs) {
-        ray_cap = fused_ray_cap(h->max_words, h->cfg.num_sectors, t->tile_envs, h->cfg.num_beams);
+        ray_cap = choose_ray_cap(h->max_words, h->cfg, t->tile_envs, beams_lds);
         if (ray_cap == 0)
             return fail(NAVSIM_E_UNSUPPORTED, "tile_envs %d does not fit LDS", t->tile_envs);
         std::vector<int32_t> perm;
@@ -535,6 +586,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     h->refill_at = t->refill_at;
     h->groups = t->groups;
     h->ray_cap = ray_cap;
+    h->beams_lds = beams_lds;
     return NAVSIM_OK;
 }
 

@@ -30,6 +30,12 @@ struct MapDesc {
     int64_t free_off;   // start of this map's free-cell list
     int32_t free_cnt;
     float res;
+    // robot/sensor profile of envs on this map
+    int32_t K;          // beams
+    int32_t beam_off;   // start of this map's beam table
+    int32_t footprint;  // NAVSIM_DISC / NAVSIM_RECT
+    float radius, len, wid;
+    double rc;          // circumradius of the footprint
 };
 
 // A group of up to tile_envs envs that share one map (one fused workgroup).
@@ -45,13 +51,13 @@ struct DevState {
 
 // Everything a step or reset launch needs, passed by value.
 struct StepParams {
-    int32_t N, K, m, horizon, footprint, tries, mode;  // mode 0 step, 1 reset
+    int32_t N, K, m, horizon, tries, mode;  // K: largest beam count; mode 0 step, 1 reset
     int32_t refill_at, groups;  // fused walk: refill threshold, 4-cell groups per check
     int32_t ray_cap;            // rays walked per chunk (LDS slots)
-    float rmax, dt, goal_r, c1, r_succ, r_coll, radius, len, wid;
+    int32_t beams_lds;          // stage the beam table in LDS
+    float rmax, dt, goal_r, c1, r_succ, r_coll;
     float vlo, vhi, wlo, whi, gmd;
     uint32_t key0, key1;
-    double rc;  // circumradius of the footprint
     DevState st;
     const int32_t *env_map;
     const MapDesc *maps;
@@ -73,7 +79,7 @@ struct StepParams {
 };
 
 size_t fused_lds_bytes(int max_words, int m, int tile_envs, int K, int ray_cap);
-int fused_ray_cap(int max_words, int m, int tile_envs, int K);
+int fused_ray_cap(int max_words, int m, int tile_envs, int K, bool beams_lds);
 bool fused_tile_envs_supported(int tile_envs);
 hipError_t launch_fused(const StepParams &p, int tile_envs, hipStream_t s);
 hipError_t launch_plain(const StepParams &p, hipStream_t s);

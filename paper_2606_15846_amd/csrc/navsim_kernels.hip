@@ -87,6 +87,16 @@ __device__ __forceinline__ uint32_t row_bits(const MapView &M, int r, int c0, in
     return len >= 32 ? bits : bits & ((1u << len) - 1u);
 }
 
+// Footprint of the robot on a map (per-map profile).
+struct Robot {
+    int footprint;
+    double radius, len, wid, rc;
+};
+
+__device__ __forceinline__ Robot robot_of(const MapDesc &md) {
+    return Robot{md.footprint, (double)md.radius, (double)md.len, (double)md.wid, md.rc};
+}
+
 // Disc of squared radius r2 at (x, y) against cell (i, j)'s closed box: the
 // closest point of the box lies strictly inside the disc.
 __device__ __forceinline__ bool disc_cell(double x, double y, double r2, int i, int j, double s) {
@@ -187,10 +197,9 @@ __device__ bool disc_hits(const MapView &M, double x, double y, double r) {
     return any_filled_cell(M, cr, [&](int i, int j) { return disc_cell(x, y, r2, i, j, s); });
 }
 
-__device__ bool footprint_hits(const MapView &M, const StepParams &p, double x, double y,
-                               double th) {
-    if (p.footprint == NAVSIM_DISC) return disc_hits(M, x, y, (double)p.radius);
-    const RectGeom g = rect_geom(th, (double)p.len, (double)p.wid, M.s);
+__device__ bool footprint_hits(const MapView &M, const Robot &rb, double x, double y, double th) {
+    if (rb.footprint == NAVSIM_DISC) return disc_hits(M, x, y, rb.radius);
+    const RectGeom g = rect_geom(th, rb.len, rb.wid, M.s);
     const CellRange cr = cells_around(x, y, g.ex, g.ey, M.s);
     const double s = M.s;
     return any_filled_cell(M, cr, [&](int i, int j) { return rect_cell(g, x, y, i, j, s); });
@@ -386,6 +395,7 @@ struct ResetPose {
 __device__ ResetPose sample_reset(const StepParams &p, const MapView &M, const MapDesc &md,
                                   int e, uint32_t ep) {
     const double s = M.s, Ws = (double)md.w * s, Hs = (double)md.h * s;
+    const Robot rb = robot_of(md);
     ResetPose r{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
     bool found = false;
     for (int a = 0; a < p.tries && !found; ++a) {
@@ -394,7 +404,7 @@ __device__ ResetPose sample_reset(const StepParams &p, const MapView &M, const M
         r.x = (float)(u[0] * Ws);
         r.y = (float)(u[1] * Hs);
         r.th = uniform_heading(u[2]);
-        found = !footprint_hits(M, p, (double)r.x, (double)r.y, (double)r.th);
+        found = !footprint_hits(M, rb, (double)r.x, (double)r.y, (double)r.th);
     }
     if (!found) {
         double u[4];
@@ -409,7 +419,7 @@ __device__ ResetPose sample_reset(const StepParams &p, const MapView &M, const M
         draw4(p, (uint32_t)e, ep, (uint32_t)b, 1u, u);
         r.gx = (float)(u[0] * Ws);
         r.gy = (float)(u[1] * Hs);
-        if (disc_hits(M, (double)r.gx, (double)r.gy, p.rc)) continue;
+        if (disc_hits(M, (double)r.gx, (double)r.gy, rb.rc)) continue;
         const double ddx = (double)r.gx - (double)r.x, ddy = (double)r.gy - (double)r.y;
         found = sqrt(ddx * ddx + ddy * ddy) >= (double)p.gmd;
     }
@@ -472,6 +482,7 @@ constexpr int kFusedThreads = 256;
 constexpr int kGroupLanes = 16;
 
 size_t fused_lds_bytes(int max_words, int m, int E, int K, int ray_cap) {
+    // K = 0 when the beam table stays in device memory
     return (size_t)max_words * 4u + 2u * (size_t)E * sizeof(TileJob) +
            2u * (size_t)E * (size_t)m * 4u + (4u * (size_t)E + 8u) * 4u + 16u * (size_t)K +
            16u * (size_t)ray_cap;
@@ -560,14 +571,14 @@ __device__ __forceinline__ bool group_any_filled(const MapView &M, const CellRan
     return group_ballot(hit) != 0u;
 }
 
-__device__ bool group_footprint_hits(const MapView &M, const StepParams &p, double x, double y,
+__device__ bool group_footprint_hits(const MapView &M, const Robot &rb, double x, double y,
                                      double th, int li) {
-    if (p.footprint == NAVSIM_DISC) {
-        const double r = (double)p.radius, r2 = r * r, s = M.s;
+    if (rb.footprint == NAVSIM_DISC) {
+        const double r = rb.radius, r2 = r * r, s = M.s;
         const CellRange cr = cells_around(x, y, r, r, s);
         return group_any_filled(M, cr, li, [&](int i, int j) { return disc_cell(x, y, r2, i, j, s); });
     }
-    const RectGeom g = rect_geom(th, (double)p.len, (double)p.wid, M.s);
+    const RectGeom g = rect_geom(th, rb.len, rb.wid, M.s);
     const CellRange cr = cells_around(x, y, g.ex, g.ey, M.s);
     const double s = M.s;
     return group_any_filled(M, cr, li, [&](int i, int j) { return rect_cell(g, x, y, i, j, s); });
@@ -579,6 +590,7 @@ __device__ bool group_footprint_hits(const MapView &M, const StepParams &p, doub
 __device__ ResetPose group_sample_reset(const StepParams &p, const MapView &M, const MapDesc &md,
                                         int e, uint32_t ep, int li) {
     const double s = M.s, Ws = (double)md.w * s, Hs = (double)md.h * s;
+    const Robot rb = robot_of(md);
     const int gbase = threadIdx.x & 48;
     ResetPose r{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
     bool found = false;
@@ -592,7 +604,7 @@ __device__ ResetPose group_sample_reset(const StepParams &p, const MapView &M, c
             cx = (float)(u[0] * Ws);
             cy = (float)(u[1] * Hs);
             ct = uniform_heading(u[2]);
-            ok = !footprint_hits(M, p, (double)cx, (double)cy, (double)ct);
+            ok = !footprint_hits(M, rb, (double)cx, (double)cy, (double)ct);
         }
         const uint32_t gm = group_ballot(ok);
         if (gm) {
@@ -621,7 +633,7 @@ __device__ ResetPose group_sample_reset(const StepParams &p, const MapView &M, c
             draw4(p, (uint32_t)e, ep, (uint32_t)b, 1u, u);
             cx = (float)(u[0] * Ws);
             cy = (float)(u[1] * Hs);
-            if (!disc_hits(M, (double)cx, (double)cy, p.rc)) {
+            if (!disc_hits(M, (double)cx, (double)cy, rb.rc)) {
                 const double ddx = (double)cx - (double)r.x, ddy = (double)cy - (double)r.y;
                 ok = sqrt(ddx * ddx + ddy * ddy) >= (double)p.gmd;
             }
@@ -702,17 +714,20 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
     uint32_t *s_pool = reinterpret_cast<uint32_t *>(s_jobs + 2 * E);      // [2E][m]
     int *s_list = reinterpret_cast<int *>(s_pool + 2 * E * p.m);          // [2E] active jobs
     int *s_misc = s_list + 2 * E;  // [0] active jobs, [1] next ray, [2..] done flags
-    double2 *s_beam = reinterpret_cast<double2 *>(s_misc + 2 * E + 8);  // [K] beam (cos, sin)
-    uint4 *s_ray = reinterpret_cast<uint4 *>(s_beam + p.K);               // [ray_cap] walks
+    double2 *s_beam = reinterpret_cast<double2 *>(s_misc + 2 * E + 8);  // [K] beams, or global
+    uint4 *s_ray = reinterpret_cast<uint4 *>(s_beam + (p.beams_lds ? p.K : 0));  // [ray_cap]
     const int tid = threadIdx.x, lane = tid & 63;
-    const int K = p.K, m = p.m, per = K / m;
     const Tile tile = p.tiles[blockIdx.x];
     const MapDesc md = p.maps[tile.map];
+    const int K = md.K, m = p.m, per = K / m;
+    const double2 *beams = p.beams + md.beam_off;  // this map's beam directions
     {
         const uint4 *g = reinterpret_cast<const uint4 *>(p.bits + md.word_off);
         for (int q = tid; q < md.words / 4; q += kFusedThreads) smem4[q] = g[q];
-        for (int q = tid; q < K; q += kFusedThreads) s_beam[q] = p.beams[q];
+        if (p.beams_lds)
+            for (int q = tid; q < K; q += kFusedThreads) s_beam[q] = beams[q];
     }
+    if (!p.beams_lds) s_beam = const_cast<double2 *>(beams);
     __syncthreads();
     const MapView M = map_view(s_bits, md);
     const bool want_debug = p.d_ranges || p.d_hits || p.d_visits;
@@ -734,7 +749,7 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
                 const Motion mo = apply_action(p, p.act[2 * (int64_t)e], p.act[2 * (int64_t)e + 1],
                                                p.st.x[e], p.st.y[e], p.st.th[e]);
                 const double x1 = (double)mo.x1, y1 = (double)mo.y1, th1 = (double)mo.th1;
-                const bool coll = group_footprint_hits(M, p, x1, y1, th1, li);
+                const bool coll = group_footprint_hits(M, robot_of(md), x1, y1, th1, li);
                 double sn, c;
                 sincos(th1, &sn, &c);
                 double d64;
@@ -945,11 +960,12 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
 // ---------------------------------------------------------------------------
 // Plain mapping: one thread per env, the whole step in sequence.
 
-__device__ void observe_serial(const StepParams &p, const MapView &M, double x, double y, double c,
-                               double sn, float *obs_row, int64_t dbg_row) {
+__device__ void observe_serial(const StepParams &p, const MapView &M, const MapDesc &md, double x,
+                               double y, double c, double sn, float *obs_row, int64_t dbg_row) {
     const RayOrigin o = ray_origin(M, x, y);
     const double rmax = (double)p.rmax, rmax_c = rmax / M.s;
-    const int per = p.K / p.m;
+    const double2 *beams = p.beams + md.beam_off;
+    const int per = md.K / p.m;
     for (int j = 0; j < p.m; ++j) {
         float l = 0.0f;
         for (int q = 0; q < per; ++q) {
@@ -961,7 +977,7 @@ __device__ void observe_serial(const StepParams &p, const MapView &M, double x, 
                 hit = o.block_hit;
                 vis = 1;
             } else {
-                const double2 cs = p.beams[k];
+                const double2 cs = beams[k];
                 const double dx = c * cs.x - sn * cs.y;
                 const double dy = sn * cs.x + c * cs.y;
                 cast_ray(M, o, dx, dy, rmax, rmax_c, rg, hit, vis);
@@ -991,7 +1007,7 @@ __global__ __launch_bounds__(64) void plain_step_kernel(StepParams p) {
         const Motion mo = apply_action(p, p.act[2 * (int64_t)e], p.act[2 * (int64_t)e + 1],
                                        p.st.x[e], p.st.y[e], p.st.th[e]);
         const double x1 = (double)mo.x1, y1 = (double)mo.y1, th1 = (double)mo.th1;
-        const bool coll = footprint_hits(M, p, x1, y1, th1);
+        const bool coll = footprint_hits(M, robot_of(md), x1, y1, th1);
         double sn, c;
         sincos(th1, &sn, &c);
         double d64;
@@ -1006,7 +1022,7 @@ __global__ __launch_bounds__(64) void plain_step_kernel(StepParams p) {
             goal ? p.r_succ
                  : (coll ? p.r_coll : (float)((double)p.c1 * ((double)p.st.dprev[e] - (double)d32)));
         float *pre = do_reset ? (p.final_obs ? p.final_obs + (int64_t)e * row : nullptr) : obs_row;
-        observe_serial(p, M, x1, y1, c, sn, pre, e);
+        observe_serial(p, M, md, x1, y1, c, sn, pre, e);
         if (pre) {
             pre[p.m] = d32;
             pre[p.m + 1] = phi;
@@ -1035,14 +1051,15 @@ __global__ __launch_bounds__(64) void plain_step_kernel(StepParams p) {
     const ResetPose r = sample_reset(p, M, md, e, ep);
     double c, sn;
     store_reset(p, e, ep, r, c, sn);
-    observe_serial(p, M, (double)r.x, (double)r.y, c, sn, obs_row, -1);
+    observe_serial(p, M, md, (double)r.x, (double)r.y, c, sn, obs_row, -1);
 }
 
 // ---------------------------------------------------------------------------
 template <int E>
 static hipError_t launch_fused_e(const StepParams &p, hipStream_t s) {
     hipLaunchKernelGGL(fused_step_kernel<E>, dim3((unsigned)p.num_tiles), dim3(kFusedThreads),
-                       fused_lds_bytes(p.max_words, p.m, E, p.K, p.ray_cap), s, p);
+                       fused_lds_bytes(p.max_words, p.m, E, p.beams_lds ? p.K : 0, p.ray_cap), s,
+                       p);
     return hipGetLastError();
 }
 
@@ -1051,8 +1068,8 @@ bool fused_tile_envs_supported(int E) { return E == 4 || E == 8 || E == 16; }
 // LDS walk slots per chunk: the rays of a full tile plus one reset pose
 // ((E + 1) K, rounded up to a wavefront), so a tile walks a second chunk only
 // when two or more of its envs reset; fewer if that does not fit 64 KiB.
-int fused_ray_cap(int max_words, int m, int E, int K) {
-    const size_t base = fused_lds_bytes(max_words, m, E, K, 0);
+int fused_ray_cap(int max_words, int m, int E, int K, bool beams_lds) {
+    const size_t base = fused_lds_bytes(max_words, m, E, beams_lds ? K : 0, 0);
     if (base + 16u * 256u > 65536u) return 0;
     const int fit = (int)((65536u - base) / 16u) & ~63;
     return std::max(std::min(((E + 1) * K + 63) & ~63, fit), 256);

@@ -23,7 +23,7 @@ NAVSIM_KERNEL_FUSED, NAVSIM_KERNEL_PLAIN = 0, 1
 STATUS = {0: "NAVSIM_OK", -1: "NAVSIM_E_INVALID_ARG", -2: "NAVSIM_E_BAD_HANDLE",
           -3: "NAVSIM_E_STATE", -4: "NAVSIM_E_NO_FREE_SPACE", -5: "NAVSIM_E_OOM",
           -6: "NAVSIM_E_HIP", -7: "NAVSIM_E_UNSUPPORTED"}
-EXPORTS = ("navsim_create", "navsim_load_maps", "navsim_reset", "navsim_step",
+EXPORTS = ("navsim_create", "navsim_load_maps", "navsim_load_maps_ex", "navsim_reset", "navsim_step",
            "navsim_step_plain", "navsim_step_debug", "navsim_set_tuning", "navsim_get_tuning",
            "navsim_get_state", "navsim_set_state", "navsim_destroy", "navsim_last_error")
 STATE_KEYS = ("x", "y", "th", "v", "w", "gx", "gy", "dprev", "t", "ep")
@@ -47,6 +47,11 @@ class NavsimDebug(C.Structure):
     _fields_ = [("ranges", C.c_void_p), ("hits", C.c_void_p), ("visits", C.c_void_p),
                 ("collision", C.c_void_p), ("goal", C.c_void_p), ("reset", C.c_void_p),
                 ("fallback", C.c_void_p)]
+
+
+class NavsimMapProfile(C.Structure):
+    _fields_ = [("num_beams", C.c_int32), ("footprint", C.c_int32), ("radius_m", C.c_float),
+                ("length_m", C.c_float), ("width_m", C.c_float)]
 
 
 class NavsimTuning(C.Structure):
@@ -73,6 +78,7 @@ def load_library(path: str = LIB_PATH):
     vp, i32 = C.c_void_p, C.c_int32
     L.navsim_create.argtypes = [C.POINTER(NavsimConfig), C.c_int, C.POINTER(vp)]
     L.navsim_load_maps.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.navsim_load_maps_ex.argtypes = [vp, i32, vp, vp, vp, vp, vp, C.POINTER(NavsimMapProfile)]
     L.navsim_reset.argtypes = [vp, vp, vp, vp]
     L.navsim_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.navsim_step_plain.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
@@ -132,15 +138,37 @@ def navsim_create(cfg: dict, hip_device: int = 0):
     return h
 
 
-def navsim_load_maps(h, maps, res, env_map):
+def _map_arrays(maps, res, env_map):
     maps = [np.ascontiguousarray(m, dtype=np.uint8) for m in maps]
     w = np.array([m.shape[1] for m in maps], np.int32)
     hh = np.array([m.shape[0] for m in maps], np.int32)
     r = np.asarray(res, np.float32)
     occ = np.ascontiguousarray(np.concatenate([m.ravel() for m in maps]))
     em = np.ascontiguousarray(env_map, dtype=np.int32)
-    _check(load_library().navsim_load_maps(h, len(maps), w.ctypes.data, hh.ctypes.data,
-                                           r.ctypes.data, occ.ctypes.data, em.ctypes.data))
+    return len(maps), w, hh, r, occ, em
+
+
+def navsim_load_maps(h, maps, res, env_map):
+    n, w, hh, r, occ, em = _map_arrays(maps, res, env_map)
+    _check(load_library().navsim_load_maps(h, n, w.ctypes.data, hh.ctypes.data, r.ctypes.data,
+                                           occ.ctypes.data, em.ctypes.data))
+
+
+def navsim_load_maps_ex(h, maps, res, env_map, profiles=None):
+    """profiles: None, or one dict per map with num_beams, footprint and the
+    footprint's sizes (radius_m, or length_m and width_m)."""
+    n, w, hh, r, occ, em = _map_arrays(maps, res, env_map)
+    arr = None
+    if profiles is not None:
+        if len(profiles) != n:
+            raise ValueError(f"{len(profiles)} profiles for {n} maps")
+        arr = (NavsimMapProfile * n)()
+        for k, q in enumerate(profiles):
+            arr[k] = NavsimMapProfile(int(q["num_beams"]), int(q["footprint"]),
+                                      float(q.get("radius_m", 0.0)), float(q.get("length_m", 0.0)),
+                                      float(q.get("width_m", 0.0)))
+    _check(load_library().navsim_load_maps_ex(h, n, w.ctypes.data, hh.ctypes.data, r.ctypes.data,
+                                              occ.ctypes.data, em.ctypes.data, arr))
 
 
 def navsim_reset(h, mask, obs, stream=None):
@@ -219,14 +247,14 @@ class NavSim:
     2.2.4): step() returns obs, reward, terminated, truncated and the final
     observation of the envs that ended."""
 
-    def __init__(self, cfg: dict, maps, res, env_map, device: int | str = 0):
+    def __init__(self, cfg: dict, maps, res, env_map, device: int | str = 0, profiles=None):
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.cfg = dict(cfg)
         self.N, self.K, self.m = int(cfg["num_envs"]), int(cfg["num_beams"]), int(cfg["num_sectors"])
         self.h = None
         self.h = navsim_create(cfg, self.device.index or 0)
         try:
-            navsim_load_maps(self.h, maps, res, env_map)
+            navsim_load_maps_ex(self.h, maps, res, env_map, profiles)
         except Exception:
             h, self.h = self.h, None
             navsim_destroy(h)

@@ -23,9 +23,22 @@ RANGE_TOL = 1e-4
 SCALAR_TOL = 1e-5
 
 
-def sectors_with_grazing(grazing: np.ndarray, m: int) -> np.ndarray:
-    n, k = grazing.shape
-    return grazing.reshape(n, m, k // m).any(axis=2)
+def env_beams(ref: oracle.OracleSim) -> np.ndarray:
+    """Beam count of every env (per-map profiles, else the configuration's)."""
+    if ref.maps.profiles is None:
+        return np.full(ref.N, ref.K, dtype=np.int64)
+    return ref.maps.p_beams.astype(np.int64)[ref.env_map]
+
+
+def sectors_with_grazing(grazing: np.ndarray, m: int, kenv: np.ndarray) -> np.ndarray:
+    """Per (env, sector): does the sector hold a grazing ray.  Env e's beams
+    are the first kenv[e] entries of its row, kenv[e] / m per sector."""
+    n = grazing.shape[0]
+    out = np.zeros((n, m), dtype=bool)
+    for k in np.unique(kenv):
+        rows = kenv == k
+        out[rows] = grazing[rows, :k].reshape(-1, m, k // m).any(axis=2)
+    return out
 
 
 def reset_scan_grazing(ref: oracle.OracleSim, rows) -> dict:
@@ -42,6 +55,7 @@ def compare_step(gpu: dict, ref_out: dict, gpu_state: dict, ref: oracle.OracleSi
                  label: str = "") -> dict:
     """Assert the acceptance rules; returns counters for reporting."""
     N, K, m = ref.N, ref.K, ref.m
+    kenv = env_beams(ref)
     for key in ("collision", "goal", "reset", "terminated", "truncated", "fallback"):
         g = gpu[key]
         r = ref_out[key]
@@ -65,7 +79,7 @@ def compare_step(gpu: dict, ref_out: dict, gpu_state: dict, ref: oracle.OracleSi
                                f"gpu={gpu_state[k][bad[:8]]} ref={ref.state[k][bad[:8]]}")
     # observations: O_{t+1} (final_obs rows for envs that ended, obs otherwise)
     done = ref_out["reset"].astype(bool)
-    sec_g = sectors_with_grazing(graze, m)
+    sec_g = sectors_with_grazing(graze, m, kenv)
     pre_g = np.where(done[:, None], gpu["final_obs"], gpu["obs"])
     pre_r = np.where(done[:, None], ref_out["final_obs"], ref_out["obs"])
     d = np.abs(pre_g[:, :m] - pre_r[:, :m])
@@ -78,13 +92,13 @@ def compare_step(gpu: dict, ref_out: dict, gpu_state: dict, ref: oracle.OracleSi
     rg = reset_scan_grazing(ref, rows)
     n_reset_graze = 0
     for e in rows:
-        sg = rg[int(e)].reshape(m, K // m).any(axis=1)
+        sg = rg[int(e)].reshape(m, -1).any(axis=1)
         n_reset_graze += int(rg[int(e)].sum())
         d = np.abs(gpu["obs"][e, :m] - ref_out["obs"][e, :m])
         assert d[~sg].max(initial=0.0) <= RANGE_TOL, f"{label}: reset obs env {e} diff {d.max()}"
         ds = np.abs(gpu["obs"][e, m:] - ref_out["obs"][e, m:]).max()
         assert ds <= SCALAR_TOL, f"{label}: reset obs scalars env {e} diff {ds}"
-    return dict(rays=N * K, grazing=int(graze.sum()),
+    return dict(rays=int(kenv.sum()), grazing=int(graze.sum()),
                 grazing_mismatch=int(((hg != hr) & graze).sum()),
                 resets=int(done.sum()), reset_grazing=n_reset_graze,
                 visits=int(vr.sum()))

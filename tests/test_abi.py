@@ -24,7 +24,7 @@ def declared_functions():
 def test_library_exports_every_declared_function():
     lib = navsim.load_library()
     names = declared_functions()
-    assert len(names) == 12
+    assert len(names) == 13
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(navsim.EXPORTS) == names
@@ -93,5 +93,6 @@ def test_abi_version_and_null_arguments():
                      ("navsim_set_tuning", (None, None)), ("navsim_get_tuning", (None, None)),
                      ("navsim_get_state", (None, None, 0, None)),
                      ("navsim_set_state", (None, None, 0, None)),
-                     ("navsim_load_maps", (None, 1, None, None, None, None, None))]:
+                     ("navsim_load_maps", (None, 1, None, None, None, None, None)),
+                     ("navsim_load_maps_ex", (None, 1, None, None, None, None, None, None))]:
         assert getattr(lib, fn)(*args) == -2, fn

@@ -22,9 +22,9 @@ def say(*a):
     sys.stdout.flush()
 
 
-def make_pair(cfg, maps, res, env_map):
-    sim = NavSim(cfg, maps, res, env_map, device=0)
-    ref = oracle.OracleSim(cfg, maps, res, env_map)
+def make_pair(cfg, maps, res, env_map, profiles=None):
+    sim = NavSim(cfg, maps, res, env_map, device=0, profiles=profiles)
+    ref = oracle.OracleSim(cfg, maps, res, env_map, profiles=profiles)
     return sim, ref
 
 
@@ -81,6 +81,83 @@ def test_c3_rect_reverse_fused():
     sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
     run_teacher_forced(sim, ref, 3, NAVSIM_KERNEL_FUSED, label="c3/fused")
     sim.close()
+
+
+def test_c4_mixed_profiles_full_size_fused():
+    say("c4 32768 envs, 128 uneven maps, per-map K and footprint, fused, 2 steps")
+    w = configs.build_workload("c4")
+    sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"], w["profiles"])
+    tot = run_teacher_forced(sim, ref, 2, NAVSIM_KERNEL_FUSED, label="c4/fused")
+    assert tot["grazing"] < 0.01 * tot["rays"]
+    sim.close()
+
+
+def _mixed_small(num_envs=96):
+    """Six maps of different sizes, one of each beam count and both footprints."""
+    from workloads import maps as gm
+    occ = [gm.gen_rect_disc_map(11, w=70, h=50, res=0.05),
+           gm.gen_rooms_map(12, w=120, h=97, res=0.05),
+           gm.gen_rect_disc_map(13, w=33, h=140, res=0.05),
+           gm.gen_rooms_map(14, w=200, h=180, res=0.05),
+           gm.gen_rect_disc_map(15, w=96, h=96, res=0.05),
+           gm.gen_rect_map(16, w=64, h=64)]
+    res = [0.05] * 5 + [0.1]
+    prof = [dict(num_beams=180, footprint=0, radius_m=0.18),
+            dict(num_beams=1080, footprint=1, length_m=0.70, width_m=0.31),
+            dict(num_beams=360, footprint=1, length_m=0.80, width_m=0.41),
+            dict(num_beams=720, footprint=0, radius_m=0.2),
+            dict(num_beams=30, footprint=0, radius_m=0.12),
+            dict(num_beams=90, footprint=1, length_m=0.5, width_m=0.3)]
+    cfg = configs.make_config(num_envs=num_envs, num_beams=1080, num_sectors=30,
+                              fov_rad=2 * math.pi, max_range_m=8.0, dt_s=0.1, footprint=0,
+                              radius_m=0.18, v_min=-0.5, v_max=0.5, w_min=-1.0, w_max=1.0)
+    # interleaved, so tiles are formed from envs that are not contiguous
+    env_map = (np.arange(num_envs) * 7 % len(occ)).astype(np.int32)
+    return cfg, occ, res, env_map, prof
+
+
+@pytest.mark.parametrize("kname", ["fused", "plain"])
+def test_mixed_profiles_rollout(kname):
+    say(f"mixed profiles: 6 maps, K 30..1080, disc+rect, 96 envs, 40 steps, kernel={kname}")
+    cfg, occ, res, env_map, prof = _mixed_small()
+    sim, ref = make_pair(cfg, occ, res, env_map, prof)
+    tot = run_teacher_forced(sim, ref, 40, KERNELS[kname], seed=9, label=f"mixed/{kname}")
+    assert tot["resets"] > 0
+    sim.close()
+
+
+def test_mixed_profiles_launch_shapes_agree():
+    say("mixed profiles: fused under every tile size == plain, bitwise, 5 steps")
+    cfg, occ, res, env_map, prof = _mixed_small(num_envs=150)
+    acts = configs.uniform_actions(5, cfg["num_envs"], seed=33)
+    runs = []
+    for kernel, te in [(NAVSIM_KERNEL_PLAIN, 4), (NAVSIM_KERNEL_FUSED, 4),
+                       (NAVSIM_KERNEL_FUSED, 8), (NAVSIM_KERNEL_FUSED, 16)]:
+        sim = NavSim(cfg, occ, res, env_map, device=0, profiles=prof)
+        sim.set_tuning(te, 48, 4)
+        sim.reset()
+        runs.append([gpu_step(sim, acts[t], kernel) for t in range(5)])
+        sim.close()
+    for other in runs[1:]:
+        for (ga, sa), (gb, sb) in zip(runs[0], other):
+            for k in ga:
+                assert np.array_equal(ga[k], gb[k]) or k == "final_obs", k
+            for k in oracle.STATE_KEYS:
+                assert np.array_equal(sa[k], sb[k]), k
+
+
+def test_profile_validation_on_device():
+    cfg, occ, res, env_map, prof = _mixed_small(num_envs=12)
+    for bad in [dict(num_beams=1110), dict(num_beams=100), dict(num_beams=0),
+                dict(footprint=3), dict(footprint=0, radius_m=0.0),
+                dict(footprint=1, length_m=0.5, width_m=-1.0)]:
+        p2 = [dict(q) for q in prof]
+        p2[2].update(bad)
+        with pytest.raises(navsim.NavsimError) as ei:
+            NavSim(cfg, occ, res, env_map, device=0, profiles=p2)
+        assert ei.value.status == -1 and "map 2" in str(ei.value), bad
+    with pytest.raises(ValueError):
+        NavSim(cfg, occ, res, env_map, device=0, profiles=prof[:3])
 
 
 def _small_cfg(**kw):

@@ -94,12 +94,45 @@ WORKLOADS = {
                         v_min=-0.5, v_max=0.5, w_min=-1.0, w_max=1.0),
                maps=dict(kind="rooms", count=64, w=256, h=256, res=0.05), steps=2000,
                name="16384 envs, 64 maps 256x256 @0.05 m, rect 0.70x0.31 m, 720 beams, r_max 8 m"),
+    # 32768 envs over 128 maps with W, H each U{96..512} at 0.05 m (rectangle+disc
+    # and rooms generators alternating), per-map beam count from
+    # {180, 360, 720, 1080} and disc (r 0.18) or rectangle (0.70 x 0.31 m)
+    # footprint, m = 30, r_max 8 m, dt 0.05, reverse allowed.
+    "c4": dict(cfg=dict(num_envs=32768, num_beams=1080, num_sectors=30, fov_rad=2 * math.pi,
+                        max_range_m=8.0, dt_s=0.05, footprint=FOOTPRINT_DISC, radius_m=0.18,
+                        v_min=-0.5, v_max=0.5, w_min=-1.0, w_max=1.0),
+               maps=dict(kind="uneven", count=128, side_lo=96, side_hi=512, res=0.05,
+                         seed=404),
+               profiles=dict(seed=405, beams=(180, 360, 720, 1080),
+                             disc=dict(footprint=FOOTPRINT_DISC, radius_m=0.18),
+                             rect=dict(footprint=FOOTPRINT_RECT, length_m=0.70, width_m=0.31)),
+               steps=64,
+               name="32768 envs, 128 maps U{96..512}^2 @0.05 m, per-map K in "
+                    "{180,360,720,1080} and disc/rect footprint, r_max 8 m"),
 }
+
+
+def build_profiles(spec: dict, count: int) -> list[dict]:
+    """Per-map robot/sensor profiles: beam count drawn uniformly from
+    spec['beams'], footprint disc or rectangle with probability 1/2."""
+    rng = np.random.default_rng(spec["seed"])
+    out = []
+    for _ in range(count):
+        k = int(rng.choice(np.asarray(spec["beams"])))
+        fp = dict(spec["rect"] if rng.integers(0, 2) else spec["disc"])
+        q = dict(num_beams=k, radius_m=0.0, length_m=0.0, width_m=0.0)
+        q.update(fp)
+        out.append(q)
+    return out
 
 
 def build_maps(spec: dict) -> tuple[list[np.ndarray], list[float]]:
     kind, count = spec["kind"], spec["count"]
     res = spec["res"]
+    if kind == "uneven":
+        occ = _maps.gen_uneven_maps(spec["seed"], count, side_lo=spec["side_lo"],
+                                    side_hi=spec["side_hi"], res=res)
+        return occ, [res] * count
     out = []
     for k in range(count):
         seed = 1000 + k
@@ -135,5 +168,6 @@ def build_workload(name: str, num_envs: int | None = None) -> dict:
         cfg["num_envs"] = int(num_envs)
     occ, res = build_maps(spec["maps"])
     env_map = contiguous_env_map(cfg["num_envs"], len(occ))
+    profiles = build_profiles(spec["profiles"], len(occ)) if "profiles" in spec else None
     return dict(cfg=cfg, maps=occ, res=res, env_map=env_map, steps=spec["steps"],
-                name=spec["name"])
+                name=spec["name"], profiles=profiles)
