@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--plain-steps", type=int, default=50)
+    ap.add_argument("--rollout-steps", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--tile-envs", type=int, default=None)
@@ -164,6 +165,26 @@ def main():
     achieved = lds_bytes_per_launch / avg_launch_s / 1e9
     traffic = hbm_traffic_from_profile()
 
+    # device rollouts: the same fused step under in-kernel actions, T steps
+    # captured once as a HIP graph and replayed
+    sim.set_state(start_state)
+    T = args.rollout_steps
+    bufs = sim.rollout_buffers(T, final_obs=True)
+    sim.rollout(T, first_step=0, buffers=bufs, graph=True)  # capture + warm
+    torch.cuda.synchronize()
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(1, args.steps // T)
+    r0.record(stream)
+    for r in range(reps):
+        sim.rollout(T, first_step=(r + 1) * T, buffers=bufs, graph=True)
+    r1.record(stream)
+    torch.cuda.synchronize()
+    rms = r0.elapsed_time(r1)
+    rollout = {"value": N * T * reps / (rms / 1e3), "unit": "env-steps/s",
+               "steps_per_rollout": T, "rollouts": reps, "ms_per_step": rms / (T * reps),
+               "actions": "in-kernel Philox stream 4", "launch": "HIP graph of T fused steps"}
+    del bufs
+
     plain = None
     if not args.no_plain:
         sim.set_state(start_state)
@@ -205,6 +226,7 @@ def main():
                    "footprint": ("per map" if w["profiles"] is not None
                                  else "disc" if cfg["footprint"] == 0 else "rect")},
         "rays_per_s": value * rays_per_step / N,
+        "graph_rollout": rollout,
         "plain": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "tuning": sim_tuning,

@@ -184,6 +184,34 @@ navsim_status navsim_step_debug(navsim_t h, const float *act, float *obs, float 
                                 uint8_t *terminated, uint8_t *truncated, float *final_obs,
                                 const navsim_debug *dbg, int32_t kernel, void *hip_stream);
 
+/* Rollout: `steps` consecutive steps (1..4096) of every env with synthetic
+ * normalised actions drawn on the device, for throughput runs and data
+ * collection under random actions (section 3 measures under random actions;
+ * the generator is this library's): env e at step n = first_step + i uses
+ * Philox4x32-10 with key = seed and counter (e, n mod 2^32, n div 2^32, 4),
+ * a_j = 2 u_j - 1 with u_j = (w_j + 1/2) 2^-32 from words 0 and 1, rounded to
+ * float32.  Step i is exactly navsim_step (or navsim_step_plain, by `kernel`)
+ * with those actions, so results equal a loop of single steps bitwise.
+ * Device outputs, row i = step i:
+ *   act        float32 [steps][N][2]     drawn actions (NULL = not written)
+ *   obs        float32 [steps][N][m+4]   as navsim_step
+ *   reward     float32 [steps][N]
+ *   terminated uint8   [steps][N]
+ *   truncated  uint8   [steps][N]
+ *   final_obs  float32 [steps][N][m+4]   (NULL = not written)
+ * flags: NAVSIM_ROLLOUT_GRAPH captures the step launches once into a HIP graph
+ * (kept in the handle: replayed while buffers, steps, kernel and launch shape
+ * stay the same, captured again otherwise; dropped by navsim_set_tuning and
+ * navsim_load_maps) and launches that graph on hip_stream; without it each
+ * step is launched on hip_stream.  The rollout's first step index lives in
+ * device memory, set on hip_stream before the steps: two rollouts of one
+ * handle in flight on different streams race.  Errors: as navsim_step, and
+ * NAVSIM_E_HIP when capture or instantiation fails. */
+enum { NAVSIM_ROLLOUT_GRAPH = 1 };
+navsim_status navsim_rollout(navsim_t h, int32_t steps, uint64_t first_step, float *act,
+                             float *obs, float *reward, uint8_t *terminated, uint8_t *truncated,
+                             float *final_obs, int32_t kernel, int32_t flags, void *hip_stream);
+
 /* Launch shape of the fused step.  Results never depend on it (bitwise); it
  * only moves work between lanes, wavefronts and workgroups. */
 typedef struct {

@@ -108,6 +108,7 @@ def lib():
     L.orc_march.argtypes = [P(OrcMaps), C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                             C.c_double, C.c_double, P(C.c_double), P(C.c_int32)]
     L.orc_cfg_for_map.argtypes = [P(OrcCfg), P(OrcMaps), C.c_int, P(OrcCfg)]
+    L.orc_rollout_actions.argtypes = [P(OrcCfg), C.c_uint64, C.c_int64, C.c_int64, P(C.c_float)]
     L.orc_beam_angle.argtypes = [P(OrcCfg), C.c_int]
     L.orc_beam_angle.restype = C.c_double
     L.orc_scan.argtypes = [P(OrcMaps), C.c_int, P(OrcCfg), C.c_double, C.c_double, C.c_double,
@@ -307,6 +308,12 @@ class OracleSim:
                        _ptr(act, C.c_float), C.byref(out), sl[0], sl[1])
         self._run(run, threads)
         return o
+
+    def rollout_actions(self, n: int) -> np.ndarray:
+        """Normalised actions [N, 2] of rollout step n (Philox stream 4)."""
+        a = np.zeros((self.N, 2), np.float32)
+        lib().orc_rollout_actions(C.byref(self.cfg), int(n), 0, self.N, _ptr(a, C.c_float))
+        return a
 
     def map_cfg(self, map_id) -> OrcCfg:
         mc = OrcCfg()

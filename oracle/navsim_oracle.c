@@ -140,6 +140,21 @@ static void orc_draw(const orc_cfg *cfg, uint32_t env, uint32_t ep, uint32_t att
     for (int i = 0; i < 4; ++i) u[i] = orc_unit(w[i]);
 }
 
+/* Synthetic rollout actions (the paper measures throughput under random
+ * actions; the generator is this project's reading).  Env e at rollout step
+ * n draws counter (e, n mod 2^32, n div 2^32, 4) and takes a_i = 2 u_i - 1
+ * from the first two words, rounded once to float32; envs [e0, e1) go to
+ * out[2 (e - e0) + i]. */
+void orc_rollout_actions(const orc_cfg *cfg, uint64_t n, int64_t e0, int64_t e1, float *out)
+{
+    for (int64_t e = e0; e < e1; ++e) {
+        double u[4];
+        orc_draw(cfg, (uint32_t)e, (uint32_t)(n & 0xffffffffu), (uint32_t)(n >> 32), 4u, u);
+        out[2 * (e - e0)] = (float)(2.0 * u[0] - 1.0);
+        out[2 * (e - e0) + 1] = (float)(2.0 * u[1] - 1.0);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Grid (section 2.2.1): cell (i, j) is the box [i s, (i+1) s] x [j s, (j+1) s]; */
 /* anything outside [0, W) x [0, H) counts as occupied.                         */

@@ -77,6 +77,12 @@ struct navsim_s {
     int ray_cap = 0;
     bool beams_lds = true;
     std::vector<int32_t> host_env_map;  // kept to rebuild the tiles when tile_envs changes
+    // rollouts: first step index on the device, and the last captured rollout
+    uint32_t *step_ctr = nullptr;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    StepParams graph_params{};  // parameters of step 0 of the captured rollout
+    int graph_steps = 0, graph_kernel = -1, graph_tile_envs = 0;
 };
 
 namespace {
@@ -155,7 +161,14 @@ bool disc_clear_host(const uint8_t *occ, int W, int H, double s, double x, doubl
     return true;
 }
 
+void drop_graph(navsim_s *h) {
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+    h->graph_steps = 0;
+}
+
 void free_device(navsim_s *h) {
+    drop_graph(h);
     void *ptrs[] = {h->bits, h->maps, h->free_cells, h->env_map, h->perm, h->tiles};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -287,6 +300,70 @@ navsim_status step_common(navsim_t h, const float *act, float *obs, float *rewar
     return run(h, p, kernel, (hipStream_t)stream);
 }
 
+bool same_outputs(const StepParams &a, const StepParams &b) {
+    return a.act_out == b.act_out && a.obs == b.obs && a.reward == b.reward &&
+           a.term == b.term && a.trunc == b.trunc && a.final_obs == b.final_obs &&
+           a.tiles == b.tiles && a.perm == b.perm && a.refill_at == b.refill_at &&
+           a.groups == b.groups && a.ray_cap == b.ray_cap;
+}
+
+// Step `i` of a rollout: outputs advanced by i rows of each buffer.
+StepParams rollout_step(const StepParams &p0, int i, int64_t N, int row) {
+    StepParams p = p0;
+    p.step_off = i;
+    if (p.act_out) p.act_out += (int64_t)i * N * 2;
+    p.obs += (int64_t)i * N * row;
+    p.reward += (int64_t)i * N;
+    p.term += (int64_t)i * N;
+    p.trunc += (int64_t)i * N;
+    if (p.final_obs) p.final_obs += (int64_t)i * N * row;
+    return p;
+}
+
+navsim_status launch_steps(navsim_t h, const StepParams &p0, int steps, int kernel,
+                           hipStream_t s) {
+    const int64_t N = h->cfg.num_envs;
+    const int row = h->cfg.num_sectors + 4;
+    for (int i = 0; i < steps; ++i) {
+        const StepParams p = rollout_step(p0, i, N, row);
+        const hipError_t e =
+            kernel == NAVSIM_KERNEL_PLAIN ? launch_plain(p, s) : launch_fused(p, h->tile_envs, s);
+        if (e != hipSuccess) return fail(NAVSIM_E_HIP, "kernel launch: %s", hipGetErrorString(e));
+    }
+    return NAVSIM_OK;
+}
+
+// Captures the rollout's step launches once into an executable graph; later
+// calls with the same buffers, step count, kernel and launch shape replay it.
+navsim_status rollout_graph(navsim_t h, const StepParams &p0, int steps, int kernel) {
+    if (h->graph && h->graph_steps == steps && h->graph_kernel == kernel &&
+        h->graph_tile_envs == h->tile_envs && same_outputs(h->graph_params, p0))
+        return NAVSIM_OK;
+    drop_graph(h);
+    if (!h->capture_stream)
+        NS_HIP(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+    NS_HIP(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+    const navsim_status st = launch_steps(h, p0, steps, kernel, h->capture_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->capture_stream, &graph);
+    if (st != NAVSIM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(NAVSIM_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess)
+        return fail(NAVSIM_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+    h->graph = exec;
+    h->graph_params = p0;
+    h->graph_steps = steps;
+    h->graph_kernel = kernel;
+    h->graph_tile_envs = h->tile_envs;
+    return NAVSIM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -317,6 +394,11 @@ navsim_status navsim_create(const navsim_config *cfg, int hip_device, navsim_t *
         (void)hipFree(h->state_buf);
         delete h;
         return fail(NAVSIM_E_HIP, "hipMemset of the env state failed");
+    }
+    if (hipMalloc(&h->step_ctr, 2 * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipFree(h->state_buf);
+        delete h;
+        return fail(NAVSIM_E_OOM, "hipMalloc of the step counter failed");
     }
     float *f = (float *)h->state_buf;
     h->st.x = f;
@@ -553,6 +635,43 @@ navsim_status navsim_set_state(navsim_t h, const void *host_soa, size_t bytes, v
     return NAVSIM_OK;
 }
 
+navsim_status navsim_rollout(navsim_t h, int32_t steps, uint64_t first_step, float *act,
+                             float *obs, float *reward, uint8_t *terminated, uint8_t *truncated,
+                             float *final_obs, int32_t kernel, int32_t flags, void *stream) {
+    if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
+    if (!h->loaded) return fail(NAVSIM_E_STATE, "navsim_load_maps has not been called");
+    if (!h->initialized) return fail(NAVSIM_E_STATE, "navsim_reset (mask NULL) must come first");
+    if (steps < 1 || steps > 4096) return fail(NAVSIM_E_INVALID_ARG, "steps must be in 1..4096");
+    if (!obs || !reward || !terminated || !truncated)
+        return fail(NAVSIM_E_INVALID_ARG, "obs, reward, terminated, truncated are required");
+    if (kernel != NAVSIM_KERNEL_FUSED && kernel != NAVSIM_KERNEL_PLAIN)
+        return fail(NAVSIM_E_INVALID_ARG, "unknown kernel %d", kernel);
+    if (flags & ~NAVSIM_ROLLOUT_GRAPH) return fail(NAVSIM_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    DeviceGuard g(h->device);
+    if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
+    StepParams p = make_params(h);
+    p.mode = 0;
+    p.act = nullptr;
+    p.step_ctr = h->step_ctr;
+    p.act_out = act;
+    p.obs = obs;
+    p.reward = reward;
+    p.term = terminated;
+    p.trunc = truncated;
+    p.final_obs = final_obs;
+    const hipStream_t s = (hipStream_t)stream;
+    if (flags & NAVSIM_ROLLOUT_GRAPH) {
+        const navsim_status st = rollout_graph(h, p, steps, kernel);
+        if (st != NAVSIM_OK) return st;
+    }
+    hipError_t e = launch_set_step(h->step_ctr, first_step, s);
+    if (e != hipSuccess) return fail(NAVSIM_E_HIP, "kernel launch: %s", hipGetErrorString(e));
+    if (!(flags & NAVSIM_ROLLOUT_GRAPH)) return launch_steps(h, p, steps, kernel, s);
+    e = hipGraphLaunch(h->graph, s);
+    if (e != hipSuccess) return fail(NAVSIM_E_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+    return NAVSIM_OK;
+}
+
 navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
     if (!t) return fail(NAVSIM_E_INVALID_ARG, "tuning is NULL");
@@ -561,6 +680,10 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     if (t->refill_at < 0 || t->refill_at > 63)
         return fail(NAVSIM_E_INVALID_ARG, "refill_at must be in 0..63");
     if (t->groups < 1 || t->groups > 64) return fail(NAVSIM_E_INVALID_ARG, "groups must be in 1..64");
+    {
+        DeviceGuard g(h->device);
+        drop_graph(h);
+    }
     int ray_cap = h->ray_cap;
     bool beams_lds = h->beams_lds;
     if (h->loaded && t->tile_envs != h->tile_envs) {
@@ -606,6 +729,8 @@ navsim_status navsim_destroy(navsim_t h) {
         free_device(h);
         if (h->beams) (void)hipFree(h->beams);
         if (h->state_buf) (void)hipFree(h->state_buf);
+        if (h->step_ctr) (void)hipFree(h->step_ctr);
+        if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
     }
     delete h;
     return NAVSIM_OK;

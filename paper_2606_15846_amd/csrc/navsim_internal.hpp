@@ -68,7 +68,10 @@ struct StepParams {
     const Tile *tiles;
     int32_t num_tiles, num_maps, max_words;
     // inputs / outputs
-    const float *act;
+    const float *act;          // normalised actions [N][2], or null in a rollout
+    const uint32_t *step_ctr;  // rollout: device {lo, hi} of the first step index
+    int32_t step_off;          // rollout: this step's offset from that index
+    float *act_out;            // rollout: the drawn actions [N][2] (may be null)
     const uint8_t *mask;
     float *obs, *reward, *final_obs;
     uint8_t *term, *trunc;
@@ -83,5 +86,6 @@ int fused_ray_cap(int max_words, int m, int tile_envs, int K, bool beams_lds);
 bool fused_tile_envs_supported(int tile_envs);
 hipError_t launch_fused(const StepParams &p, int tile_envs, hipStream_t s);
 hipError_t launch_plain(const StepParams &p, hipStream_t s);
+hipError_t launch_set_step(uint32_t *ctr, uint64_t first_step, hipStream_t s);
 
 }  // namespace navsim

@@ -57,6 +57,17 @@ __device__ __forceinline__ void draw4(const StepParams &p, uint32_t env, uint32_
     for (int i = 0; i < 4; ++i) u[i] = ((double)c[i] + 0.5) * (1.0 / kTwoPow32);
 }
 
+// Normalised action of env e: the given one, or in a rollout the draw of
+// counter (e, n mod 2^32, n div 2^32, 4) at step n, a_i = 2 u_i - 1.
+__device__ __forceinline__ float2 env_action(const StepParams &p, int e) {
+    if (!p.step_ctr) return make_float2(p.act[2 * (int64_t)e], p.act[2 * (int64_t)e + 1]);
+    const uint64_t n = (((uint64_t)p.step_ctr[1] << 32) | (uint64_t)p.step_ctr[0]) +
+                       (uint64_t)(uint32_t)p.step_off;
+    double u[4];
+    draw4(p, (uint32_t)e, (uint32_t)n, (uint32_t)(n >> 32), 4u, u);
+    return make_float2((float)(2.0 * u[0] - 1.0), (float)(2.0 * u[1] - 1.0));
+}
+
 // ---------------------------------------------------------------------------
 // Occupancy access.  `bits` points at the map's padded bitmap (LDS in the scan
 // kernel, device memory elsewhere); pitch = 32 * wpr bits per padded row.
@@ -746,8 +757,10 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
                 done = !p.mask || p.mask[e];
                 if (li == 0) s_jobs[grp].dst = 3;
             } else {
-                const Motion mo = apply_action(p, p.act[2 * (int64_t)e], p.act[2 * (int64_t)e + 1],
-                                               p.st.x[e], p.st.y[e], p.st.th[e]);
+                const float2 a = env_action(p, e);
+                if (p.act_out && li == 0)
+                    *reinterpret_cast<float2 *>(p.act_out + 2 * (int64_t)e) = a;
+                const Motion mo = apply_action(p, a.x, a.y, p.st.x[e], p.st.y[e], p.st.th[e]);
                 const double x1 = (double)mo.x1, y1 = (double)mo.y1, th1 = (double)mo.th1;
                 const bool coll = group_footprint_hits(M, robot_of(md), x1, y1, th1, li);
                 double sn, c;
@@ -1004,8 +1017,9 @@ __global__ __launch_bounds__(64) void plain_step_kernel(StepParams p) {
     if (p.mode == 1) {
         do_reset = !p.mask || p.mask[e];
     } else {
-        const Motion mo = apply_action(p, p.act[2 * (int64_t)e], p.act[2 * (int64_t)e + 1],
-                                       p.st.x[e], p.st.y[e], p.st.th[e]);
+        const float2 a = env_action(p, e);
+        if (p.act_out) *reinterpret_cast<float2 *>(p.act_out + 2 * (int64_t)e) = a;
+        const Motion mo = apply_action(p, a.x, a.y, p.st.x[e], p.st.y[e], p.st.th[e]);
         const double x1 = (double)mo.x1, y1 = (double)mo.y1, th1 = (double)mo.th1;
         const bool coll = footprint_hits(M, robot_of(md), x1, y1, th1);
         double sn, c;
@@ -1083,6 +1097,21 @@ hipError_t launch_fused(const StepParams &p, int tile_envs, hipStream_t s) {
         case 16: return launch_fused_e<16>(p, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+// Sets the rollout's first step index in device memory, so that a captured
+// sequence of steps can be replayed for any index.
+__global__ void set_step_kernel(uint32_t *ctr, uint32_t lo, uint32_t hi) {
+    if (threadIdx.x == 0) {
+        ctr[0] = lo;
+        ctr[1] = hi;
+    }
+}
+
+hipError_t launch_set_step(uint32_t *ctr, uint64_t first_step, hipStream_t s) {
+    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, s, ctr, (uint32_t)first_step,
+                       (uint32_t)(first_step >> 32));
+    return hipGetLastError();
 }
 
 hipError_t launch_plain(const StepParams &p, hipStream_t s) {

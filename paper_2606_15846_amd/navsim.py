@@ -20,11 +20,13 @@ LIB_PATH = os.path.join(_HERE, "libnavsim.so")
 NAVSIM_ABI_VERSION = 1
 NAVSIM_DISC, NAVSIM_RECT = 0, 1
 NAVSIM_KERNEL_FUSED, NAVSIM_KERNEL_PLAIN = 0, 1
+NAVSIM_ROLLOUT_GRAPH = 1
 STATUS = {0: "NAVSIM_OK", -1: "NAVSIM_E_INVALID_ARG", -2: "NAVSIM_E_BAD_HANDLE",
           -3: "NAVSIM_E_STATE", -4: "NAVSIM_E_NO_FREE_SPACE", -5: "NAVSIM_E_OOM",
           -6: "NAVSIM_E_HIP", -7: "NAVSIM_E_UNSUPPORTED"}
 EXPORTS = ("navsim_create", "navsim_load_maps", "navsim_load_maps_ex", "navsim_reset", "navsim_step",
-           "navsim_step_plain", "navsim_step_debug", "navsim_set_tuning", "navsim_get_tuning",
+           "navsim_step_plain", "navsim_step_debug", "navsim_rollout", "navsim_set_tuning",
+           "navsim_get_tuning",
            "navsim_get_state", "navsim_set_state", "navsim_destroy", "navsim_last_error")
 STATE_KEYS = ("x", "y", "th", "v", "w", "gx", "gy", "dprev", "t", "ep")
 _STATE_DT = (np.float32,) * 8 + (np.int32, np.uint32)
@@ -83,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     L.navsim_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.navsim_step_plain.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.navsim_step_debug.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(NavsimDebug), i32, vp]
+    L.navsim_rollout.argtypes = [vp, i32, C.c_uint64, vp, vp, vp, vp, vp, vp, i32, i32, vp]
     L.navsim_set_tuning.argtypes = [vp, C.POINTER(NavsimTuning)]
     L.navsim_get_tuning.argtypes = [vp, C.POINTER(NavsimTuning)]
     L.navsim_get_state.argtypes = [vp, vp, C.c_size_t, vp]
@@ -207,6 +210,24 @@ def navsim_step_debug(h, act, obs, reward, terminated, truncated, final_obs, dbg
         _stream_ptr(stream, obs.device)))
 
 
+def navsim_rollout(h, steps: int, first_step: int, act, obs, reward, terminated, truncated,
+                   final_obs=None, kernel: int = NAVSIM_KERNEL_FUSED, graph: bool = True,
+                   stream=None):
+    """Device tensors with a leading [steps] axis (act and final_obs may be None)."""
+    dev = obs.device
+    N, row = obs.shape[1], obs.shape[2]
+    T = int(steps)
+    args = (_dev_ptr(act, torch.float32, (T, N, 2), dev, "act", optional=True),
+            _dev_ptr(obs, torch.float32, (T, N, row), dev, "obs"),
+            _dev_ptr(reward, torch.float32, (T, N), dev, "reward"),
+            _dev_ptr(terminated, torch.uint8, (T, N), dev, "terminated"),
+            _dev_ptr(truncated, torch.uint8, (T, N), dev, "truncated"),
+            _dev_ptr(final_obs, torch.float32, (T, N, row), dev, "final_obs", optional=True))
+    _check(load_library().navsim_rollout(h, T, int(first_step), *args, int(kernel),
+                                         NAVSIM_ROLLOUT_GRAPH if graph else 0,
+                                         _stream_ptr(stream, dev)))
+
+
 def navsim_set_tuning(h, tile_envs: int, refill_at: int, groups: int):
     t = NavsimTuning(int(tile_envs), int(refill_at), int(groups))
     _check(load_library().navsim_set_tuning(h, C.byref(t)))
@@ -305,6 +326,26 @@ class NavSim:
         navsim_step_debug(self.h, act, self.obs, self.reward, self.terminated, self.truncated,
                           self.final_obs, dbg, kernel)
         return dbg
+
+    def rollout_buffers(self, steps: int, final_obs: bool = True) -> dict:
+        z = dict(device=self.device)
+        T, N, row = int(steps), self.N, self.m + 4
+        return dict(act=torch.zeros(T, N, 2, dtype=torch.float32, **z),
+                    obs=torch.zeros(T, N, row, dtype=torch.float32, **z),
+                    reward=torch.zeros(T, N, dtype=torch.float32, **z),
+                    terminated=torch.zeros(T, N, dtype=torch.uint8, **z),
+                    truncated=torch.zeros(T, N, dtype=torch.uint8, **z),
+                    final_obs=torch.zeros(T, N, row, dtype=torch.float32, **z) if final_obs
+                    else None)
+
+    def rollout(self, steps: int, first_step: int, buffers: dict | None = None,
+                kernel: int = NAVSIM_KERNEL_FUSED, graph: bool = True) -> dict:
+        """`steps` steps under the device-drawn actions of steps first_step,
+        first_step + 1, ...; returns the per-step buffers (reused when given)."""
+        b = buffers if buffers is not None else self.rollout_buffers(steps)
+        navsim_rollout(self.h, steps, first_step, b["act"], b["obs"], b["reward"],
+                       b["terminated"], b["truncated"], b["final_obs"], kernel, graph)
+        return b
 
     def set_tuning(self, tile_envs: int, refill_at: int, groups: int):
         navsim_set_tuning(self.h, tile_envs, refill_at, groups)

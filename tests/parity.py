@@ -54,7 +54,6 @@ def reset_scan_grazing(ref: oracle.OracleSim, rows) -> dict:
 def compare_step(gpu: dict, ref_out: dict, gpu_state: dict, ref: oracle.OracleSim,
                  label: str = "") -> dict:
     """Assert the acceptance rules; returns counters for reporting."""
-    N, K, m = ref.N, ref.K, ref.m
     kenv = env_beams(ref)
     for key in ("collision", "goal", "reset", "terminated", "truncated", "fallback"):
         g = gpu[key]
@@ -71,15 +70,31 @@ def compare_step(gpu: dict, ref_out: dict, gpu_state: dict, ref: oracle.OracleSi
     assert bad.size == 0, f"{label}: visit counts differ at {bad[:8].tolist()}"
     dr = np.abs(gpu["ranges"] - ref_out["ranges"])
     assert dr[live].max(initial=0.0) <= RANGE_TOL, f"{label}: range diff {dr[live].max()}"
-    dreward = np.abs(gpu["reward"] - ref_out["reward"]).max()
-    assert dreward <= SCALAR_TOL, f"{label}: reward diff {dreward}"
     for k in oracle.STATE_KEYS:
         bad = np.nonzero(gpu_state[k] != ref.state[k])[0]
         assert bad.size == 0, (f"{label}: state {k} differs at envs {bad[:8]} "
                                f"gpu={gpu_state[k][bad[:8]]} ref={ref.state[k][bad[:8]]}")
+    n_reset_graze = compare_outputs(gpu, ref_out, ref, label)
+    return dict(rays=int(kenv.sum()), grazing=int(graze.sum()),
+                grazing_mismatch=int(((hg != hr) & graze).sum()),
+                resets=int(ref_out["reset"].sum()), reset_grazing=n_reset_graze,
+                visits=int(vr.sum()))
+
+
+def compare_outputs(gpu: dict, ref_out: dict, ref: oracle.OracleSim, label: str = "") -> int:
+    """Reward, terminated/truncated, O_{t+1} (final_obs of the envs that ended,
+    obs otherwise) and the reset observations, against one oracle step whose
+    post-step state ref holds.  Returns the reset scans' grazing ray count."""
+    m = ref.m
+    for key in ("terminated", "truncated"):
+        bad = np.nonzero(gpu[key] != ref_out[key])[0]
+        assert bad.size == 0, f"{label}: {key} differs at envs {bad[:8]}"
+    graze = ref_out["grazing"].astype(bool)
+    dreward = np.abs(gpu["reward"] - ref_out["reward"]).max()
+    assert dreward <= SCALAR_TOL, f"{label}: reward diff {dreward}"
     # observations: O_{t+1} (final_obs rows for envs that ended, obs otherwise)
     done = ref_out["reset"].astype(bool)
-    sec_g = sectors_with_grazing(graze, m, kenv)
+    sec_g = sectors_with_grazing(graze, m, env_beams(ref))
     pre_g = np.where(done[:, None], gpu["final_obs"], gpu["obs"])
     pre_r = np.where(done[:, None], ref_out["final_obs"], ref_out["obs"])
     d = np.abs(pre_g[:, :m] - pre_r[:, :m])
@@ -98,10 +113,7 @@ def compare_step(gpu: dict, ref_out: dict, gpu_state: dict, ref: oracle.OracleSi
         assert d[~sg].max(initial=0.0) <= RANGE_TOL, f"{label}: reset obs env {e} diff {d.max()}"
         ds = np.abs(gpu["obs"][e, m:] - ref_out["obs"][e, m:]).max()
         assert ds <= SCALAR_TOL, f"{label}: reset obs scalars env {e} diff {ds}"
-    return dict(rays=int(kenv.sum()), grazing=int(graze.sum()),
-                grazing_mismatch=int(((hg != hr) & graze).sum()),
-                resets=int(done.sum()), reset_grazing=n_reset_graze,
-                visits=int(vr.sum()))
+    return n_reset_graze
 
 
 def gpu_step(sim, act_np: np.ndarray, kernel: int) -> tuple[dict, dict]:
@@ -115,3 +127,23 @@ def gpu_step(sim, act_np: np.ndarray, kernel: int) -> tuple[dict, dict]:
                terminated=sim.terminated.cpu().numpy().copy(),
                truncated=sim.truncated.cpu().numpy().copy())
     return out, sim.get_state()
+
+
+def compare_rollout(bufs: dict, ref: oracle.OracleSim, first_step: int, label: str = "",
+                    threads: int = 16) -> dict:
+    """A device rollout (host copies of its [steps] buffers) against the oracle
+    run free from the same start state under its own draws of the same
+    actions.  Poses, goals, counters and flags do not depend on ranges, so the
+    oracle's state stays bitwise on the device's path; ranges are held to the
+    step tolerance outside grazing sectors."""
+    steps = bufs["obs"].shape[0]
+    tot = dict(resets=0, grazing=0, reset_grazing=0)
+    for t in range(steps):
+        a = ref.rollout_actions(first_step + t)
+        assert np.array_equal(bufs["act"][t], a), f"{label}: actions of step {t} differ"
+        r = ref.step(a, threads=threads)
+        g = {k: bufs[k][t] for k in ("obs", "reward", "terminated", "truncated", "final_obs")}
+        tot["reset_grazing"] += compare_outputs(g, r, ref, label=f"{label} step {t}")
+        tot["resets"] += int(r["reset"].sum())
+        tot["grazing"] += int(r["grazing"].sum())
+    return tot

@@ -24,7 +24,7 @@ def declared_functions():
 def test_library_exports_every_declared_function():
     lib = navsim.load_library()
     names = declared_functions()
-    assert len(names) == 13
+    assert len(names) == 14
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(navsim.EXPORTS) == names
@@ -94,5 +94,23 @@ def test_abi_version_and_null_arguments():
                      ("navsim_get_state", (None, None, 0, None)),
                      ("navsim_set_state", (None, None, 0, None)),
                      ("navsim_load_maps", (None, 1, None, None, None, None, None)),
-                     ("navsim_load_maps_ex", (None, 1, None, None, None, None, None, None))]:
+                     ("navsim_load_maps_ex", (None, 1, None, None, None, None, None, None)),
+                     ("navsim_rollout", (None, 4, 0, None, None, None, None, None, None, 0, 1,
+                                         None))]:
         assert getattr(lib, fn)(*args) == -2, fn
+
+
+def test_map_profile_layout_matches_header(tmp_path):
+    fields = [f for f, _ in navsim.NavsimMapProfile._fields_]
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "navsim.h"', "int main(void){",
+           'printf("%zu\\n", sizeof(navsim_map_profile));']
+    src += [f'printf("%zu\\n", offsetof(navsim_map_profile, {f}));' for f in fields]
+    src += ["return 0;}"]
+    c = tmp_path / "probe.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == C.sizeof(navsim.NavsimMapProfile)
+    assert vals[1:] == [getattr(navsim.NavsimMapProfile, f).offset for f in fields]
