@@ -46,10 +46,14 @@ def best_for(key: str) -> dict:
     return dict(entry["best"]) if entry else dict(DEFAULT)
 
 
-def save(key: str, best: dict, table: list, device_name: str):
-    allt = load_all()
+def save(key: str, best: dict, table: list, device_name: str, path: str = TUNING_FILE):
+    """Merge one workload's result into the JSON file at `path`."""
+    allt = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            allt = json.load(f)
     allt[key] = {"best": best, "device": device_name, "table": table}
-    with open(TUNING_FILE, "w") as f:
+    with open(path, "w") as f:
         json.dump(allt, f, indent=1, sort_keys=True)
 
 
@@ -99,6 +103,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--out", default=TUNING_FILE, help="JSON file the result is merged into")
     args = ap.parse_args()
     w = configs.build_workload(args.workload)
     cfg = w["cfg"]
@@ -110,7 +115,7 @@ def main():
         sim.step(acts[t])
     best, table = tune(sim, acts[20:], steps=args.steps, verbose=True)
     key = workload_key(cfg, w["maps"], w["profiles"])
-    save(key, best, table, torch.cuda.get_device_name(0))
+    save(key, best, table, torch.cuda.get_device_name(0), args.out)
     print(json.dumps({"key": key, "best": best}))
     sim.close()
 
