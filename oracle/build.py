@@ -9,14 +9,14 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "navsim_oracle.c")
+SRC = [os.path.join(HERE, "navsim_oracle.c"), os.path.join(HERE, "geodesic_oracle.c")]
 LIB = os.path.join(HERE, "liborc.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared",
            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter",
-           SRC, "-o", LIB + ".tmp", "-lm"]
+           *SRC, "-o", LIB + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
