@@ -134,6 +134,16 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
  *   obs   device float32 [N][m+4] */
 navsim_status navsim_reset(navsim_t h, const uint8_t *mask, float *obs, void *hip_stream);
 
+/* navsim_reset to caller-given poses: every env with mask[e] != 0 (mask NULL =
+ * all) gets start (x, y, heading) and goal (x, y) from row e of `pose`
+ * (device float32 [N][5]: x, y, heading, goal x, goal y in metres / radians),
+ * v = w = 0, t = 0, its episode counter + 1, and the reset observation in its
+ * obs row (device float32 [N][m+4]).  The poses are not checked: callers pass
+ * verified ones (navsim_rp_propose writes such rows).  Same errors as
+ * navsim_reset. */
+navsim_status navsim_reset_to(navsim_t h, const uint8_t *mask, const float *pose, float *obs,
+                              void *hip_stream);
+
 /* One environment step for all N envs, the step data path of eq. 7:
  * action -> pose -> ranges -> (collision, reward, termination) -> O_{t+1}
  * -> reset observation where the episode ended.

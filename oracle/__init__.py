@@ -108,6 +108,8 @@ def lib():
     L.orc_march.argtypes = [P(OrcMaps), C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                             C.c_double, C.c_double, P(C.c_double), P(C.c_int32)]
     L.orc_cfg_for_map.argtypes = [P(OrcCfg), P(OrcMaps), C.c_int, P(OrcCfg)]
+    L.orc_reset_to.argtypes = [P(OrcCfg), P(OrcMaps), P(OrcState), P(C.c_uint8), P(C.c_float),
+                               P(C.c_float), C.c_int64, C.c_int64]
     L.orc_rollout_actions.argtypes = [P(OrcCfg), C.c_uint64, C.c_int64, C.c_int64, P(C.c_float)]
     L.orc_beam_angle.argtypes = [P(OrcCfg), C.c_int]
     L.orc_beam_angle.restype = C.c_double
@@ -308,6 +310,17 @@ class OracleSim:
                        _ptr(act, C.c_float), C.byref(out), sl[0], sl[1])
         self._run(run, threads)
         return o
+
+    def reset_to(self, pose, mask=None) -> np.ndarray:
+        """Reset masked envs to given poses [N, 5]; returns the obs rows (zeros
+        for unmasked envs)."""
+        obs = np.zeros((self.N, self.m + 4), dtype=np.float32)
+        pz = np.ascontiguousarray(pose, dtype=np.float32)
+        mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+        lib().orc_reset_to(C.byref(self.cfg), C.byref(self.maps.struct), C.byref(self.st),
+                           _ptr(mk, C.c_uint8), _ptr(pz, C.c_float), _ptr(obs, C.c_float), 0,
+                           self.N)
+        return obs
 
     def rollout_actions(self, n: int) -> np.ndarray:
         """Normalised actions [N, 2] of rollout step n (Philox stream 4)."""

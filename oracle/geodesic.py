@@ -36,8 +36,10 @@ def _L():
         L.orc_verify_pair.restype = i32
         L.orc_reject_sample.argtypes = [i32, i32, f64, u8p, i32p, C.c_int64, P(C.c_uint32),
                                         C.c_uint32, C.c_uint32, i32, i32, f64, f64, i32, f64,
-                                        i32p, i32p, i32p]
+                                        i32p, i32p, i32p, P(C.c_float)]
         L.orc_reject_sample.restype = i32
+        L.orc_snap_cell.argtypes = [i32, i32, u8p, i32]
+        L.orc_snap_cell.restype = i32
         L.orc_pool32.argtypes = [i32, i32, u8p, P(C.c_float)]
         L.orc_decode_proposal.argtypes = [i32, i32, P(C.c_float), i32p, i32p, P(C.c_float)]
         _DONE = True
@@ -112,13 +114,23 @@ class ReachMap:
                                   self.nbins, self.gmd, C.byref(h))
         return bool(ok), h.value
 
-    def reject(self, e: int, ep: int, k: int, max_tries: int):
-        a, b, h = C.c_int32(), C.c_int32(), C.c_int32()
+    def reject(self, e: int, ep: int, k: int, max_tries: int, with_heading: bool = False):
+        a, b, h, th = C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
         t = _L().orc_reject_sample(*self._args(), _p(self.free, C.c_int32), len(self.free),
                                    _p(self.key, C.c_uint32), int(e), int(ep), int(k),
                                    int(max_tries), self.d_lo, self.d_hi, self.nbins, self.gmd,
-                                   C.byref(a), C.byref(b), C.byref(h))
+                                   C.byref(a), C.byref(b), C.byref(h), C.byref(th))
+        if with_heading:
+            return int(t), a.value, b.value, h.value, th.value
         return int(t), a.value, b.value, h.value
+
+    def snap(self, c: int) -> int:
+        return int(_L().orc_snap_cell(self.W, self.H, _p(self.cfree, C.c_uint8), int(c)))
+
+    def centre(self, c: int) -> tuple[float, float]:
+        """Cell centre in metres, float32 as the reset poses store it."""
+        return (float(np.float32((c % self.W + 0.5) * self.s)),
+                float(np.float32((c // self.W + 0.5) * self.s)))
 
     def bin_of(self, hops: int) -> int:
         return bin_of(self.s, hops, self.d_lo, self.d_hi, self.nbins)

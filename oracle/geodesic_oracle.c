@@ -21,6 +21,10 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
 static void orc_words(const uint32_t key[2], uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
@@ -155,14 +159,16 @@ int32_t orc_reject_sample(int32_t W, int32_t H, double s, const uint8_t *cfree,
                           const int32_t *free_list, int64_t nfree, const uint32_t key[2],
                           uint32_t e, uint32_t ep, int32_t k, int32_t max_tries, double d_lo,
                           double d_hi, int32_t nbins, double gmd, int32_t *a_out, int32_t *b_out,
-                          int32_t *hops_out)
+                          int32_t *hops_out, float *heading_out)
 {
     *a_out = *b_out = *hops_out = -1;
+    *heading_out = 0.0f;
     for (int32_t t = 0; t < max_tries; ++t) {
         uint32_t w[4];
         orc_words(key, e, ep, (uint32_t)t, 7u, w);
         int32_t a = free_list[orc_pick(w[0], nfree)], b = free_list[orc_pick(w[1], nfree)];
         int32_t h;
+        *heading_out = (float)((((double)w[2] + 0.5) / 4294967296.0) * (2.0 * M_PI) - M_PI);
         if (orc_verify_pair(W, H, s, cfree, a, b, k, d_lo, d_hi, nbins, gmd, &h)) {
             *a_out = a;
             *b_out = b;
@@ -171,6 +177,23 @@ int32_t orc_reject_sample(int32_t W, int32_t H, double s, const uint8_t *cfree,
         }
     }
     return -1;
+}
+
+/* Nearest C-free cell to cell c: least |di| + |dj|, ties to the least index;
+ * -1 when the map has none. */
+int32_t orc_snap_cell(int32_t W, int32_t H, const uint8_t *cfree, int32_t c)
+{
+    int32_t ci = c % W, cj = c / W, best = -1;
+    int64_t bestd = 0;
+    for (int64_t q = 0; q < (int64_t)W * H; ++q) {
+        if (!cfree[q]) continue;
+        int64_t d = llabs((int64_t)(q % W) - ci) + llabs((int64_t)(q / W) - cj);
+        if (best < 0 || d < bestd) {
+            best = (int32_t)q;
+            bestd = d;
+        }
+    }
+    return best;
 }
 
 /* 32 x 32 max-pooled occupancy of a W x H map (W, H >= 32): block (p, q)

@@ -502,6 +502,34 @@ static void orc_reset_env(const orc_cfg *gcfg, const orc_maps *M, orc_state *st,
 }
 
 /* Reset every env whose mask byte is nonzero (mask NULL = all), envs [e0, e1). */
+/* Reset of envs [e0, e1) with mask[e] != 0 (NULL = all) to given poses
+ * pose[5 e ..] = (x, y, heading, goal x, goal y): the state and reset
+ * observation of a reset (section 2.2.3) without the sampling. */
+void orc_reset_to(const orc_cfg *gcfg, const orc_maps *M, orc_state *st, const uint8_t *mask,
+                  const float *pose, float *obs, int64_t e0, int64_t e1)
+{
+    for (int64_t e = e0; e < e1; ++e) {
+        if (mask && !mask[e]) continue;
+        int map = st->map[e];
+        orc_cfg mcfg;
+        orc_cfg_for_map(gcfg, M, map, &mcfg);
+        const float *q = pose + 5 * e;
+        st->x[e] = q[0];
+        st->y[e] = q[1];
+        st->th[e] = q[2];
+        st->v[e] = 0.0f;
+        st->w[e] = 0.0f;
+        st->gx[e] = q[3];
+        st->gy[e] = q[4];
+        st->t[e] = 0;
+        st->ep[e] = st->ep[e] + 1;
+        int m = mcfg.num_sectors;
+        st->dprev[e] = orc_observe(M, map, &mcfg, (double)q[0], (double)q[1], (double)q[2],
+                                   (double)q[3], (double)q[4], 0.0f, 0.0f,
+                                   obs ? obs + e * (m + 4) : NULL, NULL, NULL, NULL, NULL, NULL);
+    }
+}
+
 void orc_reset(const orc_cfg *cfg, const orc_maps *M, orc_state *st, const uint8_t *mask,
                float *obs, uint8_t *fallback, int64_t e0, int64_t e1)
 {

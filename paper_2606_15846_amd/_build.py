@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnavsim.so")
-SOURCES = ["navsim_kernels.hip", "navsim_api.cpp"]
+SOURCES = ["navsim_kernels.hip", "navsim_api.cpp", "mlp_kernels.hip", "reach_kernels.hip",
+           "reset_proposal.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

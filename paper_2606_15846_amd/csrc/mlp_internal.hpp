@@ -1,0 +1,64 @@
+// Small multilayer perceptrons on bfloat16 matrix cores: host-side launch
+// interface of mlp_kernels.hip (library internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace navsim {
+
+// C[m, n] = sum_k A(m, k) B(n, k), bfloat16 operands, float accumulation.
+// A(m, k) = A[m lda + k] when a_kmajor, else A[k lda + m]; B likewise.
+// Epilogue: + bias[n] (optional) + bias_rows[row_idx[m] ldbr + n] (optional),
+// activation (0 none, 1 leaky ReLU with `slope`), then stored as float to Cf
+// and/or as bfloat16 (round to nearest even) to Cb.
+struct GemmArgs {
+    int M = 0, N = 0, K = 0;
+    const uint16_t *A = nullptr;
+    int64_t lda = 0;
+    bool a_kmajor = true;
+    const uint16_t *B = nullptr;
+    int64_t ldb = 0;
+    bool b_kmajor = true;
+    const float *bias = nullptr;
+    const float *bias_rows = nullptr;
+    const int32_t *row_idx = nullptr;
+    int64_t ldbr = 0;
+    int act = 0;
+    float slope = 0.0f;
+    float *Cf = nullptr;
+    int64_t ldcf = 0;
+    uint16_t *Cb = nullptr;
+    int64_t ldcb = 0;
+};
+
+hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
+
+// dZ = dH * act'(H) for leaky ReLU (H is the layer's bfloat16 output, whose
+// sign is that of its input); writes float dZf and bfloat16 dZb, [M, N] rows
+// of stride ld.  act 0: dZ = dH.
+hipError_t launch_act_backward(int M, int N, const float *dH, const uint16_t *H, int act,
+                               float slope, float *dZf, uint16_t *dZb, hipStream_t s);
+
+// out[n] = sum over m of X[m, n] (float, [M, N] rows), in a fixed order:
+// chunks of 256 rows in order, then the chunk sums in order.  `partial`
+// holds ceil(M / 256) * N floats.
+hipError_t launch_col_sum(int M, int N, const float *X, float *partial, float *out,
+                          hipStream_t s);
+
+// Weighted squared error of outputs Y [M, D] to targets T [M, D]: row loss
+// L[m] = sum_d w[d] (Y - T)^2 and dY = 2 w (Y - T) / M (float and bfloat16).
+hipError_t launch_sq_loss(int M, int D, const float *Y, const float *T, const float *w,
+                          float *L, float *dYf, uint16_t *dYb, hipStream_t s);
+
+// AdamW (decoupled weight decay): for i < n,
+//   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+//   p = p (1 - lr wd) - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
+// decay applied where decay_mask[i] != 0; pb = bfloat16(p).
+hipError_t launch_adamw(int64_t n, float *p, uint16_t *pb, const float *g, float *m, float *v,
+                        const uint8_t *decay_mask, float lr, float b1, float b2, float eps,
+                        float wd, int64_t t, hipStream_t s);
+
+// Float to bfloat16 (round to nearest even), n elements.
+hipError_t launch_to_bf16(int64_t n, const float *x, uint16_t *y, hipStream_t s);
+
+}  // namespace navsim

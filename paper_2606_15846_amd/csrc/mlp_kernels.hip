@@ -1,0 +1,255 @@
+// Kernels of the small bfloat16 perceptrons (the learned reset proposal's
+// network): a tiled GEMM on the gfx950 matrix cores with a fused
+// bias/activation epilogue, the activation backward, column sums, the squared
+// error loss and AdamW.  Accumulation is always float.
+#include <math.h>
+
+#include "mlp_internal.hpp"
+
+namespace navsim {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBM = 64, kBN = 64, kBK = 32;
+constexpr int kLdsK = kBK + 8;  // padded row (80 bytes) of a staged tile
+constexpr int kGemmThreads = 256;
+
+__device__ __forceinline__ uint16_t to_bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;  // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                    // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16_bits(uint16_t b) {
+    return __uint_as_float((uint32_t)b << 16);
+}
+
+// Stage rows [r0, r0 + 64) x k [k0, k0 + 32) of a matrix whose element (r, k)
+// is X[r ld + k] (kmajor) or X[k ld + r], as T[r][k] in LDS; zeros outside
+// [0, R) x [0, K).
+template <bool KMAJOR>
+__device__ __forceinline__ void stage_tile(uint16_t (*T)[kLdsK], const uint16_t *X, int64_t ld,
+                                           int R, int K, int r0, int k0, bool vec_ok, int tid) {
+    if (KMAJOR) {
+        const int r = tid >> 2, kk = (tid & 3) * 8;
+        const int gr = r0 + r, gk = k0 + kk;
+        uint16_t v[8];
+        if (vec_ok && gr < R && gk + 8 <= K) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(X + (int64_t)gr * ld + gk);
+            *reinterpret_cast<uint4 *>(&T[r][kk]) = q;
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            v[j] = (gr < R && gk + j < K) ? X[(int64_t)gr * ld + gk + j] : (uint16_t)0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) T[r][kk + j] = v[j];
+    } else {
+        const int kr = tid >> 3, rr = (tid & 7) * 8;
+        const int gk = k0 + kr, gr = r0 + rr;
+        uint16_t v[8];
+        if (vec_ok && gk < K && gr + 8 <= R) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(X + (int64_t)gk * ld + gr);
+            const uint16_t *w = reinterpret_cast<const uint16_t *>(&q);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = w[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                v[j] = (gk < K && gr + j < R) ? X[(int64_t)gk * ld + gr + j] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) T[rr + j][kr] = v[j];
+    }
+}
+
+// One workgroup computes a 64 x 64 block of C; each of its four wavefronts a
+// 32 x 32 quarter as 2 x 2 tiles of the 16 x 16 x 32 bfloat16 MFMA.
+// Fragment layout of v_mfma_f32_16x16x32_bf16: lane l supplies row l % 16 of
+// A and column l % 16 of B, k = 8 (l / 16) .. 8 (l / 16) + 7; it receives
+// C[4 (l / 16) + r][l % 16], r = 0..3.
+template <bool AK, bool BK>
+__global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kBM][kLdsK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kLdsK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const bool a_vec = (g.lda % 8 == 0) && (((uintptr_t)g.A & 15) == 0);
+    const bool b_vec = (g.ldb % 8 == 0) && (((uintptr_t)g.B & 15) == 0);
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+        stage_tile<AK>(As, g.A, g.lda, g.M, g.K, m0, k0, a_vec, tid);
+        stage_tile<BK>(Bs, g.B, g.ldb, g.N, g.K, n0, k0, b_vec, tid);
+        __syncthreads();
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * i + fr][fk]);
+            b[i] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * i + fr][fk]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + wn + 16 * j + fr;
+            if (n >= g.N) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + (lane >> 4) * 4 + r;
+                if (m >= g.M) continue;
+                float v = acc[i][j][r];
+                if (g.bias) v += g.bias[n];
+                if (g.bias_rows) v += g.bias_rows[(int64_t)g.row_idx[m] * g.ldbr + n];
+                if (g.act == 1 && !(v > 0.0f)) v *= g.slope;
+                if (g.Cf) g.Cf[(int64_t)m * g.ldcf + n] = v;
+                if (g.Cb) g.Cb[(int64_t)m * g.ldcb + n] = to_bf16_bits(v);
+            }
+        }
+}
+
+__global__ void act_backward_kernel(int64_t n, int N, const float *dH, const uint16_t *H, int act,
+                                    float slope, float *dZf, uint16_t *dZb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float d = dH[i];
+    if (act == 1 && !(from_bf16_bits(H[i]) > 0.0f)) d *= slope;
+    if (dZf) dZf[i] = d;
+    if (dZb) dZb[i] = to_bf16_bits(d);
+}
+
+__global__ void col_sum_chunks_kernel(int M, int N, const float *X, float *partial) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (n >= N) return;
+    const int m1 = min(M, (c + 1) * 256);
+    float s = 0.0f;
+    for (int m = c * 256; m < m1; ++m) s += X[(int64_t)m * N + n];
+    partial[(int64_t)c * N + n] = s;
+}
+
+__global__ void col_sum_final_kernel(int chunks, int N, const float *partial, float *out) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int c = 0; c < chunks; ++c) s += partial[(int64_t)c * N + n];
+    out[n] = s;
+}
+
+__global__ void sq_loss_kernel(int M, int D, const float *Y, const float *T, const float *w,
+                               float *L, float *dYf, uint16_t *dYb) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    float l = 0.0f;
+    for (int d = 0; d < D; ++d) {
+        const float e = Y[(int64_t)m * D + d] - T[(int64_t)m * D + d];
+        l += w[d] * (e * e);
+        const float gd = (2.0f * w[d] * e) / (float)M;
+        if (dYf) dYf[(int64_t)m * D + d] = gd;
+        if (dYb) dYb[(int64_t)m * D + d] = to_bf16_bits(gd);
+    }
+    if (L) L[m] = l;
+}
+
+__global__ void adamw_kernel(int64_t n, float *p, uint16_t *pb, const float *g, float *m, float *v,
+                             const uint8_t *decay_mask, float lr, float b1, float b2, float eps,
+                             float wd, float bc1, float bc2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * (gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    float pi = p[i];
+    if (!decay_mask || decay_mask[i]) pi = pi * (1.0f - lr * wd);
+    pi = pi - lr * ((mi / bc1) / (sqrtf(vi / bc2) + eps));
+    p[i] = pi;
+    if (pb) pb[i] = to_bf16_bits(pi);
+}
+
+__global__ void to_bf16_kernel(int64_t n, const float *x, uint16_t *y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = to_bf16_bits(x[i]);
+}
+
+unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((g.N + kBN - 1) / kBN), (unsigned)((g.M + kBM - 1) / kBM));
+    if (g.a_kmajor && g.b_kmajor)
+        hipLaunchKernelGGL((gemm_kernel<true, true>), grid, dim3(kGemmThreads), 0, s, g);
+    else if (g.a_kmajor)
+        hipLaunchKernelGGL((gemm_kernel<true, false>), grid, dim3(kGemmThreads), 0, s, g);
+    else if (g.b_kmajor)
+        hipLaunchKernelGGL((gemm_kernel<false, true>), grid, dim3(kGemmThreads), 0, s, g);
+    else
+        hipLaunchKernelGGL((gemm_kernel<false, false>), grid, dim3(kGemmThreads), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_act_backward(int M, int N, const float *dH, const uint16_t *H, int act,
+                               float slope, float *dZf, uint16_t *dZb, hipStream_t s) {
+    const int64_t n = (int64_t)M * N;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(act_backward_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, N, dH, H,
+                       act, slope, dZf, dZb);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_sum(int M, int N, const float *X, float *partial, float *out,
+                          hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    const int chunks = (M + 255) / 256;
+    if (chunks > 0)
+        hipLaunchKernelGGL(col_sum_chunks_kernel, dim3(blocks_for(N, 256), (unsigned)chunks),
+                           dim3(256), 0, s, M, N, X, partial);
+    hipLaunchKernelGGL(col_sum_final_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, chunks, N,
+                       partial, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sq_loss(int M, int D, const float *Y, const float *T, const float *w,
+                          float *L, float *dYf, uint16_t *dYb, hipStream_t s) {
+    if (M == 0) return hipSuccess;
+    hipLaunchKernelGGL(sq_loss_kernel, dim3(blocks_for(M, 256)), dim3(256), 0, s, M, D, Y, T, w,
+                       L, dYf, dYb);
+    return hipGetLastError();
+}
+
+hipError_t launch_adamw(int64_t n, float *p, uint16_t *pb, const float *g, float *m, float *v,
+                        const uint8_t *decay_mask, float lr, float b1, float b2, float eps,
+                        float wd, int64_t t, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const float bc1 = (float)(1.0 - pow((double)b1, (double)t));
+    const float bc2 = (float)(1.0 - pow((double)b2, (double)t));
+    hipLaunchKernelGGL(adamw_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, p, pb, g, m, v,
+                       decay_mask, lr, b1, b2, eps, wd, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(int64_t n, const float *x, uint16_t *y, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, y);
+    return hipGetLastError();
+}
+
+}  // namespace navsim

@@ -14,11 +14,12 @@
 #include <vector>
 
 #include "navsim.h"
+#include "navsim_host.hpp"
 #include "navsim_internal.hpp"
 
 using namespace navsim;
 
-namespace {
+namespace navsim {
 
 thread_local std::string g_err;
 
@@ -32,58 +33,7 @@ navsim_status fail(navsim_status s, const char *fmt, ...) {
     return s;
 }
 
-#define NS_HIP(call)                                                                        \
-    do {                                                                                    \
-        hipError_t _e = (call);                                                             \
-        if (_e != hipSuccess) return fail(NAVSIM_E_HIP, "%s: %s", #call, hipGetErrorString(_e)); \
-    } while (0)
-
-// Makes the handle's device current for the duration of a call and restores
-// the caller's device afterwards.
-struct DeviceGuard {
-    int prev = -1;
-    hipError_t err = hipSuccess;
-    explicit DeviceGuard(int dev) {
-        err = hipGetDevice(&prev);
-        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
-bool finite_pos(float v) { return isfinite(v) && v > 0.0f; }
-
-}  // namespace
-
-struct navsim_s {
-    navsim_config cfg;
-    int device = 0;
-    bool loaded = false;
-    bool initialized = false;
-    // device memory
-    void *state_buf = nullptr;
-    DevState st{};
-    double2 *beams = nullptr;
-    uint32_t *bits = nullptr;
-    MapDesc *maps = nullptr;
-    int32_t *free_cells = nullptr;
-    int32_t *env_map = nullptr;
-    int32_t *perm = nullptr;
-    Tile *tiles = nullptr;
-    int num_maps = 0, num_tiles = 0, max_words = 0;
-    int tile_envs = kDefaultTileEnvs, refill_at = kDefaultRefillAt, groups = kDefaultGroups;
-    int ray_cap = 0;
-    bool beams_lds = true;
-    std::vector<int32_t> host_env_map;  // kept to rebuild the tiles when tile_envs changes
-    // rollouts: first step index on the device, and the last captured rollout
-    uint32_t *step_ctr = nullptr;
-    hipStream_t capture_stream = nullptr;
-    hipGraphExec_t graph = nullptr;
-    StepParams graph_params{};  // parameters of step 0 of the captured rollout
-    int graph_steps = 0, graph_kernel = -1, graph_tile_envs = 0;
-};
+}  // namespace navsim
 
 namespace {
 
@@ -569,6 +519,20 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
     h->ray_cap = ray_cap;
     h->beams_lds = beams_lds;
     h->host_env_map.swap(host_env_map);
+    h->host_occ.assign(occ, occ + occ_off[num_maps]);
+    h->host_occ_off = occ_off;
+    h->host_w.assign(width, width + num_maps);
+    h->host_h.assign(height, height + num_maps);
+    h->host_res.assign(res_m, res_m + num_maps);
+    h->host_rc.resize(num_maps);
+    h->host_free_off.resize(num_maps);
+    h->host_free_cnt.resize(num_maps);
+    for (int k = 0; k < num_maps; ++k) {
+        h->host_rc[k] = descs[k].rc;
+        h->host_free_off[k] = descs[k].free_off;
+        h->host_free_cnt[k] = descs[k].free_cnt;
+    }
+    h->host_free.swap(free_cells);
     h->loaded = true;
     return NAVSIM_OK;
 }
@@ -582,6 +546,23 @@ navsim_status navsim_reset(navsim_t h, const uint8_t *mask, float *obs, void *hi
     StepParams p = make_params(h);
     p.mode = 1;
     p.mask = mask;
+    p.obs = obs;
+    const navsim_status s = run(h, p, NAVSIM_KERNEL_FUSED, (hipStream_t)hip_stream);
+    if (s == NAVSIM_OK) h->initialized = true;
+    return s;
+}
+
+navsim_status navsim_reset_to(navsim_t h, const uint8_t *mask, const float *pose, float *obs,
+                              void *hip_stream) {
+    if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
+    if (!h->loaded) return fail(NAVSIM_E_STATE, "navsim_load_maps has not been called");
+    if (!pose || !obs) return fail(NAVSIM_E_INVALID_ARG, "pose and obs are required");
+    if (mask && !h->initialized)
+        return fail(NAVSIM_E_STATE, "the first reset must cover all envs (mask NULL)");
+    StepParams p = make_params(h);
+    p.mode = 1;
+    p.mask = mask;
+    p.pose = pose;
     p.obs = obs;
     const navsim_status s = run(h, p, NAVSIM_KERNEL_FUSED, (hipStream_t)hip_stream);
     if (s == NAVSIM_OK) h->initialized = true;

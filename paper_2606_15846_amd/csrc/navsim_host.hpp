@@ -1,0 +1,80 @@
+// Library-internal host declarations shared by the C ABI sources: the handle
+// behind navsim_t, error reporting and the device guard.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <string>
+#include <vector>
+
+#include "navsim.h"
+#include "navsim_internal.hpp"
+
+namespace navsim {
+
+// Records the message returned by navsim_last_error() and returns s.
+navsim_status fail(navsim_status s, const char *fmt, ...);
+
+#define NS_HIP(call)                                                                        \
+    do {                                                                                    \
+        hipError_t _e = (call);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return ::navsim::fail(NAVSIM_E_HIP, "%s: %s", #call, hipGetErrorString(_e));    \
+    } while (0)
+
+// Makes the handle's device current for the duration of a call and restores
+// the caller's device afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+inline bool finite_pos(float v) { return isfinite(v) && v > 0.0f; }
+
+}  // namespace navsim
+
+struct navsim_s {
+    navsim_config cfg;
+    int device = 0;
+    bool loaded = false;
+    bool initialized = false;
+    // device memory
+    void *state_buf = nullptr;
+    navsim::DevState st{};
+    double2 *beams = nullptr;
+    uint32_t *bits = nullptr;
+    navsim::MapDesc *maps = nullptr;
+    int32_t *free_cells = nullptr;
+    int32_t *env_map = nullptr;
+    int32_t *perm = nullptr;
+    navsim::Tile *tiles = nullptr;
+    int num_maps = 0, num_tiles = 0, max_words = 0;
+    int tile_envs = navsim::kDefaultTileEnvs, refill_at = navsim::kDefaultRefillAt, groups = navsim::kDefaultGroups;
+    int ray_cap = 0;
+    bool beams_lds = true;
+    std::vector<int32_t> host_env_map;  // kept to rebuild the tiles when tile_envs changes
+    // host copies of the loaded maps (reset proposals build their own tables)
+    std::vector<uint8_t> host_occ;
+    std::vector<int64_t> host_occ_off;
+    std::vector<int32_t> host_w, host_h;
+    std::vector<float> host_res;
+    std::vector<double> host_rc;
+    std::vector<int32_t> host_free;
+    std::vector<int64_t> host_free_off;
+    std::vector<int32_t> host_free_cnt;
+    // rollouts: first step index on the device, and the last captured rollout
+    uint32_t *step_ctr = nullptr;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    navsim::StepParams graph_params{};  // parameters of step 0 of the captured rollout
+    int graph_steps = 0, graph_kernel = -1, graph_tile_envs = 0;
+};
+

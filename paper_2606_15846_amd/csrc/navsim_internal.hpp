@@ -73,6 +73,7 @@ struct StepParams {
     int32_t step_off;          // rollout: this step's offset from that index
     float *act_out;            // rollout: the drawn actions [N][2] (may be null)
     const uint8_t *mask;
+    const float *pose;         // reset to given poses [N][5] (x, y, heading, goal x, goal y), or null
     float *obs, *reward, *final_obs;
     uint8_t *term, *trunc;
     // diagnostics (may be null)

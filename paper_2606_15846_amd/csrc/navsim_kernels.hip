@@ -22,6 +22,7 @@
 #include <algorithm>
 
 #include "navsim_internal.hpp"
+#include "philox.hpp"
 
 namespace navsim {
 
@@ -29,25 +30,8 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPow32 = 4294967296.0;
 constexpr double kTwoPow30 = 1073741824.0;
 
-// ---------------------------------------------------------------------------
-// Counter-based generator for the reset draws: Philox4x32-10 (Salmon et al.,
-// SC'11).  Counter (env, episode, attempt, stream), key = 64-bit seed.
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
-        const uint32_t n0 = hi1 ^ c[1] ^ k0;
-        const uint32_t n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
+// Reset draws use Philox4x32-10 (philox.hpp) with counter (env, episode,
+// attempt, stream) and key = 64-bit seed.
 // Four uniforms in (0, 1): (w + 1/2) 2^-32, exact in double.
 __device__ __forceinline__ void draw4(const StepParams &p, uint32_t env, uint32_t ep,
                                       uint32_t attempt, uint32_t stream, double u[4]) {
@@ -443,6 +427,19 @@ __device__ ResetPose sample_reset(const StepParams &p, const MapView &M, const M
     return r;
 }
 
+// A reset pose supplied by the caller (row e of p.pose).
+__device__ __forceinline__ ResetPose given_pose(const StepParams &p, int e) {
+    const float *q = p.pose + 5 * (int64_t)e;
+    ResetPose r;
+    r.x = q[0];
+    r.y = q[1];
+    r.th = q[2];
+    r.gx = q[3];
+    r.gy = q[4];
+    r.fb = 0u;
+    return r;
+}
+
 // Store a reset: new state and the reset observation's scalar part (d, phi,
 // v = w = 0); c, sn receive the new heading's cosine and sine for its scan.
 __device__ void store_reset(const StepParams &p, int e, uint32_t ep, const ResetPose &r,
@@ -809,7 +806,8 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
             }
             if (done) {
                 const uint32_t ep = p.st.ep[e];
-                const ResetPose r = group_sample_reset(p, M, md, e, ep, li);
+                const ResetPose r =
+                    p.pose ? given_pose(p, e) : group_sample_reset(p, M, md, e, ep, li);
                 if (li == 0) {
                     double c, sn;
                     store_reset(p, e, ep, r, c, sn);
@@ -1062,7 +1060,7 @@ __global__ __launch_bounds__(64) void plain_step_kernel(StepParams p) {
     }
     if (!do_reset) return;
     const uint32_t ep = p.st.ep[e];
-    const ResetPose r = sample_reset(p, M, md, e, ep);
+    const ResetPose r = p.pose ? given_pose(p, e) : sample_reset(p, M, md, e, ep);
     double c, sn;
     store_reset(p, e, ep, r, c, sn);
     observe_serial(p, M, md, (double)r.x, (double)r.y, c, sn, obs_row, -1);

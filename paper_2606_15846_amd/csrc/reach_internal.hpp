@@ -1,0 +1,102 @@
+// Reachability kernels of the learned reset proposal (library internal):
+// geodesic search on C-free bitsets, labelled pairs, the exact pair check,
+// proposals with the rejection sampler behind them, and the network's inputs.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace navsim {
+
+constexpr int kReachMaxWords = 2048;  // C-free bitset words per map (e.g. 256 x 256 cells)
+constexpr int kReachMaxBins = 16;
+constexpr int kReachThreads = 256;
+constexpr int kPoolCells = 1024;      // 32 x 32 pooled occupancy
+
+// One map's C-free bitset: row j, column i is bit i & 31 of word
+// j * wpr + (i >> 5); bits at i >= W are 0.
+struct ReachDesc {
+    int32_t W, H, wpr, words;
+    int64_t bit_off;   // into the bitset array
+    int64_t free_off;  // into the C-free cell list
+    int32_t free_cnt;
+    float s;           // cell size, metres
+};
+
+struct ReachParams {
+    const ReachDesc *maps;
+    const uint32_t *bits;
+    const int32_t *free_cells;
+    const int8_t *hop_bin;   // bin of each hop count 0..max_hops, -1 outside
+    const int32_t *bin_hi;   // largest hop count of each bin
+    int32_t max_hops, nbins, num_maps;
+    double gmd;              // least start-goal distance between cell centres
+    uint32_t key0, key1;     // Philox key
+};
+
+// Labelling: request i uses map map[i] and start id first_sid + i.
+hipError_t launch_label(const ReachParams &rp, int n, const int32_t *map, uint32_t first_sid,
+                        int32_t *start, int32_t *goal, int32_t *hops, hipStream_t s);
+
+// Proposals: request i (map, bin, env, episode) tries the network's `props`
+// outputs y[(i props + j) 5 ..] in order (decoded, snapped to C-free cells,
+// checked), then rejection attempts 0 .. tries - 1.
+struct ProposeArgs {
+    int n, props, tries;
+    const int32_t *map, *bin;
+    const uint32_t *env, *episode;
+    const float *y;
+    float *pose;
+    int32_t *hops, *source, *checks;
+};
+hipError_t launch_propose(const ReachParams &rp, const ProposeArgs &a, hipStream_t s);
+
+// Noise inputs: row r = i * per + j of z (bfloat16, nz columns) draws
+// Philox(c0[i], c1[i] or c1_const, (j << 8) | q, stream) words for
+// q = 0 .. ceil(nz / 4) - 1, z = 2 u - 1 with u = (w + 1/2) 2^-32.
+// row_idx[r] = map[i] * nbins + bin[i].
+struct NoiseArgs {
+    int n, per, nz, nbins, num_maps;  // row_idx = 0 for a request with map or bin out of range
+    const uint32_t *c0;  // per request (null: c0 = i)
+    const uint32_t *c1;  // per request (null: c1_const)
+    uint32_t c1_const, stream;
+    const int32_t *map, *bin;
+    uint16_t *z;
+    int32_t *row_idx;
+};
+hipError_t launch_noise(const NoiseArgs &a, uint32_t key0, uint32_t key1, hipStream_t s);
+
+// Rows [pool(map) | one-hot(bin)] of every (map, bin), bfloat16, width
+// 1024 + nbins (the constant part of the first layer's input).
+hipError_t launch_pool_rows(int num_maps, int nbins, const float *pool, uint16_t *rows,
+                            hipStream_t s);
+
+// Training batch of step t: target i draws pair (w0 P) >> 32, w = Philox(t, i,
+// 0, 10); writes its map and bin, the float targets ((a_x + 1/2) / W,
+// (a_y + 1/2) / H, 0, (b_x + 1/2) / W, (b_y + 1/2) / H).
+struct BatchArgs {
+    int batch, num_pairs, num_maps, nbins;  // a pair out of range trains as map 0, bin 0, zeros
+    uint32_t step;
+    const int32_t *pair_map, *pair_bin, *pair_start, *pair_goal;
+    const ReachDesc *maps;
+    int32_t *map, *bin;
+    float *target;
+};
+hipError_t launch_batch(const BatchArgs &a, uint32_t key0, uint32_t key1, hipStream_t s);
+
+// IMLE choice: for target i the candidate j < per with the smallest
+// sum_d w_d (y - t)^2 (first on ties); writes the training input row
+// [pool(map) | one-hot(bin) | z of that candidate].
+struct SelectArgs {
+    int batch, per, nz, nbins;
+    const float *y;        // [batch per][5]
+    const float *target;   // [batch][5]
+    const float *w;        // [5]
+    const uint16_t *z;     // [batch per][nz]
+    const int32_t *map, *bin;
+    const float *pool;     // [maps][1024]
+    uint16_t *x;           // [batch][1024 + nbins + nz]
+    int32_t *chosen;
+};
+hipError_t launch_select(const SelectArgs &a, hipStream_t s);
+
+}  // namespace navsim

@@ -1,0 +1,447 @@
+// Reachability kernels of the learned reset proposal: breadth-first search on
+// C-free bitsets staged in LDS, one workgroup per request.  Each search level
+// dilates the frontier by one 4-neighbour move with word shifts (left/right
+// within a row, carries across words) and row offsets (up/down), masks it with
+// the C-free bits and the visited set, and stops as soon as the target bit
+// appears, the frontier empties or the depth limit is reached.
+#include <limits.h>
+#include <math.h>
+
+#include "mlp_internal.hpp"
+#include "philox.hpp"
+#include "reach_internal.hpp"
+
+namespace navsim {
+namespace {
+
+constexpr double kPiR = 3.14159265358979323846;
+constexpr double kTwo32 = 4294967296.0;
+
+__device__ __forceinline__ bool cell_bit(const uint32_t *b, const ReachDesc &d, int cell) {
+    const int i = cell % d.W, j = cell / d.W;
+    return (b[j * d.wpr + (i >> 5)] >> (i & 31)) & 1u;
+}
+
+__device__ __forceinline__ void set_cell(uint32_t *b, const ReachDesc &d, int cell) {
+    const int i = cell % d.W, j = cell / d.W;
+    b[j * d.wpr + (i >> 5)] |= 1u << (i & 31);
+}
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ void stage_free(const ReachParams &rp, const ReachDesc &d, uint32_t *fb) {
+    const uint32_t *g = rp.bits + d.bit_off;
+    for (int w = threadIdx.x; w < d.words; w += blockDim.x) fb[w] = g[w];
+}
+
+// One search level: nx = (frontier moved by one step) & C-free & ~visited,
+// visited |= nx.  Returns the OR of this thread's nx words.
+__device__ uint32_t search_level(const ReachDesc &d, const uint32_t *fb, uint32_t *vis,
+                                 const uint32_t *fr, uint32_t *nx) {
+    uint32_t any = 0;
+    const int wpr = d.wpr;
+    for (int w = threadIdx.x; w < d.words; w += blockDim.x) {
+        const int c = w % wpr, r = w / wpr;
+        const uint32_t f = fr[w];
+        uint32_t g = (f << 1) | (f >> 1);
+        if (c > 0) g |= fr[w - 1] >> 31;
+        if (c + 1 < wpr) g |= fr[w + 1] << 31;
+        if (r > 0) g |= fr[w - wpr];
+        if (r + 1 < d.H) g |= fr[w + wpr];
+        const uint32_t n = g & fb[w] & ~vis[w];
+        nx[w] = n;
+        vis[w] |= n;
+        any |= n;
+    }
+    return any;
+}
+
+// Clears vis and fr and seeds both with cell a (which must be C-free).
+__device__ void search_start(const ReachDesc &d, uint32_t *vis, uint32_t *fr, int a) {
+    for (int w = threadIdx.x; w < d.words; w += blockDim.x) {
+        vis[w] = 0u;
+        fr[w] = 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        set_cell(vis, d, a);
+        set_cell(fr, d, a);
+    }
+    __syncthreads();
+}
+
+// Hop count from C-free a to b within max_hops moves, else -1 (uniform
+// across the workgroup).
+__device__ int hops_to(const ReachDesc &d, const uint32_t *fb, uint32_t *vis, uint32_t *fr,
+                       uint32_t *nx, int a, int b, int max_hops) {
+    if (a == b) return 0;
+    search_start(d, vis, fr, a);
+    for (int level = 0; level < max_hops; ++level) {
+        const uint32_t any = search_level(d, fb, vis, fr, nx);
+        const int more = __syncthreads_or(any != 0u);
+        if (cell_bit(nx, d, b)) return level + 1;
+        if (!more) return -1;
+        uint32_t *t = fr;
+        fr = nx;
+        nx = t;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ double centre_dist(const ReachDesc &d, int a, int b) {
+    const double dx = (double)(b % d.W - a % d.W) * (double)d.s;
+    const double dy = (double)(b / d.W - a / d.W) * (double)d.s;
+    return sqrt(dx * dx + dy * dy);
+}
+
+// The exact check of (a, b) for bin k: hop count when valid, else -1.
+__device__ int check_pair(const ReachParams &rp, const ReachDesc &d, const uint32_t *fb,
+                          uint32_t *vis, uint32_t *fr, uint32_t *nx, int a, int b, int k) {
+    if (a < 0 || b < 0 || !cell_bit(fb, d, a) || !cell_bit(fb, d, b)) return -1;
+    if (centre_dist(d, a, b) < rp.gmd) return -1;
+    const int h = hops_to(d, fb, vis, fr, nx, a, b, rp.bin_hi[k]);
+    return (h >= 0 && rp.hop_bin[h] == k) ? h : -1;
+}
+
+// Nearest C-free cell to c: least |di| + |dj|, then least index; -1 if none.
+__device__ int snap_cell(const ReachDesc &d, const uint32_t *fb, int c, int *s_min) {
+    if (cell_bit(fb, d, c)) return c;
+    const int i0 = c % d.W, j0 = c / d.W;
+    for (int r = 1; r <= d.W + d.H; ++r) {
+        __syncthreads();
+        if (threadIdx.x == 0) *s_min = INT_MAX;
+        __syncthreads();
+        for (int q = threadIdx.x; q < 4 * r; q += blockDim.x) {
+            const int side = q / r, t = q % r;
+            int di, dj;
+            if (side == 0) {
+                di = r - t;
+                dj = t;
+            } else if (side == 1) {
+                di = -t;
+                dj = r - t;
+            } else if (side == 2) {
+                di = t - r;
+                dj = -t;
+            } else {
+                di = t;
+                dj = t - r;
+            }
+            const int i = i0 + di, j = j0 + dj;
+            if (i >= 0 && i < d.W && j >= 0 && j < d.H && cell_bit(fb, d, j * d.W + i))
+                atomicMin(s_min, j * d.W + i);
+        }
+        __syncthreads();
+        const int m = *s_min;
+        if (m != INT_MAX) return m;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ int decode_axis(float y, int n) {
+    const double v = (double)y * (double)n;
+    if (v != v) return 0;
+    const double f = floor(v);
+    return f < 0.0 ? 0 : (f > (double)(n - 1) ? n - 1 : (int)f);
+}
+
+__device__ __forceinline__ float decode_heading(float y) {
+    double t = (double)y;
+    t = t != t ? 0.0 : (t < -1.0 ? -1.0 : (t > 1.0 ? 1.0 : t));
+    return (float)(t * kPiR);
+}
+
+__device__ __forceinline__ float cell_x(const ReachDesc &d, int c) {
+    return (float)(((double)(c % d.W) + 0.5) * (double)d.s);
+}
+
+__device__ __forceinline__ float cell_y(const ReachDesc &d, int c) {
+    return (float)(((double)(c / d.W) + 0.5) * (double)d.s);
+}
+
+__global__ __launch_bounds__(kReachThreads) void label_kernel(ReachParams rp, const int32_t *map,
+                                                              uint32_t first_sid, int32_t *start,
+                                                              int32_t *goal, int32_t *hops) {
+    extern __shared__ uint32_t lds[];
+    __shared__ unsigned long long s_best[kReachMaxBins];
+    const int i = blockIdx.x, tid = threadIdx.x;
+    const int mk = map[i];
+    const ReachDesc d = rp.maps[(mk >= 0 && mk < rp.num_maps) ? mk : 0];
+    const uint32_t sid = first_sid + (uint32_t)i;
+    if (d.free_cnt == 0 || mk < 0 || mk >= rp.num_maps) {
+        if (tid < rp.nbins) {
+            goal[(int64_t)i * rp.nbins + tid] = -1;
+            hops[(int64_t)i * rp.nbins + tid] = -1;
+        }
+        if (tid == 0) start[i] = -1;
+        return;
+    }
+    uint32_t *fb = lds, *vis = fb + kReachMaxWords, *fr = vis + kReachMaxWords,
+             *nx = fr + kReachMaxWords;
+    uint32_t c[4] = {sid, 0u, 0u, 6u};
+    philox4x32_10(c, rp.key0, rp.key1);
+    const int a = rp.free_cells[d.free_off + pick_of(c[0], d.free_cnt)];
+    stage_free(rp, d, fb);
+    if (tid < kReachMaxBins) s_best[tid] = ~0ull;
+    search_start(d, vis, fr, a);
+    for (int level = 0; level < rp.max_hops; ++level) {
+        const uint32_t any = search_level(d, fb, vis, fr, nx);
+        const int h = level + 1;
+        const int k = rp.hop_bin[h];
+        if (k >= 0 && any) {
+            unsigned long long best = ~0ull;
+            for (int w = tid; w < d.words; w += blockDim.x) {
+                uint32_t n = nx[w];
+                const int row = w / d.wpr, col0 = (w % d.wpr) * 32;
+                while (n) {
+                    const int bit = __ffs(n) - 1;
+                    n &= n - 1u;
+                    const int cell = row * d.W + col0 + bit;
+                    if (centre_dist(d, a, cell) < rp.gmd) continue;
+                    uint32_t q[4] = {sid, (uint32_t)cell, 0u, 5u};
+                    philox4x32_10(q, rp.key0, rp.key1);
+                    const unsigned long long v = ((unsigned long long)q[0] << 32) |
+                                                 ((unsigned long long)cell << 16) |
+                                                 (unsigned long long)h;
+                    best = v < best ? v : best;
+                }
+            }
+            if (best != ~0ull) atomicMin(&s_best[k], best);
+        }
+        if (!__syncthreads_or(any != 0u)) break;
+        uint32_t *t = fr;
+        fr = nx;
+        nx = t;
+    }
+    __syncthreads();
+    if (tid < rp.nbins) {
+        const unsigned long long v = s_best[tid];
+        goal[(int64_t)i * rp.nbins + tid] = v == ~0ull ? -1 : (int32_t)((v >> 16) & 0xffffu);
+        hops[(int64_t)i * rp.nbins + tid] = v == ~0ull ? -1 : (int32_t)(v & 0xffffu);
+    }
+    if (tid == 0) start[i] = a;
+}
+
+__global__ __launch_bounds__(kReachThreads) void propose_kernel(ReachParams rp, ProposeArgs pa) {
+    extern __shared__ uint32_t lds[];
+    __shared__ int s_min;
+    const int i = blockIdx.x, tid = threadIdx.x;
+    const int mk = pa.map[i], k = pa.bin[i];
+    if (mk < 0 || mk >= rp.num_maps || k < 0 || k >= rp.nbins) {  // rejected request
+        if (tid < 5) pa.pose[(int64_t)i * 5 + tid] = 0.0f;
+        if (tid == 0) {
+            pa.hops[i] = -1;
+            pa.source[i] = -1;
+            pa.checks[i] = 0;
+        }
+        return;
+    }
+    const ReachDesc d = rp.maps[mk];
+    uint32_t *fb = lds, *vis = fb + kReachMaxWords, *fr = vis + kReachMaxWords,
+             *nx = fr + kReachMaxWords;
+    stage_free(rp, d, fb);
+    __syncthreads();
+    int checks = 0, src = -1, ra = -1, rb = -1, rh = -1;
+    float th = 0.0f;
+    for (int j = 0; j < pa.props && src < 0; ++j) {
+        const float *y = pa.y + ((int64_t)i * pa.props + j) * 5;
+        const int a0 = decode_axis(y[1], d.H) * d.W + decode_axis(y[0], d.W);
+        const int b0 = decode_axis(y[4], d.H) * d.W + decode_axis(y[3], d.W);
+        const int a = snap_cell(d, fb, a0, &s_min);
+        const int b = snap_cell(d, fb, b0, &s_min);
+        ++checks;
+        const int h = check_pair(rp, d, fb, vis, fr, nx, a, b, k);
+        if (h >= 0) {
+            src = j;
+            ra = a;
+            rb = b;
+            rh = h;
+            th = decode_heading(y[2]);
+        }
+    }
+    for (int t = 0; t < pa.tries && src < 0 && d.free_cnt > 0; ++t) {
+        uint32_t c[4] = {pa.env[i], pa.episode[i], (uint32_t)t, 7u};
+        philox4x32_10(c, rp.key0, rp.key1);
+        const int a = rp.free_cells[d.free_off + pick_of(c[0], d.free_cnt)];
+        const int b = rp.free_cells[d.free_off + pick_of(c[1], d.free_cnt)];
+        ++checks;
+        const int h = check_pair(rp, d, fb, vis, fr, nx, a, b, k);
+        ra = a;
+        rb = b;
+        th = (float)((((double)c[2] + 0.5) / kTwo32) * (2.0 * kPiR) - kPiR);
+        if (h >= 0) {
+            src = pa.props + t;
+            rh = h;
+        }
+    }
+    if (tid == 0) {
+        float *p = pa.pose + (int64_t)i * 5;
+        p[0] = ra >= 0 ? cell_x(d, ra) : 0.0f;
+        p[1] = ra >= 0 ? cell_y(d, ra) : 0.0f;
+        p[2] = th;
+        p[3] = rb >= 0 ? cell_x(d, rb) : 0.0f;
+        p[4] = rb >= 0 ? cell_y(d, rb) : 0.0f;
+        pa.hops[i] = rh;
+        pa.source[i] = src;
+        pa.checks[i] = checks;
+    }
+}
+
+__global__ void noise_kernel(NoiseArgs a, uint32_t key0, uint32_t key1) {
+    const int nq = (a.nz + 3) / 4;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t rows = (int64_t)a.n * a.per;
+    if (idx >= rows * nq) return;
+    const int64_t r = idx / nq;
+    const int q = (int)(idx % nq);
+    const int i = (int)(r / a.per), j = (int)(r % a.per);
+    uint32_t c[4] = {a.c0 ? a.c0[i] : (uint32_t)i, a.c1 ? a.c1[i] : a.c1_const,
+                     ((uint32_t)j << 8) | (uint32_t)q, a.stream};
+    philox4x32_10(c, key0, key1);
+    for (int t = 0; t < 4; ++t) {
+        const int col = 4 * q + t;
+        if (col < a.nz) {
+            const double u = ((double)c[t] + 0.5) / kTwo32;
+            a.z[r * a.nz + col] = bf16_bits((float)(2.0 * u - 1.0));
+        }
+    }
+    if (q == 0 && a.row_idx) {
+        const int m = a.map[i], b = a.bin[i];
+        a.row_idx[r] = (m >= 0 && m < a.num_maps && b >= 0 && b < a.nbins) ? m * a.nbins + b : 0;
+    }
+}
+
+__global__ void pool_rows_kernel(int num_maps, int nbins, const float *pool, uint16_t *rows) {
+    const int width = kPoolCells + nbins;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)num_maps * nbins * width) return;
+    const int64_t row = idx / width;
+    const int col = (int)(idx % width);
+    const int m = (int)(row / nbins), b = (int)(row % nbins);
+    const float v = col < kPoolCells ? pool[(int64_t)m * kPoolCells + col]
+                                     : (col - kPoolCells == b ? 1.0f : 0.0f);
+    rows[idx] = bf16_bits(v);
+}
+
+__global__ void batch_kernel(BatchArgs a, uint32_t key0, uint32_t key1) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.batch) return;
+    uint32_t c[4] = {a.step, (uint32_t)i, 0u, 10u};
+    philox4x32_10(c, key0, key1);
+    const int p = pick_of(c[0], a.num_pairs);
+    int m = a.pair_map[p], b = a.pair_bin[p];
+    const bool ok_mb = m >= 0 && m < a.num_maps && b >= 0 && b < a.nbins;
+    const ReachDesc d = a.maps[ok_mb ? m : 0];
+    int s = a.pair_start[p], g = a.pair_goal[p];
+    const int cells = d.W * d.H;
+    float *t = a.target + (int64_t)i * 5;
+    if (!ok_mb || s < 0 || s >= cells || g < 0 || g >= cells) {
+        a.map[i] = 0;
+        a.bin[i] = 0;
+        for (int q = 0; q < 5; ++q) t[q] = 0.0f;
+        return;
+    }
+    a.map[i] = m;
+    a.bin[i] = b;
+    t[0] = (float)(((double)(s % d.W) + 0.5) / (double)d.W);
+    t[1] = (float)(((double)(s / d.W) + 0.5) / (double)d.H);
+    t[2] = 0.0f;
+    t[3] = (float)(((double)(g % d.W) + 0.5) / (double)d.W);
+    t[4] = (float)(((double)(g / d.W) + 0.5) / (double)d.H);
+}
+
+__global__ __launch_bounds__(256) void select_kernel(SelectArgs a) {
+    __shared__ int s_j;
+    const int i = blockIdx.x, tid = threadIdx.x;
+    if (tid == 0) {
+        const float *t = a.target + (int64_t)i * 5;
+        int bj = 0;
+        float bd = 0.0f;
+        for (int j = 0; j < a.per; ++j) {
+            const float *y = a.y + ((int64_t)i * a.per + j) * 5;
+            float dsum = 0.0f;
+            for (int q = 0; q < 5; ++q) {
+                const float e = y[q] - t[q];
+                dsum += a.w[q] * (e * e);
+            }
+            if (j == 0 || dsum < bd) {
+                bd = dsum;
+                bj = j;
+            }
+        }
+        s_j = bj;
+        if (a.chosen) a.chosen[i] = bj;
+    }
+    __syncthreads();
+    const int j = s_j;
+    const int width = kPoolCells + a.nbins + a.nz;
+    const int m = a.map[i], b = a.bin[i];
+    uint16_t *x = a.x + (int64_t)i * width;
+    const uint16_t *z = a.z + ((int64_t)i * a.per + j) * a.nz;
+    for (int col = tid; col < width; col += blockDim.x) {
+        uint16_t v;
+        if (col < kPoolCells)
+            v = bf16_bits(a.pool[(int64_t)m * kPoolCells + col]);
+        else if (col < kPoolCells + a.nbins)
+            v = bf16_bits(col - kPoolCells == b ? 1.0f : 0.0f);
+        else
+            v = z[col - kPoolCells - a.nbins];
+        x[col] = v;
+    }
+}
+
+unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+constexpr size_t kSearchLds = 4u * kReachMaxWords * sizeof(uint32_t);
+
+}  // namespace
+
+hipError_t launch_label(const ReachParams &rp, int n, const int32_t *map, uint32_t first_sid,
+                        int32_t *start, int32_t *goal, int32_t *hops, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(label_kernel, dim3((unsigned)n), dim3(kReachThreads), kSearchLds, s, rp,
+                       map, first_sid, start, goal, hops);
+    return hipGetLastError();
+}
+
+hipError_t launch_propose(const ReachParams &rp, const ProposeArgs &a, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(propose_kernel, dim3((unsigned)a.n), dim3(kReachThreads), kSearchLds, s,
+                       rp, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise(const NoiseArgs &a, uint32_t key0, uint32_t key1, hipStream_t s) {
+    const int64_t total = (int64_t)a.n * a.per * ((a.nz + 3) / 4);
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(noise_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, a, key0, key1);
+    return hipGetLastError();
+}
+
+hipError_t launch_pool_rows(int num_maps, int nbins, const float *pool, uint16_t *rows,
+                            hipStream_t s) {
+    const int64_t total = (int64_t)num_maps * nbins * (kPoolCells + nbins);
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pool_rows_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, num_maps,
+                       nbins, pool, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs &a, uint32_t key0, uint32_t key1, hipStream_t s) {
+    if (a.batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_kernel, dim3(nblocks(a.batch, 256)), dim3(256), 0, s, a, key0, key1);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const SelectArgs &a, hipStream_t s) {
+    if (a.batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(select_kernel, dim3((unsigned)a.batch), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace navsim

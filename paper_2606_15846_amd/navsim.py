@@ -24,7 +24,8 @@ NAVSIM_ROLLOUT_GRAPH = 1
 STATUS = {0: "NAVSIM_OK", -1: "NAVSIM_E_INVALID_ARG", -2: "NAVSIM_E_BAD_HANDLE",
           -3: "NAVSIM_E_STATE", -4: "NAVSIM_E_NO_FREE_SPACE", -5: "NAVSIM_E_OOM",
           -6: "NAVSIM_E_HIP", -7: "NAVSIM_E_UNSUPPORTED"}
-EXPORTS = ("navsim_create", "navsim_load_maps", "navsim_load_maps_ex", "navsim_reset", "navsim_step",
+EXPORTS = ("navsim_create", "navsim_load_maps", "navsim_load_maps_ex", "navsim_reset",
+           "navsim_reset_to", "navsim_step",
            "navsim_step_plain", "navsim_step_debug", "navsim_rollout", "navsim_set_tuning",
            "navsim_get_tuning",
            "navsim_get_state", "navsim_set_state", "navsim_destroy", "navsim_last_error")
@@ -82,6 +83,7 @@ def load_library(path: str = LIB_PATH):
     L.navsim_load_maps.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.navsim_load_maps_ex.argtypes = [vp, i32, vp, vp, vp, vp, vp, C.POINTER(NavsimMapProfile)]
     L.navsim_reset.argtypes = [vp, vp, vp, vp]
+    L.navsim_reset_to.argtypes = [vp, vp, vp, vp, vp]
     L.navsim_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.navsim_step_plain.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.navsim_step_debug.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(NavsimDebug), i32, vp]
@@ -305,6 +307,18 @@ class NavSim:
         if mask is not None:
             _dev_ptr(mask, torch.uint8, (self.N,), self.device, "mask")
         navsim_reset(self.h, mask, self.obs)
+        return self.obs
+
+    def reset_to(self, pose, mask=None):
+        """Reset the masked envs (all when mask is None) to the rows of pose
+        (device float32 [N, 5]: x, y, heading, goal x, goal y)."""
+        _dev_ptr(pose, torch.float32, (self.N, 5), self.device, "pose")
+        if mask is not None:
+            _dev_ptr(mask, torch.uint8, (self.N,), self.device, "mask")
+        _check(load_library().navsim_reset_to(
+            self.h, None if mask is None else C.c_void_p(mask.data_ptr()),
+            C.c_void_p(pose.data_ptr()), C.c_void_p(self.obs.data_ptr()),
+            _stream_ptr(None, self.device)))
         return self.obs
 
     def step(self, act, plain: bool = False):

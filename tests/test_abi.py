@@ -16,18 +16,23 @@ HEADER = os.path.join(ROOT, "include", "navsim.h")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:navsim_status|const char \*)\s*(navsim_\w+)\s*\(", text,
-                                 re.M)))
+    names = set()
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if hdr.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", hdr)).read()
+            names |= set(re.findall(r"^\s*(?:navsim_status|const char \*)\s*(navsim_\w+)\s*\(",
+                                    text, re.M))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_function():
     lib = navsim.load_library()
     names = declared_functions()
-    assert len(names) == 14
+    assert len(names) == 26
     for n in names:
         assert hasattr(lib, n), n
-    assert sorted(navsim.EXPORTS) == names
+    from paper_2606_15846_amd import reset_proposal
+    assert sorted(navsim.EXPORTS + reset_proposal.EXPORTS) == names
 
 
 def test_struct_layout_matches_header(tmp_path):
@@ -81,6 +86,8 @@ def test_config_validation_before_any_device_call(bad):
 
 def test_abi_version_and_null_arguments():
     lib = navsim.load_library()
+    from paper_2606_15846_amd import reset_proposal
+    reset_proposal._lib()  # argument types of the proposer's entry points
     c = navsim.make_config(_cfg())
     c.abi_version = 99
     h = C.c_void_p()
@@ -96,7 +103,21 @@ def test_abi_version_and_null_arguments():
                      ("navsim_load_maps", (None, 1, None, None, None, None, None)),
                      ("navsim_load_maps_ex", (None, 1, None, None, None, None, None, None)),
                      ("navsim_rollout", (None, 4, 0, None, None, None, None, None, None, 0, 1,
-                                         None))]:
+                                         None)),
+                     ("navsim_reset_to", (None, None, None, None, None)),
+                     ("navsim_rp_create", (None, None, C.byref(C.c_void_p()))),
+                     ("navsim_rp_label", (None, 0, None, 0, None, None, None, None)),
+                     ("navsim_rp_train", (None, 1, None, None, None, None, 1, 1, 1, 1e-3, 0.0,
+                                          None, None)),
+                     ("navsim_rp_propose", (None, 1, None, None, None, None, 0, 1, None, None,
+                                            None, None, None, None)),
+                     ("navsim_rp_forward", (None, 0, None, None, None)),
+                     ("navsim_rp_loss_grad", (None, 1, None, None, None, None, None)),
+                     ("navsim_rp_adamw", (None, None, 1e-3, 0.0, None)),
+                     ("navsim_rp_layout", (None, None, None, None, None)),
+                     ("navsim_rp_get_params", (None, None, 0)),
+                     ("navsim_rp_set_params", (None, None, 0)),
+                     ("navsim_rp_destroy", (None,))]:
         assert getattr(lib, fn)(*args) == -2, fn
 
 

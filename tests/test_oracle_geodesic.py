@@ -170,3 +170,50 @@ def test_decode_proposal_closed_forms():
     assert th == np.float32(0.5 * math.pi)
     a, b, th = G.decode_proposal(W, H, [float("nan"), 0.26, 2.0, 0.1, float("nan")])
     assert a == 7 * W + 0 and b == 0 * W + 4 and th == np.float32(math.pi)
+
+
+def test_snap_cell_closed_forms():
+    cf = np.ones((10, 12), np.uint8)
+    R = G.ReachMap(cf, 0.1, seed=1, d_lo=0.2, d_hi=1.0, nbins=2, gmd=0.1)
+    assert all(R.snap(c) == c for c in range(120))
+    cf = np.zeros((10, 12), np.uint8)
+    cf[7, 3] = 1
+    R = G.ReachMap(cf, 0.1, seed=1, d_lo=0.2, d_hi=1.0, nbins=2, gmd=0.1)
+    assert all(R.snap(c) == 7 * 12 + 3 for c in range(120))
+    # two free cells at L1 distance 2 from (5, 5): (5, 3) and (7, 5); the
+    # smaller index wins the tie
+    cf = np.zeros((10, 12), np.uint8)
+    cf[3, 5] = 1
+    cf[5, 7] = 1
+    R = G.ReachMap(cf, 0.1, seed=1, d_lo=0.2, d_hi=1.0, nbins=2, gmd=0.1)
+    assert R.snap(5 * 12 + 5) == 3 * 12 + 5
+    assert R.snap(5 * 12 + 6) == 5 * 12 + 7  # distance 1 beats distance 3
+    assert G.ReachMap(np.zeros((4, 4), np.uint8), 0.1, seed=1).snap(5) == -1
+
+
+def test_reset_to_reproduces_a_sampled_reset():
+    # resetting to the pose a sampled reset chose gives that reset's state and
+    # observation (the same observation, without the sampling)
+    from workloads import configs, maps as gm
+    occ = gm.gen_rect_disc_map(3, w=80, h=64, res=0.05)
+    cfg = configs.make_config(num_envs=12, num_beams=60, num_sectors=6, fov_rad=6.283185307,
+                              max_range_m=3.0, dt_s=0.1, footprint=0, radius_m=0.18,
+                              v_min=0.0, v_max=0.5, w_min=-1.0, w_max=1.0)
+    a = oracle.OracleSim(cfg, [occ], [0.05], np.zeros(12, np.int32))
+    obs_a, _ = a.reset()
+    st = a.get_state()
+    pose = np.stack([st["x"], st["y"], st["th"], st["gx"], st["gy"]], 1)
+    b = oracle.OracleSim(cfg, [occ], [0.05], np.zeros(12, np.int32))
+    b.reset()
+    b.state["ep"][:] = 0
+    obs_b = b.reset_to(pose)
+    for k in oracle.STATE_KEYS:
+        assert np.array_equal(a.state[k], b.state[k]), k
+    assert np.array_equal(obs_a, obs_b)
+    # masked: untouched rows keep their state
+    keep = b.get_state()
+    mask = (np.arange(12) % 3 == 0).astype(np.uint8)
+    b.reset_to(np.zeros((12, 5), np.float32) + 0.5, mask)
+    for k in oracle.STATE_KEYS:
+        assert np.array_equal(b.state[k][mask == 0], keep[k][mask == 0]), k
+    assert (b.state["x"][mask == 1] == np.float32(0.5)).all()

@@ -109,6 +109,18 @@ WORKLOADS = {
                steps=64,
                name="32768 envs, 128 maps U{96..512}^2 @0.05 m, per-map K in "
                     "{180,360,720,1080} and disc/rect footprint, r_max 8 m"),
+    # 65536 envs over 64 maps 256x256 at 0.05 m (rooms and corridors with disc
+    # clutter), disc r 0.18 m, 360 beams -> 30 sectors, r_max 6 m; resets at a
+    # requested geodesic difficulty (8 bins over 1-12 m) by the learned proposal.
+    "c5": dict(cfg=dict(num_envs=65536, num_beams=360, num_sectors=30, fov_rad=2 * math.pi,
+                        max_range_m=6.0, dt_s=0.1, footprint=FOOTPRINT_DISC, radius_m=0.18,
+                        v_min=0.0, v_max=0.5, w_min=-1.0, w_max=1.0),
+               maps=dict(kind="rooms", count=64, w=256, h=256, res=0.05, seed0=3000),
+               proposer=dict(num_bins=8, d_lo_m=1.0, d_hi_m=12.0, noise_dim=16, hidden=256,
+                             hidden_layers=3, leaky_slope=0.01, seed=0xC0FFEE),
+               steps=200,
+               name="65536 envs, 64 rooms maps 256x256 @0.05 m, disc r 0.18 m, 360 beams, "
+                    "difficulty resets (8 bins, 1-12 m)"),
 }
 
 
@@ -135,7 +147,7 @@ def build_maps(spec: dict) -> tuple[list[np.ndarray], list[float]]:
         return occ, [res] * count
     out = []
     for k in range(count):
-        seed = 1000 + k
+        seed = spec.get("seed0", 1000) + k
         if kind == "rect":
             out.append(_maps.gen_rect_map(seed, w=spec["w"], h=spec["h"]))
         elif kind == "rect_disc":
@@ -170,4 +182,4 @@ def build_workload(name: str, num_envs: int | None = None) -> dict:
     env_map = contiguous_env_map(cfg["num_envs"], len(occ))
     profiles = build_profiles(spec["profiles"], len(occ)) if "profiles" in spec else None
     return dict(cfg=cfg, maps=occ, res=res, env_map=env_map, steps=spec["steps"],
-                name=spec["name"], profiles=profiles)
+                name=spec["name"], profiles=profiles, proposer=spec.get("proposer"))
