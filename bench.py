@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--plain-steps", type=int, default=50)
     ap.add_argument("--rollout-steps", type=int, default=64)
+    ap.add_argument("--no-march", action="store_true")
+    ap.add_argument("--march-step", type=float, default=0.03)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--tile-envs", type=int, default=None)
@@ -165,6 +167,28 @@ def main():
     achieved = lds_bytes_per_launch / avg_launch_s / 1e9
     traffic = hbm_traffic_from_profile()
 
+    # the paper's fixed-step range query (0.03 m) on the same fused step
+    march = None
+    if not args.no_march:
+        sim.set_state(start_state)
+        sim.set_scan(1, args.march_step)
+        for t in range(5):
+            sim.step(acts[args.warmup + t])
+        sim.set_state(start_state)
+        torch.cuda.synchronize()
+        m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        msteps = min(args.steps, 200)
+        m0.record(stream)
+        for t in range(msteps):
+            sim.step(acts[args.warmup + t])
+        m1.record(stream)
+        torch.cuda.synchronize()
+        mms = m0.elapsed_time(m1) / msteps
+        march = {"value": N / (mms / 1e3), "unit": "env-steps/s", "ms_per_step": mms,
+                 "steps": msteps, "step_m": args.march_step,
+                 "traversal_speedup": mms / ms_per_step}
+        sim.set_scan(0, 0.03)
+
     # device rollouts: the same fused step under in-kernel actions, T steps
     # captured once as a HIP graph and replayed
     sim.set_state(start_state)
@@ -227,6 +251,7 @@ def main():
                                  else "disc" if cfg["footprint"] == 0 else "rect")},
         "rays_per_s": value * rays_per_step / N,
         "graph_rollout": rollout,
+        "march_scan": march,
         "plain": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "tuning": sim_tuning,

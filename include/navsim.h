@@ -222,6 +222,18 @@ navsim_status navsim_rollout(navsim_t h, int32_t steps, uint64_t first_step, flo
                              float *obs, float *reward, uint8_t *terminated, uint8_t *truncated,
                              float *final_obs, int32_t kernel, int32_t flags, void *hip_stream);
 
+/* Range query of both step mappings.  NAVSIM_SCAN_TRAVERSAL (default): the
+ * exact first occupied or out-of-bounds cell along each beam (integer grid
+ * traversal), range = its entry distance.  NAVSIM_SCAN_MARCH: the paper's
+ * fixed-step query (section 2.2.2, table 7: 0.03 m): samples at tau = k step_m,
+ * k = 0, 1, ... while tau <= r_max; the first sample whose cell floor(p / s)
+ * (double precision) is occupied or outside the map ends the beam at
+ * range = tau, else range = r_max; visits = samples evaluated.  It can step
+ * over a cell the beam only clips.  Errors: INVALID_ARG (unknown mode,
+ * step_m <= 0, r_max / step_m > 2^20).  Drops a captured rollout graph. */
+enum { NAVSIM_SCAN_TRAVERSAL = 0, NAVSIM_SCAN_MARCH = 1 };
+navsim_status navsim_set_scan(navsim_t h, int32_t mode, float step_m);
+
 /* Launch shape of the fused step.  Results never depend on it (bitwise); it
  * only moves work between lanes, wavefronts and workgroups. */
 typedef struct {

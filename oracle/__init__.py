@@ -39,6 +39,7 @@ class OrcCfg(C.Structure):
         ("goal_min_dist_m", C.c_float),
         ("reset_max_tries", C.c_int32),
         ("seed", C.c_uint64),
+        ("scan_mode", C.c_int32), ("march_step_m", C.c_float),
     ]
 
 
@@ -106,7 +107,8 @@ def lib():
     L.orc_cast.argtypes = [P(OrcMaps), C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                            C.c_double, C.c_double, P(OrcRay)]
     L.orc_march.argtypes = [P(OrcMaps), C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
-                            C.c_double, C.c_double, P(C.c_double), P(C.c_int32)]
+                            C.c_double, C.c_double, P(C.c_double), P(C.c_int32), P(C.c_int32),
+                            P(C.c_double)]
     L.orc_cfg_for_map.argtypes = [P(OrcCfg), P(OrcMaps), C.c_int, P(OrcCfg)]
     L.orc_reset_to.argtypes = [P(OrcCfg), P(OrcMaps), P(OrcState), P(C.c_uint8), P(C.c_float),
                                P(C.c_float), C.c_int64, C.c_int64]
@@ -137,10 +139,16 @@ def philox4x32_10(ctr, key) -> tuple:
     return tuple(int(v) for v in o)
 
 
+_CFG_DEFAULTS = dict(scan_mode=0, march_step_m=0.03)
+
+
 def make_cfg(cfg: dict) -> OrcCfg:
+    """scan_mode (0 traversal, 1 fixed-step march) and march_step_m default to
+    0 and 0.03 m (table 7) when the dict does not give them."""
     c = OrcCfg()
     for name, _ in OrcCfg._fields_:
-        setattr(c, name, cfg[name])
+        setattr(c, name, cfg.get(name, _CFG_DEFAULTS.get(name)) if name in _CFG_DEFAULTS
+                else cfg[name])
     return c
 
 
@@ -219,8 +227,10 @@ class OracleMaps:
     def march(self, k, ox, oy, dx, dy, rmax, h):
         rg = C.c_double()
         hit = C.c_int32()
+        ns = C.c_int32()
+        nr = C.c_double()
         lib().orc_march(C.byref(self.struct), k, float(ox), float(oy), float(dx), float(dy),
-                        float(rmax), float(h), C.byref(rg), C.byref(hit))
+                        float(rmax), float(h), C.byref(rg), C.byref(hit), C.byref(ns), C.byref(nr))
         return rg.value, hit.value
 
 

@@ -43,6 +43,8 @@ typedef struct {
     float goal_min_dist_m;
     int32_t reset_max_tries;
     uint64_t seed;
+    int32_t scan_mode;  /* 0 exact grid traversal, 1 fixed-step march */
+    float march_step_m; /* the march's sample spacing h */
 } orc_cfg;
 
 typedef struct {
@@ -330,32 +332,44 @@ void orc_cast(const orc_maps *M, int map, double ox, double oy, double dx, doubl
 /* The paper's own range query (section 2.2.2, table 7): sample the ray at a
  * fixed spacing h, tau_j = j h for j = 0, 1, ..., until the sample's cell is
  * occupied or out of bounds (range = tau_j) or tau_j exceeds r_max (range =
- * r_max).  Sampling can step over the corner of a cell the ray only clips. */
+ * r_max).  Sampling can step over the corner of a cell the ray only clips.
+ * Optional: *samples = samples evaluated, *near = least distance (in cells)
+ * of an evaluated sample's coordinate to a grid line. */
 void orc_march(const orc_maps *M, int map, double ox, double oy, double dx, double dy,
-               double rmax, double h, double *range, int32_t *hit)
+               double rmax, double h, double *range, int32_t *hit, int32_t *samples,
+               double *near)
 {
     int64_t W = M->w[map], H = M->h[map];
     double s = (double)M->res[map];
+    double nr = 1.0;
     for (int64_t k = 0;; ++k) {
         double tau = (double)k * h;
         if (tau > rmax) {
             *range = rmax;
             *hit = -1;
-            return;
+            if (samples) *samples = (int32_t)k;
+            break;
         }
         double px = ox + tau * dx, py = oy + tau * dy;
-        int64_t i = (int64_t)floor(px / s), j = (int64_t)floor(py / s);
+        double fx = px / s, fy = py / s;
+        double gx = fabs(fx - nearbyint(fx)), gy = fabs(fy - nearbyint(fy));
+        nr = gx < nr ? gx : nr;
+        nr = gy < nr ? gy : nr;
+        int64_t i = (int64_t)floor(fx), j = (int64_t)floor(fy);
         if (i < 0 || j < 0 || i >= W || j >= H) {
             *range = tau;
             *hit = -2;
-            return;
+            if (samples) *samples = (int32_t)(k + 1);
+            break;
         }
         if (M->occ[M->off[map] + j * W + i]) {
             *range = tau;
             *hit = (int32_t)(j * W + i);
-            return;
+            if (samples) *samples = (int32_t)(k + 1);
+            break;
         }
     }
+    if (near) *near = nr;
 }
 
 /* Beam k's angle relative to the heading.  The paper only says the beams are
@@ -378,6 +392,18 @@ void orc_scan(const orc_maps *M, int map, const orc_cfg *cfg, double x, double y
     double rmax = (double)cfg->max_range_m;
     for (int k = 0; k < cfg->num_beams; ++k) {
         double psi = th + orc_beam_angle(cfg, k);
+        if (cfg->scan_mode == 1) {
+            /* grazing: a sample within 1e-9 cells of a grid line */
+            double rg, nr;
+            int32_t hit, ns;
+            orc_march(M, map, x, y, cos(psi), sin(psi), rmax, (double)cfg->march_step_m, &rg,
+                      &hit, &ns, &nr);
+            if (ranges) ranges[k] = (float)rg;
+            if (hits) hits[k] = hit;
+            if (grazing) grazing[k] = (uint8_t)(nr < 1e-9);
+            if (visits) visits[k] = ns;
+            continue;
+        }
         orc_ray r;
         orc_cast(M, map, x, y, cos(psi), sin(psi), rmax, 1e-6, &r);
         if (ranges) ranges[k] = (float)r.range;

@@ -176,6 +176,9 @@ StepParams make_params(const navsim_s *h) {
     p.groups = h->groups;
     p.ray_cap = h->ray_cap;
     p.beams_lds = h->beams_lds ? 1 : 0;
+    p.scan_mode = h->scan_mode;
+    p.march_kmax = h->march_kmax;
+    p.march_h = h->march_h;
     return p;
 }
 
@@ -650,6 +653,31 @@ navsim_status navsim_rollout(navsim_t h, int32_t steps, uint64_t first_step, flo
     if (!(flags & NAVSIM_ROLLOUT_GRAPH)) return launch_steps(h, p, steps, kernel, s);
     e = hipGraphLaunch(h->graph, s);
     if (e != hipSuccess) return fail(NAVSIM_E_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+    return NAVSIM_OK;
+}
+
+navsim_status navsim_set_scan(navsim_t h, int32_t mode, float step_m) {
+    if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
+    if (mode != NAVSIM_SCAN_TRAVERSAL && mode != NAVSIM_SCAN_MARCH)
+        return fail(NAVSIM_E_INVALID_ARG, "unknown scan mode %d", mode);
+    int kmax = 0;
+    if (mode == NAVSIM_SCAN_MARCH) {
+        if (!finite_pos(step_m)) return fail(NAVSIM_E_INVALID_ARG, "step_m must be > 0");
+        const double hh = (double)step_m, rmax = (double)h->cfg.max_range_m;
+        const double q = floor(rmax / hh);
+        if (q > (double)(1 << 20))
+            return fail(NAVSIM_E_INVALID_ARG, "max_range_m / step_m must be <= 2^20");
+        kmax = (int)q;
+        while ((double)(kmax + 1) * hh <= rmax) ++kmax;
+        while (kmax > 0 && (double)kmax * hh > rmax) --kmax;
+    }
+    {
+        DeviceGuard g(h->device);
+        drop_graph(h);
+    }
+    h->scan_mode = mode;
+    h->march_h = mode == NAVSIM_SCAN_MARCH ? (double)step_m : 0.0;
+    h->march_kmax = kmax;
     return NAVSIM_OK;
 }
 

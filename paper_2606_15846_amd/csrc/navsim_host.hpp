@@ -60,6 +60,9 @@ struct navsim_s {
     int tile_envs = navsim::kDefaultTileEnvs, refill_at = navsim::kDefaultRefillAt, groups = navsim::kDefaultGroups;
     int ray_cap = 0;
     bool beams_lds = true;
+    int scan_mode = 0;       // 0 exact traversal, 1 fixed-step march
+    int march_kmax = 0;
+    double march_h = 0.03;
     std::vector<int32_t> host_env_map;  // kept to rebuild the tiles when tile_envs changes
     // host copies of the loaded maps (reset proposals build their own tables)
     std::vector<uint8_t> host_occ;

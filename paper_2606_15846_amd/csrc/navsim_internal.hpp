@@ -55,6 +55,9 @@ struct StepParams {
     int32_t refill_at, groups;  // fused walk: refill threshold, 4-cell groups per check
     int32_t ray_cap;            // rays walked per chunk (LDS slots)
     int32_t beams_lds;          // stage the beam table in LDS
+    int32_t scan_mode;          // 0 exact traversal, 1 fixed-step march
+    int32_t march_kmax;         // march: last sample index with k h <= r_max
+    double march_h;             // march: sample spacing, metres
     float rmax, dt, goal_r, c1, r_succ, r_coll;
     float vlo, vhi, wlo, whi, gmd;
     uint32_t key0, key1;

@@ -320,6 +320,56 @@ __device__ __forceinline__ void cast_ray(const MapView &M, const RayOrigin &o, d
     }
 }
 
+// Fixed-step march (the paper's range query, section 2.2.2, table 7): sample
+// k at tau = k h, k = 0 .. march_kmax; returns 0 when the sample's cell is
+// free, 1 occupied (cell id in *cell), 2 outside the map.  Cells come from
+// floor(p / s) in double precision.
+__device__ __forceinline__ int march_sample(const MapView &M, double x, double y, double dx,
+                                            double dy, double h, int k, int *cell) {
+    const double tau = (double)k * h;
+    const double px = x + tau * dx, py = y + tau * dy;
+    const double fi = floor(px / M.s), fj = floor(py / M.s);
+    if (fi < 0.0 || fj < 0.0 || fi >= (double)M.w || fj >= (double)M.h) return 2;
+    const int i = (int)fi, j = (int)fj;
+    *cell = j * M.w + i;
+    const int b = (j + kPad) * M.pitch + (i + kPad);
+    return (int)((M.bits[b >> 5] >> (b & 31)) & 1u);
+}
+
+// Range, hit id and samples of a march that ended at sample k with outcome
+// `type` (0: no hit up to k = march_kmax).
+__device__ __forceinline__ void march_result(const StepParams &p, const MapView &M, double x,
+                                             double y, double dx, double dy, int k, int type,
+                                             float &range, int &hit, int &samples) {
+    if (type == 0) {
+        range = p.rmax;
+        hit = -1;
+        samples = p.march_kmax + 1;
+        return;
+    }
+    range = (float)((double)k * p.march_h);
+    samples = k + 1;
+    if (type == 2) {
+        hit = -2;
+    } else {
+        int cell = -1;
+        (void)march_sample(M, x, y, dx, dy, p.march_h, k, &cell);
+        hit = cell;
+    }
+}
+
+__device__ __forceinline__ void march_ray(const StepParams &p, const MapView &M, double x,
+                                          double y, double dx, double dy, float &range, int &hit,
+                                          int &samples) {
+    int k = 0, type = 0, cell = -1;
+    for (; k <= p.march_kmax; ++k) {
+        type = march_sample(M, x, y, dx, dy, p.march_h, k, &cell);
+        if (type) break;
+    }
+    if (!type) k = p.march_kmax;
+    march_result(p, M, x, y, dx, dy, k, type, range, hit, samples);
+}
+
 // ---------------------------------------------------------------------------
 // Per-env scalar pieces (section 2.2.3; eq. 1, eq. 3).
 struct Motion {
@@ -714,6 +764,100 @@ __device__ __forceinline__ void finish_ray(const StepParams &p, const MapView &M
     }
 }
 
+// finish_ray for the fixed-step march: res.x = k | outcome << 28.
+__device__ __forceinline__ void finish_march(const StepParams &p, const MapView &M,
+                                             const TileJob &j, const double2 *s_beam, int job,
+                                             int beam, uint32_t res, uint32_t *s_pool, int per,
+                                             float inv_per, int E) {
+    const double2 cs = s_beam[beam];
+    const double dx = j.c * cs.x - j.s * cs.y;
+    const double dy = j.s * cs.x + j.c * cs.y;
+    float rg;
+    int hit, vis;
+    march_result(p, M, j.x, j.y, dx, dy, (int)(res & 0x0FFFFFFFu), (int)(res >> 28), rg, hit, vis);
+    atomicMin(&s_pool[job * p.m + small_div(beam, per, inv_per)], __float_as_uint(rg));
+    if (job < E) {
+        const int64_t o = (int64_t)j.env * p.K + beam;
+        if (p.d_ranges) p.d_ranges[o] = rg;
+        if (p.d_hits) p.d_hits[o] = hit;
+        if (p.d_visits) p.d_visits[o] = vis;
+    }
+}
+
+// Phase (2) for the fixed-step march: the refilling walk of the traversal
+// with each lane marching its ray in groups of 4 samples (bitmap in LDS);
+// the result k | outcome << 28 goes back to the ray's slot.
+__device__ __forceinline__ void march_walk(const StepParams &p, const MapView &M,
+                                           const TileJob *s_jobs, const int *s_list,
+                                           const double2 *s_beam, uint4 *s_ray, int *s_misc,
+                                           int c0, int Rc, int K, float inv_K, int lane) {
+    int r = -1, k = 0, type = 0;
+    bool act = false, exhausted = false;
+    double x = 0.0, y = 0.0, dx = 0.0, dy = 0.0;
+    const int kmax = p.march_kmax;
+    const double h = p.march_h;
+    for (;;) {
+        uint64_t am = __ballot(act);
+        if (!exhausted && __popcll(am) <= p.refill_at) {
+            if (!act && r >= 0) {
+                reinterpret_cast<uint2 *>(s_ray)[2 * r] =
+                    make_uint2((uint32_t)k | ((uint32_t)type << 28), 0u);
+                r = -1;
+            }
+            const uint64_t idle = ~am;
+            const int nidle = 64 - __popcll(am);
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
+            base = __shfl(base, 0);
+            const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
+            if (!act && my < Rc) {
+                const int g = c0 + my, jl = small_div(g, K, inv_K), beam = g - jl * K;
+                const TileJob &j = s_jobs[s_list[jl]];
+                const double2 cs = s_beam[beam];
+                dx = j.c * cs.x - j.s * cs.y;
+                dy = j.s * cs.x + j.c * cs.y;
+                x = j.x;
+                y = j.y;
+                r = my;
+                k = 0;
+                type = 0;
+                act = true;
+            }
+            exhausted = base + nidle >= Rc;
+            am = __ballot(act);
+        }
+        if (am == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+        if (act) {
+#pragma unroll 1
+            for (int gi = 0; gi < p.groups; ++gi) {
+                int cell, t[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    t[q] = (k + q <= kmax) ? march_sample(M, x, y, dx, dy, h, k + q, &cell) : 0;
+                const int f = t[0] ? 0 : (t[1] ? 1 : (t[2] ? 2 : (t[3] ? 3 : 4)));
+                if (f < 4) {
+                    k += f;
+                    type = t[f];
+                    act = false;
+                    break;
+                }
+                if (k + 3 >= kmax) {
+                    k = kmax;
+                    type = 0;
+                    act = false;
+                    break;
+                }
+                k += 4;
+            }
+        }
+    }
+    if (r >= 0)
+        reinterpret_cast<uint2 *>(s_ray)[2 * r] = make_uint2((uint32_t)k | ((uint32_t)type << 28), 0u);
+}
+
 template <int E>
 __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p) {
     extern __shared__ uint4 smem4[];
@@ -842,8 +986,8 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
     const int max_n = M.w + M.h + 2 * kPad;  // a walk meets the padding ring before this
     for (int c0 = 0; c0 < R; c0 += p.ray_cap) {
         const int Rc = min(p.ray_cap, R - c0);
-        // (1) every ray's walk start, all lanes busy
-        for (int r = tid; r < Rc; r += kFusedThreads) {
+        // (1) every ray's walk start, all lanes busy (the march needs none)
+        for (int r = tid; r < Rc && p.scan_mode != 1; r += kFusedThreads) {
             const int g = c0 + r, jl = small_div(g, K, inv_K), beam = g - jl * K;
             const TileJob &j = s_jobs[s_list[jl]];
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
@@ -860,6 +1004,9 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
         // (2) walk: lanes take rays from s_misc[1]; a lane whose ray is done
         // writes its result back and takes a new one once at most refill_at
         // lanes of its wavefront are still walking
+        if (p.scan_mode == 1) {
+            march_walk(p, M, s_jobs, s_list, s_beam, s_ray, s_misc, c0, Rc, K, inv_K, lane);
+        } else {
         int r = -1;
         bool act = false, exhausted = false;
         int B = 0, Eh = 0, incx = 0, incy = 0, dEx = 0, dEy = 0, n = 0, k = 0;
@@ -947,14 +1094,18 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
         }
         if (r >= 0)
             reinterpret_cast<uint2 *>(s_ray)[2 * r] = make_uint2((uint32_t)B | ((uint32_t)k << 19), flags);
+        }
         __syncthreads();
         // (3) ranges, hits, pooling, all lanes busy
         for (int q = tid; q < Rc; q += kFusedThreads) {
             const int g = c0 + q, jl = small_div(g, K, inv_K), beam = g - jl * K;
             const int job = s_list[jl];
             const uint4 v = s_ray[q];
-            finish_ray(p, M, s_jobs[job], s_beam, job, beam, make_uint2(v.x, v.y), s_pool, per,
-                       inv_per, E);
+            if (p.scan_mode == 1)
+                finish_march(p, M, s_jobs[job], s_beam, job, beam, v.x, s_pool, per, inv_per, E);
+            else
+                finish_ray(p, M, s_jobs[job], s_beam, job, beam, make_uint2(v.x, v.y), s_pool,
+                           per, inv_per, E);
         }
         __syncthreads();
     }
@@ -983,7 +1134,12 @@ __device__ void observe_serial(const StepParams &p, const MapView &M, const MapD
             const int k = j * per + q;
             float rg;
             int hit, vis;
-            if (o.blocked) {
+            if (p.scan_mode == 1) {
+                const double2 cs = beams[k];
+                const double dx = c * cs.x - sn * cs.y;
+                const double dy = sn * cs.x + c * cs.y;
+                march_ray(p, M, x, y, dx, dy, rg, hit, vis);
+            } else if (o.blocked) {
                 rg = 0.0f;
                 hit = o.block_hit;
                 vis = 1;

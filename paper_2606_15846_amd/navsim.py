@@ -21,12 +21,14 @@ NAVSIM_ABI_VERSION = 1
 NAVSIM_DISC, NAVSIM_RECT = 0, 1
 NAVSIM_KERNEL_FUSED, NAVSIM_KERNEL_PLAIN = 0, 1
 NAVSIM_ROLLOUT_GRAPH = 1
+NAVSIM_SCAN_TRAVERSAL, NAVSIM_SCAN_MARCH = 0, 1
 STATUS = {0: "NAVSIM_OK", -1: "NAVSIM_E_INVALID_ARG", -2: "NAVSIM_E_BAD_HANDLE",
           -3: "NAVSIM_E_STATE", -4: "NAVSIM_E_NO_FREE_SPACE", -5: "NAVSIM_E_OOM",
           -6: "NAVSIM_E_HIP", -7: "NAVSIM_E_UNSUPPORTED"}
 EXPORTS = ("navsim_create", "navsim_load_maps", "navsim_load_maps_ex", "navsim_reset",
            "navsim_reset_to", "navsim_step",
-           "navsim_step_plain", "navsim_step_debug", "navsim_rollout", "navsim_set_tuning",
+           "navsim_step_plain", "navsim_step_debug", "navsim_rollout", "navsim_set_scan",
+           "navsim_set_tuning",
            "navsim_get_tuning",
            "navsim_get_state", "navsim_set_state", "navsim_destroy", "navsim_last_error")
 STATE_KEYS = ("x", "y", "th", "v", "w", "gx", "gy", "dprev", "t", "ep")
@@ -88,6 +90,7 @@ def load_library(path: str = LIB_PATH):
     L.navsim_step_plain.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.navsim_step_debug.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.POINTER(NavsimDebug), i32, vp]
     L.navsim_rollout.argtypes = [vp, i32, C.c_uint64, vp, vp, vp, vp, vp, vp, i32, i32, vp]
+    L.navsim_set_scan.argtypes = [vp, i32, C.c_float]
     L.navsim_set_tuning.argtypes = [vp, C.POINTER(NavsimTuning)]
     L.navsim_get_tuning.argtypes = [vp, C.POINTER(NavsimTuning)]
     L.navsim_get_state.argtypes = [vp, vp, C.c_size_t, vp]
@@ -360,6 +363,10 @@ class NavSim:
         navsim_rollout(self.h, steps, first_step, b["act"], b["obs"], b["reward"],
                        b["terminated"], b["truncated"], b["final_obs"], kernel, graph)
         return b
+
+    def set_scan(self, mode: int, step_m: float = 0.03):
+        """NAVSIM_SCAN_TRAVERSAL (exact) or NAVSIM_SCAN_MARCH (fixed step)."""
+        _check(load_library().navsim_set_scan(self.h, int(mode), float(step_m)))
 
     def set_tuning(self, tile_envs: int, refill_at: int, groups: int):
         navsim_set_tuning(self.h, tile_envs, refill_at, groups)

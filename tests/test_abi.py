@@ -28,7 +28,7 @@ def declared_functions():
 def test_library_exports_every_declared_function():
     lib = navsim.load_library()
     names = declared_functions()
-    assert len(names) == 26
+    assert len(names) == 27
     for n in names:
         assert hasattr(lib, n), n
     from paper_2606_15846_amd import reset_proposal
@@ -105,6 +105,7 @@ def test_abi_version_and_null_arguments():
                      ("navsim_rollout", (None, 4, 0, None, None, None, None, None, None, 0, 1,
                                          None)),
                      ("navsim_reset_to", (None, None, None, None, None)),
+                     ("navsim_set_scan", (None, 1, 0.03)),
                      ("navsim_rp_create", (None, None, C.byref(C.c_void_p()))),
                      ("navsim_rp_label", (None, 0, None, 0, None, None, None, None)),
                      ("navsim_rp_train", (None, 1, None, None, None, None, 1, 1, 1, 1e-3, 0.0,

@@ -160,6 +160,45 @@ def test_profile_validation_on_device():
         NavSim(cfg, occ, res, env_map, device=0, profiles=prof[:3])
 
 
+@pytest.mark.parametrize("kname", ["fused", "plain"])
+def test_march_scan_mode_against_oracle(kname):
+    say(f"fixed-step march (0.03 m), c2 maps, 512 envs, 4 steps, kernel={kname}")
+    w = configs.build_workload("c2", num_envs=512)
+    cfg = dict(w["cfg"], scan_mode=1, march_step_m=0.03)
+    sim, ref = make_pair(cfg, w["maps"], w["res"], w["env_map"])
+    sim.set_scan(navsim.NAVSIM_SCAN_MARCH, 0.03)
+    tot = run_teacher_forced(sim, ref, 4, KERNELS[kname], label=f"march/{kname}")
+    assert tot["grazing"] < 1e-3 * tot["rays"]
+    sim.close()
+
+
+def test_march_mixed_profiles_and_launch_shapes():
+    say("fixed-step march on mixed profiles: fused (tile 4, 16) == plain, and vs oracle")
+    cfg, occ, res, env_map, prof = _mixed_small(num_envs=60)
+    cfg = dict(cfg, scan_mode=1, march_step_m=0.05)
+    sim, ref = make_pair(cfg, occ, res, env_map, prof)
+    sim.set_scan(navsim.NAVSIM_SCAN_MARCH, 0.05)
+    run_teacher_forced(sim, ref, 6, NAVSIM_KERNEL_FUSED, seed=4, label="march-mixed")
+    acts = configs.uniform_actions(3, 60, seed=8)
+    runs = []
+    for kernel, te in [(NAVSIM_KERNEL_PLAIN, 4), (NAVSIM_KERNEL_FUSED, 4), (NAVSIM_KERNEL_FUSED, 16)]:
+        s2 = NavSim(cfg, occ, res, env_map, device=0, profiles=prof)
+        s2.set_scan(navsim.NAVSIM_SCAN_MARCH, 0.05)
+        s2.set_tuning(te, 40, 2)
+        s2.reset()
+        runs.append([gpu_step(s2, acts[t], kernel) for t in range(3)])
+        s2.close()
+    for other in runs[1:]:
+        for (ga, sa), (gb, sb) in zip(runs[0], other):
+            for k in ga:
+                assert np.array_equal(ga[k], gb[k]) or k == "final_obs", k
+    with pytest.raises(navsim.NavsimError):
+        sim.set_scan(7, 0.03)
+    with pytest.raises(navsim.NavsimError):
+        sim.set_scan(navsim.NAVSIM_SCAN_MARCH, 0.0)
+    sim.close()
+
+
 def _small_cfg(**kw):
     c = configs.make_config(num_envs=13, num_beams=100, num_sectors=10, fov_rad=2 * math.pi,
                             max_range_m=2.5, dt_s=0.1, footprint=0, radius_m=0.18,

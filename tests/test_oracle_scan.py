@@ -296,3 +296,52 @@ def test_beam_angles_full_circle_and_fov():
     got = [sim.beam_angle(k) for k in range(5)]
     fov = float(np.float32(math.radians(270.0)))
     assert abs(got[0] + fov / 2) < 1e-15 and abs(got[-1] - fov / 2) < 1e-12
+
+
+def test_march_at_the_paper_step_closed_forms():
+    # h = 0.03 m on 0.05 m cells: samples are closer than a cell, so an
+    # axis-aligned ray cannot step over a cell: it stops at the first sample
+    # past the wall's entry distance, range in [d, d + h), same cell
+    s = float(np.float32(0.05))
+    occ = np.zeros((40, 40), np.uint8)
+    occ[:, 30] = 1
+    M = _maps(occ, s)
+    h = 0.03
+    for ox in (0.101, 0.4, 0.77, 1.2345):
+        oy = 0.9
+        r = M.cast(0, ox, oy, 1.0, 0.0, 5.0)
+        rm, hm = M.march(0, ox, oy, 1.0, 0.0, 5.0, h)
+        assert hm == r.hit == int(oy / s) * 40 + 30
+        assert r.range <= rm < r.range + h
+        k = rm / h
+        assert abs(k - round(k)) < 1e-9  # range is a whole number of steps
+    # beyond r_max: the largest sample not past r_max decides, range = r_max
+    rm, hm = M.march(0, 0.1, 0.9, 1.0, 0.0, 0.5, h)
+    assert (rm, hm) == (0.5, -1)
+    # origin out of bounds: sample 0 is outside, range 0, hit -2
+    assert M.march(0, -0.01, 0.9, 1.0, 0.0, 5.0, h) == (0.0, -2)
+
+
+def test_march_scan_mode_step_pools_the_marched_beams():
+    # a step in scan mode 1 observes the per-sector minima of orc_march ranges
+    from workloads import configs, maps as gm
+    occ = gm.gen_rect_disc_map(4, w=70, h=60, res=0.05)
+    cfg = configs.make_config(num_envs=10, num_beams=60, num_sectors=6, fov_rad=2 * math.pi,
+                              max_range_m=2.5, dt_s=0.1, footprint=0, radius_m=0.18,
+                              v_min=0.0, v_max=0.5, w_min=-1.0, w_max=1.0)
+    cfg.update(scan_mode=1, march_step_m=0.03)
+    sim = oracle.OracleSim(cfg, [occ], [0.05], np.zeros(10, np.int32))
+    sim.reset()
+    out = sim.step(np.zeros((10, 2), np.float32))
+    st = sim.state
+    for e in range(10):
+        if out["reset"][e]:
+            continue
+        want = []
+        for k in range(60):
+            a = float(st["th"][e]) + sim.beam_angle(k)
+            rg, _ = sim.maps.march(0, float(st["x"][e]), float(st["y"][e]), math.cos(a),
+                                   math.sin(a), float(np.float32(2.5)), float(np.float32(0.03)))
+            want.append(np.float32(rg))
+        want = np.array(want).reshape(6, 10).min(axis=1)
+        assert np.array_equal(out["obs"][e, :6], want), e
