@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnavsim.so")
 SOURCES = ["navsim_kernels.hip", "navsim_api.cpp", "mlp_kernels.hip", "reach_kernels.hip",
-           "reset_proposal.cpp"]
+           "reset_proposal.cpp", "policy.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

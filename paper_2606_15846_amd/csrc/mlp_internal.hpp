@@ -9,7 +9,7 @@ namespace navsim {
 // C[m, n] = sum_k A(m, k) B(n, k), bfloat16 operands, float accumulation.
 // A(m, k) = A[m lda + k] when a_kmajor, else A[k lda + m]; B likewise.
 // Epilogue: + bias[n] (optional) + bias_rows[row_idx[m] ldbr + n] (optional),
-// activation (0 none, 1 leaky ReLU with `slope`), then stored as float to Cf
+// activation (0 none, 1 leaky ReLU with `slope`, 2 tanh), then stored as float to Cf
 // and/or as bfloat16 (round to nearest even) to Cb.
 struct GemmArgs {
     int M = 0, N = 0, K = 0;
@@ -57,6 +57,17 @@ hipError_t launch_sq_loss(int M, int D, const float *Y, const float *T, const fl
 hipError_t launch_adamw(int64_t n, float *p, uint16_t *pb, const float *g, float *m, float *v,
                         const uint8_t *decay_mask, float lr, float b1, float b2, float eps,
                         float wd, int64_t t, hipStream_t s);
+
+// Actor input rows [N][m + 4] in bfloat16: 1 / (obs - beta) for the m pooled
+// ranges (reciprocal transform, beta device scalar), the 4 other features as
+// they are.
+hipError_t launch_actor_input(int N, int m, const float *obs, const float *beta, uint16_t *x,
+                              hipStream_t s);
+
+// Gaussian exploration noise on actions [N][2], clipped to [-1, 1]; the step
+// index is *step_ctr (device {lo, hi}) + step_off.
+hipError_t launch_actor_noise(int N, float *act, float std, const uint32_t *step_ctr, int step_off,
+                              uint32_t key0, uint32_t key1, hipStream_t s);
 
 // Float to bfloat16 (round to nearest even), n elements.
 hipError_t launch_to_bf16(int64_t n, const float *x, uint16_t *y, hipStream_t s);

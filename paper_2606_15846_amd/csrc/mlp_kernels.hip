@@ -5,6 +5,7 @@
 #include <math.h>
 
 #include "mlp_internal.hpp"
+#include "philox.hpp"
 
 namespace navsim {
 namespace {
@@ -117,6 +118,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
                 if (g.bias) v += g.bias[n];
                 if (g.bias_rows) v += g.bias_rows[(int64_t)g.row_idx[m] * g.ldbr + n];
                 if (g.act == 1 && !(v > 0.0f)) v *= g.slope;
+                if (g.act == 2) v = tanhf(v);
                 if (g.Cf) g.Cf[(int64_t)m * g.ldcf + n] = v;
                 if (g.Cb) g.Cb[(int64_t)m * g.ldcb + n] = to_bf16_bits(v);
             }
@@ -188,6 +190,37 @@ __global__ void to_bf16_kernel(int64_t n, const float *x, uint16_t *y) {
     if (i < n) y[i] = to_bf16_bits(x[i]);
 }
 
+// Actor input: x[e][j] = bf16(1 / (obs[e][j] - beta)) for the m pooled
+// ranges (the reciprocal transform), bf16(obs[e][j]) for the 4 goal and
+// velocity features.
+__global__ void actor_input_kernel(int N, int m, const float *obs, const float *beta,
+                                   uint16_t *x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int row = m + 4;
+    if (i >= (int64_t)N * row) return;
+    const int j = (int)(i % row);
+    const float v = obs[i];
+    x[i] = to_bf16_bits(j < m ? 1.0f / (v - *beta) : v);
+}
+
+// Exploration noise: a = clip(a + std n, -1, 1) with n standard normal from
+// Box-Muller on Philox(e, n mod 2^32, n div 2^32, 11) words 0 and 1 at step
+// n = *step_ctr + step_off (double precision, rounded to float).
+__global__ void actor_noise_kernel(int N, float *act, float std, const uint32_t *step_ctr,
+                                   int step_off, uint32_t key0, uint32_t key1) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= N) return;
+    const uint64_t n = (((uint64_t)step_ctr[1] << 32) | (uint64_t)step_ctr[0]) + (uint64_t)step_off;
+    uint32_t c[4] = {(uint32_t)e, (uint32_t)n, (uint32_t)(n >> 32), 11u};
+    philox4x32_10(c, key0, key1);
+    const double u1 = ((double)c[0] + 0.5) / 4294967296.0, u2 = ((double)c[1] + 0.5) / 4294967296.0;
+    const double r = sqrt(-2.0 * log(u1)), t = 2.0 * 3.14159265358979323846 * u2;
+    const float n0 = (float)(r * cos(t)), n1 = (float)(r * sin(t));
+    float a0 = act[2 * e] + std * n0, a1 = act[2 * e + 1] + std * n1;
+    act[2 * e] = fminf(1.0f, fmaxf(-1.0f, a0));
+    act[2 * e + 1] = fminf(1.0f, fmaxf(-1.0f, a1));
+}
+
 unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -243,6 +276,23 @@ hipError_t launch_adamw(int64_t n, float *p, uint16_t *pb, const float *g, float
     const float bc2 = (float)(1.0 - pow((double)b2, (double)t));
     hipLaunchKernelGGL(adamw_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, p, pb, g, m, v,
                        decay_mask, lr, b1, b2, eps, wd, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_actor_input(int N, int m, const float *obs, const float *beta, uint16_t *x,
+                              hipStream_t s) {
+    const int64_t n = (int64_t)N * (m + 4);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(actor_input_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, N, m, obs,
+                       beta, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_actor_noise(int N, float *act, float std, const uint32_t *step_ctr, int step_off,
+                              uint32_t key0, uint32_t key1, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(actor_noise_kernel, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, act, std,
+                       step_ctr, step_off, key0, key1);
     return hipGetLastError();
 }
 

@@ -139,48 +139,6 @@ navsim_status upload(T **dst, const std::vector<T> &src) {
     return NAVSIM_OK;
 }
 
-StepParams make_params(const navsim_s *h) {
-    const navsim_config &c = h->cfg;
-    StepParams p;
-    memset(&p, 0, sizeof p);
-    p.N = c.num_envs;
-    p.K = c.num_beams;  // the largest per-map beam count
-    p.m = c.num_sectors;
-    p.horizon = c.horizon;
-    p.tries = c.reset_max_tries;
-    p.rmax = c.max_range_m;
-    p.dt = c.dt_s;
-    p.goal_r = c.goal_radius_m;
-    p.c1 = c.c_progress;
-    p.r_succ = c.r_success;
-    p.r_coll = c.r_collision;
-    p.vlo = c.v_min;
-    p.vhi = c.v_max;
-    p.wlo = c.w_min;
-    p.whi = c.w_max;
-    p.gmd = c.goal_min_dist_m;
-    p.key0 = (uint32_t)(c.seed & 0xffffffffu);
-    p.key1 = (uint32_t)(c.seed >> 32);
-    p.st = h->st;
-    p.env_map = h->env_map;
-    p.maps = h->maps;
-    p.bits = h->bits;
-    p.free_cells = h->free_cells;
-    p.beams = h->beams;
-    p.perm = h->perm;
-    p.tiles = h->tiles;
-    p.num_tiles = h->num_tiles;
-    p.num_maps = h->num_maps;
-    p.max_words = h->max_words;
-    p.refill_at = h->refill_at;
-    p.groups = h->groups;
-    p.ray_cap = h->ray_cap;
-    p.beams_lds = h->beams_lds ? 1 : 0;
-    p.scan_mode = h->scan_mode;
-    p.march_kmax = h->march_kmax;
-    p.march_h = h->march_h;
-    return p;
-}
 
 // LDS walk slots per chunk, keeping the beam table in LDS when a full tile's
 // rays still fit next to it, else reading it from device memory.
@@ -233,7 +191,7 @@ navsim_status step_common(navsim_t h, const float *act, float *obs, float *rewar
         return fail(NAVSIM_E_INVALID_ARG, "act, obs, reward, terminated, truncated are required");
     if (kernel != NAVSIM_KERNEL_FUSED && kernel != NAVSIM_KERNEL_PLAIN)
         return fail(NAVSIM_E_INVALID_ARG, "unknown kernel %d", kernel);
-    StepParams p = make_params(h);
+    StepParams p = make_step_params(h);
     p.mode = 0;
     p.act = act;
     p.obs = obs;
@@ -318,6 +276,50 @@ navsim_status rollout_graph(navsim_t h, const StepParams &p0, int steps, int ker
 }
 
 }  // namespace
+
+// Launch parameters of the handle's current maps, state and settings.
+StepParams navsim::make_step_params(const navsim_s *h) {
+    const navsim_config &c = h->cfg;
+    StepParams p;
+    memset(&p, 0, sizeof p);
+    p.N = c.num_envs;
+    p.K = c.num_beams;  // the largest per-map beam count
+    p.m = c.num_sectors;
+    p.horizon = c.horizon;
+    p.tries = c.reset_max_tries;
+    p.rmax = c.max_range_m;
+    p.dt = c.dt_s;
+    p.goal_r = c.goal_radius_m;
+    p.c1 = c.c_progress;
+    p.r_succ = c.r_success;
+    p.r_coll = c.r_collision;
+    p.vlo = c.v_min;
+    p.vhi = c.v_max;
+    p.wlo = c.w_min;
+    p.whi = c.w_max;
+    p.gmd = c.goal_min_dist_m;
+    p.key0 = (uint32_t)(c.seed & 0xffffffffu);
+    p.key1 = (uint32_t)(c.seed >> 32);
+    p.st = h->st;
+    p.env_map = h->env_map;
+    p.maps = h->maps;
+    p.bits = h->bits;
+    p.free_cells = h->free_cells;
+    p.beams = h->beams;
+    p.perm = h->perm;
+    p.tiles = h->tiles;
+    p.num_tiles = h->num_tiles;
+    p.num_maps = h->num_maps;
+    p.max_words = h->max_words;
+    p.refill_at = h->refill_at;
+    p.groups = h->groups;
+    p.ray_cap = h->ray_cap;
+    p.beams_lds = h->beams_lds ? 1 : 0;
+    p.scan_mode = h->scan_mode;
+    p.march_kmax = h->march_kmax;
+    p.march_h = h->march_h;
+    return p;
+}
 
 extern "C" {
 
@@ -546,7 +548,7 @@ navsim_status navsim_reset(navsim_t h, const uint8_t *mask, float *obs, void *hi
     if (!obs) return fail(NAVSIM_E_INVALID_ARG, "obs is required");
     if (mask && !h->initialized)
         return fail(NAVSIM_E_STATE, "the first reset must cover all envs (mask NULL)");
-    StepParams p = make_params(h);
+    StepParams p = make_step_params(h);
     p.mode = 1;
     p.mask = mask;
     p.obs = obs;
@@ -562,7 +564,7 @@ navsim_status navsim_reset_to(navsim_t h, const uint8_t *mask, const float *pose
     if (!pose || !obs) return fail(NAVSIM_E_INVALID_ARG, "pose and obs are required");
     if (mask && !h->initialized)
         return fail(NAVSIM_E_STATE, "the first reset must cover all envs (mask NULL)");
-    StepParams p = make_params(h);
+    StepParams p = make_step_params(h);
     p.mode = 1;
     p.mask = mask;
     p.pose = pose;
@@ -633,7 +635,7 @@ navsim_status navsim_rollout(navsim_t h, int32_t steps, uint64_t first_step, flo
     if (flags & ~NAVSIM_ROLLOUT_GRAPH) return fail(NAVSIM_E_INVALID_ARG, "unknown flags 0x%x", flags);
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
-    StepParams p = make_params(h);
+    StepParams p = make_step_params(h);
     p.mode = 0;
     p.act = nullptr;
     p.step_ctr = h->step_ctr;

@@ -81,3 +81,9 @@ struct navsim_s {
     int graph_steps = 0, graph_kernel = -1, graph_tile_envs = 0;
 };
 
+
+namespace navsim {
+// Launch parameters of the handle's current maps, state and settings (all
+// optional inputs and outputs null).
+StepParams make_step_params(const navsim_s *h);
+}  // namespace navsim

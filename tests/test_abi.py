@@ -28,11 +28,11 @@ def declared_functions():
 def test_library_exports_every_declared_function():
     lib = navsim.load_library()
     names = declared_functions()
-    assert len(names) == 27
+    assert len(names) == 33
     for n in names:
         assert hasattr(lib, n), n
-    from paper_2606_15846_amd import reset_proposal
-    assert sorted(navsim.EXPORTS + reset_proposal.EXPORTS) == names
+    from paper_2606_15846_amd import policy, reset_proposal
+    assert sorted(navsim.EXPORTS + reset_proposal.EXPORTS + policy.EXPORTS) == names
 
 
 def test_struct_layout_matches_header(tmp_path):
@@ -86,8 +86,9 @@ def test_config_validation_before_any_device_call(bad):
 
 def test_abi_version_and_null_arguments():
     lib = navsim.load_library()
-    from paper_2606_15846_amd import reset_proposal
-    reset_proposal._lib()  # argument types of the proposer's entry points
+    from paper_2606_15846_amd import policy, reset_proposal
+    reset_proposal._lib()  # argument types of the proposer's and the actor's entry points
+    policy._lib()
     c = navsim.make_config(_cfg())
     c.abi_version = 99
     h = C.c_void_p()
@@ -118,7 +119,14 @@ def test_abi_version_and_null_arguments():
                      ("navsim_rp_layout", (None, None, None, None, None)),
                      ("navsim_rp_get_params", (None, None, 0)),
                      ("navsim_rp_set_params", (None, None, 0)),
-                     ("navsim_rp_destroy", (None,))]:
+                     ("navsim_rp_destroy", (None,)),
+                     ("navsim_policy_create", (None, 100, 3, 0.01, C.byref(C.c_void_p()))),
+                     ("navsim_policy_layout", (None, None, None, None, None)),
+                     ("navsim_policy_set_params", (None, None, 0)),
+                     ("navsim_policy_act", (None, None, None, 0.0, 0, None)),
+                     ("navsim_policy_rollout", (None, None, 1, 0, None, 0.0, None, None, None,
+                                               None, None, None, 0, 1, None)),
+                     ("navsim_policy_destroy", (None,))]:
         assert getattr(lib, fn)(*args) == -2, fn
 
 

@@ -1,0 +1,123 @@
+"""GPU parity of the policy in the loop (through the C ABI): the bfloat16
+actor against the oracle actor, the exploration noise against its oracle twin,
+and actor-driven rollouts (graph and eager) against single steps and against
+the oracle stepping with the same actions."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import mlp as OM
+from oracle import policy as OP
+from paper_2606_15846_amd.navsim import NAVSIM_KERNEL_PLAIN, NavSim
+from paper_2606_15846_amd.policy import Policy
+from tests.parity import compare_outputs
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def setup(num_envs=512, beta=-0.1, seed=1):
+    w = configs.build_workload("c2", num_envs=num_envs)
+    sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
+    ref = oracle.OracleSim(w["cfg"], w["maps"], w["res"], w["env_map"])
+    pol = Policy(sim)
+    flat = pol.init_params(seed=seed, beta=beta)
+    net = OM.MLP(pol.dims, OP.policy_params(flat, pol.dims, pol.offsets), pol.slope)
+    return sim, ref, pol, net, flat[pol.beta_off], w["cfg"]
+
+
+def _oracle_act(net, obs, beta, m):
+    return OP.actor_forward(net, OP.actor_input(obs, beta, m), emulate=True)
+
+
+def test_actor_matches_oracle_and_noise_twin():
+    # bfloat16 at the same points on both sides; float32 vs float64
+    # accumulation over <= 100 products, then tanh (slope <= 1): differences
+    # of order 1e-6, a rare bfloat16 boundary flip moves an action by < 1e-3
+    sim, ref, pol, net, beta, cfg = setup()
+    obs = sim.reset()
+    a = pol.act(obs).cpu().numpy()
+    want = _oracle_act(net, obs.cpu().numpy(), beta, cfg["num_sectors"])
+    d = np.abs(a - want)
+    say(f"actor: max |da| {d.max():.2e}, median {np.median(d):.2e}")
+    assert d.max() <= 2e-3 and np.median(d) <= 1e-5
+    an = pol.act(obs, noise_std=0.3, step=77).cpu().numpy()
+    key = [cfg["seed"] & 0xFFFFFFFF, cfg["seed"] >> 32]
+    wn = np.clip(a + np.float32(0.3) * OP.noise(sim.N, 77, key), -1, 1)
+    assert np.abs(an - wn).max() <= 1e-5
+    sim.close()
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_policy_rollout_against_oracle_steps(graph):
+    say(f"policy rollout: 512 envs, 24 steps, graph={graph}")
+    sim, ref, pol, net, beta, cfg = setup()
+    obs0 = sim.reset().clone()
+    ref.reset(threads=16)
+    torch.cuda.synchronize()
+    st = sim.get_state()
+    for k in oracle.STATE_KEYS:
+        assert np.array_equal(st[k], ref.state[k])
+    b = pol.rollout(24, first_step=5, obs0=obs0, noise_std=0.2, graph=graph)
+    torch.cuda.synchronize()
+    h = {k: v.cpu().numpy() for k, v in b.items()}
+    m = cfg["num_sectors"]
+    prev = obs0.cpu().numpy()
+    resets = 0
+    for t in range(24):
+        # the actor saw the previous observation row
+        want = np.clip(_oracle_act(net, prev, beta, m)
+                       + np.float32(0.2) * OP.noise(sim.N, 5 + t,
+                                                    [cfg["seed"] & 0xFFFFFFFF, cfg["seed"] >> 32]),
+                       -1, 1)
+        assert np.abs(h["act"][t] - want).max() <= 2e-3, t
+        # the step with exactly the device's actions
+        r = ref.step(h["act"][t], threads=16)
+        compare_outputs({k: h[k][t] for k in ("obs", "reward", "terminated", "truncated",
+                                               "final_obs")}, r, ref, label=f"step {t}")
+        resets += int(r["reset"].sum())
+        prev = h["obs"][t]
+    st = sim.get_state()
+    for k in oracle.STATE_KEYS:
+        assert np.array_equal(st[k], ref.state[k]), k
+    say(f"resets in the rollout: {resets}")
+    sim.close()
+
+
+def test_graph_rollout_equals_eager_and_single_steps():
+    sim, ref, pol, net, beta, cfg = setup(num_envs=300)
+    obs0 = sim.reset().clone()
+    s0 = sim.get_state()
+    eager = {k: v.cpu().numpy() for k, v in pol.rollout(10, 3, obs0, 0.1, graph=False).items()}
+    s_end = sim.get_state()
+    # single steps with those actions
+    sim.set_state(s0)
+    for t in range(10):
+        o, r, te, tr, _ = sim.step(torch.from_numpy(eager["act"][t]).cuda())
+        torch.cuda.synchronize()
+        assert np.array_equal(o.cpu().numpy(), eager["obs"][t]), t
+    bufs = sim.rollout_buffers(10)
+    for rep in range(3):
+        sim.set_state(s0)
+        junk = torch.randn(1 << 18, device="cuda").sum()
+        g = {k: v.cpu().numpy() for k, v in pol.rollout(10, 3, obs0, 0.1, buffers=bufs).items()}
+        assert float(junk.item()) == float(junk.item())
+        for k in eager:
+            assert np.array_equal(g[k], eager[k]), (rep, k)
+        st = sim.get_state()
+        assert all(np.array_equal(st[k], s_end[k]) for k in oracle.STATE_KEYS)
+    # plain kernel: same results
+    sim.set_state(s0)
+    pl = {k: v.cpu().numpy() for k, v in
+          pol.rollout(10, 3, obs0, 0.1, kernel=NAVSIM_KERNEL_PLAIN, graph=True).items()}
+    for k in eager:
+        assert np.array_equal(pl[k], eager[k]), k
+    sim.close()
