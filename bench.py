@@ -72,6 +72,64 @@ def cpu_baseline(w, acts, rays_per_env_step: float, target_s: float = 10.0) -> d
                       f"{threads} threads over env slices), {dt:.1f} s"}
 
 
+def reset_proposal_gain(sim, w, args) -> dict:
+    """Learned reset proposal against the plain rejection sampler on the
+    workload's maps: label pairs with the GPU search, train the network, then
+    answer the same requests (uniform over the bins) both ways and time them.
+    Both return only pairs that passed the exact check."""
+    import torch
+    from paper_2606_15846_amd.reset_proposal import ResetProposer
+
+    rp = ResetProposer(sim, **w["proposer"])
+    nm = len(w["maps"])
+    ns = args.label_starts
+    t0 = time.perf_counter()
+    lab = rp.label(np.arange(ns) % nm, first_sid=0)
+    torch.cuda.synchronize()
+    t_label = time.perf_counter() - t0
+    nb = rp.nb
+    keep = lab["goal"] >= 0
+    ids = torch.arange(ns, device=sim.device, dtype=torch.int32)
+    pairs = dict(map=(ids % nm)[:, None].expand(ns, nb)[keep].contiguous(),
+                 bin=torch.arange(nb, device=sim.device, dtype=torch.int32)[None, :]
+                 .expand(ns, nb)[keep].contiguous(),
+                 start=lab["start"][:, None].expand(ns, nb)[keep].contiguous(),
+                 goal=lab["goal"][keep].contiguous())
+    loss = torch.zeros(args.train_steps, device=sim.device)
+    t0 = time.perf_counter()
+    rp.train(pairs, steps=args.train_steps, batch=1024, samples=16, lr=1e-3, weight_decay=1e-4,
+             loss=loss)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    lv = loss.cpu().numpy() / 1024
+    n = args.proposal_requests
+    rng = np.random.default_rng(11)
+    mp = rng.integers(0, nm, n)
+    bins = np.arange(n) % nb
+    env = np.arange(n)
+    ep = rng.integers(0, 1 << 20, n)
+    out = {"pairs": int(pairs["map"].numel()), "label_s": t_label, "train_steps": args.train_steps,
+           "train_s": t_train, "loss_first_50": float(lv[:50].mean()),
+           "loss_last_50": float(lv[-50:].mean()), "requests": n}
+    for name, M, tries in (("learned", 32, 400), ("rejection", 0, 432)):
+        rp.propose(mp, bins, env, ep, proposals=M, max_tries=tries)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        res = rp.propose(mp, bins, env, ep, proposals=M, max_tries=tries)
+        e1.record()
+        torch.cuda.synchronize()
+        src = res["source"].cpu().numpy()
+        ok = src >= 0
+        out[name] = {"valid_fraction": float(ok.mean()),
+                     "checks_per_request": float(res["checks"].float().mean().item()),
+                     "resets_per_s": float(ok.sum() / (e0.elapsed_time(e1) / 1e3)),
+                     "from_network": float(((src >= 0) & (src < M)).mean()) if M else 0.0}
+    out["gain_resets_per_s"] = out["learned"]["resets_per_s"] / out["rejection"]["resets_per_s"]
+    rp.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,12 +139,17 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=50)
     ap.add_argument("--rollout-steps", type=int, default=64)
     ap.add_argument("--no-march", action="store_true")
+    ap.add_argument("--no-proposal", action="store_true")
+    ap.add_argument("--label-starts", type=int, default=16384)
+    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--proposal-requests", type=int, default=8192)
     ap.add_argument("--march-step", type=float, default=0.03)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--tile-envs", type=int, default=None)
     ap.add_argument("--refill-at", type=int, default=None)
     ap.add_argument("--groups", type=int, default=None)
+    ap.add_argument("--ray-slots", type=int, default=None)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 device-to-device copies of 256 MiB (HBM counter scale)")
     args = ap.parse_args()
@@ -129,7 +192,7 @@ def main():
     # tuning.json) unless given on the command line; results do not depend on it
     from paper_2606_15846_amd import autotune
     tuning = autotune.best_for(autotune.workload_key(cfg, w["maps"], w["profiles"]))
-    for k in ("tile_envs", "refill_at", "groups"):
+    for k in ("tile_envs", "refill_at", "groups", "ray_slots"):
         if getattr(args, k) is not None:
             tuning[k] = getattr(args, k)
     sim.set_tuning(**tuning)
@@ -225,6 +288,9 @@ def main():
                  "ms_per_step": pms / args.plain_steps,
                  "mapping": "one thread per env, beams in sequence, bitmap in HBM"}
     sim_tuning = sim.get_tuning()
+    proposal = None
+    if w.get("proposer") and not args.no_proposal:
+        proposal = reset_proposal_gain(sim, w, args)
     sim.close()
 
     cpu = None if args.no_cpu else cpu_baseline(w, acts_np[args.warmup:], rays_per_step / N)
@@ -252,6 +318,7 @@ def main():
         "rays_per_s": value * rays_per_step / N,
         "graph_rollout": rollout,
         "march_scan": march,
+        "reset_proposal": proposal,
         "plain": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "tuning": sim_tuning,

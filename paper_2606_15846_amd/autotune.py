@@ -20,8 +20,9 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_FILE = os.path.join(HERE, "tuning.json")
-DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4}
-SPACE = {"tile_envs": (4, 8, 16), "refill_at": (32, 40, 48, 56), "groups": (2, 4, 8)}
+DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4, "ray_slots": 0}
+SPACE = {"tile_envs": (4, 8, 16), "refill_at": (32, 40, 48, 56), "groups": (4, 8, 16),
+         "ray_slots": (0, 512, 1024)}
 
 
 def workload_key(cfg: dict, maps, profiles=None) -> str:
@@ -43,7 +44,10 @@ def load_all() -> dict:
 
 def best_for(key: str) -> dict:
     entry = load_all().get(key)
-    return dict(entry["best"]) if entry else dict(DEFAULT)
+    best = dict(DEFAULT)
+    if entry:
+        best.update(entry["best"])
+    return best
 
 
 def save(key: str, best: dict, table: list, device_name: str, path: str = TUNING_FILE):
@@ -75,21 +79,23 @@ def tune(sim, acts, steps: int = 50, space: dict | None = None, verbose: bool = 
     space = space or SPACE
     start = sim.get_state()
     table = []
-    for te, ra, gr in itertools.product(space["tile_envs"], space["refill_at"], space["groups"]):
+    for te, ra, gr, rs in itertools.product(space["tile_envs"], space["refill_at"],
+                                            space["groups"], space["ray_slots"]):
+        shape = {"tile_envs": te, "refill_at": ra, "groups": gr, "ray_slots": rs}
         try:
-            sim.set_tuning(te, ra, gr)
+            sim.set_tuning(**shape)
         except Exception as exc:  # a shape the map does not fit (LDS)
-            table.append({"tile_envs": te, "refill_at": ra, "groups": gr, "error": str(exc)})
+            table.append(dict(shape, error=str(exc)))
             continue
         time_steps(sim, acts, start, min(5, steps))  # settle
         ms = time_steps(sim, acts, start, steps)
-        table.append({"tile_envs": te, "refill_at": ra, "groups": gr, "ms_per_step": ms})
+        table.append(dict(shape, ms_per_step=ms))
         if verbose:
-            print(f"tile_envs={te:2d} refill_at={ra:2d} groups={gr} -> {ms * 1e3:8.1f} us/step",
-                  flush=True)
+            print(f"tile_envs={te:2d} refill_at={ra:2d} groups={gr:2d} ray_slots={rs:4d} -> "
+                  f"{ms * 1e3:8.1f} us/step", flush=True)
     ok = [r for r in table if "ms_per_step" in r]
     best = min(ok, key=lambda r: r["ms_per_step"])
-    best = {k: best[k] for k in ("tile_envs", "refill_at", "groups")}
+    best = {k: best[k] for k in ("tile_envs", "refill_at", "groups", "ray_slots")}
     sim.set_tuning(**best)
     sim.set_state(start)
     return best, table

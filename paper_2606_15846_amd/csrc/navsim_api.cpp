@@ -142,15 +142,20 @@ navsim_status upload(T **dst, const std::vector<T> &src) {
 
 // LDS walk slots per chunk, keeping the beam table in LDS when a full tile's
 // rays still fit next to it, else reading it from device memory.
-int choose_ray_cap(int max_words, const navsim_config &c, int tile_envs, bool &beams_lds) {
+int choose_ray_cap(int max_words, const navsim_config &c, int tile_envs, int slots,
+                   bool &beams_lds) {
+    int cap;
     const int with = fused_ray_cap(max_words, c.num_sectors, tile_envs, c.num_beams, true);
     if (with >= tile_envs * c.num_beams) {
         beams_lds = true;
-        return with;
+        cap = with;
+    } else {
+        const int without = fused_ray_cap(max_words, c.num_sectors, tile_envs, c.num_beams, false);
+        beams_lds = without <= with;
+        cap = beams_lds ? with : without;
     }
-    const int without = fused_ray_cap(max_words, c.num_sectors, tile_envs, c.num_beams, false);
-    beams_lds = without <= with;
-    return beams_lds ? with : without;
+    if (cap > 0 && slots > 0) cap = std::min(cap, std::max(256, (slots + 63) & ~63));
+    return cap;
 }
 
 // Envs grouped by map (stable in env order) into tiles of up to tile_envs envs,
@@ -492,7 +497,7 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
     }
 
     bool beams_lds = true;
-    const int ray_cap = choose_ray_cap(max_words, cfg, h->tile_envs, beams_lds);
+    const int ray_cap = choose_ray_cap(max_words, cfg, h->tile_envs, h->ray_slots, beams_lds);
     if (ray_cap == 0)
         return fail(NAVSIM_E_UNSUPPORTED,
                     "largest map, %d beams and %d sectors do not fit 64 KiB of LDS per workgroup",
@@ -691,16 +696,20 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     if (t->refill_at < 0 || t->refill_at > 63)
         return fail(NAVSIM_E_INVALID_ARG, "refill_at must be in 0..63");
     if (t->groups < 1 || t->groups > 64) return fail(NAVSIM_E_INVALID_ARG, "groups must be in 1..64");
+    if (t->ray_slots < 0 || (t->ray_slots > 0 && t->ray_slots < 256))
+        return fail(NAVSIM_E_INVALID_ARG, "ray_slots must be 0 or >= 256");
     {
         DeviceGuard g(h->device);
         drop_graph(h);
     }
     int ray_cap = h->ray_cap;
     bool beams_lds = h->beams_lds;
-    if (h->loaded && t->tile_envs != h->tile_envs) {
-        ray_cap = choose_ray_cap(h->max_words, h->cfg, t->tile_envs, beams_lds);
+    if (h->loaded) {
+        ray_cap = choose_ray_cap(h->max_words, h->cfg, t->tile_envs, t->ray_slots, beams_lds);
         if (ray_cap == 0)
             return fail(NAVSIM_E_UNSUPPORTED, "tile_envs %d does not fit LDS", t->tile_envs);
+    }
+    if (h->loaded && t->tile_envs != h->tile_envs) {
         std::vector<int32_t> perm;
         std::vector<Tile> tiles;
         build_tiles(h->host_env_map, t->tile_envs, perm, tiles);
@@ -719,6 +728,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     h->tile_envs = t->tile_envs;
     h->refill_at = t->refill_at;
     h->groups = t->groups;
+    h->ray_slots = t->ray_slots;
     h->ray_cap = ray_cap;
     h->beams_lds = beams_lds;
     return NAVSIM_OK;
@@ -730,6 +740,7 @@ navsim_status navsim_get_tuning(navsim_t h, navsim_tuning *t) {
     t->tile_envs = h->tile_envs;
     t->refill_at = h->refill_at;
     t->groups = h->groups;
+    t->ray_slots = h->ray_slots;
     return NAVSIM_OK;
 }
 

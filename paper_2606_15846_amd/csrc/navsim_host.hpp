@@ -59,6 +59,7 @@ struct navsim_s {
     int num_maps = 0, num_tiles = 0, max_words = 0;
     int tile_envs = navsim::kDefaultTileEnvs, refill_at = navsim::kDefaultRefillAt, groups = navsim::kDefaultGroups;
     int ray_cap = 0;
+    int ray_slots = 0;  // requested cap on ray_cap (0 = automatic)
     bool beams_lds = true;
     int scan_mode = 0;       // 0 exact traversal, 1 fixed-step march
     int march_kmax = 0;

@@ -363,10 +363,12 @@ def test_launch_shape_does_not_change_results():
     w = configs.build_workload("c2", num_envs=600)
     acts = configs.uniform_actions(3, 600, seed=21)
     ref_out = None
-    for te, ra, gr in [(4, 48, 4), (8, 32, 2), (16, 56, 8), (4, 0, 1), (8, 63, 64)]:
+    for te, ra, gr, rs in [(4, 48, 4, 0), (8, 32, 2, 0), (16, 56, 8, 0), (4, 0, 1, 0),
+                           (8, 63, 64, 0), (4, 40, 8, 256), (16, 48, 4, 600)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
-        sim.set_tuning(te, ra, gr)
-        assert sim.get_tuning() == {"tile_envs": te, "refill_at": ra, "groups": gr}
+        sim.set_tuning(te, ra, gr, rs)
+        assert sim.get_tuning() == {"tile_envs": te, "refill_at": ra, "groups": gr,
+                                    "ray_slots": rs}
         sim.reset()
         outs = []
         for t in range(3):
@@ -377,7 +379,7 @@ def test_launch_shape_does_not_change_results():
         else:
             for (ga, sa), (gb, sb) in zip(ref_out, outs):
                 for k in ga:
-                    assert np.array_equal(ga[k], gb[k]) or k == "final_obs", (te, ra, gr, k)
+                    assert np.array_equal(ga[k], gb[k]) or k == "final_obs", (te, ra, gr, rs, k)
                 for k in oracle.STATE_KEYS:
-                    assert np.array_equal(sa[k], sb[k]), (te, ra, gr, k)
+                    assert np.array_equal(sa[k], sb[k]), (te, ra, gr, rs, k)
         sim.close()
