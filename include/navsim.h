@@ -237,7 +237,7 @@ navsim_status navsim_set_scan(navsim_t h, int32_t mode, float step_m);
 /* Launch shape of the fused step.  Results never depend on it (bitwise); it
  * only moves work between lanes, wavefronts and workgroups. */
 typedef struct {
-    int32_t tile_envs;  /* envs per workgroup (they share one staged map): 4, 8 or 16     */
+    int32_t tile_envs;  /* envs per workgroup (they share one staged map): 1, 2, 4, 8, 16 */
     int32_t refill_at;  /* a wavefront hands new rays to its idle lanes once at most this
                            many of its 64 lanes are still walking, 0..63                  */
     int32_t groups;     /* 4-cell groups a lane walks between refill checks, 1..64        */

@@ -21,7 +21,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_FILE = os.path.join(HERE, "tuning.json")
 DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4, "ray_slots": 0}
-SPACE = {"tile_envs": (4, 8, 16), "refill_at": (32, 40, 48, 56), "groups": (4, 8, 16),
+SPACE = {"tile_envs": (1, 2, 4, 8), "refill_at": (32, 40, 48, 56), "groups": (4, 8, 16),
          "ray_slots": (0, 512, 1024)}
 
 

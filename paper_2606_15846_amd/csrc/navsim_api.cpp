@@ -692,7 +692,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
     if (!t) return fail(NAVSIM_E_INVALID_ARG, "tuning is NULL");
     if (!fused_tile_envs_supported(t->tile_envs))
-        return fail(NAVSIM_E_INVALID_ARG, "tile_envs must be 4, 8 or 16");
+        return fail(NAVSIM_E_INVALID_ARG, "tile_envs must be 1, 2, 4, 8 or 16");
     if (t->refill_at < 0 || t->refill_at > 63)
         return fail(NAVSIM_E_INVALID_ARG, "refill_at must be in 0..63");
     if (t->groups < 1 || t->groups > 64) return fail(NAVSIM_E_INVALID_ARG, "groups must be in 1..64");

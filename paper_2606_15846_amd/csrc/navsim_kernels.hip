@@ -539,10 +539,14 @@ struct TileJob {
 constexpr int kFusedThreads = 256;
 constexpr int kGroupLanes = 16;
 
+// Sector-pool words of a tile ([2E][m]), rounded up to keep the LDS regions
+// after it 16-byte aligned.
+__host__ __device__ constexpr int pool_words(int E, int m) { return (2 * E * m + 3) & ~3; }
+
 size_t fused_lds_bytes(int max_words, int m, int E, int K, int ray_cap) {
     // K = 0 when the beam table stays in device memory
     return (size_t)max_words * 4u + 2u * (size_t)E * sizeof(TileJob) +
-           2u * (size_t)E * (size_t)m * 4u + (4u * (size_t)E + 8u) * 4u + 16u * (size_t)K +
+           (size_t)pool_words(E, m) * 4u + (4u * (size_t)E + 8u) * 4u + 16u * (size_t)K +
            16u * (size_t)ray_cap;
 }
 
@@ -864,7 +868,7 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
     uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem4);
     TileJob *s_jobs = reinterpret_cast<TileJob *>(s_bits + p.max_words);  // [2E]: main, reset
     uint32_t *s_pool = reinterpret_cast<uint32_t *>(s_jobs + 2 * E);      // [2E][m]
-    int *s_list = reinterpret_cast<int *>(s_pool + 2 * E * p.m);          // [2E] active jobs
+    int *s_list = reinterpret_cast<int *>(s_pool + pool_words(E, p.m));   // [2E] active jobs
     int *s_misc = s_list + 2 * E;  // [0] active jobs, [1] next ray, [2..] done flags
     double2 *s_beam = reinterpret_cast<double2 *>(s_misc + 2 * E + 8);  // [K] beams, or global
     uint4 *s_ray = reinterpret_cast<uint4 *>(s_beam + (p.beams_lds ? p.K : 0));  // [ray_cap]
@@ -1231,7 +1235,7 @@ static hipError_t launch_fused_e(const StepParams &p, hipStream_t s) {
     return hipGetLastError();
 }
 
-bool fused_tile_envs_supported(int E) { return E == 4 || E == 8 || E == 16; }
+bool fused_tile_envs_supported(int E) { return E == 1 || E == 2 || E == 4 || E == 8 || E == 16; }
 
 // LDS walk slots per chunk: the rays of a full tile plus one reset pose
 // ((E + 1) K, rounded up to a wavefront), so a tile walks a second chunk only
@@ -1246,6 +1250,8 @@ int fused_ray_cap(int max_words, int m, int E, int K, bool beams_lds) {
 hipError_t launch_fused(const StepParams &p, int tile_envs, hipStream_t s) {
     if (p.num_tiles == 0) return hipSuccess;
     switch (tile_envs) {
+        case 1: return launch_fused_e<1>(p, s);
+        case 2: return launch_fused_e<2>(p, s);
         case 4: return launch_fused_e<4>(p, s);
         case 8: return launch_fused_e<8>(p, s);
         case 16: return launch_fused_e<16>(p, s);

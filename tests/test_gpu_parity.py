@@ -146,6 +146,21 @@ def test_mixed_profiles_launch_shapes_agree():
                 assert np.array_equal(sa[k], sb[k]), k
 
 
+@pytest.mark.parametrize("te", [1, 2, 4])
+def test_small_tiles_with_an_odd_sector_count(te):
+    # m = 9: a tile's sector pool is 2 E m words, padded to keep the LDS
+    # regions after it aligned
+    say(f"odd m = 9, K = 99, tile_envs = {te}: fused == plain == oracle")
+    from workloads import maps as gm
+    occ = gm.gen_rect_disc_map(17, w=80, h=72, res=0.05)
+    cfg = _small_cfg(num_envs=21, num_beams=99, num_sectors=9)
+    env_map = np.zeros(21, np.int32)
+    sim, ref = make_pair(cfg, [occ], [0.05], env_map)
+    sim.set_tuning(te, 48, 4)
+    run_teacher_forced(sim, ref, 12, NAVSIM_KERNEL_FUSED, seed=3, label=f"m9/E{te}")
+    sim.close()
+
+
 def test_profile_validation_on_device():
     cfg, occ, res, env_map, prof = _mixed_small(num_envs=12)
     for bad in [dict(num_beams=1110), dict(num_beams=100), dict(num_beams=0),
@@ -364,7 +379,8 @@ def test_launch_shape_does_not_change_results():
     acts = configs.uniform_actions(3, 600, seed=21)
     ref_out = None
     for te, ra, gr, rs in [(4, 48, 4, 0), (8, 32, 2, 0), (16, 56, 8, 0), (4, 0, 1, 0),
-                           (8, 63, 64, 0), (4, 40, 8, 256), (16, 48, 4, 600)]:
+                           (8, 63, 64, 0), (4, 40, 8, 256), (16, 48, 4, 600), (1, 48, 8, 0),
+                           (2, 40, 8, 0), (1, 32, 16, 256)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
         sim.set_tuning(te, ra, gr, rs)
         assert sim.get_tuning() == {"tile_envs": te, "refill_at": ra, "groups": gr,
