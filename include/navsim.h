@@ -245,9 +245,11 @@ typedef struct {
                            one reset scan, as LDS allows; else at most this many (>= 256,
                            rounded up to 64).  Fewer slots: less LDS, more workgroups per
                            CU, more chunks per tile                                       */
+    int32_t walk;       /* 0: cells in groups of 4; 1: runs of cells between minor-axis
+                           steps (32 cells per test along x) -- same cells, same results  */
 } navsim_tuning;
 
-/* Set the fused step's launch shape (defaults: 4, 48, 4, 0).  Changing tile_envs
+/* Set the fused step's launch shape (defaults: 4, 48, 4, 0, 0).  Changing tile_envs
  * after navsim_load_maps waits for the device and re-groups the envs; returns
  * NAVSIM_E_UNSUPPORTED if the larger tile would not fit LDS. */
 navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t);

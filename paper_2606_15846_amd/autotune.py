@@ -20,9 +20,9 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_FILE = os.path.join(HERE, "tuning.json")
-DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4, "ray_slots": 0}
-SPACE = {"tile_envs": (1, 2, 4, 8), "refill_at": (32, 40, 48, 56), "groups": (4, 8, 16),
-         "ray_slots": (0, 512, 1024)}
+DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4, "ray_slots": 0, "walk": 0}
+SPACE = {"tile_envs": (1, 2, 4, 8), "refill_at": (32, 48, 56), "groups": (2, 4, 8),
+         "ray_slots": (0, 512), "walk": (0, 1)}
 
 
 def workload_key(cfg: dict, maps, profiles=None) -> str:
@@ -79,9 +79,9 @@ def tune(sim, acts, steps: int = 50, space: dict | None = None, verbose: bool = 
     space = space or SPACE
     start = sim.get_state()
     table = []
-    for te, ra, gr, rs in itertools.product(space["tile_envs"], space["refill_at"],
-                                            space["groups"], space["ray_slots"]):
-        shape = {"tile_envs": te, "refill_at": ra, "groups": gr, "ray_slots": rs}
+    for te, ra, gr, rs, wk in itertools.product(space["tile_envs"], space["refill_at"],
+                                                space["groups"], space["ray_slots"], space["walk"]):
+        shape = {"tile_envs": te, "refill_at": ra, "groups": gr, "ray_slots": rs, "walk": wk}
         try:
             sim.set_tuning(**shape)
         except Exception as exc:  # a shape the map does not fit (LDS)
@@ -91,11 +91,11 @@ def tune(sim, acts, steps: int = 50, space: dict | None = None, verbose: bool = 
         ms = time_steps(sim, acts, start, steps)
         table.append(dict(shape, ms_per_step=ms))
         if verbose:
-            print(f"tile_envs={te:2d} refill_at={ra:2d} groups={gr:2d} ray_slots={rs:4d} -> "
-                  f"{ms * 1e3:8.1f} us/step", flush=True)
+            print(f"tile_envs={te:2d} refill_at={ra:2d} groups={gr:2d} ray_slots={rs:4d} "
+                  f"walk={wk} -> {ms * 1e3:8.1f} us/step", flush=True)
     ok = [r for r in table if "ms_per_step" in r]
     best = min(ok, key=lambda r: r["ms_per_step"])
-    best = {k: best[k] for k in ("tile_envs", "refill_at", "groups", "ray_slots")}
+    best = {k: best[k] for k in ("tile_envs", "refill_at", "groups", "ray_slots", "walk")}
     sim.set_tuning(**best)
     sim.set_state(start)
     return best, table

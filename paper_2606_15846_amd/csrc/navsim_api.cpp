@@ -321,6 +321,7 @@ StepParams navsim::make_step_params(const navsim_s *h) {
     p.ray_cap = h->ray_cap;
     p.beams_lds = h->beams_lds ? 1 : 0;
     p.scan_mode = h->scan_mode;
+    p.walk_mode = h->walk_mode;
     p.march_kmax = h->march_kmax;
     p.march_h = h->march_h;
     return p;
@@ -698,6 +699,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     if (t->groups < 1 || t->groups > 64) return fail(NAVSIM_E_INVALID_ARG, "groups must be in 1..64");
     if (t->ray_slots < 0 || (t->ray_slots > 0 && t->ray_slots < 256))
         return fail(NAVSIM_E_INVALID_ARG, "ray_slots must be 0 or >= 256");
+    if (t->walk != 0 && t->walk != 1) return fail(NAVSIM_E_INVALID_ARG, "walk must be 0 or 1");
     {
         DeviceGuard g(h->device);
         drop_graph(h);
@@ -729,6 +731,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     h->refill_at = t->refill_at;
     h->groups = t->groups;
     h->ray_slots = t->ray_slots;
+    h->walk_mode = t->walk;
     h->ray_cap = ray_cap;
     h->beams_lds = beams_lds;
     return NAVSIM_OK;
@@ -741,6 +744,7 @@ navsim_status navsim_get_tuning(navsim_t h, navsim_tuning *t) {
     t->refill_at = h->refill_at;
     t->groups = h->groups;
     t->ray_slots = h->ray_slots;
+    t->walk = h->walk_mode;
     return NAVSIM_OK;
 }
 

@@ -60,6 +60,7 @@ struct navsim_s {
     int tile_envs = navsim::kDefaultTileEnvs, refill_at = navsim::kDefaultRefillAt, groups = navsim::kDefaultGroups;
     int ray_cap = 0;
     int ray_slots = 0;  // requested cap on ray_cap (0 = automatic)
+    int walk_mode = 0;  // fused walk: 0 cells in groups of 4, 1 runs
     bool beams_lds = true;
     int scan_mode = 0;       // 0 exact traversal, 1 fixed-step march
     int march_kmax = 0;

@@ -53,6 +53,7 @@ struct DevState {
 struct StepParams {
     int32_t N, K, m, horizon, tries, mode;  // K: largest beam count; mode 0 step, 1 reset
     int32_t refill_at, groups;  // fused walk: refill threshold, 4-cell groups per check
+    int32_t walk_mode;          // fused walk: 0 cells in groups of 4, 1 runs
     int32_t ray_cap;            // rays walked per chunk (LDS slots)
     int32_t beams_lds;          // stage the beam table in LDS
     int32_t scan_mode;          // 0 exact traversal, 1 fixed-step march

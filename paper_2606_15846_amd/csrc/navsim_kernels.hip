@@ -788,6 +788,153 @@ __device__ __forceinline__ void finish_march(const StepParams &p, const MapView 
     }
 }
 
+// Run walk (launch shape walk = 1): the same cell sequence as the 4-cell
+// group walk, taken a run at a time.  Along the ray's major axis the cells
+// between two minor-axis steps form a run; with E' the decision variable
+// (x step iff E' < 0, +DY after an x step, -DX after a y step) a run's length
+// follows from E' by one division for the first two runs and afterwards from
+// the recurrence c = q + [v < r], v <- v - r + [v < r] Dmin (q, r: quotient
+// and remainder of Dmaj / Dmin; v the residual of E' at the run's end), with
+// no division.  A run along x is tested 32 cells at a time from a 64-bit
+// window of two bitmap words (bit-reversed when walking toward -x), a run
+// along y 4 cells at a time.
+__device__ __forceinline__ int run_length(bool xmaj, int &Ep, int DX, int DY, int Dmin, int q,
+                                          int rr, int &vv, int &exact, int rem) {
+    if (exact > 0 || Dmin == 0) {
+        int c;
+        if (xmaj) {
+            c = Ep < 0 ? (DY ? (int)(((uint32_t)(-Ep) + (uint32_t)DY - 1u) / (uint32_t)DY) : rem)
+                       : 0;
+            if (DY) Ep += c * DY;
+        } else {
+            c = Ep >= 0 ? (DX ? (int)((uint32_t)Ep / (uint32_t)DX) + 1 : rem) : 0;
+            if (DX) Ep -= c * DX;
+        }
+        if (Dmin != 0 && --exact == 0) vv = xmaj ? Ep : -1 - Ep;
+        return c;
+    }
+    const int b = vv < rr ? 1 : 0;
+    vv = vv - rr + (b ? Dmin : 0);
+    return q + b;
+}
+
+__device__ __forceinline__ void run_walk(const StepParams &p, const MapView &M,
+                                         const uint32_t *s_bits, uint4 *s_ray, int *s_misc,
+                                         int Rc, int lane) {
+    int r = -1, B = 0, k = 0, rem = 0, Ep = 0, vv = 0, q = 0, rr = 0, Dmin = 0, DX = 0, DY = 0;
+    int inc_maj = 0, inc_min = 0, exact = 0, cl = 0;
+    bool act = false, exhausted = false, xmaj = false;
+    uint32_t flags = 0u;
+    for (;;) {
+        uint64_t am = __ballot(act);
+        if (!exhausted && __popcll(am) <= p.refill_at) {
+            if (!act && r >= 0) {
+                reinterpret_cast<uint2 *>(s_ray)[2 * r] =
+                    make_uint2((uint32_t)B | ((uint32_t)k << 19), flags);
+                r = -1;
+            }
+            const uint64_t idle = ~am;
+            const int nidle = 64 - __popcll(am);
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
+            base = __shfl(base, 0);
+            const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
+            if (!act && my < Rc) {
+                const uint4 v = s_ray[my];
+                r = my;
+                B = (int)(v.x & 0x7FFFFu);
+                rem = (int)(v.x >> 19);
+                Ep = (int)v.y;
+                DX = (int)(v.z & 0x7FFFFFFFu);
+                DY = (int)(v.w & 0x7FFFFFFFu);
+                const int incx = (v.z >> 31) ? 1 : -1;
+                const int incy = (v.w >> 31) ? M.pitch : -M.pitch;
+                xmaj = DX >= DY;
+                inc_maj = xmaj ? incx : incy;
+                inc_min = xmaj ? incy : incx;
+                Dmin = xmaj ? DY : DX;
+                const int Dmaj = xmaj ? DX : DY;
+                q = Dmin ? (int)((uint32_t)Dmaj / (uint32_t)Dmin) : 0;
+                rr = Dmaj - q * Dmin;
+                exact = 2;
+                k = 0;
+                flags = 0u;
+                cl = run_length(xmaj, Ep, DX, DY, Dmin, q, rr, vv, exact, rem);
+                act = rem > 0;
+            }
+            exhausted = base + nidle >= Rc;
+            am = __ballot(act);
+        }
+        if (am == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+        if (act) {
+#pragma unroll 1
+            for (int gi = 0; gi < p.groups; ++gi) {
+                const int chunk = min(min(cl, rem), xmaj ? 32 : 4);
+                uint32_t mk = 0u;
+                if (chunk > 0) {
+                    if (xmaj) {
+                        if (inc_maj > 0) {
+                            const int s0 = B + 1;
+                            const uint64_t w = ((uint64_t)s_bits[(s0 >> 5) + 1] << 32) |
+                                               (uint64_t)s_bits[s0 >> 5];
+                            mk = (uint32_t)(w >> (s0 & 31));
+                        } else {
+                            const int e = B - 1;
+                            const uint64_t w = ((uint64_t)s_bits[e >> 5] << 32) |
+                                               (uint64_t)s_bits[(e >> 5) - 1];
+                            mk = __brev((uint32_t)((w << (31 - (e & 31))) >> 32));
+                        }
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int Bt = B + inc_maj * (t + 1);
+                            mk |= ((s_bits[Bt >> 5] >> (Bt & 31)) & 1u) << t;
+                        }
+                    }
+                    if (chunk < 32) mk &= (1u << chunk) - 1u;
+                }
+                if (mk) {
+                    const int t = (int)__builtin_ctz(mk);
+                    B += inc_maj * (t + 1);
+                    k += t + 1;
+                    flags = 1u;
+                    act = false;
+                    break;
+                }
+                B += inc_maj * chunk;
+                k += chunk;
+                rem -= chunk;
+                cl -= chunk;
+                if (rem <= 0) {
+                    act = false;
+                    break;
+                }
+                if (cl > 0) continue;
+                // the minor-axis step that ends the run
+                B += inc_min;
+                k += 1;
+                rem -= 1;
+                if (exact > 0 || Dmin == 0) Ep = xmaj ? Ep - DX : Ep + DY;
+                if ((s_bits[B >> 5] >> (B & 31)) & 1u) {
+                    flags = 1u;
+                    act = false;
+                    break;
+                }
+                if (rem <= 0) {
+                    act = false;
+                    break;
+                }
+                cl = run_length(xmaj, Ep, DX, DY, Dmin, q, rr, vv, exact, rem);
+            }
+        }
+    }
+    if (r >= 0)
+        reinterpret_cast<uint2 *>(s_ray)[2 * r] = make_uint2((uint32_t)B | ((uint32_t)k << 19), flags);
+}
+
 // Phase (2) for the fixed-step march: the refilling walk of the traversal
 // with each lane marching its ray in groups of 4 samples (bitmap in LDS);
 // the result k | outcome << 28 goes back to the ray's slot.
@@ -1010,6 +1157,8 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
         // lanes of its wavefront are still walking
         if (p.scan_mode == 1) {
             march_walk(p, M, s_jobs, s_list, s_beam, s_ray, s_misc, c0, Rc, K, inv_K, lane);
+        } else if (p.walk_mode == 1) {
+            run_walk(p, M, s_bits, s_ray, s_misc, Rc, lane);
         } else {
         int r = -1;
         bool act = false, exhausted = false;

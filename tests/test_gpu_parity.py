@@ -75,6 +75,20 @@ def test_c2_plain_subset():
     sim.close()
 
 
+def test_run_walk_against_oracle():
+    say("run walk (walk = 1): c2 full size and c3 maps, fused, teacher-forced")
+    w = configs.build_workload("c2")
+    sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
+    sim.set_tuning(4, 48, 4, 0, 1)
+    run_teacher_forced(sim, ref, 3, NAVSIM_KERNEL_FUSED, label="c2/runs")
+    sim.close()
+    w = configs.build_workload("c3", num_envs=1024)
+    sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
+    sim.set_tuning(2, 40, 8, 0, 1)
+    run_teacher_forced(sim, ref, 3, NAVSIM_KERNEL_FUSED, label="c3/runs")
+    sim.close()
+
+
 def test_c3_rect_reverse_fused():
     say("c3 maps 256^2, rectangle footprint, 720 beams, 2048 envs, fused, 3 steps")
     w = configs.build_workload("c3", num_envs=2048)
@@ -378,13 +392,15 @@ def test_launch_shape_does_not_change_results():
     w = configs.build_workload("c2", num_envs=600)
     acts = configs.uniform_actions(3, 600, seed=21)
     ref_out = None
-    for te, ra, gr, rs in [(4, 48, 4, 0), (8, 32, 2, 0), (16, 56, 8, 0), (4, 0, 1, 0),
-                           (8, 63, 64, 0), (4, 40, 8, 256), (16, 48, 4, 600), (1, 48, 8, 0),
-                           (2, 40, 8, 0), (1, 32, 16, 256)]:
+    for te, ra, gr, rs, wk in [(4, 48, 4, 0, 0), (8, 32, 2, 0, 0), (16, 56, 8, 0, 0),
+                               (4, 0, 1, 0, 0), (8, 63, 64, 0, 0), (4, 40, 8, 256, 0),
+                               (16, 48, 4, 600, 0), (1, 48, 8, 0, 0), (2, 40, 8, 0, 0),
+                               (1, 32, 16, 256, 0), (4, 48, 4, 0, 1), (1, 40, 2, 0, 1),
+                               (16, 0, 1, 256, 1), (8, 63, 64, 0, 1)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
-        sim.set_tuning(te, ra, gr, rs)
+        sim.set_tuning(te, ra, gr, rs, wk)
         assert sim.get_tuning() == {"tile_envs": te, "refill_at": ra, "groups": gr,
-                                    "ray_slots": rs}
+                                    "ray_slots": rs, "walk": wk}
         sim.reset()
         outs = []
         for t in range(3):
@@ -395,7 +411,7 @@ def test_launch_shape_does_not_change_results():
         else:
             for (ga, sa), (gb, sb) in zip(ref_out, outs):
                 for k in ga:
-                    assert np.array_equal(ga[k], gb[k]) or k == "final_obs", (te, ra, gr, rs, k)
+                    assert np.array_equal(ga[k], gb[k]) or k == "final_obs", (te, ra, gr, rs, wk, k)
                 for k in oracle.STATE_KEYS:
-                    assert np.array_equal(sa[k], sb[k]), (te, ra, gr, rs, k)
+                    assert np.array_equal(sa[k], sb[k]), (te, ra, gr, rs, wk, k)
         sim.close()
