@@ -140,6 +140,7 @@ def main():
     ap.add_argument("--rollout-steps", type=int, default=64)
     ap.add_argument("--no-march", action="store_true")
     ap.add_argument("--no-proposal", action="store_true")
+    ap.add_argument("--no-policy", action="store_true")
     ap.add_argument("--label-starts", type=int, default=16384)
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--proposal-requests", type=int, default=8192)
@@ -271,6 +272,28 @@ def main():
     rollout = {"value": N * T * reps / (rms / 1e3), "unit": "env-steps/s",
                "steps_per_rollout": T, "rollouts": reps, "ms_per_step": rms / (T * reps),
                "actions": "in-kernel Philox stream 4", "launch": "HIP graph of T fused steps"}
+    # the paper's actor in front of every step (graph of T actor + step launches)
+    policy = None
+    if not args.no_policy:
+        from paper_2606_15846_amd.policy import Policy
+        pol = Policy(sim)
+        pol.init_params(seed=3, beta=-0.1)
+        sim.set_state(start_state)
+        obs0 = sim.obs.clone()
+        pol.rollout(T, 0, obs0, noise_std=0.1, buffers=bufs)  # capture + warm
+        torch.cuda.synchronize()
+        q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        q0.record(stream)
+        for r in range(reps):
+            pol.rollout(T, (r + 1) * T, obs0, noise_std=0.1, buffers=bufs)
+        q1.record(stream)
+        torch.cuda.synchronize()
+        qms = q0.elapsed_time(q1)
+        policy = {"value": N * T * reps / (qms / 1e3), "unit": "env-steps/s",
+                  "ms_per_step": qms / (T * reps), "steps_per_rollout": T,
+                  "actor": f"{pol.dims} leaky ReLU, tanh, bf16 matrix cores",
+                  "launch": "HIP graph of T (actor + fused step)"}
+        pol.close()
     del bufs
 
     plain = None
@@ -318,6 +341,7 @@ def main():
                                  else "disc" if cfg["footprint"] == 0 else "rect")},
         "rays_per_s": value * rays_per_step / N,
         "graph_rollout": rollout,
+        "policy_rollout": policy,
         "march_scan": march,
         "reset_proposal": proposal,
         "plain": plain,
