@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--no-march", action="store_true")
     ap.add_argument("--no-proposal", action="store_true")
     ap.add_argument("--no-policy", action="store_true")
-    ap.add_argument("--label-starts", type=int, default=16384)
+    ap.add_argument("--label-starts", type=int, default=131072)
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--proposal-requests", type=int, default=8192)
     ap.add_argument("--march-step", type=float, default=0.03)

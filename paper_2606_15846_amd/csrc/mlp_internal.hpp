@@ -69,6 +69,27 @@ hipError_t launch_actor_input(int N, int m, const float *obs, const float *beta,
 hipError_t launch_actor_noise(int N, float *act, float std, const uint32_t *step_ctr, int step_off,
                               uint32_t key0, uint32_t key1, hipStream_t s);
 
+// The whole actor in one launch (inputs, every layer, tanh, noise): weights
+// as a padded bf16 image, layer l [npad[l]][kpad[l]] at w_off[l], zeros in
+// the padding; npad[l] <= kpad[l + 1]; kpad and kmax multiples of 32, npad of
+// 16, kmax >= every kpad.
+constexpr int kActorMaxLayers = 5;
+struct ActorArgs {
+    int N = 0, m = 0, layers = 0, kmax = 0;
+    int kpad[kActorMaxLayers] = {}, npad[kActorMaxLayers] = {};
+    int64_t w_off[kActorMaxLayers] = {}, b_off[kActorMaxLayers] = {};
+    const uint16_t *w = nullptr;
+    const float *b = nullptr;  // biases, padded with zeros to npad
+    const float *beta = nullptr;
+    const float *obs = nullptr;
+    float *act = nullptr;
+    float slope = 0.01f, std = 0.0f;
+    const uint32_t *step_ctr = nullptr;
+    int step_off = 0;
+    uint32_t key0 = 0, key1 = 0;
+};
+hipError_t launch_actor_fused(const ActorArgs &a, hipStream_t s);
+
 // Float to bfloat16 (round to nearest even), n elements.
 hipError_t launch_to_bf16(int64_t n, const float *x, uint16_t *y, hipStream_t s);
 

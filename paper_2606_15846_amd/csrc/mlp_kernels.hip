@@ -221,9 +221,99 @@ __global__ void actor_noise_kernel(int N, float *act, float std, const uint32_t 
     act[2 * e + 1] = fminf(1.0f, fmaxf(-1.0f, a1));
 }
 
+// Whole actor in one launch: each wavefront takes 16 observation rows, builds
+// their bf16 inputs in LDS (reciprocal range transform), then runs every
+// layer as 16 x 16 x 32 bf16 MFMA tiles with its weights read from a padded
+// bf16 image (k-contiguous rows, K padded to 32, N to 16, zeros outside) and
+// writes bias + activation back to its LDS rows as the next layer's input;
+// the last layer applies tanh, the exploration noise and the clip, and
+// stores the two action components.  Same tiles, k order and rounding points
+// as the layer-by-layer GEMM path.
+__global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t act_lds[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = (blockIdx.x * 4 + wave) * 16;
+    const int ld = a.kmax;  // LDS row pitch (bf16), multiple of 32
+    uint16_t *buf[2] = {act_lds + (size_t)wave * 32 * ld, act_lds + (size_t)wave * 32 * ld + 16 * ld};
+    const int row = a.m + 4;
+    // inputs
+    for (int q = lane; q < 16 * a.kpad[0]; q += 64) {
+        const int r = q / a.kpad[0], j = q - r * a.kpad[0];
+        const int e = row0 + r;
+        float v = 0.0f;
+        if (e < a.N && j < row) {
+            const float o = a.obs[(int64_t)e * row + j];
+            v = j < a.m ? 1.0f / (o - *a.beta) : o;
+        }
+        buf[0][r * ld + j] = to_bf16_bits(v);
+    }
+    __syncthreads();
+    int cur = 0;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    for (int l = 0; l < a.layers; ++l) {
+        const int kp = a.kpad[l], np = a.npad[l];
+        const uint16_t *W = a.w + a.w_off[l];
+        const float *bias = a.b + a.b_off[l];
+        const bool last = l + 1 == a.layers;
+        for (int n0 = 0; n0 < np; n0 += 16) {
+            f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int k0 = 0; k0 < kp; k0 += 32) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&buf[cur][fr * ld + k0 + fk]);
+                const bf16x8 bv =
+                    *reinterpret_cast<const bf16x8 *>(W + (int64_t)(n0 + fr) * kp + k0 + fk);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+            }
+            const int n = n0 + fr;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = (lane >> 4) * 4 + r;
+                float v = acc[r] + bias[n];
+                if (!last) {
+                    if (!(v > 0.0f)) v *= a.slope;
+                    buf[1 - cur][rr * ld + n] = to_bf16_bits(v);
+                } else if (n < 2) {
+                    const int e = row0 + rr;
+                    if (e < a.N) {
+                        v = tanhf(v);
+                        if (a.std > 0.0f) {
+                            const uint64_t st = (((uint64_t)a.step_ctr[1] << 32) |
+                                                 (uint64_t)a.step_ctr[0]) + (uint64_t)a.step_off;
+                            uint32_t c[4] = {(uint32_t)e, (uint32_t)st, (uint32_t)(st >> 32), 11u};
+                            philox4x32_10(c, a.key0, a.key1);
+                            const double u1 = ((double)c[0] + 0.5) / 4294967296.0;
+                            const double u2 = ((double)c[1] + 0.5) / 4294967296.0;
+                            const double rad = sqrt(-2.0 * log(u1));
+                            const double t = 2.0 * 3.14159265358979323846 * u2;
+                            const float z = (float)(n == 0 ? rad * cos(t) : rad * sin(t));
+                            v = fminf(1.0f, fmaxf(-1.0f, v + a.std * z));
+                        }
+                        a.act[(int64_t)e * 2 + n] = v;
+                    }
+                }
+            }
+        }
+        if (!last) {
+            // zero the padding columns of the next input, then swap
+            for (int q = lane; q < 16 * (a.kpad[l + 1] - a.npad[l]); q += 64) {
+                const int w = a.kpad[l + 1] - a.npad[l];
+                buf[1 - cur][(q / w) * ld + a.npad[l] + (q % w)] = 0;
+            }
+            __syncthreads();
+            cur = 1 - cur;
+        }
+    }
+}
+
 unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+hipError_t launch_actor_fused(const ActorArgs &a, hipStream_t s) {
+    if (a.N <= 0) return hipSuccess;
+    const size_t lds = (size_t)4 * 32 * a.kmax * sizeof(uint16_t);
+    hipLaunchKernelGGL(actor_fused_kernel, dim3((unsigned)((a.N + 63) / 64)), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;

@@ -26,6 +26,11 @@ struct navsim_policy_s {
     uint16_t *pb = nullptr;
     uint16_t *x = nullptr, *hid[2] = {nullptr, nullptr};
     uint32_t *step_ctr = nullptr;
+    // one-launch actor: padded bf16 weights and padded biases
+    bool fused = false;
+    ActorArgs fa{};
+    uint16_t *wpad = nullptr;
+    float *bpad = nullptr;
     // captured rollout
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -46,6 +51,15 @@ void drop_policy_graph(navsim_policy_s *q) {
 // act = actor(obs) (+ noise at step index *step_ctr + step_off).
 navsim_status actor_forward(navsim_policy_s *q, const float *obs, float *act, float std,
                             int step_off, hipStream_t s) {
+    if (q->fused) {
+        ActorArgs a = q->fa;
+        a.obs = obs;
+        a.act = act;
+        a.std = std;
+        a.step_off = step_off;
+        NS_HIP(launch_actor_fused(a, s));
+        return NAVSIM_OK;
+    }
     NS_HIP(launch_actor_input(q->N, q->m, obs, q->p + q->beta_off, q->x, s));
     const uint16_t *in = q->x;
     for (int l = 0; l < q->L; ++l) {
@@ -136,6 +150,20 @@ navsim_status navsim_policy_create(navsim_t h, int32_t hidden, int32_t hidden_la
     }
     q->beta_off = off;
     q->nparams = off + 8;
+    // the one-launch actor when every layer fits 128 inputs
+    int kmax = 0;
+    q->fused = q->L <= kActorMaxLayers;
+    int64_t wo = 0, bo = 0;
+    for (int l = 0; l < q->L && q->fused; ++l) {
+        q->fa.kpad[l] = (q->dims[l] + 31) & ~31;
+        q->fa.npad[l] = (q->dims[l + 1] + 15) & ~15;
+        q->fa.w_off[l] = wo;
+        q->fa.b_off[l] = bo;
+        wo += (int64_t)q->fa.kpad[l] * q->fa.npad[l];
+        bo += q->fa.npad[l];
+        kmax = std::max(kmax, q->fa.kpad[l]);
+        q->fused = q->fa.kpad[l] <= 128;
+    }
     const size_t N = (size_t)q->N;
     bool ok = hipMalloc((void **)&q->p, (size_t)q->nparams * 4) == hipSuccess &&
               hipMalloc((void **)&q->pb, (size_t)q->nparams * 2) == hipSuccess &&
@@ -146,6 +174,25 @@ navsim_status navsim_policy_create(navsim_t h, int32_t hidden, int32_t hidden_la
     ok = ok && hipMemset(q->p, 0, (size_t)q->nparams * 4) == hipSuccess &&
          hipMemset(q->pb, 0, (size_t)q->nparams * 2) == hipSuccess &&
          hipMemset(q->step_ctr, 0, 8) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    if (ok && q->fused) {
+        ok = hipMalloc((void **)&q->wpad, (size_t)wo * 2) == hipSuccess &&
+             hipMalloc((void **)&q->bpad, (size_t)bo * 4) == hipSuccess &&
+             hipMemset(q->wpad, 0, (size_t)wo * 2) == hipSuccess &&
+             hipMemset(q->bpad, 0, (size_t)bo * 4) == hipSuccess &&
+             hipDeviceSynchronize() == hipSuccess;
+        ActorArgs &a = q->fa;
+        a.N = q->N;
+        a.m = q->m;
+        a.layers = q->L;
+        a.kmax = kmax;
+        a.w = q->wpad;
+        a.b = q->bpad;
+        a.beta = q->p + q->beta_off;
+        a.slope = q->slope;
+        a.step_ctr = q->step_ctr;
+        a.key0 = (uint32_t)(h->cfg.seed & 0xffffffffu);
+        a.key1 = (uint32_t)(h->cfg.seed >> 32);
+    }
     if (!ok) {
         (void)navsim_policy_destroy(q);
         return fail(NAVSIM_E_OOM, "allocating the actor failed");
@@ -180,6 +227,32 @@ navsim_status navsim_policy_set_params(navsim_policy_t q, const float *host, int
     NS_HIP(hipDeviceSynchronize());
     NS_HIP(hipMemcpy(q->p, host, (size_t)count * 4, hipMemcpyHostToDevice));
     NS_HIP(launch_to_bf16(count, q->p, q->pb, nullptr));
+    if (q->fused) {
+        // padded images for the one-launch actor (same bf16 rounding as the
+        // layer-by-layer path: nearest even)
+        std::vector<uint16_t> w((size_t)q->fa.w_off[q->L - 1] +
+                                    (size_t)q->fa.npad[q->L - 1] * q->fa.kpad[q->L - 1],
+                                0);
+        std::vector<float> b((size_t)q->fa.b_off[q->L - 1] + q->fa.npad[q->L - 1], 0.0f);
+        for (int l = 0; l < q->L; ++l) {
+            for (int o = 0; o < q->dims[l + 1]; ++o) {
+                for (int i = 0; i < q->dims[l]; ++i) {
+                    uint32_t u;
+                    const float f = host[q->w_off[l] + (int64_t)o * q->dims[l] + i];
+                    memcpy(&u, &f, 4);
+                    uint16_t bits;
+                    if ((u & 0x7fffffffu) > 0x7f800000u)
+                        bits = 0x7fc0u;
+                    else
+                        bits = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+                    w[q->fa.w_off[l] + (int64_t)o * q->fa.kpad[l] + i] = bits;
+                }
+                b[q->fa.b_off[l] + o] = host[q->b_off[l] + o];
+            }
+        }
+        NS_HIP(hipMemcpy(q->wpad, w.data(), w.size() * 2, hipMemcpyHostToDevice));
+        NS_HIP(hipMemcpy(q->bpad, b.data(), b.size() * 4, hipMemcpyHostToDevice));
+    }
     NS_HIP(hipDeviceSynchronize());
     return NAVSIM_OK;
 }
@@ -270,7 +343,7 @@ navsim_status navsim_policy_destroy(navsim_policy_t q) {
         DeviceGuard dg(q->device);
         (void)hipDeviceSynchronize();
         drop_policy_graph(q);
-        void *ptrs[] = {q->p, q->pb, q->x, q->hid[0], q->hid[1], q->step_ctr};
+        void *ptrs[] = {q->p, q->pb, q->x, q->hid[0], q->hid[1], q->step_ctr, q->wpad, q->bpad};
         for (void *v : ptrs)
             if (v) (void)hipFree(v);
         if (q->capture_stream) (void)hipStreamDestroy(q->capture_stream);

@@ -89,6 +89,24 @@ def test_run_walk_against_oracle():
     sim.close()
 
 
+def test_c3_full_size_fused():
+    say("c3 full size: 16384 envs, 64 rooms maps 256^2, rectangle, 720 beams, 2 steps")
+    w = configs.build_workload("c3")
+    sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
+    tot = run_teacher_forced(sim, ref, 2, NAVSIM_KERNEL_FUSED, label="c3-full/fused")
+    assert tot["grazing"] < 0.01 * tot["rays"]
+    sim.close()
+
+
+def test_c5_full_size_fused():
+    say("c5 full size: 65536 envs, 64 rooms maps 256^2, 360 beams, 2 steps")
+    w = configs.build_workload("c5")
+    sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
+    tot = run_teacher_forced(sim, ref, 2, NAVSIM_KERNEL_FUSED, label="c5-full/fused")
+    assert tot["grazing"] < 0.01 * tot["rays"]
+    sim.close()
+
+
 def test_c3_rect_reverse_fused():
     say("c3 maps 256^2, rectangle footprint, 720 beams, 2048 envs, fused, 3 steps")
     w = configs.build_workload("c3", num_envs=2048)
