@@ -40,8 +40,8 @@ hipError_t launch_act_backward(int M, int N, const float *dH, const uint16_t *H,
                                float slope, float *dZf, uint16_t *dZb, hipStream_t s);
 
 // out[n] = sum over m of X[m, n] (float, [M, N] rows), in a fixed order:
-// chunks of 256 rows in order, then the chunk sums in order.  `partial`
-// holds ceil(M / 256) * N floats.
+// chunks of 32 rows in order, then the chunk sums in order.  `partial`
+// holds ceil(M / 32) * N floats.
 hipError_t launch_col_sum(int M, int N, const float *X, float *partial, float *out,
                           hipStream_t s);
 

@@ -4,6 +4,8 @@
 // error loss and AdamW.  Accumulation is always float.
 #include <math.h>
 
+#include <algorithm>
+
 #include "mlp_internal.hpp"
 #include "philox.hpp"
 
@@ -16,6 +18,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBM = 64, kBN = 64, kBK = 32;
 constexpr int kLdsK = kBK + 8;  // padded row (80 bytes) of a staged tile
 constexpr int kGemmThreads = 256;
+constexpr int kColChunk = 32;  // rows per partial column sum
 
 __device__ __forceinline__ uint16_t to_bf16_bits(float f) {
     uint32_t u = __float_as_uint(f);
@@ -139,9 +142,9 @@ __global__ void col_sum_chunks_kernel(int M, int N, const float *X, float *parti
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (n >= N) return;
-    const int m1 = min(M, (c + 1) * 256);
+    const int m1 = min(M, (c + 1) * kColChunk);
     float s = 0.0f;
-    for (int m = c * 256; m < m1; ++m) s += X[(int64_t)m * N + n];
+    for (int m = c * kColChunk; m < m1; ++m) s += X[(int64_t)m * N + n];
     partial[(int64_t)c * N + n] = s;
 }
 
@@ -223,9 +226,10 @@ __global__ void actor_noise_kernel(int N, float *act, float std, const uint32_t 
 
 // Whole actor in one launch: each wavefront takes 16 observation rows, builds
 // their bf16 inputs in LDS (reciprocal range transform), then runs every
-// layer as 16 x 16 x 32 bf16 MFMA tiles with its weights read from a padded
-// bf16 image (k-contiguous rows, K padded to 32, N to 16, zeros outside) and
-// writes bias + activation back to its LDS rows as the next layer's input;
+// layer as 16 x 16 x 32 bf16 MFMA tiles with its weights staged in LDS by the
+// workgroup from a padded bf16 image (k-contiguous rows, K padded to 32, N to
+// 16, zeros outside) and writes bias + activation back to its LDS rows as the
+// next layer's input;
 // the last layer applies tanh, the exploration noise and the clip, and
 // stores the two action components.  Same tiles, k order and rounding points
 // as the layer-by-layer GEMM path.
@@ -236,6 +240,7 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
     const int ld = a.kmax;  // LDS row pitch (bf16), multiple of 32
     uint16_t *buf[2] = {act_lds + (size_t)wave * 32 * ld, act_lds + (size_t)wave * 32 * ld + 16 * ld};
     const int row = a.m + 4;
+    uint16_t *wl = act_lds + (size_t)4 * 32 * ld;  // this layer's weights
     // inputs
     for (int q = lane; q < 16 * a.kpad[0]; q += 64) {
         const int r = q / a.kpad[0], j = q - r * a.kpad[0];
@@ -252,7 +257,13 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     for (int l = 0; l < a.layers; ++l) {
         const int kp = a.kpad[l], np = a.npad[l];
-        const uint16_t *W = a.w + a.w_off[l];
+        {
+            const uint4 *src = reinterpret_cast<const uint4 *>(a.w + a.w_off[l]);
+            uint4 *dst = reinterpret_cast<uint4 *>(wl);
+            for (int q = threadIdx.x; q < np * kp / 8; q += 256) dst[q] = src[q];
+        }
+        __syncthreads();
+        const uint16_t *W = wl;
         const float *bias = a.b + a.b_off[l];
         const bool last = l + 1 == a.layers;
         for (int n0 = 0; n0 < np; n0 += 16) {
@@ -298,9 +309,9 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
                 const int w = a.kpad[l + 1] - a.npad[l];
                 buf[1 - cur][(q / w) * ld + a.npad[l] + (q % w)] = 0;
             }
-            __syncthreads();
             cur = 1 - cur;
         }
+        __syncthreads();  // next layer's inputs written, this layer's weights no longer read
     }
 }
 
@@ -310,7 +321,9 @@ unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 hipError_t launch_actor_fused(const ActorArgs &a, hipStream_t s) {
     if (a.N <= 0) return hipSuccess;
-    const size_t lds = (size_t)4 * 32 * a.kmax * sizeof(uint16_t);
+    size_t wmax = 0;
+    for (int l = 0; l < a.layers; ++l) wmax = std::max(wmax, (size_t)a.kpad[l] * a.npad[l]);
+    const size_t lds = ((size_t)4 * 32 * a.kmax + wmax) * sizeof(uint16_t);
     hipLaunchKernelGGL(actor_fused_kernel, dim3((unsigned)((a.N + 63) / 64)), dim3(256), lds, s, a);
     return hipGetLastError();
 }
@@ -341,7 +354,7 @@ hipError_t launch_act_backward(int M, int N, const float *dH, const uint16_t *H,
 hipError_t launch_col_sum(int M, int N, const float *X, float *partial, float *out,
                           hipStream_t s) {
     if (N == 0) return hipSuccess;
-    const int chunks = (M + 255) / 256;
+    const int chunks = (M + kColChunk - 1) / kColChunk;
     if (chunks > 0)
         hipLaunchKernelGGL(col_sum_chunks_kernel, dim3(blocks_for(N, 256), (unsigned)chunks),
                            dim3(256), 0, s, M, N, X, partial);

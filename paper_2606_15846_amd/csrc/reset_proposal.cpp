@@ -238,7 +238,7 @@ navsim_status backward_full(navsim_rp_s *r, int n, const uint16_t *X, const floa
     RP_BUF(r->dzf, (size_t)n * Hmax * 4);
     RP_BUF(r->dzb, (size_t)n * Hmax * 2);
     RP_BUF(r->dh, (size_t)n * Hmax * 4);
-    RP_BUF(r->colsum, (size_t)((n + 255) / 256 + 1) * Hmax * 4);
+    RP_BUF(r->colsum, (size_t)((n + 31) / 32 + 1) * Hmax * 4);
     float *zf[2] = {r->dyf.as<float>(), r->dzf.as<float>()};
     uint16_t *zb[2] = {r->dyb.as<uint16_t>(), r->dzb.as<uint16_t>()};
     RP_HIP(launch_sq_loss(n, out, Y, T, r->wloss, loss_rows, zf[0], zb[0], s));
@@ -551,7 +551,7 @@ navsim_status navsim_rp_train(navsim_rp_t r, int32_t num_pairs, const int32_t *p
             return st;
         if ((st = adamw_step(r, r->g, lr, weight_decay, s)) != NAVSIM_OK) return st;
         if (loss) {
-            RP_BUF(r->colsum, (size_t)((batch + 255) / 256 + 1) * 4);
+            RP_BUF(r->colsum, (size_t)((batch + 31) / 32 + 1) * 4);
             RP_HIP(launch_col_sum(batch, 1, r->lrows.as<float>(), r->colsum.as<float>(),
                                   loss + t, s));
         }
