@@ -89,6 +89,8 @@ struct ActorArgs {
     uint32_t key0 = 0, key1 = 0;
 };
 hipError_t launch_actor_fused(const ActorArgs &a, hipStream_t s);
+// LDS bytes of that launch (it is used only when this is <= 64 KiB).
+size_t actor_fused_lds_bytes(int layers, const int *kpad, const int *npad, int kmax);
 
 // Float to bfloat16 (round to nearest even), n elements.
 hipError_t launch_to_bf16(int64_t n, const float *x, uint16_t *y, hipStream_t s);

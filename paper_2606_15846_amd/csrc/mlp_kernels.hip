@@ -237,51 +237,84 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint16_t act_lds[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row0 = (blockIdx.x * 4 + wave) * 16;
-    const int ld = a.kmax;  // LDS row pitch (bf16), multiple of 32
-    uint16_t *buf[2] = {act_lds + (size_t)wave * 32 * ld, act_lds + (size_t)wave * 32 * ld + 16 * ld};
+    const int ld = a.kmax + 8;  // LDS row pitch (bf16): 16 B past a bank cycle
+    uint16_t *cur_in = act_lds + (size_t)wave * 32 * ld;  // this layer's input rows
+    uint16_t *nxt_in = cur_in + 16 * ld;                  // the next layer's
     const int row = a.m + 4;
     uint16_t *wl = act_lds + (size_t)4 * 32 * ld;  // this layer's weights
-    // inputs
-    for (int q = lane; q < 16 * a.kpad[0]; q += 64) {
-        const int r = q / a.kpad[0], j = q - r * a.kpad[0];
-        const int e = row0 + r;
-        float v = 0.0f;
-        if (e < a.N && j < row) {
-            const float o = a.obs[(int64_t)e * row + j];
-            v = j < a.m ? 1.0f / (o - *a.beta) : o;
+    // inputs: all loads issued first; row r, columns lane and lane + 64
+    {
+        const int kp0 = a.kpad[0];
+        const float beta = *a.beta;
+        float v[32];
+#pragma unroll
+        for (int t = 0; t < 32; ++t) {
+            const int r = t >> 1, j = lane + 64 * (t & 1), e = row0 + r;
+            v[t] = (e < a.N && j < row) ? a.obs[(int64_t)e * row + j] : 0.0f;
         }
-        buf[0][r * ld + j] = to_bf16_bits(v);
+#pragma unroll
+        for (int t = 0; t < 32; ++t) {
+            const int r = t >> 1, j = lane + 64 * (t & 1);
+            if (j < kp0)
+                cur_in[r * ld + j] =
+                    to_bf16_bits(j < a.m && row0 + r < a.N ? 1.0f / (v[t] - beta) : v[t]);
+        }
     }
     __syncthreads();
-    int cur = 0;
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     for (int l = 0; l < a.layers; ++l) {
         const int kp = a.kpad[l], np = a.npad[l];
         {
+            // np kp / 8 <= 128 * 128 / 8 = 2048 vectors: at most 8 per thread, loads first
+            // rows of kp bf16 stored with pitch kp + 8 (conflict-free fragment reads);
+            // thread t copies 16-byte column t % 16 of rows t / 16 + 16 i
             const uint4 *src = reinterpret_cast<const uint4 *>(a.w + a.w_off[l]);
             uint4 *dst = reinterpret_cast<uint4 *>(wl);
-            for (int q = threadIdx.x; q < np * kp / 8; q += 256) dst[q] = src[q];
+            const int rv = kp / 8, c = threadIdx.x & 15, r0 = threadIdx.x >> 4;
+            uint4 t8[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int rw = r0 + 16 * t;
+                t8[t] = (c < rv && rw < np) ? src[rw * rv + c] : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int rw = r0 + 16 * t;
+                if (c < rv && rw < np) dst[rw * (rv + 1) + c] = t8[t];
+            }
         }
+        // this lane's biases, one per 16-column block (np <= 128)
+        float bias[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) bias[t] = 16 * t < np ? a.b[a.b_off[l] + 16 * t + fr] : 0.0f;
         __syncthreads();
         const uint16_t *W = wl;
-        const float *bias = a.b + a.b_off[l];
         const bool last = l + 1 == a.layers;
-        for (int n0 = 0; n0 < np; n0 += 16) {
+        bf16x8 av[4];  // this wave's input fragments, shared by every column block
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+            if (32 * kb < kp) av[kb] = *reinterpret_cast<const bf16x8 *>(&cur_in[fr * ld + 32 * kb + fk]);
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) {
+            const int n0 = 16 * nb;
+            if (n0 >= np) break;
             f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            for (int k0 = 0; k0 < kp; k0 += 32) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&buf[cur][fr * ld + k0 + fk]);
-                const bf16x8 bv =
-                    *reinterpret_cast<const bf16x8 *>(W + (int64_t)(n0 + fr) * kp + k0 + fk);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                if (32 * kb < kp) {
+                    const bf16x8 bv =
+                        *reinterpret_cast<const bf16x8 *>(W + (n0 + fr) * (kp + 8) + 32 * kb + fk);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[kb], bv, acc, 0, 0, 0);
+                }
             }
             const int n = n0 + fr;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int rr = (lane >> 4) * 4 + r;
-                float v = acc[r] + bias[n];
+                float v = acc[r] + bias[nb];
                 if (!last) {
                     if (!(v > 0.0f)) v *= a.slope;
-                    buf[1 - cur][rr * ld + n] = to_bf16_bits(v);
+                    nxt_in[rr * ld + n] = to_bf16_bits(v);
                 } else if (n < 2) {
                     const int e = row0 + rr;
                     if (e < a.N) {
@@ -304,12 +337,13 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
             }
         }
         if (!last) {
-            // zero the padding columns of the next input, then swap
-            for (int q = lane; q < 16 * (a.kpad[l + 1] - a.npad[l]); q += 64) {
-                const int w = a.kpad[l + 1] - a.npad[l];
-                buf[1 - cur][(q / w) * ld + a.npad[l] + (q % w)] = 0;
-            }
-            cur = 1 - cur;
+            // zero the padding columns [np, kpad[l + 1]) of the next input, then swap
+            const int kn = a.kpad[l + 1];
+            for (int r = 0; r < 16; ++r)
+                for (int j = np + lane; j < kn; j += 64) nxt_in[r * ld + j] = 0;
+            uint16_t *t = cur_in;
+            cur_in = nxt_in;
+            nxt_in = t;
         }
         __syncthreads();  // next layer's inputs written, this layer's weights no longer read
     }
@@ -319,11 +353,15 @@ unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
+size_t actor_fused_lds_bytes(int layers, const int *kpad, const int *npad, int kmax) {
+    size_t wmax = 0;
+    for (int l = 0; l < layers; ++l) wmax = std::max(wmax, (size_t)(kpad[l] + 8) * npad[l]);
+    return ((size_t)4 * 32 * (kmax + 8) + wmax) * sizeof(uint16_t);
+}
+
 hipError_t launch_actor_fused(const ActorArgs &a, hipStream_t s) {
     if (a.N <= 0) return hipSuccess;
-    size_t wmax = 0;
-    for (int l = 0; l < a.layers; ++l) wmax = std::max(wmax, (size_t)a.kpad[l] * a.npad[l]);
-    const size_t lds = ((size_t)4 * 32 * a.kmax + wmax) * sizeof(uint16_t);
+    const size_t lds = actor_fused_lds_bytes(a.layers, a.kpad, a.npad, a.kmax);
     hipLaunchKernelGGL(actor_fused_kernel, dim3((unsigned)((a.N + 63) / 64)), dim3(256), lds, s, a);
     return hipGetLastError();
 }

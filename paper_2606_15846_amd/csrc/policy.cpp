@@ -164,6 +164,7 @@ navsim_status navsim_policy_create(navsim_t h, int32_t hidden, int32_t hidden_la
         kmax = std::max(kmax, q->fa.kpad[l]);
         q->fused = q->fa.kpad[l] <= 128;
     }
+    q->fused = q->fused && actor_fused_lds_bytes(q->L, q->fa.kpad, q->fa.npad, kmax) <= 65536;
     const size_t N = (size_t)q->N;
     bool ok = hipMalloc((void **)&q->p, (size_t)q->nparams * 4) == hipSuccess &&
               hipMalloc((void **)&q->pb, (size_t)q->nparams * 2) == hipSuccess &&
