@@ -241,15 +241,21 @@ typedef struct {
     int32_t refill_at;  /* a wavefront hands new rays to its idle lanes once at most this
                            many of its 64 lanes are still walking, 0..63                  */
     int32_t groups;     /* 4-cell groups a lane walks between refill checks, 1..64        */
-    int32_t ray_slots;  /* LDS ray slots per workgroup (each 16 B): 0 = the tile's rays plus
-                           one reset scan, as LDS allows; else at most this many (>= 256,
-                           rounded up to 64).  Fewer slots: less LDS, more workgroups per
-                           CU, more chunks per tile                                       */
+    int32_t ray_slots;  /* LDS ray slots per workgroup (each 16 B): 0 = automatic (the
+                           tile's rays plus one reset scan, or as many as fit in 40 KiB of
+                           LDS so that 4 workgroups share a CU; up to 64 KiB for maps too
+                           large for that); else at most this many (>= 256, rounded up to
+                           64) in 64 KiB.  Fewer slots: less LDS, more workgroups per CU,
+                           more chunks per tile                                           */
     int32_t walk;       /* 0: cells in groups of 4; 1: runs of cells between minor-axis
                            steps (32 cells per test along x) -- same cells, same results  */
+    int32_t persist;    /* 0: one workgroup per tile; c in 1..64: only as many workgroups
+                           as stay resident, each taking c consecutive tiles at a time from
+                           a device counter and keeping its staged map while the tiles'
+                           map does not change                                             */
 } navsim_tuning;
 
-/* Set the fused step's launch shape (defaults: 4, 48, 4, 0, 0).  Changing tile_envs
+/* Set the fused step's launch shape (defaults: 4, 48, 4, 0, 0, 0).  Changing tile_envs
  * after navsim_load_maps waits for the device and re-groups the envs; returns
  * NAVSIM_E_UNSUPPORTED if the larger tile would not fit LDS. */
 navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t);

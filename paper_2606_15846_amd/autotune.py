@@ -1,7 +1,8 @@
 """Launch-shape autotuner for the fused step.
 
 The fused step's results do not depend on its launch shape (tile_envs,
-refill_at, groups; see navsim_set_tuning in include/navsim.h), only its speed
+refill_at, groups, ray_slots, walk, persist; see navsim_set_tuning in
+include/navsim.h), only its speed
 does.  The tuner replays the same seeded steps from the same saved state under
 every candidate shape, times them with HIP events on the simulator's stream,
 and keeps the fastest.  Results are stored per workload key in tuning.json
@@ -20,9 +21,10 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_FILE = os.path.join(HERE, "tuning.json")
-DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4, "ray_slots": 0, "walk": 0}
+DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4, "ray_slots": 0, "walk": 0, "persist": 0}
 SPACE = {"tile_envs": (1, 2, 4, 8), "refill_at": (32, 48, 56), "groups": (2, 4, 8),
-         "ray_slots": (0, 512), "walk": (0, 1)}
+         "ray_slots": (0, 512, 1024, 2048), "walk": (0, 1), "persist": (0, 2)}
+FIELDS = tuple(DEFAULT)
 
 
 def workload_key(cfg: dict, maps, profiles=None) -> str:
@@ -79,9 +81,8 @@ def tune(sim, acts, steps: int = 50, space: dict | None = None, verbose: bool = 
     space = space or SPACE
     start = sim.get_state()
     table = []
-    for te, ra, gr, rs, wk in itertools.product(space["tile_envs"], space["refill_at"],
-                                                space["groups"], space["ray_slots"], space["walk"]):
-        shape = {"tile_envs": te, "refill_at": ra, "groups": gr, "ray_slots": rs, "walk": wk}
+    for values in itertools.product(*(space[k] for k in FIELDS)):
+        shape = dict(zip(FIELDS, values))
         try:
             sim.set_tuning(**shape)
         except Exception as exc:  # a shape the map does not fit (LDS)
@@ -91,11 +92,11 @@ def tune(sim, acts, steps: int = 50, space: dict | None = None, verbose: bool = 
         ms = time_steps(sim, acts, start, steps)
         table.append(dict(shape, ms_per_step=ms))
         if verbose:
-            print(f"tile_envs={te:2d} refill_at={ra:2d} groups={gr:2d} ray_slots={rs:4d} "
-                  f"walk={wk} -> {ms * 1e3:8.1f} us/step", flush=True)
+            print(" ".join(f"{k}={v}" for k, v in shape.items()) + f" -> {ms * 1e3:8.1f} us/step",
+                  flush=True)
     ok = [r for r in table if "ms_per_step" in r]
     best = min(ok, key=lambda r: r["ms_per_step"])
-    best = {k: best[k] for k in ("tile_envs", "refill_at", "groups", "ray_slots", "walk")}
+    best = {k: best[k] for k in FIELDS}
     sim.set_tuning(**best)
     sim.set_state(start)
     return best, table

@@ -140,17 +140,32 @@ navsim_status upload(T **dst, const std::vector<T> &src) {
 }
 
 
-// LDS walk slots per chunk, keeping the beam table in LDS when a full tile's
-// rays still fit next to it, else reading it from device memory.
+// LDS walk slots per chunk.  Automatic (slots 0): within the LDS share that
+// lets four workgroups run per CU, beam table in LDS if at least 512 slots (or
+// a whole tile's) still fit beside it, else in device memory; maps too large
+// for that share get up to 64 KiB as below.  Otherwise at most `slots`
+// slots in 64 KiB, keeping the beam table in LDS when a full tile's rays
+// still fit next to it.
 int choose_ray_cap(int max_words, const navsim_config &c, int tile_envs, int slots,
                    bool &beams_lds) {
+    const int m = c.num_sectors, K = c.num_beams;
+    if (slots == 0) {
+        const int full = ((tile_envs + 1) * K + 63) & ~63;
+        for (const bool b : {true, false}) {
+            const int cap = fused_ray_cap(max_words, m, tile_envs, K, b, kFusedLdsShare);
+            if (cap > 0 && (cap >= 512 || cap >= full)) {
+                beams_lds = b;
+                return cap;
+            }
+        }
+    }
     int cap;
-    const int with = fused_ray_cap(max_words, c.num_sectors, tile_envs, c.num_beams, true);
-    if (with >= tile_envs * c.num_beams) {
+    const int with = fused_ray_cap(max_words, m, tile_envs, K, true, 65536);
+    if (with >= tile_envs * K) {
         beams_lds = true;
         cap = with;
     } else {
-        const int without = fused_ray_cap(max_words, c.num_sectors, tile_envs, c.num_beams, false);
+        const int without = fused_ray_cap(max_words, m, tile_envs, K, false, 65536);
         beams_lds = without <= with;
         cap = beams_lds ? with : without;
     }
@@ -321,6 +336,9 @@ StepParams navsim::make_step_params(const navsim_s *h) {
     p.beams_lds = h->beams_lds ? 1 : 0;
     p.scan_mode = h->scan_mode;
     p.walk_mode = h->walk_mode;
+    p.queue = h->persist ? h->queue : nullptr;
+    p.chunk = h->persist;
+    p.resident = h->resident;
     p.march_kmax = h->march_kmax;
     p.march_h = h->march_h;
     return p;
@@ -359,6 +377,16 @@ navsim_status navsim_create(const navsim_config *cfg, int hip_device, navsim_t *
         (void)hipFree(h->state_buf);
         delete h;
         return fail(NAVSIM_E_OOM, "hipMalloc of the step counter failed");
+    }
+    // the tile queue starts at zero; every persistent launch leaves it there
+    if (hipMalloc(&h->queue, 2 * sizeof(int32_t)) != hipSuccess ||
+        hipMemset(h->queue, 0, 2 * sizeof(int32_t)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        if (h->queue) (void)hipFree(h->queue);
+        (void)hipFree(h->step_ctr);
+        (void)hipFree(h->state_buf);
+        delete h;
+        return fail(NAVSIM_E_HIP, "tile queue allocation failed");
     }
     float *f = (float *)h->state_buf;
     h->st.x = f;
@@ -528,6 +556,8 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
     h->max_words = max_words;
     h->ray_cap = ray_cap;
     h->beams_lds = beams_lds;
+    h->resident = fused_resident_groups(max_words, cfg.num_sectors, h->tile_envs, cfg.num_beams,
+                                        beams_lds, ray_cap);
     h->host_env_map.swap(host_env_map);
     h->host_occ.assign(occ, occ + occ_off[num_maps]);
     h->host_occ_off = occ_off;
@@ -699,16 +729,22 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     if (t->ray_slots < 0 || (t->ray_slots > 0 && t->ray_slots < 256))
         return fail(NAVSIM_E_INVALID_ARG, "ray_slots must be 0 or >= 256");
     if (t->walk != 0 && t->walk != 1) return fail(NAVSIM_E_INVALID_ARG, "walk must be 0 or 1");
+    if (t->persist < 0 || t->persist > 64)
+        return fail(NAVSIM_E_INVALID_ARG, "persist must be in 0..64");
     {
         DeviceGuard g(h->device);
         drop_graph(h);
     }
-    int ray_cap = h->ray_cap;
+    int ray_cap = h->ray_cap, resident = h->resident;
     bool beams_lds = h->beams_lds;
     if (h->loaded) {
         ray_cap = choose_ray_cap(h->max_words, h->cfg, t->tile_envs, t->ray_slots, beams_lds);
         if (ray_cap == 0)
             return fail(NAVSIM_E_UNSUPPORTED, "tile_envs %d does not fit LDS", t->tile_envs);
+        DeviceGuard g(h->device);
+        resident = fused_resident_groups(h->max_words, h->cfg.num_sectors, t->tile_envs,
+                                         h->cfg.num_beams, beams_lds, ray_cap);
+        if (resident <= 0) return fail(NAVSIM_E_HIP, "occupancy query of the fused step failed");
     }
     if (h->loaded && t->tile_envs != h->tile_envs) {
         std::vector<int32_t> perm;
@@ -731,7 +767,9 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     h->groups = t->groups;
     h->ray_slots = t->ray_slots;
     h->walk_mode = t->walk;
+    h->persist = t->persist;
     h->ray_cap = ray_cap;
+    h->resident = resident;
     h->beams_lds = beams_lds;
     return NAVSIM_OK;
 }
@@ -744,6 +782,7 @@ navsim_status navsim_get_tuning(navsim_t h, navsim_tuning *t) {
     t->groups = h->groups;
     t->ray_slots = h->ray_slots;
     t->walk = h->walk_mode;
+    t->persist = h->persist;
     return NAVSIM_OK;
 }
 
@@ -755,6 +794,7 @@ navsim_status navsim_destroy(navsim_t h) {
         if (h->beams) (void)hipFree(h->beams);
         if (h->state_buf) (void)hipFree(h->state_buf);
         if (h->step_ctr) (void)hipFree(h->step_ctr);
+        if (h->queue) (void)hipFree(h->queue);
         if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
     }
     delete h;

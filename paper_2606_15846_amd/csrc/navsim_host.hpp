@@ -62,6 +62,9 @@ struct navsim_s {
     int ray_slots = 0;  // requested cap on ray_cap (0 = automatic)
     int walk_mode = 0;  // fused walk: 0 cells in groups of 4, 1 runs
     bool beams_lds = true;
+    int persist = 0;    // persistent workgroups: tiles per grab (0 = one workgroup per tile)
+    int resident = 0;   // workgroups of the fused step resident at once on the device
+    int32_t *queue = nullptr;  // device {next tile, finished workgroups}, zero between launches
     int scan_mode = 0;       // 0 exact traversal, 1 fixed-step march
     int march_kmax = 0;
     double march_h = 0.03;

@@ -537,6 +537,7 @@ struct TileJob {
 };
 
 constexpr int kFusedThreads = 256;
+constexpr int kFusedWavesPerSimd = 4;
 constexpr int kGroupLanes = 16;
 
 // Sector-pool words of a tile ([2E][m]), rounded up to keep the LDS regions
@@ -1009,26 +1010,40 @@ __device__ __forceinline__ void march_walk(const StepParams &p, const MapView &M
         reinterpret_cast<uint2 *>(s_ray)[2 * r] = make_uint2((uint32_t)k | ((uint32_t)type << 28), 0u);
 }
 
+// LDS of the fused step, in order: bitmap [max_words], jobs [2E] (main,
+// reset), pooled minima [2E][m] (+ padding), active job list [2E], misc
+// [2E + 8] ([0] active jobs, [1] next ray, [2, 2 + E) done flags, [2E + 7]
+// next tile of a persistent workgroup), beams [K] when staged, ray slots.
 template <int E>
-__global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p) {
+__device__ __forceinline__ int *fused_list(const StepParams &p) {
     extern __shared__ uint4 smem4[];
     uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem4);
-    TileJob *s_jobs = reinterpret_cast<TileJob *>(s_bits + p.max_words);  // [2E]: main, reset
-    uint32_t *s_pool = reinterpret_cast<uint32_t *>(s_jobs + 2 * E);      // [2E][m]
-    int *s_list = reinterpret_cast<int *>(s_pool + pool_words(E, p.m));   // [2E] active jobs
-    int *s_misc = s_list + 2 * E;  // [0] active jobs, [1] next ray, [2..] done flags
+    TileJob *s_jobs = reinterpret_cast<TileJob *>(s_bits + p.max_words);
+    uint32_t *s_pool = reinterpret_cast<uint32_t *>(s_jobs + 2 * E);
+    return reinterpret_cast<int *>(s_pool + pool_words(E, p.m));
+}
+
+template <int E>
+__device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, int &staged_map) {
+    extern __shared__ uint4 smem4[];
+    uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem4);
+    TileJob *s_jobs = reinterpret_cast<TileJob *>(s_bits + p.max_words);
+    uint32_t *s_pool = reinterpret_cast<uint32_t *>(s_jobs + 2 * E);
+    int *s_list = fused_list<E>(p);
+    int *s_misc = s_list + 2 * E;
     double2 *s_beam = reinterpret_cast<double2 *>(s_misc + 2 * E + 8);  // [K] beams, or global
     uint4 *s_ray = reinterpret_cast<uint4 *>(s_beam + (p.beams_lds ? p.K : 0));  // [ray_cap]
     const int tid = threadIdx.x, lane = tid & 63;
-    const Tile tile = p.tiles[blockIdx.x];
+    const Tile tile = p.tiles[tile_index];
     const MapDesc md = p.maps[tile.map];
     const int K = md.K, m = p.m, per = K / m;
     const double2 *beams = p.beams + md.beam_off;  // this map's beam directions
-    {
+    if (tile.map != staged_map) {  // a persistent workgroup keeps its map between tiles
         const uint4 *g = reinterpret_cast<const uint4 *>(p.bits + md.word_off);
         for (int q = tid; q < md.words / 4; q += kFusedThreads) smem4[q] = g[q];
         if (p.beams_lds)
             for (int q = tid; q < K; q += kFusedThreads) s_beam[q] = beams[q];
+        staged_map = tile.map;
     }
     if (!p.beams_lds) s_beam = const_cast<double2 *>(beams);
     __syncthreads();
@@ -1272,6 +1287,43 @@ __global__ __launch_bounds__(kFusedThreads) void fused_step_kernel(StepParams p)
     }
 }
 
+// One workgroup per tile (queue null), or persistent workgroups that take
+// `chunk` consecutive tiles at a time from a device counter; the last
+// workgroup to finish sets the counter back to zero for the next launch.
+// Register budget: 128 VGPRs, so that 4 wavefronts share each SIMD and hide
+// one another's LDS latency in the walk (the compiler's own choice, ~200,
+// leaves 2).  The motion phase spills a few values to scratch memory; the
+// walk loop keeps everything in registers.
+template <int E>
+__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerSimd)))
+void fused_step_kernel(StepParams p) {
+    int staged = -1;
+    if (!p.queue) {
+        fused_tile<E>(p, (int)blockIdx.x, staged);
+        return;
+    }
+    int *s_next = fused_list<E>(p) + 4 * E + 7;
+    for (;;) {
+        if (threadIdx.x == 0) *s_next = atomicAdd(&p.queue[0], p.chunk);
+        __syncthreads();
+        const int t0 = *s_next;
+        __syncthreads();
+        if (t0 >= p.num_tiles) break;
+        const int t1 = min(t0 + p.chunk, p.num_tiles);
+        for (int t = t0; t < t1; ++t) {
+            fused_tile<E>(p, t, staged);
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&p.queue[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&p.queue[0], 0);
+            atomicExch(&p.queue[1], 0);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Plain mapping: one thread per env, the whole step in sequence.
 
@@ -1378,21 +1430,50 @@ __global__ __launch_bounds__(64) void plain_step_kernel(StepParams p) {
 // ---------------------------------------------------------------------------
 template <int E>
 static hipError_t launch_fused_e(const StepParams &p, hipStream_t s) {
-    hipLaunchKernelGGL(fused_step_kernel<E>, dim3((unsigned)p.num_tiles), dim3(kFusedThreads),
-                       fused_lds_bytes(p.max_words, p.m, E, p.beams_lds ? p.K : 0, p.ray_cap), s,
-                       p);
+    const size_t lds = fused_lds_bytes(p.max_words, p.m, E, p.beams_lds ? p.K : 0, p.ray_cap);
+    unsigned grid = (unsigned)p.num_tiles;
+    if (p.queue) {
+        // at most the resident workgroups, and one per chunk of tiles
+        const int chunks = (p.num_tiles + p.chunk - 1) / p.chunk;
+        grid = (unsigned)std::max(1, std::min(chunks, p.resident));
+    }
+    hipLaunchKernelGGL(fused_step_kernel<E>, dim3(grid), dim3(kFusedThreads), lds, s, p);
     return hipGetLastError();
+}
+
+template <int E>
+static int resident_e(size_t lds) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_step_kernel<E>, kFusedThreads,
+                                                     lds) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+int fused_resident_groups(int max_words, int m, int E, int K, bool beams_lds, int ray_cap) {
+    const size_t lds = fused_lds_bytes(max_words, m, E, beams_lds ? K : 0, ray_cap);
+    switch (E) {
+        case 1: return resident_e<1>(lds);
+        case 2: return resident_e<2>(lds);
+        case 4: return resident_e<4>(lds);
+        case 8: return resident_e<8>(lds);
+        case 16: return resident_e<16>(lds);
+        default: return 0;
+    }
 }
 
 bool fused_tile_envs_supported(int E) { return E == 1 || E == 2 || E == 4 || E == 8 || E == 16; }
 
 // LDS walk slots per chunk: the rays of a full tile plus one reset pose
 // ((E + 1) K, rounded up to a wavefront), so a tile walks a second chunk only
-// when two or more of its envs reset; fewer if that does not fit 64 KiB.
-int fused_ray_cap(int max_words, int m, int E, int K, bool beams_lds) {
+// when two or more of its envs reset; fewer if that does not fit `budget`
+// bytes of LDS; 0 if not even 256 do.
+int fused_ray_cap(int max_words, int m, int E, int K, bool beams_lds, int budget) {
     const size_t base = fused_lds_bytes(max_words, m, E, beams_lds ? K : 0, 0);
-    if (base + 16u * 256u > 65536u) return 0;
-    const int fit = (int)((65536u - base) / 16u) & ~63;
+    if (base + 16u * 256u > (size_t)budget) return 0;
+    const int fit = (int)(((size_t)budget - base) / 16u) & ~63;
     return std::max(std::min(((E + 1) * K + 63) & ~63, fit), 256);
 }
 

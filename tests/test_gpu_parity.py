@@ -124,6 +124,33 @@ def test_c4_mixed_profiles_full_size_fused():
     sim.close()
 
 
+def test_c4_full_size_persistent_equals_one_workgroup_per_tile():
+    # the launch configuration the C4 line of the bench times, against the
+    # per-tile launch that the test above holds to the oracle
+    say("c4 full size: persistent workgroups (chunks of 1, 4, 16 tiles) == per-tile, 3 steps")
+    w = configs.build_workload("c4")
+    acts = torch.from_numpy(configs.uniform_actions(3, w["cfg"]["num_envs"], seed=5)).cuda()
+    runs = []
+    for te, pe in [(8, 0), (8, 4), (4, 1), (16, 16)]:
+        sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0,
+                     profiles=w["profiles"])
+        sim.set_tuning(te, 48, 8, persist=pe)
+        outs = [sim.reset().cpu().numpy().copy()]
+        for t in range(3):
+            o, r, te_, tr, info = sim.step(acts[t])
+            fo = info["final_obs"]
+            done = (te_ | tr).cpu().numpy().astype(bool)
+            outs += [o.cpu().numpy().copy(), r.cpu().numpy().copy(), done,
+                     fo.cpu().numpy()[done].copy()]
+        st = sim.get_state()
+        outs += [st[k] for k in oracle.STATE_KEYS]
+        runs.append(outs)
+        sim.close()
+    for other in runs[1:]:
+        for i, (a, b) in enumerate(zip(runs[0], other)):
+            assert np.array_equal(a, b), i
+
+
 def _mixed_small(num_envs=96):
     """Six maps of different sizes, one of each beam count and both footprints."""
     from workloads import maps as gm
@@ -163,10 +190,11 @@ def test_mixed_profiles_launch_shapes_agree():
     cfg, occ, res, env_map, prof = _mixed_small(num_envs=150)
     acts = configs.uniform_actions(5, cfg["num_envs"], seed=33)
     runs = []
-    for kernel, te in [(NAVSIM_KERNEL_PLAIN, 4), (NAVSIM_KERNEL_FUSED, 4),
-                       (NAVSIM_KERNEL_FUSED, 8), (NAVSIM_KERNEL_FUSED, 16)]:
+    for kernel, te, pe in [(NAVSIM_KERNEL_PLAIN, 4, 0), (NAVSIM_KERNEL_FUSED, 4, 0),
+                           (NAVSIM_KERNEL_FUSED, 8, 0), (NAVSIM_KERNEL_FUSED, 16, 0),
+                           (NAVSIM_KERNEL_FUSED, 4, 3), (NAVSIM_KERNEL_FUSED, 2, 16)]:
         sim = NavSim(cfg, occ, res, env_map, device=0, profiles=prof)
-        sim.set_tuning(te, 48, 4)
+        sim.set_tuning(te, 48, 4, persist=pe)
         sim.reset()
         runs.append([gpu_step(sim, acts[t], kernel) for t in range(5)])
         sim.close()
@@ -410,15 +438,20 @@ def test_launch_shape_does_not_change_results():
     w = configs.build_workload("c2", num_envs=600)
     acts = configs.uniform_actions(3, 600, seed=21)
     ref_out = None
-    for te, ra, gr, rs, wk in [(4, 48, 4, 0, 0), (8, 32, 2, 0, 0), (16, 56, 8, 0, 0),
-                               (4, 0, 1, 0, 0), (8, 63, 64, 0, 0), (4, 40, 8, 256, 0),
-                               (16, 48, 4, 600, 0), (1, 48, 8, 0, 0), (2, 40, 8, 0, 0),
-                               (1, 32, 16, 256, 0), (4, 48, 4, 0, 1), (1, 40, 2, 0, 1),
-                               (16, 0, 1, 256, 1), (8, 63, 64, 0, 1)]:
+    # persist > 0: persistent workgroups; 600 envs over 16 maps make chunks
+    # of tiles that cross map boundaries
+    for te, ra, gr, rs, wk, pe in [(4, 48, 4, 0, 0, 0), (8, 32, 2, 0, 0, 0), (16, 56, 8, 0, 0, 0),
+                                   (4, 0, 1, 0, 0, 0), (8, 63, 64, 0, 0, 0), (4, 40, 8, 256, 0, 0),
+                                   (16, 48, 4, 600, 0, 0), (1, 48, 8, 0, 0, 0), (2, 40, 8, 0, 0, 0),
+                                   (1, 32, 16, 256, 0, 0), (4, 48, 4, 0, 1, 0), (1, 40, 2, 0, 1, 0),
+                                   (16, 0, 1, 256, 1, 0), (8, 63, 64, 0, 1, 0),
+                                   (4, 48, 4, 0, 0, 1), (4, 56, 8, 0, 0, 3), (1, 48, 8, 0, 0, 8),
+                                   (8, 32, 2, 256, 0, 2), (16, 48, 4, 0, 1, 64),
+                                   (2, 40, 8, 0, 0, 5)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
-        sim.set_tuning(te, ra, gr, rs, wk)
+        sim.set_tuning(te, ra, gr, rs, wk, pe)
         assert sim.get_tuning() == {"tile_envs": te, "refill_at": ra, "groups": gr,
-                                    "ray_slots": rs, "walk": wk}
+                                    "ray_slots": rs, "walk": wk, "persist": pe}
         sim.reset()
         outs = []
         for t in range(3):
@@ -429,7 +462,8 @@ def test_launch_shape_does_not_change_results():
         else:
             for (ga, sa), (gb, sb) in zip(ref_out, outs):
                 for k in ga:
-                    assert np.array_equal(ga[k], gb[k]) or k == "final_obs", (te, ra, gr, rs, wk, k)
+                    assert np.array_equal(ga[k], gb[k]) or k == "final_obs", (te, ra, gr, rs, wk,
+                                                                               pe, k)
                 for k in oracle.STATE_KEYS:
-                    assert np.array_equal(sa[k], sb[k]), (te, ra, gr, rs, wk, k)
+                    assert np.array_equal(sa[k], sb[k]), (te, ra, gr, rs, wk, pe, k)
         sim.close()
