@@ -242,20 +242,24 @@ typedef struct {
                            many of its 64 lanes are still walking, 0..63                  */
     int32_t groups;     /* 4-cell groups a lane walks between refill checks, 1..64        */
     int32_t ray_slots;  /* LDS ray slots per workgroup (each 16 B): 0 = automatic (the
-                           tile's rays plus one reset scan, or as many as fit in 40 KiB of
-                           LDS so that 4 workgroups share a CU; up to 64 KiB for maps too
-                           large for that); else at most this many (>= 256, rounded up to
-                           64) in 64 KiB.  Fewer slots: less LDS, more workgroups per CU,
-                           more chunks per tile                                           */
+                           tile's rays plus one reset scan, or as many as fit in the LDS
+                           share that lets 1024 / threads workgroups run per CU, i.e. 40 KiB
+                           at 256 threads on a 160 KiB CU; up to max(share, 64 KiB) for
+                           maps too large for that); else at most this many (>= 256,
+                           rounded up to 64) within the device's LDS per workgroup.  Fewer
+                           slots: less LDS, more workgroups per CU, more chunks per tile  */
     int32_t walk;       /* 0: cells in groups of 4; 1: runs of cells between minor-axis
                            steps (32 cells per test along x) -- same cells, same results  */
     int32_t persist;    /* 0: one workgroup per tile; c in 1..64: only as many workgroups
                            as stay resident, each taking c consecutive tiles at a time from
                            a device counter and keeping its staged map while the tiles'
                            map does not change                                             */
+    int32_t threads;    /* threads per workgroup, 256, 512 or 1024: the tile's envs share
+                           this many lanes (and one ray pool); automatic ray slots grow with
+                           it (the CU's LDS split between 1024 / threads workgroups)       */
 } navsim_tuning;
 
-/* Set the fused step's launch shape (defaults: 4, 48, 4, 0, 0, 0).  Changing tile_envs
+/* Set the fused step's launch shape (defaults: 4, 48, 4, 0, 0, 0, 256).  Changing tile_envs
  * after navsim_load_maps waits for the device and re-groups the envs; returns
  * NAVSIM_E_UNSUPPORTED if the larger tile would not fit LDS. */
 navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t);

@@ -1,7 +1,7 @@
 """Launch-shape autotuner for the fused step.
 
 The fused step's results do not depend on its launch shape (tile_envs,
-refill_at, groups, ray_slots, walk, persist; see navsim_set_tuning in
+refill_at, groups, ray_slots, walk, persist, threads; see navsim_set_tuning in
 include/navsim.h), only its speed
 does.  The tuner replays the same seeded steps from the same saved state under
 every candidate shape, times them with HIP events on the simulator's stream,
@@ -21,9 +21,14 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_FILE = os.path.join(HERE, "tuning.json")
-DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4, "ray_slots": 0, "walk": 0, "persist": 0}
-SPACE = {"tile_envs": (1, 2, 4, 8), "refill_at": (32, 48, 56), "groups": (2, 4, 8),
-         "ray_slots": (0, 512, 1024, 2048), "walk": (0, 1), "persist": (0, 2)}
+DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4, "ray_slots": 0, "walk": 0, "persist": 0,
+           "threads": 256}
+# walk = 1 (run walk) measured about 2x slower than the group walk on every
+# workload here; --full-space includes it
+SPACE = {"tile_envs": (1, 2, 4, 8, 16), "refill_at": (48, 56), "groups": (4, 8),
+         "ray_slots": (0, 1024), "walk": (0,), "persist": (0, 2), "threads": (256, 512, 1024)}
+FULL_SPACE = dict(SPACE, refill_at=(32, 48, 56), groups=(2, 4, 8), ray_slots=(0, 512, 1024, 2048),
+                  walk=(0, 1))
 FIELDS = tuple(DEFAULT)
 
 
@@ -111,6 +116,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--out", default=TUNING_FILE, help="JSON file the result is merged into")
+    ap.add_argument("--full-space", action="store_true")
     args = ap.parse_args()
     w = configs.build_workload(args.workload)
     cfg = w["cfg"]
@@ -120,7 +126,8 @@ def main():
     acts = torch.from_numpy(configs.uniform_actions(args.steps + 20, cfg["num_envs"], seed=7)).to(dev)
     for t in range(20):
         sim.step(acts[t])
-    best, table = tune(sim, acts[20:], steps=args.steps, verbose=True)
+    best, table = tune(sim, acts[20:], steps=args.steps, verbose=True,
+                       space=FULL_SPACE if args.full_space else SPACE)
     key = workload_key(cfg, w["maps"], w["profiles"])
     save(key, best, table, torch.cuda.get_device_name(0), args.out)
     print(json.dumps({"key": key, "best": best}))

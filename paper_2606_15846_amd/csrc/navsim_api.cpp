@@ -140,32 +140,38 @@ navsim_status upload(T **dst, const std::vector<T> &src) {
 }
 
 
-// LDS walk slots per chunk.  Automatic (slots 0): within the LDS share that
-// lets four workgroups run per CU, beam table in LDS if at least 512 slots (or
+// LDS walk slots per chunk for workgroups of `threads` threads, given the
+// device's LDS per workgroup (lds_block) and per CU (lds_cu).  Automatic (slots
+// 0): within the share of a CU's LDS that lets the register budget's 16
+// wavefronts per CU run together, beam table in LDS if at least 512 slots (or
 // a whole tile's) still fit beside it, else in device memory; maps too large
-// for that share get up to 64 KiB as below.  Otherwise at most `slots`
-// slots in 64 KiB, keeping the beam table in LDS when a full tile's rays
-// still fit next to it.
-int choose_ray_cap(int max_words, const navsim_config &c, int tile_envs, int slots,
-                   bool &beams_lds) {
+// for that share get up to max(share, 64 KiB) as below.  Otherwise at most
+// `slots` slots in lds_block, keeping the beam table in LDS when a full tile's
+// rays still fit next to it.
+int choose_ray_cap(int max_words, const navsim_config &c, int tile_envs, int threads, int slots,
+                   int lds_block, int lds_cu, bool &beams_lds) {
     const int m = c.num_sectors, K = c.num_beams;
+    const int share =
+        std::min(lds_block, (int)((int64_t)lds_cu * (threads / 64) / kFusedWavesPerCu));
+    int budget = lds_block;
     if (slots == 0) {
         const int full = ((tile_envs + 1) * K + 63) & ~63;
         for (const bool b : {true, false}) {
-            const int cap = fused_ray_cap(max_words, m, tile_envs, K, b, kFusedLdsShare);
+            const int cap = fused_ray_cap(max_words, m, tile_envs, K, b, share);
             if (cap > 0 && (cap >= 512 || cap >= full)) {
                 beams_lds = b;
                 return cap;
             }
         }
+        budget = std::min(lds_block, std::max(share, 65536));
     }
     int cap;
-    const int with = fused_ray_cap(max_words, m, tile_envs, K, true, 65536);
+    const int with = fused_ray_cap(max_words, m, tile_envs, K, true, budget);
     if (with >= tile_envs * K) {
         beams_lds = true;
         cap = with;
     } else {
-        const int without = fused_ray_cap(max_words, m, tile_envs, K, false, 65536);
+        const int without = fused_ray_cap(max_words, m, tile_envs, K, false, budget);
         beams_lds = without <= with;
         cap = beams_lds ? with : without;
     }
@@ -339,6 +345,7 @@ StepParams navsim::make_step_params(const navsim_s *h) {
     p.queue = h->persist ? h->queue : nullptr;
     p.chunk = h->persist;
     p.resident = h->resident;
+    p.wg_threads = h->wg_threads;
     p.march_kmax = h->march_kmax;
     p.march_h = h->march_h;
     return p;
@@ -378,6 +385,18 @@ navsim_status navsim_create(const navsim_config *cfg, int hip_device, navsim_t *
         delete h;
         return fail(NAVSIM_E_OOM, "hipMalloc of the step counter failed");
     }
+    // LDS limits of the device (gfx950: 160 KiB per CU, and per workgroup)
+    if (hipDeviceGetAttribute(&h->lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                              hip_device) != hipSuccess ||
+        hipDeviceGetAttribute(&h->lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              hip_device) != hipSuccess) {
+        (void)hipFree(h->step_ctr);
+        (void)hipFree(h->state_buf);
+        delete h;
+        return fail(NAVSIM_E_HIP, "LDS size query failed");
+    }
+    h->lds_block = std::max(h->lds_block, 65536);
+    h->lds_cu = std::max(h->lds_cu, h->lds_block);
     // the tile queue starts at zero; every persistent launch leaves it there
     if (hipMalloc(&h->queue, 2 * sizeof(int32_t)) != hipSuccess ||
         hipMemset(h->queue, 0, 2 * sizeof(int32_t)) != hipSuccess ||
@@ -525,7 +544,8 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
     }
 
     bool beams_lds = true;
-    const int ray_cap = choose_ray_cap(max_words, cfg, h->tile_envs, h->ray_slots, beams_lds);
+    const int ray_cap = choose_ray_cap(max_words, cfg, h->tile_envs, h->wg_threads, h->ray_slots,
+                                       h->lds_block, h->lds_cu, beams_lds);
     if (ray_cap == 0)
         return fail(NAVSIM_E_UNSUPPORTED,
                     "largest map, %d beams and %d sectors do not fit 64 KiB of LDS per workgroup",
@@ -556,8 +576,8 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
     h->max_words = max_words;
     h->ray_cap = ray_cap;
     h->beams_lds = beams_lds;
-    h->resident = fused_resident_groups(max_words, cfg.num_sectors, h->tile_envs, cfg.num_beams,
-                                        beams_lds, ray_cap);
+    h->resident = fused_resident_groups(max_words, cfg.num_sectors, h->tile_envs, h->wg_threads,
+                                        cfg.num_beams, beams_lds, ray_cap);
     h->host_env_map.swap(host_env_map);
     h->host_occ.assign(occ, occ + occ_off[num_maps]);
     h->host_occ_off = occ_off;
@@ -731,6 +751,8 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     if (t->walk != 0 && t->walk != 1) return fail(NAVSIM_E_INVALID_ARG, "walk must be 0 or 1");
     if (t->persist < 0 || t->persist > 64)
         return fail(NAVSIM_E_INVALID_ARG, "persist must be in 0..64");
+    if (!fused_threads_supported(t->threads))
+        return fail(NAVSIM_E_INVALID_ARG, "threads must be 256, 512 or 1024");
     {
         DeviceGuard g(h->device);
         drop_graph(h);
@@ -738,12 +760,13 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     int ray_cap = h->ray_cap, resident = h->resident;
     bool beams_lds = h->beams_lds;
     if (h->loaded) {
-        ray_cap = choose_ray_cap(h->max_words, h->cfg, t->tile_envs, t->ray_slots, beams_lds);
+        ray_cap = choose_ray_cap(h->max_words, h->cfg, t->tile_envs, t->threads, t->ray_slots,
+                                 h->lds_block, h->lds_cu, beams_lds);
         if (ray_cap == 0)
             return fail(NAVSIM_E_UNSUPPORTED, "tile_envs %d does not fit LDS", t->tile_envs);
         DeviceGuard g(h->device);
         resident = fused_resident_groups(h->max_words, h->cfg.num_sectors, t->tile_envs,
-                                         h->cfg.num_beams, beams_lds, ray_cap);
+                                         t->threads, h->cfg.num_beams, beams_lds, ray_cap);
         if (resident <= 0) return fail(NAVSIM_E_HIP, "occupancy query of the fused step failed");
     }
     if (h->loaded && t->tile_envs != h->tile_envs) {
@@ -768,6 +791,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     h->ray_slots = t->ray_slots;
     h->walk_mode = t->walk;
     h->persist = t->persist;
+    h->wg_threads = t->threads;
     h->ray_cap = ray_cap;
     h->resident = resident;
     h->beams_lds = beams_lds;
@@ -783,6 +807,7 @@ navsim_status navsim_get_tuning(navsim_t h, navsim_tuning *t) {
     t->ray_slots = h->ray_slots;
     t->walk = h->walk_mode;
     t->persist = h->persist;
+    t->threads = h->wg_threads;
     return NAVSIM_OK;
 }
 

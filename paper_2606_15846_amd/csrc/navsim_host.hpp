@@ -63,6 +63,8 @@ struct navsim_s {
     int walk_mode = 0;  // fused walk: 0 cells in groups of 4, 1 runs
     bool beams_lds = true;
     int persist = 0;    // persistent workgroups: tiles per grab (0 = one workgroup per tile)
+    int wg_threads = 256;  // fused step: threads per workgroup
+    int lds_block = 65536, lds_cu = 65536;  // device LDS bytes per workgroup and per CU
     int resident = 0;   // workgroups of the fused step resident at once on the device
     int32_t *queue = nullptr;  // device {next tile, finished workgroups}, zero between launches
     int scan_mode = 0;       // 0 exact traversal, 1 fixed-step march

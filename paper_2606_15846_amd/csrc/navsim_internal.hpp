@@ -57,6 +57,7 @@ struct StepParams {
     int32_t *queue;             // persistent workgroups: {next tile, finished groups}, or null
     int32_t chunk;              // persistent workgroups: tiles taken at a time
     int32_t resident;           // persistent workgroups: how many stay resident on the device
+    int32_t wg_threads;         // fused step: threads per workgroup (256, 512, 1024)
     int32_t ray_cap;            // rays walked per chunk (LDS slots)
     int32_t beams_lds;          // stage the beam table in LDS
     int32_t scan_mode;          // 0 exact traversal, 1 fixed-step march
@@ -91,12 +92,13 @@ struct StepParams {
 
 size_t fused_lds_bytes(int max_words, int m, int tile_envs, int K, int ray_cap);
 int fused_ray_cap(int max_words, int m, int tile_envs, int K, bool beams_lds, int budget);
-// LDS share per fused workgroup that lets four of them (the wavefronts its
-// register budget allows per CU) run together in a CU's 160 KiB.
-constexpr int kFusedLdsShare = 40960;
+// Wavefronts per CU that the fused step's register budget allows (4 per SIMD).
+constexpr int kFusedWavesPerCu = 16;
 // Workgroups of the fused step that fit on the current device at once (0 on error).
-int fused_resident_groups(int max_words, int m, int tile_envs, int K, bool beams_lds, int ray_cap);
+int fused_resident_groups(int max_words, int m, int tile_envs, int threads, int K, bool beams_lds,
+                          int ray_cap);
 bool fused_tile_envs_supported(int tile_envs);
+bool fused_threads_supported(int threads);
 hipError_t launch_fused(const StepParams &p, int tile_envs, hipStream_t s);
 hipError_t launch_plain(const StepParams &p, hipStream_t s);
 hipError_t launch_set_step(uint32_t *ctr, uint64_t first_step, hipStream_t s);

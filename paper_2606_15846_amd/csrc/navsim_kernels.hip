@@ -20,6 +20,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "navsim_internal.hpp"
 #include "philox.hpp"
@@ -536,7 +537,7 @@ struct TileJob {
     int i0, j0, blocked, block_hit, env, dst;  // dst 0 obs row, 1 final_obs row, 2 none
 };
 
-constexpr int kFusedThreads = 256;
+// Register budget of the fused step: 4 wavefronts per SIMD (16 per CU).
 constexpr int kFusedWavesPerSimd = 4;
 constexpr int kGroupLanes = 16;
 
@@ -1023,7 +1024,8 @@ __device__ __forceinline__ int *fused_list(const StepParams &p) {
     return reinterpret_cast<int *>(s_pool + pool_words(E, p.m));
 }
 
-template <int E>
+// One tile with a workgroup of T threads (T / 64 wavefronts).
+template <int E, int T>
 __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, int &staged_map) {
     extern __shared__ uint4 smem4[];
     uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem4);
@@ -1040,9 +1042,9 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
     const double2 *beams = p.beams + md.beam_off;  // this map's beam directions
     if (tile.map != staged_map) {  // a persistent workgroup keeps its map between tiles
         const uint4 *g = reinterpret_cast<const uint4 *>(p.bits + md.word_off);
-        for (int q = tid; q < md.words / 4; q += kFusedThreads) smem4[q] = g[q];
+        for (int q = tid; q < md.words / 4; q += T) smem4[q] = g[q];
         if (p.beams_lds)
-            for (int q = tid; q < K; q += kFusedThreads) s_beam[q] = beams[q];
+            for (int q = tid; q < K; q += T) s_beam[q] = beams[q];
         staged_map = tile.map;
     }
     if (!p.beams_lds) s_beam = const_cast<double2 *>(beams);
@@ -1141,7 +1143,7 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
         s_misc[0] = nj;
         s_misc[1] = 0;
     }
-    for (int q = tid; q < 2 * E * m; q += kFusedThreads) s_pool[q] = 0x7f800000u;  // +inf
+    for (int q = tid; q < 2 * E * m; q += T) s_pool[q] = 0x7f800000u;  // +inf
     __syncthreads();
 
     // ---- scan, in chunks of at most ray_cap rays ----
@@ -1153,7 +1155,7 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
     for (int c0 = 0; c0 < R; c0 += p.ray_cap) {
         const int Rc = min(p.ray_cap, R - c0);
         // (1) every ray's walk start, all lanes busy (the march needs none)
-        for (int r = tid; r < Rc && p.scan_mode != 1; r += kFusedThreads) {
+        for (int r = tid; r < Rc && p.scan_mode != 1; r += T) {
             const int g = c0 + r, jl = small_div(g, K, inv_K), beam = g - jl * K;
             const TileJob &j = s_jobs[s_list[jl]];
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
@@ -1265,7 +1267,7 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
         }
         __syncthreads();
         // (3) ranges, hits, pooling, all lanes busy
-        for (int q = tid; q < Rc; q += kFusedThreads) {
+        for (int q = tid; q < Rc; q += T) {
             const int g = c0 + q, jl = small_div(g, K, inv_K), beam = g - jl * K;
             const int job = s_list[jl];
             const uint4 v = s_ray[q];
@@ -1279,7 +1281,7 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
     }
 
     // ---- pooled sector minima -> observation rows ----
-    for (int q = tid; q < nj * m; q += kFusedThreads) {
+    for (int q = tid; q < nj * m; q += T) {
         const int jl = q / m, sec = q - jl * m;
         const TileJob &j = s_jobs[s_list[jl]];
         float *dst = j.dst == 0 ? p.obs : (j.dst == 1 ? p.final_obs : nullptr);
@@ -1294,12 +1296,12 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
 // one another's LDS latency in the walk (the compiler's own choice, ~200,
 // leaves 2).  The motion phase spills a few values to scratch memory; the
 // walk loop keeps everything in registers.
-template <int E>
-__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerSimd)))
+template <int E, int T>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerSimd)))
 void fused_step_kernel(StepParams p) {
     int staged = -1;
     if (!p.queue) {
-        fused_tile<E>(p, (int)blockIdx.x, staged);
+        fused_tile<E, T>(p, (int)blockIdx.x, staged);
         return;
     }
     int *s_next = fused_list<E>(p) + 4 * E + 7;
@@ -1311,7 +1313,7 @@ void fused_step_kernel(StepParams p) {
         if (t0 >= p.num_tiles) break;
         const int t1 = min(t0 + p.chunk, p.num_tiles);
         for (int t = t0; t < t1; ++t) {
-            fused_tile<E>(p, t, staged);
+            fused_tile<E, T>(p, t, staged);
             __syncthreads();
         }
     }
@@ -1428,43 +1430,57 @@ __global__ __launch_bounds__(64) void plain_step_kernel(StepParams p) {
 }
 
 // ---------------------------------------------------------------------------
-template <int E>
-static hipError_t launch_fused_e(const StepParams &p, hipStream_t s) {
+template <int E, int T>
+static hipError_t launch_fused_et(const StepParams &p, hipStream_t s) {
     const size_t lds = fused_lds_bytes(p.max_words, p.m, E, p.beams_lds ? p.K : 0, p.ray_cap);
+    if (lds > 65536u) {
+        // dynamic LDS beyond 64 KiB (gfx950 allows up to 160 KiB per workgroup)
+        static std::atomic<int> raised{65536};
+        if ((int)lds > raised.load()) {
+            const hipError_t e = hipFuncSetAttribute(
+                reinterpret_cast<const void *>(fused_step_kernel<E, T>),
+                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            raised.store((int)lds);
+        }
+    }
     unsigned grid = (unsigned)p.num_tiles;
     if (p.queue) {
         // at most the resident workgroups, and one per chunk of tiles
         const int chunks = (p.num_tiles + p.chunk - 1) / p.chunk;
         grid = (unsigned)std::max(1, std::min(chunks, p.resident));
     }
-    hipLaunchKernelGGL(fused_step_kernel<E>, dim3(grid), dim3(kFusedThreads), lds, s, p);
+    hipLaunchKernelGGL((fused_step_kernel<E, T>), dim3(grid), dim3(T), lds, s, p);
     return hipGetLastError();
 }
 
-template <int E>
-static int resident_e(size_t lds) {
+template <int E, int T>
+static int resident_et(size_t lds) {
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_step_kernel<E>, kFusedThreads,
-                                                     lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_step_kernel<E, T>, T, lds) !=
+            hipSuccess ||
         hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     return per_cu * cus;
 }
 
-int fused_resident_groups(int max_words, int m, int E, int K, bool beams_lds, int ray_cap) {
+// Every supported (tile_envs, threads) pair.
+#define NAVSIM_FUSED_SHAPES(X)                                                                \
+    X(1, 256) X(1, 512) X(1, 1024) X(2, 256) X(2, 512) X(2, 1024) X(4, 256) X(4, 512)        \
+    X(4, 1024) X(8, 256) X(8, 512) X(8, 1024) X(16, 256) X(16, 512) X(16, 1024)
+
+int fused_resident_groups(int max_words, int m, int E, int T, int K, bool beams_lds, int ray_cap) {
     const size_t lds = fused_lds_bytes(max_words, m, E, beams_lds ? K : 0, ray_cap);
-    switch (E) {
-        case 1: return resident_e<1>(lds);
-        case 2: return resident_e<2>(lds);
-        case 4: return resident_e<4>(lds);
-        case 8: return resident_e<8>(lds);
-        case 16: return resident_e<16>(lds);
-        default: return 0;
-    }
+#define NAVSIM_X(e, t) \
+    if (E == e && T == t) return resident_et<e, t>(lds);
+    NAVSIM_FUSED_SHAPES(NAVSIM_X)
+#undef NAVSIM_X
+    return 0;
 }
 
 bool fused_tile_envs_supported(int E) { return E == 1 || E == 2 || E == 4 || E == 8 || E == 16; }
+bool fused_threads_supported(int T) { return T == 256 || T == 512 || T == 1024; }
 
 // LDS walk slots per chunk: the rays of a full tile plus one reset pose
 // ((E + 1) K, rounded up to a wavefront), so a tile walks a second chunk only
@@ -1479,14 +1495,11 @@ int fused_ray_cap(int max_words, int m, int E, int K, bool beams_lds, int budget
 
 hipError_t launch_fused(const StepParams &p, int tile_envs, hipStream_t s) {
     if (p.num_tiles == 0) return hipSuccess;
-    switch (tile_envs) {
-        case 1: return launch_fused_e<1>(p, s);
-        case 2: return launch_fused_e<2>(p, s);
-        case 4: return launch_fused_e<4>(p, s);
-        case 8: return launch_fused_e<8>(p, s);
-        case 16: return launch_fused_e<16>(p, s);
-        default: return hipErrorInvalidValue;
-    }
+#define NAVSIM_X(e, t) \
+    if (tile_envs == e && p.wg_threads == t) return launch_fused_et<e, t>(p, s);
+    NAVSIM_FUSED_SHAPES(NAVSIM_X)
+#undef NAVSIM_X
+    return hipErrorInvalidValue;
 }
 
 // Sets the rollout's first step index in device memory, so that a captured

@@ -124,17 +124,19 @@ def test_c4_mixed_profiles_full_size_fused():
     sim.close()
 
 
-def test_c4_full_size_persistent_equals_one_workgroup_per_tile():
-    # the launch configuration the C4 line of the bench times, against the
-    # per-tile launch that the test above holds to the oracle
-    say("c4 full size: persistent workgroups (chunks of 1, 4, 16 tiles) == per-tile, 3 steps")
+def test_c4_full_size_launch_shapes_agree():
+    # launch shapes the C4 line of the bench may time, against the per-tile
+    # 256-thread launch that the test above holds to the oracle; 1024 threads
+    # take more than 64 KiB of LDS per workgroup
+    say("c4 full size: persistent workgroups and 512 / 1024 threads == per-tile, 3 steps")
     w = configs.build_workload("c4")
     acts = torch.from_numpy(configs.uniform_actions(3, w["cfg"]["num_envs"], seed=5)).cuda()
     runs = []
-    for te, pe in [(8, 0), (8, 4), (4, 1), (16, 16)]:
+    for te, pe, th in [(8, 0, 256), (8, 4, 256), (4, 1, 256), (16, 16, 256), (8, 0, 512),
+                       (16, 0, 1024), (4, 0, 1024)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0,
                      profiles=w["profiles"])
-        sim.set_tuning(te, 48, 8, persist=pe)
+        sim.set_tuning(te, 48, 8, persist=pe, threads=th)
         outs = [sim.reset().cpu().numpy().copy()]
         for t in range(3):
             o, r, te_, tr, info = sim.step(acts[t])
@@ -190,11 +192,12 @@ def test_mixed_profiles_launch_shapes_agree():
     cfg, occ, res, env_map, prof = _mixed_small(num_envs=150)
     acts = configs.uniform_actions(5, cfg["num_envs"], seed=33)
     runs = []
-    for kernel, te, pe in [(NAVSIM_KERNEL_PLAIN, 4, 0), (NAVSIM_KERNEL_FUSED, 4, 0),
-                           (NAVSIM_KERNEL_FUSED, 8, 0), (NAVSIM_KERNEL_FUSED, 16, 0),
-                           (NAVSIM_KERNEL_FUSED, 4, 3), (NAVSIM_KERNEL_FUSED, 2, 16)]:
+    for kernel, te, pe, th in [(NAVSIM_KERNEL_PLAIN, 4, 0, 256), (NAVSIM_KERNEL_FUSED, 4, 0, 256),
+                               (NAVSIM_KERNEL_FUSED, 8, 0, 256), (NAVSIM_KERNEL_FUSED, 16, 0, 256),
+                               (NAVSIM_KERNEL_FUSED, 4, 3, 256), (NAVSIM_KERNEL_FUSED, 2, 16, 256),
+                               (NAVSIM_KERNEL_FUSED, 8, 0, 512), (NAVSIM_KERNEL_FUSED, 16, 0, 1024)]:
         sim = NavSim(cfg, occ, res, env_map, device=0, profiles=prof)
-        sim.set_tuning(te, 48, 4, persist=pe)
+        sim.set_tuning(te, 48, 4, persist=pe, threads=th)
         sim.reset()
         runs.append([gpu_step(sim, acts[t], kernel) for t in range(5)])
         sim.close()
@@ -439,19 +442,22 @@ def test_launch_shape_does_not_change_results():
     acts = configs.uniform_actions(3, 600, seed=21)
     ref_out = None
     # persist > 0: persistent workgroups; 600 envs over 16 maps make chunks
-    # of tiles that cross map boundaries
-    for te, ra, gr, rs, wk, pe in [(4, 48, 4, 0, 0, 0), (8, 32, 2, 0, 0, 0), (16, 56, 8, 0, 0, 0),
-                                   (4, 0, 1, 0, 0, 0), (8, 63, 64, 0, 0, 0), (4, 40, 8, 256, 0, 0),
-                                   (16, 48, 4, 600, 0, 0), (1, 48, 8, 0, 0, 0), (2, 40, 8, 0, 0, 0),
-                                   (1, 32, 16, 256, 0, 0), (4, 48, 4, 0, 1, 0), (1, 40, 2, 0, 1, 0),
-                                   (16, 0, 1, 256, 1, 0), (8, 63, 64, 0, 1, 0),
-                                   (4, 48, 4, 0, 0, 1), (4, 56, 8, 0, 0, 3), (1, 48, 8, 0, 0, 8),
-                                   (8, 32, 2, 256, 0, 2), (16, 48, 4, 0, 1, 64),
-                                   (2, 40, 8, 0, 0, 5)]:
+    # of tiles that cross map boundaries.  th: threads per workgroup.
+    for te, ra, gr, rs, wk, pe, th in [
+            (4, 48, 4, 0, 0, 0, 256), (8, 32, 2, 0, 0, 0, 256), (16, 56, 8, 0, 0, 0, 256),
+            (4, 0, 1, 0, 0, 0, 256), (8, 63, 64, 0, 0, 0, 256), (4, 40, 8, 256, 0, 0, 256),
+            (16, 48, 4, 600, 0, 0, 256), (1, 48, 8, 0, 0, 0, 256), (2, 40, 8, 0, 0, 0, 256),
+            (1, 32, 16, 256, 0, 0, 256), (4, 48, 4, 0, 1, 0, 256), (1, 40, 2, 0, 1, 0, 256),
+            (16, 0, 1, 256, 1, 0, 256), (8, 63, 64, 0, 1, 0, 256),
+            (4, 48, 4, 0, 0, 1, 256), (4, 56, 8, 0, 0, 3, 256), (1, 48, 8, 0, 0, 8, 256),
+            (8, 32, 2, 256, 0, 2, 256), (16, 48, 4, 0, 1, 64, 256), (2, 40, 8, 0, 0, 5, 256),
+            (4, 56, 8, 0, 0, 0, 512), (16, 56, 8, 0, 0, 0, 1024), (1, 48, 4, 0, 0, 0, 1024),
+            (8, 32, 2, 256, 0, 0, 512), (2, 48, 8, 0, 1, 0, 512), (16, 48, 4, 0, 0, 2, 1024),
+            (8, 0, 1, 4096, 0, 0, 1024)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
-        sim.set_tuning(te, ra, gr, rs, wk, pe)
+        sim.set_tuning(te, ra, gr, rs, wk, pe, th)
         assert sim.get_tuning() == {"tile_envs": te, "refill_at": ra, "groups": gr,
-                                    "ray_slots": rs, "walk": wk, "persist": pe}
+                                    "ray_slots": rs, "walk": wk, "persist": pe, "threads": th}
         sim.reset()
         outs = []
         for t in range(3):
@@ -463,7 +469,7 @@ def test_launch_shape_does_not_change_results():
             for (ga, sa), (gb, sb) in zip(ref_out, outs):
                 for k in ga:
                     assert np.array_equal(ga[k], gb[k]) or k == "final_obs", (te, ra, gr, rs, wk,
-                                                                               pe, k)
+                                                                               pe, th, k)
                 for k in oracle.STATE_KEYS:
-                    assert np.array_equal(sa[k], sb[k]), (te, ra, gr, rs, wk, pe, k)
+                    assert np.array_equal(sa[k], sb[k]), (te, ra, gr, rs, wk, pe, th, k)
         sim.close()
