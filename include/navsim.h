@@ -249,7 +249,10 @@ typedef struct {
                            rounded up to 64) within the device's LDS per workgroup.  Fewer
                            slots: less LDS, more workgroups per CU, more chunks per tile  */
     int32_t walk;       /* 0: cells in groups of 4; 1: runs of cells between minor-axis
-                           steps (32 cells per test along x) -- same cells, same results  */
+                           steps (32 cells per test along x); 2: cells in groups of 4 read
+                           from a one-byte-per-cell copy of the map staged next to the
+                           bitmap (32x its LDS; no address arithmetic or bit extraction per
+                           cell) -- same cells, same results                              */
     int32_t persist;    /* 0: one workgroup per tile; c in 1..64: only as many workgroups
                            as stay resident, each taking c consecutive tiles at a time from
                            a device counter and keeping its staged map while the tiles'

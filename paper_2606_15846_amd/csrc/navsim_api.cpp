@@ -149,7 +149,7 @@ navsim_status upload(T **dst, const std::vector<T> &src) {
 // `slots` slots in lds_block, keeping the beam table in LDS when a full tile's
 // rays still fit next to it.
 int choose_ray_cap(int max_words, const navsim_config &c, int tile_envs, int threads, int slots,
-                   int lds_block, int lds_cu, bool &beams_lds) {
+                   int lds_block, int lds_cu, int cell_bytes, bool &beams_lds) {
     const int m = c.num_sectors, K = c.num_beams;
     const int share =
         std::min(lds_block, (int)((int64_t)lds_cu * (threads / 64) / kFusedWavesPerCu));
@@ -157,7 +157,7 @@ int choose_ray_cap(int max_words, const navsim_config &c, int tile_envs, int thr
     if (slots == 0) {
         const int full = ((tile_envs + 1) * K + 63) & ~63;
         for (const bool b : {true, false}) {
-            const int cap = fused_ray_cap(max_words, m, tile_envs, K, b, share);
+            const int cap = fused_ray_cap(max_words, m, tile_envs, K, b, share, cell_bytes);
             if (cap > 0 && (cap >= 512 || cap >= full)) {
                 beams_lds = b;
                 return cap;
@@ -166,17 +166,67 @@ int choose_ray_cap(int max_words, const navsim_config &c, int tile_envs, int thr
         budget = std::min(lds_block, std::max(share, 65536));
     }
     int cap;
-    const int with = fused_ray_cap(max_words, m, tile_envs, K, true, budget);
+    const int with = fused_ray_cap(max_words, m, tile_envs, K, true, budget, cell_bytes);
     if (with >= tile_envs * K) {
         beams_lds = true;
         cap = with;
     } else {
-        const int without = fused_ray_cap(max_words, m, tile_envs, K, false, budget);
+        const int without = fused_ray_cap(max_words, m, tile_envs, K, false, budget, cell_bytes);
         beams_lds = without <= with;
         cap = beams_lds ? with : without;
     }
     if (cap > 0 && slots > 0) cap = std::min(cap, std::max(256, (slots + 63) & ~63));
     return cap;
+}
+
+// LDS layout of the fused step for one launch shape and scan mode.  The claim
+// walk (walk 3, 4; exact traversal only) keeps no ray slots; the chunked
+// walks (and the march) use ray_cap slots.  walk 2 and 4 stage the map's
+// byte-per-cell copy.  Fails with UNSUPPORTED when nothing fits.
+struct FusedShape {
+    int ray_cap = 0, cell_bytes = 0, claim = 0, resident = 0;
+    bool beams_lds = true;
+};
+
+navsim_status fused_shape(const navsim_s *h, int max_words, int tile_envs, int threads, int slots,
+                          int walk, int scan_mode, FusedShape &out) {
+    const navsim_config &c = h->cfg;
+    const int m = c.num_sectors, K = c.num_beams;
+    out.claim = scan_mode == NAVSIM_SCAN_TRAVERSAL && walk >= 3;
+    out.cell_bytes =
+        (scan_mode == NAVSIM_SCAN_TRAVERSAL && (walk == 2 || walk == 4)) ? max_words * 32 : 0;
+    if (out.claim) {
+        const size_t share = std::min<size_t>(
+            (size_t)h->lds_block, (size_t)h->lds_cu * (threads / 64) / kFusedWavesPerCu);
+        const size_t with = fused_lds_bytes(max_words, m, tile_envs, K, 0, out.cell_bytes);
+        const size_t without = fused_lds_bytes(max_words, m, tile_envs, 0, 0, out.cell_bytes);
+        if (without > (size_t)h->lds_block)
+            return fail(NAVSIM_E_UNSUPPORTED,
+                        "launch shape (tile_envs %d, threads %d, walk %d) does not fit LDS",
+                        tile_envs, threads, walk);
+        out.beams_lds = with <= (size_t)h->lds_block && (with <= share || without > share);
+        out.ray_cap = 256;  // unused by the claim walk
+    } else {
+        out.ray_cap = choose_ray_cap(max_words, c, tile_envs, threads, slots, h->lds_block,
+                                     h->lds_cu, out.cell_bytes, out.beams_lds);
+        if (out.ray_cap == 0)
+            return fail(NAVSIM_E_UNSUPPORTED,
+                        "launch shape (tile_envs %d, threads %d, walk %d) and the largest map, "
+                        "%d beams, %d sectors do not fit the LDS of one workgroup (%d bytes)",
+                        tile_envs, threads, walk, K, m, h->lds_block);
+    }
+    out.resident = fused_resident_groups(max_words, m, tile_envs, threads, K, out.beams_lds,
+                                         out.claim ? 0 : out.ray_cap, out.cell_bytes);
+    if (out.resident <= 0) return fail(NAVSIM_E_HIP, "occupancy query of the fused step failed");
+    return NAVSIM_OK;
+}
+
+void apply_shape(navsim_s *h, const FusedShape &f) {
+    h->ray_cap = f.ray_cap;
+    h->cell_bytes = f.cell_bytes;
+    h->claim = f.claim;
+    h->resident = f.resident;
+    h->beams_lds = f.beams_lds;
 }
 
 // Envs grouped by map (stable in env order) into tiles of up to tile_envs envs,
@@ -342,6 +392,8 @@ StepParams navsim::make_step_params(const navsim_s *h) {
     p.beams_lds = h->beams_lds ? 1 : 0;
     p.scan_mode = h->scan_mode;
     p.walk_mode = h->walk_mode;
+    p.cell_bytes = h->cell_bytes;
+    p.claim = h->claim;
     p.queue = h->persist ? h->queue : nullptr;
     p.chunk = h->persist;
     p.resident = h->resident;
@@ -543,13 +595,13 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
             return fail(NAVSIM_E_NO_FREE_SPACE, "map %d has no cell where the footprint fits", k);
     }
 
-    bool beams_lds = true;
-    const int ray_cap = choose_ray_cap(max_words, cfg, h->tile_envs, h->wg_threads, h->ray_slots,
-                                       h->lds_block, h->lds_cu, beams_lds);
-    if (ray_cap == 0)
-        return fail(NAVSIM_E_UNSUPPORTED,
-                    "largest map, %d beams and %d sectors do not fit 64 KiB of LDS per workgroup",
-                    cfg.num_beams, cfg.num_sectors);
+    FusedShape shape;
+    {
+        DeviceGuard g(h->device);
+        const navsim_status fs = fused_shape(h, max_words, h->tile_envs, h->wg_threads,
+                                             h->ray_slots, h->walk_mode, h->scan_mode, shape);
+        if (fs != NAVSIM_OK) return fs;
+    }
     std::vector<int32_t> host_env_map(env_map, env_map + N);
     std::vector<int32_t> perm;
     std::vector<Tile> tiles;
@@ -574,10 +626,7 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
     h->num_maps = num_maps;
     h->num_tiles = (int)tiles.size();
     h->max_words = max_words;
-    h->ray_cap = ray_cap;
-    h->beams_lds = beams_lds;
-    h->resident = fused_resident_groups(max_words, cfg.num_sectors, h->tile_envs, h->wg_threads,
-                                        cfg.num_beams, beams_lds, ray_cap);
+    apply_shape(h, shape);
     h->host_env_map.swap(host_env_map);
     h->host_occ.assign(occ, occ + occ_off[num_maps]);
     h->host_occ_off = occ_off;
@@ -728,10 +777,18 @@ navsim_status navsim_set_scan(navsim_t h, int32_t mode, float step_m) {
         while ((double)(kmax + 1) * hh <= rmax) ++kmax;
         while (kmax > 0 && (double)kmax * hh > rmax) --kmax;
     }
+    FusedShape shape;
+    if (h->loaded) {
+        DeviceGuard g(h->device);
+        const navsim_status fs = fused_shape(h, h->max_words, h->tile_envs, h->wg_threads,
+                                             h->ray_slots, h->walk_mode, mode, shape);
+        if (fs != NAVSIM_OK) return fs;
+    }
     {
         DeviceGuard g(h->device);
         drop_graph(h);
     }
+    if (h->loaded) apply_shape(h, shape);
     h->scan_mode = mode;
     h->march_h = mode == NAVSIM_SCAN_MARCH ? (double)step_m : 0.0;
     h->march_kmax = kmax;
@@ -748,7 +805,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     if (t->groups < 1 || t->groups > 64) return fail(NAVSIM_E_INVALID_ARG, "groups must be in 1..64");
     if (t->ray_slots < 0 || (t->ray_slots > 0 && t->ray_slots < 256))
         return fail(NAVSIM_E_INVALID_ARG, "ray_slots must be 0 or >= 256");
-    if (t->walk != 0 && t->walk != 1) return fail(NAVSIM_E_INVALID_ARG, "walk must be 0 or 1");
+    if (t->walk < 0 || t->walk > 4) return fail(NAVSIM_E_INVALID_ARG, "walk must be in 0..4");
     if (t->persist < 0 || t->persist > 64)
         return fail(NAVSIM_E_INVALID_ARG, "persist must be in 0..64");
     if (!fused_threads_supported(t->threads))
@@ -757,17 +814,12 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
         DeviceGuard g(h->device);
         drop_graph(h);
     }
-    int ray_cap = h->ray_cap, resident = h->resident;
-    bool beams_lds = h->beams_lds;
+    FusedShape shape;
     if (h->loaded) {
-        ray_cap = choose_ray_cap(h->max_words, h->cfg, t->tile_envs, t->threads, t->ray_slots,
-                                 h->lds_block, h->lds_cu, beams_lds);
-        if (ray_cap == 0)
-            return fail(NAVSIM_E_UNSUPPORTED, "tile_envs %d does not fit LDS", t->tile_envs);
         DeviceGuard g(h->device);
-        resident = fused_resident_groups(h->max_words, h->cfg.num_sectors, t->tile_envs,
-                                         t->threads, h->cfg.num_beams, beams_lds, ray_cap);
-        if (resident <= 0) return fail(NAVSIM_E_HIP, "occupancy query of the fused step failed");
+        const navsim_status fs = fused_shape(h, h->max_words, t->tile_envs, t->threads,
+                                             t->ray_slots, t->walk, h->scan_mode, shape);
+        if (fs != NAVSIM_OK) return fs;
     }
     if (h->loaded && t->tile_envs != h->tile_envs) {
         std::vector<int32_t> perm;
@@ -792,9 +844,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     h->walk_mode = t->walk;
     h->persist = t->persist;
     h->wg_threads = t->threads;
-    h->ray_cap = ray_cap;
-    h->resident = resident;
-    h->beams_lds = beams_lds;
+    if (h->loaded) apply_shape(h, shape);
     return NAVSIM_OK;
 }
 

@@ -60,10 +60,12 @@ struct navsim_s {
     int tile_envs = navsim::kDefaultTileEnvs, refill_at = navsim::kDefaultRefillAt, groups = navsim::kDefaultGroups;
     int ray_cap = 0;
     int ray_slots = 0;  // requested cap on ray_cap (0 = automatic)
-    int walk_mode = 0;  // fused walk: 0 cells in groups of 4, 1 runs
+    int walk_mode = 0;  // fused walk: 0 cells in groups of 4, 1 runs, 2 groups of 4 on bytes
     bool beams_lds = true;
     int persist = 0;    // persistent workgroups: tiles per grab (0 = one workgroup per tile)
     int wg_threads = 256;  // fused step: threads per workgroup
+    int cell_bytes = 0;    // walk 2, 4: LDS bytes of the byte-per-cell map copy
+    int claim = 0;         // walk 3, 4 with the exact traversal: claim walk, no ray slots
     int lds_block = 65536, lds_cu = 65536;  // device LDS bytes per workgroup and per CU
     int resident = 0;   // workgroups of the fused step resident at once on the device
     int32_t *queue = nullptr;  // device {next tile, finished workgroups}, zero between launches

@@ -53,7 +53,10 @@ struct DevState {
 struct StepParams {
     int32_t N, K, m, horizon, tries, mode;  // K: largest beam count; mode 0 step, 1 reset
     int32_t refill_at, groups;  // fused walk: refill threshold, 4-cell groups per check
-    int32_t walk_mode;          // fused walk: 0 cells in groups of 4, 1 runs
+    int32_t walk_mode;          // fused walk: 0 groups of 4 cells, 1 runs, 2 groups on bytes,
+                                // 3 claim walk (setup and finish per claimed ray), 4 on bytes
+    int32_t cell_bytes;         // walk 2, 4: LDS bytes of the byte-per-cell map copy (else 0)
+    int32_t claim;              // claim walk in use (walk 3, 4 with the exact traversal)
     int32_t *queue;             // persistent workgroups: {next tile, finished groups}, or null
     int32_t chunk;              // persistent workgroups: tiles taken at a time
     int32_t resident;           // persistent workgroups: how many stay resident on the device
@@ -90,13 +93,14 @@ struct StepParams {
     uint8_t *d_coll, *d_goal, *d_reset, *d_fb;
 };
 
-size_t fused_lds_bytes(int max_words, int m, int tile_envs, int K, int ray_cap);
-int fused_ray_cap(int max_words, int m, int tile_envs, int K, bool beams_lds, int budget);
+size_t fused_lds_bytes(int max_words, int m, int tile_envs, int K, int ray_cap, int cell_bytes);
+int fused_ray_cap(int max_words, int m, int tile_envs, int K, bool beams_lds, int budget,
+                  int cell_bytes);
 // Wavefronts per CU that the fused step's register budget allows (4 per SIMD).
 constexpr int kFusedWavesPerCu = 16;
 // Workgroups of the fused step that fit on the current device at once (0 on error).
 int fused_resident_groups(int max_words, int m, int tile_envs, int threads, int K, bool beams_lds,
-                          int ray_cap);
+                          int ray_cap, int cell_bytes);
 bool fused_tile_envs_supported(int tile_envs);
 bool fused_threads_supported(int threads);
 hipError_t launch_fused(const StepParams &p, int tile_envs, hipStream_t s);

@@ -545,9 +545,9 @@ constexpr int kGroupLanes = 16;
 // after it 16-byte aligned.
 __host__ __device__ constexpr int pool_words(int E, int m) { return (2 * E * m + 3) & ~3; }
 
-size_t fused_lds_bytes(int max_words, int m, int E, int K, int ray_cap) {
+size_t fused_lds_bytes(int max_words, int m, int E, int K, int ray_cap, int cell_bytes) {
     // K = 0 when the beam table stays in device memory
-    return (size_t)max_words * 4u + 2u * (size_t)E * sizeof(TileJob) +
+    return (size_t)max_words * 4u + (size_t)cell_bytes + 2u * (size_t)E * sizeof(TileJob) +
            (size_t)pool_words(E, m) * 4u + (4u * (size_t)E + 8u) * 4u + 16u * (size_t)K +
            16u * (size_t)ray_cap;
 }
@@ -1011,14 +1011,200 @@ __device__ __forceinline__ void march_walk(const StepParams &p, const MapView &M
         reinterpret_cast<uint2 *>(s_ray)[2 * r] = make_uint2((uint32_t)k | ((uint32_t)type << 28), 0u);
 }
 
-// LDS of the fused step, in order: bitmap [max_words], jobs [2E] (main,
+// Up to `groups` groups of 4 cells of one lane's walk; the 4 cells of a group
+// are read before any is tested (the padding ring keeps them in the stored
+// map).  Stops at the first occupied cell (flags = 1) or when the r_max
+// budget n is used up; act turns false then.
+template <bool BYTES>
+__device__ __forceinline__ void walk_groups(const StepParams &p, const uint32_t *s_bits,
+                                            const uint8_t *s_cells, int &B, int &Eh, int incx,
+                                            int incy, int dEx, int dEy, int n, int &k,
+                                            uint32_t &flags, bool &act) {
+#pragma unroll 1
+    for (int gi = 0; gi < p.groups; ++gi) {
+        const bool x0 = Eh < 0;
+        const int B0 = B + (x0 ? incx : incy);
+        const int E1 = Eh + (x0 ? dEx : dEy);
+        const bool x1 = E1 < 0;
+        const int B1 = B0 + (x1 ? incx : incy);
+        const int E2 = E1 + (x1 ? dEx : dEy);
+        const bool x2 = E2 < 0;
+        const int B2 = B1 + (x2 ? incx : incy);
+        const int E3 = E2 + (x2 ? dEx : dEy);
+        const bool x3 = E3 < 0;
+        const int B3 = B2 + (x3 ? incx : incy);
+        const int E4 = E3 + (x3 ? dEx : dEy);
+        uint32_t h;
+        if (BYTES) {  // one byte per cell: the cell index is the LDS address
+            h = (uint32_t)s_cells[B0] | ((uint32_t)s_cells[B1] << 1) |
+                ((uint32_t)s_cells[B2] << 2) | ((uint32_t)s_cells[B3] << 3);
+        } else {
+            const uint32_t w0 = s_bits[B0 >> 5], w1 = s_bits[B1 >> 5];
+            const uint32_t w2 = s_bits[B2 >> 5], w3 = s_bits[B3 >> 5];
+            h = __builtin_amdgcn_ubfe(w0, (uint32_t)B0, 1u) |
+                (__builtin_amdgcn_ubfe(w1, (uint32_t)B1, 1u) << 1) |
+                (__builtin_amdgcn_ubfe(w2, (uint32_t)B2, 1u) << 2) |
+                (__builtin_amdgcn_ubfe(w3, (uint32_t)B3, 1u) << 3);
+        }
+        // first occupied cell of the group (4 when none); cells past
+        // the r_max budget do not count
+        const int rem = n - k;
+        const int f = (int)__builtin_ctz(h | 16u);
+        if (f < rem && f < 4) {
+            B = f == 0 ? B0 : (f == 1 ? B1 : (f == 2 ? B2 : B3));
+            flags = 1u;
+            k += f + 1;
+            act = false;
+            break;
+        }
+        if (rem <= 4) {
+            k = n;
+            act = false;
+            break;
+        }
+        B = B3;
+        Eh = E4;
+        k += 4;
+    }
+}
+
+// Group walk: lanes take rays from s_misc[1]; a lane whose ray is done
+// writes its result back and takes a new one once at most refill_at lanes of
+// its wavefront are still walking.  Cells are read from the bitmap, or (BYTES)
+// from its one-byte-per-cell copy, which needs no address arithmetic or bit
+// extraction; both give the same cells.
+template <bool BYTES>
+__device__ __forceinline__ void group_walk(const StepParams &p, const MapView &M,
+                                           const uint32_t *s_bits, const uint8_t *s_cells,
+                                           uint4 *s_ray, int *s_misc, int Rc, int lane) {
+    int r = -1;
+    bool act = false, exhausted = false;
+    int B = 0, Eh = 0, incx = 0, incy = 0, dEx = 0, dEy = 0, n = 0, k = 0;
+    uint32_t flags = 0u;
+    for (;;) {
+        uint64_t am = __ballot(act);
+        if (!exhausted && __popcll(am) <= p.refill_at) {
+            if (!act && r >= 0) {
+                reinterpret_cast<uint2 *>(s_ray)[2 * r] =
+                    make_uint2((uint32_t)B | ((uint32_t)k << 19), flags);
+                r = -1;
+            }
+            const uint64_t idle = ~am;
+            const int nidle = 64 - __popcll(am);
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
+            base = __shfl(base, 0);
+            const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
+            if (!act && my < Rc) {
+                const uint4 v = s_ray[my];
+                r = my;
+                B = (int)(v.x & 0x7FFFFu);
+                n = (int)(v.x >> 19);
+                Eh = (int)v.y;
+                dEy = -(int)(v.z & 0x7FFFFFFFu);
+                dEx = (int)(v.w & 0x7FFFFFFFu);
+                incx = (v.z >> 31) ? 1 : -1;
+                incy = (v.w >> 31) ? M.pitch : -M.pitch;
+                k = 0;
+                flags = 0u;
+                act = n > 0;
+            }
+            exhausted = base + nidle >= Rc;
+            am = __ballot(act);
+        }
+        if (am == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+        if (act)
+            walk_groups<BYTES>(p, s_bits, s_cells, B, Eh, incx, incy, dEx, dEy, n, k, flags, act);
+    }
+    if (r >= 0)
+        reinterpret_cast<uint2 *>(s_ray)[2 * r] = make_uint2((uint32_t)B | ((uint32_t)k << 19), flags);
+}
+
+// Claim walk: the group walk over all R rays of the tile, where a lane sets up
+// the walk of each ray it claims (the job's origin, the rotated beam) and
+// folds the ray's range into the sector pool once it is done.  The tile then
+// needs no ray slots, no chunks and no separate setup and finish passes, and
+// that work overlaps other wavefronts' walks.
+template <bool BYTES>
+__device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M,
+                                           const uint32_t *s_bits, const uint8_t *s_cells,
+                                           const TileJob *s_jobs, const int *s_list,
+                                           const double2 *s_beam, uint32_t *s_pool, int *s_misc,
+                                           int R, int K, float inv_K, int per, float inv_per,
+                                           double rmax_c, int max_n, int E, int lane) {
+    int g = -1, job = 0, beam = 0;
+    bool act = false, exhausted = false;
+    int B = 0, Eh = 0, incx = 0, incy = 0, dEx = 0, dEy = 0, n = 0, k = 0;
+    uint32_t flags = 0u;
+    for (;;) {
+        uint64_t am = __ballot(act);
+        if (!exhausted && __popcll(am) <= p.refill_at) {
+            if (!act && g >= 0) {
+                finish_ray(p, M, s_jobs[job], s_beam, job, beam,
+                           make_uint2((uint32_t)B | ((uint32_t)k << 19), flags), s_pool, per,
+                           inv_per, E);
+                g = -1;
+            }
+            const uint64_t idle = ~am;
+            const int nidle = 64 - __popcll(am);
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
+            base = __shfl(base, 0);
+            const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
+            if (!act && my < R) {
+                g = my;
+                const int jl = small_div(g, K, inv_K);
+                beam = g - jl * K;
+                job = s_list[jl];
+                const TileJob &j = s_jobs[job];
+                B = 0;
+                n = 0;
+                if (!j.blocked) {
+                    const double2 cs = s_beam[beam];
+                    const double dx = j.c * cs.x - j.s * cs.y;
+                    const double dy = j.s * cs.x + j.c * cs.y;
+                    const Walk w = walk_setup(M.pitch, tile_origin(j, M.s), dx, dy, rmax_c);
+                    B = w.B;
+                    n = min(w.n, max_n);
+                    Eh = w.Eh - w.thr;
+                    dEx = w.dEx;
+                    dEy = w.dEy;
+                    incx = w.incx;
+                    incy = w.incy;
+                }
+                k = 0;
+                flags = 0u;
+                act = n > 0;
+            }
+            exhausted = base + nidle >= R;
+            am = __ballot(act);
+        }
+        if (am == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+        if (act)
+            walk_groups<BYTES>(p, s_bits, s_cells, B, Eh, incx, incy, dEx, dEy, n, k, flags, act);
+    }
+    if (g >= 0)
+        finish_ray(p, M, s_jobs[job], s_beam, job, beam,
+                   make_uint2((uint32_t)B | ((uint32_t)k << 19), flags), s_pool, per, inv_per, E);
+}
+
+// LDS of the fused step, in order: the map's byte-per-cell copy [cell_bytes]
+// (byte walk only: at address 0, so that a cell index is its LDS address),
+// bitmap [max_words], jobs [2E] (main,
 // reset), pooled minima [2E][m] (+ padding), active job list [2E], misc
 // [2E + 8] ([0] active jobs, [1] next ray, [2, 2 + E) done flags, [2E + 7]
-// next tile of a persistent workgroup), beams [K] when staged, ray slots.
+// next tile of a persistent workgroup), beams [K] when staged, ray slots
+// [ray_cap] (none for the claim walk).
 template <int E>
 __device__ __forceinline__ int *fused_list(const StepParams &p) {
     extern __shared__ uint4 smem4[];
-    uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem4);
+    uint32_t *s_bits = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(smem4) + p.cell_bytes);
     TileJob *s_jobs = reinterpret_cast<TileJob *>(s_bits + p.max_words);
     uint32_t *s_pool = reinterpret_cast<uint32_t *>(s_jobs + 2 * E);
     return reinterpret_cast<int *>(s_pool + pool_words(E, p.m));
@@ -1028,7 +1214,8 @@ __device__ __forceinline__ int *fused_list(const StepParams &p) {
 template <int E, int T>
 __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, int &staged_map) {
     extern __shared__ uint4 smem4[];
-    uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem4);
+    uint8_t *s_cells = reinterpret_cast<uint8_t *>(smem4);
+    uint32_t *s_bits = reinterpret_cast<uint32_t *>(s_cells + p.cell_bytes);
     TileJob *s_jobs = reinterpret_cast<TileJob *>(s_bits + p.max_words);
     uint32_t *s_pool = reinterpret_cast<uint32_t *>(s_jobs + 2 * E);
     int *s_list = fused_list<E>(p);
@@ -1042,7 +1229,22 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
     const double2 *beams = p.beams + md.beam_off;  // this map's beam directions
     if (tile.map != staged_map) {  // a persistent workgroup keeps its map between tiles
         const uint4 *g = reinterpret_cast<const uint4 *>(p.bits + md.word_off);
-        for (int q = tid; q < md.words / 4; q += T) smem4[q] = g[q];
+        uint4 *b4 = reinterpret_cast<uint4 *>(s_bits);
+        for (int q = tid; q < md.words / 4; q += T) b4[q] = g[q];
+        if (p.cell_bytes) {
+            // byte copy: bit b of word q becomes byte 32 q + b (0 or 1); a
+            // nibble times 0x00204081 moves its bit i to bit 8 i
+            const uint32_t *gw = p.bits + md.word_off;
+            uint4 *c4 = reinterpret_cast<uint4 *>(s_cells);
+            for (int q = tid; q < md.words; q += T) {
+                const uint32_t w = gw[q];
+                uint32_t d[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) d[j] = (((w >> (4 * j)) & 0xFu) * 0x00204081u) & 0x01010101u;
+                c4[2 * q] = make_uint4(d[0], d[1], d[2], d[3]);
+                c4[2 * q + 1] = make_uint4(d[4], d[5], d[6], d[7]);
+            }
+        }
         if (p.beams_lds)
             for (int q = tid; q < K; q += T) s_beam[q] = beams[q];
         staged_map = tile.map;
@@ -1152,7 +1354,17 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
     const float inv_K = 1.0f / (float)K, inv_per = 1.0f / (float)per;
     const double rmax_c = (double)p.rmax / M.s;
     const int max_n = M.w + M.h + 2 * kPad;  // a walk meets the padding ring before this
-    for (int c0 = 0; c0 < R; c0 += p.ray_cap) {
+    if (p.claim) {
+        // s_misc[1] (next ray) and the pool were cleared before the last barrier
+        if (p.cell_bytes)
+            claim_walk<true>(p, M, s_bits, s_cells, s_jobs, s_list, s_beam, s_pool, s_misc, R, K,
+                             inv_K, per, inv_per, rmax_c, max_n, E, lane);
+        else
+            claim_walk<false>(p, M, s_bits, s_cells, s_jobs, s_list, s_beam, s_pool, s_misc, R,
+                              K, inv_K, per, inv_per, rmax_c, max_n, E, lane);
+        __syncthreads();
+    }
+    for (int c0 = 0; c0 < R && !p.claim; c0 += p.ray_cap) {
         const int Rc = min(p.ray_cap, R - c0);
         // (1) every ray's walk start, all lanes busy (the march needs none)
         for (int r = tid; r < Rc && p.scan_mode != 1; r += T) {
@@ -1176,94 +1388,10 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
             march_walk(p, M, s_jobs, s_list, s_beam, s_ray, s_misc, c0, Rc, K, inv_K, lane);
         } else if (p.walk_mode == 1) {
             run_walk(p, M, s_bits, s_ray, s_misc, Rc, lane);
+        } else if (p.walk_mode == 2) {
+            group_walk<true>(p, M, s_bits, s_cells, s_ray, s_misc, Rc, lane);
         } else {
-        int r = -1;
-        bool act = false, exhausted = false;
-        int B = 0, Eh = 0, incx = 0, incy = 0, dEx = 0, dEy = 0, n = 0, k = 0;
-        uint32_t flags = 0u;
-        for (;;) {
-            uint64_t am = __ballot(act);
-            if (!exhausted && __popcll(am) <= p.refill_at) {
-                if (!act && r >= 0) {
-                    reinterpret_cast<uint2 *>(s_ray)[2 * r] =
-                        make_uint2((uint32_t)B | ((uint32_t)k << 19), flags);
-                    r = -1;
-                }
-                const uint64_t idle = ~am;
-                const int nidle = 64 - __popcll(am);
-                int base = 0;
-                if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
-                base = __shfl(base, 0);
-                const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
-                if (!act && my < Rc) {
-                    const uint4 v = s_ray[my];
-                    r = my;
-                    B = (int)(v.x & 0x7FFFFu);
-                    n = (int)(v.x >> 19);
-                    Eh = (int)v.y;
-                    dEy = -(int)(v.z & 0x7FFFFFFFu);
-                    dEx = (int)(v.w & 0x7FFFFFFFu);
-                    incx = (v.z >> 31) ? 1 : -1;
-                    incy = (v.w >> 31) ? M.pitch : -M.pitch;
-                    k = 0;
-                    flags = 0u;
-                    act = n > 0;
-                }
-                exhausted = base + nidle >= Rc;
-                am = __ballot(act);
-            }
-            if (am == 0ull) {
-                if (exhausted) break;
-                continue;
-            }
-            if (act) {
-                // up to `groups` groups of 4 cells; the 4 cells of a group are
-                // read before any is tested (the padding ring keeps them in the
-                // stored bitmap)
-#pragma unroll 1
-                for (int gi = 0; gi < p.groups; ++gi) {
-                    const bool x0 = Eh < 0;
-                    const int B0 = B + (x0 ? incx : incy);
-                    const int E1 = Eh + (x0 ? dEx : dEy);
-                    const bool x1 = E1 < 0;
-                    const int B1 = B0 + (x1 ? incx : incy);
-                    const int E2 = E1 + (x1 ? dEx : dEy);
-                    const bool x2 = E2 < 0;
-                    const int B2 = B1 + (x2 ? incx : incy);
-                    const int E3 = E2 + (x2 ? dEx : dEy);
-                    const bool x3 = E3 < 0;
-                    const int B3 = B2 + (x3 ? incx : incy);
-                    const int E4 = E3 + (x3 ? dEx : dEy);
-                    const uint32_t w0 = s_bits[B0 >> 5], w1 = s_bits[B1 >> 5];
-                    const uint32_t w2 = s_bits[B2 >> 5], w3 = s_bits[B3 >> 5];
-                    const uint32_t h = __builtin_amdgcn_ubfe(w0, (uint32_t)B0, 1u) |
-                                       (__builtin_amdgcn_ubfe(w1, (uint32_t)B1, 1u) << 1) |
-                                       (__builtin_amdgcn_ubfe(w2, (uint32_t)B2, 1u) << 2) |
-                                       (__builtin_amdgcn_ubfe(w3, (uint32_t)B3, 1u) << 3);
-                    // first occupied cell of the group (4 when none); cells past
-                    // the r_max budget do not count
-                    const int rem = n - k;
-                    const int f = (int)__builtin_ctz(h | 16u);
-                    if (f < rem && f < 4) {
-                        B = f == 0 ? B0 : (f == 1 ? B1 : (f == 2 ? B2 : B3));
-                        flags = 1u;
-                        k += f + 1;
-                        act = false;
-                        break;
-                    }
-                    if (rem <= 4) {
-                        k = n;
-                        act = false;
-                        break;
-                    }
-                    B = B3;
-                    Eh = E4;
-                    k += 4;
-                }
-            }
-        }
-        if (r >= 0)
-            reinterpret_cast<uint2 *>(s_ray)[2 * r] = make_uint2((uint32_t)B | ((uint32_t)k << 19), flags);
+            group_walk<false>(p, M, s_bits, s_cells, s_ray, s_misc, Rc, lane);
         }
         __syncthreads();
         // (3) ranges, hits, pooling, all lanes busy
@@ -1432,7 +1560,8 @@ __global__ __launch_bounds__(64) void plain_step_kernel(StepParams p) {
 // ---------------------------------------------------------------------------
 template <int E, int T>
 static hipError_t launch_fused_et(const StepParams &p, hipStream_t s) {
-    const size_t lds = fused_lds_bytes(p.max_words, p.m, E, p.beams_lds ? p.K : 0, p.ray_cap);
+    const size_t lds = fused_lds_bytes(p.max_words, p.m, E, p.beams_lds ? p.K : 0,
+                                       p.claim ? 0 : p.ray_cap, p.cell_bytes);
     if (lds > 65536u) {
         // dynamic LDS beyond 64 KiB (gfx950 allows up to 160 KiB per workgroup)
         static std::atomic<int> raised{65536};
@@ -1470,8 +1599,9 @@ static int resident_et(size_t lds) {
     X(1, 256) X(1, 512) X(1, 1024) X(2, 256) X(2, 512) X(2, 1024) X(4, 256) X(4, 512)        \
     X(4, 1024) X(8, 256) X(8, 512) X(8, 1024) X(16, 256) X(16, 512) X(16, 1024)
 
-int fused_resident_groups(int max_words, int m, int E, int T, int K, bool beams_lds, int ray_cap) {
-    const size_t lds = fused_lds_bytes(max_words, m, E, beams_lds ? K : 0, ray_cap);
+int fused_resident_groups(int max_words, int m, int E, int T, int K, bool beams_lds, int ray_cap,
+                          int cell_bytes) {
+    const size_t lds = fused_lds_bytes(max_words, m, E, beams_lds ? K : 0, ray_cap, cell_bytes);
 #define NAVSIM_X(e, t) \
     if (E == e && T == t) return resident_et<e, t>(lds);
     NAVSIM_FUSED_SHAPES(NAVSIM_X)
@@ -1486,8 +1616,8 @@ bool fused_threads_supported(int T) { return T == 256 || T == 512 || T == 1024; 
 // ((E + 1) K, rounded up to a wavefront), so a tile walks a second chunk only
 // when two or more of its envs reset; fewer if that does not fit `budget`
 // bytes of LDS; 0 if not even 256 do.
-int fused_ray_cap(int max_words, int m, int E, int K, bool beams_lds, int budget) {
-    const size_t base = fused_lds_bytes(max_words, m, E, beams_lds ? K : 0, 0);
+int fused_ray_cap(int max_words, int m, int E, int K, bool beams_lds, int budget, int cell_bytes) {
+    const size_t base = fused_lds_bytes(max_words, m, E, beams_lds ? K : 0, 0, cell_bytes);
     if (base + 16u * 256u > (size_t)budget) return 0;
     const int fit = (int)(((size_t)budget - base) / 16u) & ~63;
     return std::max(std::min(((E + 1) * K + 63) & ~63, fit), 256);

@@ -75,17 +75,20 @@ def test_c2_plain_subset():
     sim.close()
 
 
-def test_run_walk_against_oracle():
-    say("run walk (walk = 1): c2 full size and c3 maps, fused, teacher-forced")
+@pytest.mark.parametrize("walk", [1, 2, 3, 4])
+def test_walk_variants_against_oracle(walk):
+    say(f"walk = {walk} (1 runs, 2 byte-per-cell map, 3 claim walk, 4 claim walk on bytes): "
+        f"c2 full size and c3 maps, fused, teacher-forced")
     w = configs.build_workload("c2")
     sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
-    sim.set_tuning(4, 48, 4, 0, 1)
-    run_teacher_forced(sim, ref, 3, NAVSIM_KERNEL_FUSED, label="c2/runs")
+    sim.set_tuning(4, 48, 4, 0, walk)
+    run_teacher_forced(sim, ref, 3, NAVSIM_KERNEL_FUSED, label=f"c2/walk{walk}")
     sim.close()
     w = configs.build_workload("c3", num_envs=1024)
     sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
-    sim.set_tuning(2, 40, 8, 0, 1)
-    run_teacher_forced(sim, ref, 3, NAVSIM_KERNEL_FUSED, label="c3/runs")
+    big = walk in (2, 4)  # the byte copy of a 256^2 map needs 1024-thread workgroups' LDS
+    sim.set_tuning(4 if big else 2, 40, 8, 0, walk, threads=1024 if big else 256)
+    run_teacher_forced(sim, ref, 3, NAVSIM_KERNEL_FUSED, label=f"c3/walk{walk}")
     sim.close()
 
 
@@ -132,11 +135,12 @@ def test_c4_full_size_launch_shapes_agree():
     w = configs.build_workload("c4")
     acts = torch.from_numpy(configs.uniform_actions(3, w["cfg"]["num_envs"], seed=5)).cuda()
     runs = []
-    for te, pe, th in [(8, 0, 256), (8, 4, 256), (4, 1, 256), (16, 16, 256), (8, 0, 512),
-                       (16, 0, 1024), (4, 0, 1024)]:
+    for te, pe, th, wk in [(8, 0, 256, 0), (8, 4, 256, 0), (4, 1, 256, 0), (16, 16, 256, 0),
+                           (8, 0, 512, 0), (16, 0, 1024, 0), (4, 0, 1024, 0), (4, 0, 512, 3),
+                           (8, 2, 256, 3)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0,
                      profiles=w["profiles"])
-        sim.set_tuning(te, 48, 8, persist=pe, threads=th)
+        sim.set_tuning(te, 48, 8, walk=wk, persist=pe, threads=th)
         outs = [sim.reset().cpu().numpy().copy()]
         for t in range(3):
             o, r, te_, tr, info = sim.step(acts[t])
@@ -195,9 +199,15 @@ def test_mixed_profiles_launch_shapes_agree():
     for kernel, te, pe, th in [(NAVSIM_KERNEL_PLAIN, 4, 0, 256), (NAVSIM_KERNEL_FUSED, 4, 0, 256),
                                (NAVSIM_KERNEL_FUSED, 8, 0, 256), (NAVSIM_KERNEL_FUSED, 16, 0, 256),
                                (NAVSIM_KERNEL_FUSED, 4, 3, 256), (NAVSIM_KERNEL_FUSED, 2, 16, 256),
-                               (NAVSIM_KERNEL_FUSED, 8, 0, 512), (NAVSIM_KERNEL_FUSED, 16, 0, 1024)]:
+                               (NAVSIM_KERNEL_FUSED, 8, 0, 512), (NAVSIM_KERNEL_FUSED, 16, 0, 1024),
+                               (NAVSIM_KERNEL_FUSED, 4, 0, -256), (NAVSIM_KERNEL_FUSED, 8, 2, -1024),
+                               (NAVSIM_KERNEL_FUSED, 4, 0, 3256), (NAVSIM_KERNEL_FUSED, 16, 0, 41024)]:
+        # th < 0: the byte-per-cell walk with |th| threads; th = 3xxx / 4xxxx: claim
+        # walk (bitmap / bytes) with xxx threads
+        walk, thr = (2, -th) if th < 0 else ((3, th - 3000) if 3000 < th < 4000 else
+                                             ((4, th - 40000) if th > 40000 else (0, th)))
         sim = NavSim(cfg, occ, res, env_map, device=0, profiles=prof)
-        sim.set_tuning(te, 48, 4, persist=pe, threads=th)
+        sim.set_tuning(te, 48, 4, walk=walk, persist=pe, threads=thr)
         sim.reset()
         runs.append([gpu_step(sim, acts[t], kernel) for t in range(5)])
         sim.close()
@@ -259,10 +269,13 @@ def test_march_mixed_profiles_and_launch_shapes():
     run_teacher_forced(sim, ref, 6, NAVSIM_KERNEL_FUSED, seed=4, label="march-mixed")
     acts = configs.uniform_actions(3, 60, seed=8)
     runs = []
-    for kernel, te in [(NAVSIM_KERNEL_PLAIN, 4), (NAVSIM_KERNEL_FUSED, 4), (NAVSIM_KERNEL_FUSED, 16)]:
+    # walk 4 (claim walk on bytes) applies to the exact traversal only: the
+    # march keeps its chunked path under it
+    for kernel, te, wk in [(NAVSIM_KERNEL_PLAIN, 4, 0), (NAVSIM_KERNEL_FUSED, 4, 0),
+                           (NAVSIM_KERNEL_FUSED, 16, 0), (NAVSIM_KERNEL_FUSED, 4, 4)]:
         s2 = NavSim(cfg, occ, res, env_map, device=0, profiles=prof)
         s2.set_scan(navsim.NAVSIM_SCAN_MARCH, 0.05)
-        s2.set_tuning(te, 40, 2)
+        s2.set_tuning(te, 40, 2, walk=wk)
         s2.reset()
         runs.append([gpu_step(s2, acts[t], kernel) for t in range(3)])
         s2.close()
@@ -453,7 +466,10 @@ def test_launch_shape_does_not_change_results():
             (8, 32, 2, 256, 0, 2, 256), (16, 48, 4, 0, 1, 64, 256), (2, 40, 8, 0, 0, 5, 256),
             (4, 56, 8, 0, 0, 0, 512), (16, 56, 8, 0, 0, 0, 1024), (1, 48, 4, 0, 0, 0, 1024),
             (8, 32, 2, 256, 0, 0, 512), (2, 48, 8, 0, 1, 0, 512), (16, 48, 4, 0, 0, 2, 1024),
-            (8, 0, 1, 4096, 0, 0, 1024)]:
+            (8, 0, 1, 4096, 0, 0, 1024), (4, 56, 8, 0, 2, 0, 256), (1, 0, 1, 256, 2, 0, 256),
+            (16, 48, 4, 0, 2, 0, 1024), (8, 63, 64, 0, 2, 3, 512), (2, 32, 2, 512, 2, 0, 256),
+            (4, 56, 8, 0, 3, 0, 256), (1, 0, 1, 0, 3, 0, 256), (16, 48, 4, 0, 3, 2, 1024),
+            (8, 63, 64, 0, 4, 0, 512), (4, 56, 8, 0, 4, 0, 256), (2, 32, 2, 0, 4, 5, 256)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
         sim.set_tuning(te, ra, gr, rs, wk, pe, th)
         assert sim.get_tuning() == {"tile_envs": te, "refill_at": ra, "groups": gr,

@@ -105,7 +105,7 @@ def test_graph_recaptured_for_new_buffers_steps_and_tuning():
     s0 = start(sim, ref)
     want = host(sim.rollout(8, first_step=5, graph=False))
     s8 = sim.get_state()
-    for case in ("same", "new_buffers", "tuning", "persist", "threads", "first_step"):
+    for case in ("same", "new_buffers", "tuning", "persist", "threads", "claim", "first_step"):
         sim.set_state(s0)
         if case == "tuning":
             sim.set_tuning(8, 32, 2)
@@ -113,6 +113,8 @@ def test_graph_recaptured_for_new_buffers_steps_and_tuning():
             sim.set_tuning(4, 48, 4, persist=2)
         if case == "threads":
             sim.set_tuning(16, 48, 4, threads=1024)
+        if case == "claim":
+            sim.set_tuning(4, 56, 8, walk=4)
         if case == "first_step":
             sim.rollout(4, first_step=5, graph=True)
             torch.cuda.synchronize()
