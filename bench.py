@@ -27,28 +27,55 @@ import numpy as np  # noqa: E402
 LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
 KERNEL_SRC = os.path.join(ROOT, "paper_2606_15846_amd", "csrc", "navsim_kernels.hip")
 PMC_FILE = os.path.join(ROOT, "profiles", "fused_step_c2_hbm_traffic.txt")
+SQ_FILE = os.path.join(ROOT, "profiles", "fused_step_c2_sq_counters.txt")
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9  # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (int32 ops/s)
 
 
 def kernel_source_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def hbm_traffic_from_profile():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when absent or taken on a different kernel source."""
-    if not os.path.exists(PMC_FILE):
+def profile_values(path: str):
+    """`key: value` lines of a committed rocprofv3 summary, or None when absent
+    or taken on a different kernel source."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(PMC_FILE):
-        if ":" in line:
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
+    return vals
+
+
+def hbm_traffic_from_profile():
+    """HBM bytes per launch from the committed counter summary (or None)."""
+    vals = profile_values(PMC_FILE)
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_launch"]) if vals else None
     except (KeyError, ValueError):
         return None
+
+
+def valu_from_profile(avg_launch_s: float, visits_per_launch: float):
+    """VALU issue of the same launches from the committed SQ counter summary:
+    wave instructions per launch, the share of the SIMDs' VALU issue they fill
+    over the live launch time (4 cycles per wave64 instruction), and lane
+    slots per cell visit; None when absent or stale."""
+    vals = profile_values(SQ_FILE)
+    if not vals:
+        return None
+    try:
+        insts = float(vals["valu_wave_insts_per_launch"])
+    except (KeyError, ValueError):
+        return None
+    lane_ops = insts * 64.0
+    return {"wave_insts_per_launch": insts,
+            "issue_frac": lane_ops / (VALU_LANE_OPS_PEAK * avg_launch_s),
+            "lane_slots_per_visit": lane_ops / max(visits_per_launch, 1.0),
+            "peak_lane_ops_per_s": VALU_LANE_OPS_PEAK}
 
 
 def cpu_baseline(w, acts, rays_per_env_step: float, target_s: float = 10.0) -> dict:
@@ -233,6 +260,7 @@ def main():
     avg_launch_s = float(per_launch_ms.mean()) / 1e3
     achieved = lds_bytes_per_launch / avg_launch_s / 1e9
     traffic = hbm_traffic_from_profile()
+    valu = valu_from_profile(avg_launch_s, visits / args.steps)
 
     # the paper's fixed-step range query (0.03 m) on the same fused step
     march = None
@@ -356,7 +384,8 @@ def main():
                      "kernel": "fused_step_kernel",
                      "avg_launch_us": avg_launch_s * 1e6,
                      "algorithmic_bytes_per_launch": lds_bytes_per_launch,
-                     "bytes_per_unit": "4 B of bitmap word per DDA cell visit of the step's pre-reset scan"},
+                     "bytes_per_unit": "4 B of bitmap word per DDA cell visit of the step's pre-reset scan",
+                     "valu": valu},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

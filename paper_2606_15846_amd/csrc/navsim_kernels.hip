@@ -276,6 +276,16 @@ __device__ __forceinline__ Walk walk_setup(int pitch, const RayOrigin &o, double
     return w;
 }
 
+// q = floor(a / b) for 0 <= a < 2^24, b >= 1 and a / b < 2^20, given inv_b
+// within a few float ulps of 1 / b: the float estimate is then within one of
+// the quotient, and the two tests fix it.
+__device__ __forceinline__ int small_div(int a, int b, float inv_b) {
+    int q = (int)((float)a * inv_b);
+    if (q * b > a) --q;
+    if ((q + 1) * b <= a) ++q;
+    return q;
+}
+
 // Range and hit id of a walk that stopped in cell B.  The ray enters a cell
 // when it has crossed both the cell's x line and its y line facing it, so the
 // range is the later of the two crossing distances (a line behind the origin,
@@ -283,7 +293,7 @@ __device__ __forceinline__ Walk walk_setup(int pitch, const RayOrigin &o, double
 __device__ __forceinline__ void walk_result(const RayOrigin &o, int pitch, int W, int H, int B,
                                             double dx, double dy, double rmax, float &range,
                                             int &hit) {
-    const int row = B / pitch, col = B - row * pitch;
+    const int row = small_div(B, pitch, __builtin_amdgcn_rcpf((float)pitch)), col = B - row * pitch;
     const int ix = col - kPad, iy = row - kPad;
     const double ninf = -__builtin_huge_val();
     const double tx = dx != 0.0 ? (((double)(dx > 0.0 ? ix : ix + 1)) * o.s - o.x) / dx : ninf;
@@ -585,14 +595,6 @@ __device__ __forceinline__ RayOrigin tile_origin(const TileJob &j, double s) {
     o.blocked = j.blocked;
     o.block_hit = j.block_hit;
     return o;
-}
-
-// q = floor(a / b) for 0 <= a < 2^24, 1 <= b < 2^24 (float estimate, then fixed).
-__device__ __forceinline__ int small_div(int a, int b, float inv_b) {
-    int q = (int)((float)a * inv_b);
-    if (q * b > a) --q;
-    if ((q + 1) * b <= a) ++q;
-    return q;
 }
 
 // The 16 ballot bits of this lane's group of 16.
