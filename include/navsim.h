@@ -252,7 +252,11 @@ typedef struct {
                            steps (32 cells per test along x); 2: cells in groups of 4 read
                            from a one-byte-per-cell copy of the map staged next to the
                            bitmap (32x its LDS; no address arithmetic or bit extraction per
-                           cell) -- same cells, same results                              */
+                           cell); 3: as 0, but each lane sets up the rays it claims and
+                           pools each ray when done (no LDS ray slots, no chunks; ray_slots
+                           is ignored); 4: as 3 on the byte copy.  3 and 4 apply to the
+                           exact traversal; the fixed-step march keeps its chunked walk.
+                           Same cells, same results                                       */
     int32_t persist;    /* 0: one workgroup per tile; c in 1..64: only as many workgroups
                            as stay resident, each taking c consecutive tiles at a time from
                            a device counter and keeping its staged map while the tiles'
