@@ -76,6 +76,7 @@ hipError_t launch_actor_noise(int N, float *act, float std, const uint32_t *step
 constexpr int kActorMaxLayers = 5;
 struct ActorArgs {
     int N = 0, m = 0, layers = 0, kmax = 0;
+    int wmax = 0;  // actor_fused_wmax: bf16 elements of the largest padded weight block
     int kpad[kActorMaxLayers] = {}, npad[kActorMaxLayers] = {};
     int64_t w_off[kActorMaxLayers] = {}, b_off[kActorMaxLayers] = {};
     const uint16_t *w = nullptr;
@@ -89,8 +90,11 @@ struct ActorArgs {
     uint32_t key0 = 0, key1 = 0;
 };
 hipError_t launch_actor_fused(const ActorArgs &a, hipStream_t s);
-// LDS bytes of that launch (it is used only when this is <= 64 KiB).
+// LDS bytes of that launch: two [16][kmax + 8] bf16 activation buffers, the
+// largest layer's padded weights and 16 action pairs (it is used only when
+// this is <= 64 KiB).
 size_t actor_fused_lds_bytes(int layers, const int *kpad, const int *npad, int kmax);
+int actor_fused_wmax(int layers, const int *kpad, const int *npad);
 
 // Float to bfloat16 (round to nearest even), n elements.
 hipError_t launch_to_bf16(int64_t n, const float *x, uint16_t *y, hipStream_t s);

@@ -224,43 +224,44 @@ __global__ void actor_noise_kernel(int N, float *act, float std, const uint32_t 
     act[2 * e + 1] = fminf(1.0f, fmaxf(-1.0f, a1));
 }
 
-// Whole actor in one launch: each wavefront takes 16 observation rows, builds
-// their bf16 inputs in LDS (reciprocal range transform), then runs every
-// layer as 16 x 16 x 32 bf16 MFMA tiles with its weights staged in LDS by the
-// workgroup from a padded bf16 image (k-contiguous rows, K padded to 32, N to
-// 16, zeros outside) and writes bias + activation back to its LDS rows as the
-// next layer's input;
-// the last layer applies tanh, the exploration noise and the clip, and
-// stores the two action components.  Same tiles, k order and rounding points
-// as the layer-by-layer GEMM path.
+// Whole actor in one launch: a workgroup of 4 wavefronts takes 16 observation
+// rows, builds their bf16 inputs in LDS (reciprocal range transform), then
+// runs every layer as 16 x 16 x 32 bf16 MFMA tiles, wavefront w taking the
+// layer's 16-column blocks w, w + 4, ..., with the weights staged in LDS by
+// the workgroup from a padded bf16 image (k-contiguous rows, K padded to 32,
+// N to 16, zeros outside), and writes bias + activation to the next layer's
+// input rows.  The last layer applies tanh; then one lane per row draws the
+// row's exploration noise pair (one Box-Muller transform), adds, clips and
+// stores both action components.  Same tiles, k order and rounding points as
+// the layer-by-layer GEMM path.
 __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint16_t act_lds[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row0 = (blockIdx.x * 4 + wave) * 16;
+    const int row0 = blockIdx.x * 16;
     const int ld = a.kmax + 8;  // LDS row pitch (bf16): 16 B past a bank cycle
-    uint16_t *cur_in = act_lds + (size_t)wave * 32 * ld;  // this layer's input rows
-    uint16_t *nxt_in = cur_in + 16 * ld;                  // the next layer's
+    uint16_t *cur_in = act_lds;        // this layer's input rows [16][ld]
+    uint16_t *nxt_in = act_lds + 16 * ld;  // the next layer's
+    uint16_t *wl = act_lds + 32 * ld;  // this layer's weights
+    float *s_act = reinterpret_cast<float *>(wl + a.wmax);  // [16][2] actions before noise
     const int row = a.m + 4;
-    uint16_t *wl = act_lds + (size_t)4 * 32 * ld;  // this layer's weights
-    // inputs: all loads issued first; row r, columns lane and lane + 64
+    // inputs: 16 rows x kpad[0] (<= 128) columns, 8 per thread, loads first
     {
         const int kp0 = a.kpad[0];
         const float beta = *a.beta;
-        float v[32];
+        float v[8];
 #pragma unroll
-        for (int t = 0; t < 32; ++t) {
-            const int r = t >> 1, j = lane + 64 * (t & 1), e = row0 + r;
+        for (int t = 0; t < 8; ++t) {
+            const int q = threadIdx.x + 256 * t, r = q >> 7, j = q & 127, e = row0 + r;
             v[t] = (e < a.N && j < row) ? a.obs[(int64_t)e * row + j] : 0.0f;
         }
 #pragma unroll
-        for (int t = 0; t < 32; ++t) {
-            const int r = t >> 1, j = lane + 64 * (t & 1);
+        for (int t = 0; t < 8; ++t) {
+            const int q = threadIdx.x + 256 * t, r = q >> 7, j = q & 127;
             if (j < kp0)
                 cur_in[r * ld + j] =
                     to_bf16_bits(j < a.m && row0 + r < a.N ? 1.0f / (v[t] - beta) : v[t]);
         }
     }
-    __syncthreads();
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     for (int l = 0; l < a.layers; ++l) {
         const int kp = a.kpad[l], np = a.npad[l];
@@ -283,20 +284,23 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
                 if (c < rv && rw < np) dst[rw * (rv + 1) + c] = t8[t];
             }
         }
-        // this lane's biases, one per 16-column block (np <= 128)
-        float bias[8];
+        // this lane's biases, for its wavefront's column blocks (np <= 128)
+        float bias[2];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) bias[t] = 16 * t < np ? a.b[a.b_off[l] + 16 * t + fr] : 0.0f;
-        __syncthreads();
+        for (int t = 0; t < 2; ++t) {
+            const int n0 = 16 * (wave + 4 * t);
+            bias[t] = n0 < np ? a.b[a.b_off[l] + n0 + fr] : 0.0f;
+        }
+        __syncthreads();  // inputs and weights in LDS
         const uint16_t *W = wl;
         const bool last = l + 1 == a.layers;
-        bf16x8 av[4];  // this wave's input fragments, shared by every column block
+        bf16x8 av[4];  // the rows' input fragments, shared by every column block
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb)
             if (32 * kb < kp) av[kb] = *reinterpret_cast<const bf16x8 *>(&cur_in[fr * ld + 32 * kb + fk]);
 #pragma unroll
-        for (int nb = 0; nb < 8; ++nb) {
-            const int n0 = 16 * nb;
+        for (int t = 0; t < 2; ++t) {
+            const int n0 = 16 * (wave + 4 * t);
             if (n0 >= np) break;
             f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -311,41 +315,48 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int rr = (lane >> 4) * 4 + r;
-                float v = acc[r] + bias[nb];
+                float v = acc[r] + bias[t];
                 if (!last) {
                     if (!(v > 0.0f)) v *= a.slope;
                     nxt_in[rr * ld + n] = to_bf16_bits(v);
                 } else if (n < 2) {
-                    const int e = row0 + rr;
-                    if (e < a.N) {
-                        v = tanhf(v);
-                        if (a.std > 0.0f) {
-                            const uint64_t st = (((uint64_t)a.step_ctr[1] << 32) |
-                                                 (uint64_t)a.step_ctr[0]) + (uint64_t)a.step_off;
-                            uint32_t c[4] = {(uint32_t)e, (uint32_t)st, (uint32_t)(st >> 32), 11u};
-                            philox4x32_10(c, a.key0, a.key1);
-                            const double u1 = ((double)c[0] + 0.5) / 4294967296.0;
-                            const double u2 = ((double)c[1] + 0.5) / 4294967296.0;
-                            const double rad = sqrt(-2.0 * log(u1));
-                            const double t = 2.0 * 3.14159265358979323846 * u2;
-                            const float z = (float)(n == 0 ? rad * cos(t) : rad * sin(t));
-                            v = fminf(1.0f, fmaxf(-1.0f, v + a.std * z));
-                        }
-                        a.act[(int64_t)e * 2 + n] = v;
-                    }
+                    s_act[rr * 2 + n] = tanhf(v);
                 }
             }
         }
         if (!last) {
-            // zero the padding columns [np, kpad[l + 1]) of the next input, then swap
-            const int kn = a.kpad[l + 1];
-            for (int r = 0; r < 16; ++r)
-                for (int j = np + lane; j < kn; j += 64) nxt_in[r * ld + j] = 0;
+            // zero the padding columns [np, kpad[l + 1]) of the next input
+            const int kn = a.kpad[l + 1], wpad = kn - np;
+            for (int q = threadIdx.x; q < 16 * wpad; q += 256) {
+                const int r = q / wpad;
+                nxt_in[r * ld + np + (q - r * wpad)] = 0;
+            }
             uint16_t *t = cur_in;
             cur_in = nxt_in;
             nxt_in = t;
         }
         __syncthreads();  // next layer's inputs written, this layer's weights no longer read
+    }
+    // noise, clip and store: one lane per row
+    if (threadIdx.x < 16) {
+        const int e = row0 + threadIdx.x;
+        if (e < a.N) {
+            float v0 = s_act[threadIdx.x * 2], v1 = s_act[threadIdx.x * 2 + 1];
+            if (a.std > 0.0f) {
+                const uint64_t st =
+                    (((uint64_t)a.step_ctr[1] << 32) | (uint64_t)a.step_ctr[0]) + (uint64_t)a.step_off;
+                uint32_t c[4] = {(uint32_t)e, (uint32_t)st, (uint32_t)(st >> 32), 11u};
+                philox4x32_10(c, a.key0, a.key1);
+                const double u1 = ((double)c[0] + 0.5) / 4294967296.0;
+                const double u2 = ((double)c[1] + 0.5) / 4294967296.0;
+                const double rad = sqrt(-2.0 * log(u1));
+                const double t = 2.0 * 3.14159265358979323846 * u2;
+                v0 = fminf(1.0f, fmaxf(-1.0f, v0 + a.std * (float)(rad * cos(t))));
+                v1 = fminf(1.0f, fmaxf(-1.0f, v1 + a.std * (float)(rad * sin(t))));
+            }
+            a.act[(int64_t)e * 2] = v0;
+            a.act[(int64_t)e * 2 + 1] = v1;
+        }
     }
 }
 
@@ -354,15 +365,21 @@ unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 }  // namespace
 
 size_t actor_fused_lds_bytes(int layers, const int *kpad, const int *npad, int kmax) {
-    size_t wmax = 0;
-    for (int l = 0; l < layers; ++l) wmax = std::max(wmax, (size_t)(kpad[l] + 8) * npad[l]);
-    return ((size_t)4 * 32 * (kmax + 8) + wmax) * sizeof(uint16_t);
+    return ((size_t)32 * (kmax + 8) + (size_t)actor_fused_wmax(layers, kpad, npad)) *
+               sizeof(uint16_t) +
+           16 * 2 * sizeof(float);
+}
+
+int actor_fused_wmax(int layers, const int *kpad, const int *npad) {
+    int wmax = 0;
+    for (int l = 0; l < layers; ++l) wmax = std::max(wmax, (kpad[l] + 8) * npad[l]);
+    return (wmax + 7) & ~7;  // keeps the action floats after it 16-byte aligned
 }
 
 hipError_t launch_actor_fused(const ActorArgs &a, hipStream_t s) {
     if (a.N <= 0) return hipSuccess;
     const size_t lds = actor_fused_lds_bytes(a.layers, a.kpad, a.npad, a.kmax);
-    hipLaunchKernelGGL(actor_fused_kernel, dim3((unsigned)((a.N + 63) / 64)), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(actor_fused_kernel, dim3((unsigned)((a.N + 15) / 16)), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 

@@ -186,6 +186,7 @@ navsim_status navsim_policy_create(navsim_t h, int32_t hidden, int32_t hidden_la
         a.m = q->m;
         a.layers = q->L;
         a.kmax = kmax;
+        a.wmax = actor_fused_wmax(q->L, a.kpad, a.npad);
         a.w = q->wpad;
         a.b = q->bpad;
         a.beta = q->p + q->beta_off;
