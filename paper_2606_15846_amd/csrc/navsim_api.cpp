@@ -195,6 +195,11 @@ navsim_status fused_shape(const navsim_s *h, int max_words, int tile_envs, int t
     out.claim = scan_mode == NAVSIM_SCAN_TRAVERSAL && walk >= 3;
     out.cell_bytes =
         (scan_mode == NAVSIM_SCAN_TRAVERSAL && (walk == 2 || walk == 4)) ? max_words * 32 : 0;
+    if (out.cell_bytes && fused_static_lds(tile_envs, threads) != 0)
+        return fail(NAVSIM_E_UNSUPPORTED,
+                    "the byte walk needs a fused kernel without static LDS (tile_envs %d, "
+                    "threads %d)",
+                    tile_envs, threads);
     if (out.claim) {
         const size_t share = std::min<size_t>(
             (size_t)h->lds_block, (size_t)h->lds_cu * (threads / 64) / kFusedWavesPerCu);

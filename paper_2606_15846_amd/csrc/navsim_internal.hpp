@@ -103,6 +103,9 @@ int fused_resident_groups(int max_words, int m, int tile_envs, int threads, int 
                           int ray_cap, int cell_bytes);
 bool fused_tile_envs_supported(int tile_envs);
 bool fused_threads_supported(int threads);
+// Static LDS bytes of the fused kernel for a shape (-1 on error).  The byte
+// walk needs 0: its map copy must start at LDS address 0.
+int fused_static_lds(int tile_envs, int threads);
 hipError_t launch_fused(const StepParams &p, int tile_envs, hipStream_t s);
 hipError_t launch_plain(const StepParams &p, hipStream_t s);
 hipError_t launch_set_step(uint32_t *ctr, uint64_t first_step, hipStream_t s);

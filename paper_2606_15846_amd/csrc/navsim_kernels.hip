@@ -1016,30 +1016,36 @@ __device__ __forceinline__ void march_walk(const StepParams &p, const MapView &M
 // Up to `groups` groups of 4 cells of one lane's walk; the 4 cells of a group
 // are read before any is tested (the padding ring keeps them in the stored
 // map).  Stops at the first occupied cell (flags = 1) or when the r_max
-// budget n is used up; act turns false then.
+// budget n is used up; act turns false then.  The decision variable's high
+// word and the cell index travel as one 64-bit value S = Eh : B, so a step is
+// a compare, a 64-bit select and one 64-bit add: an x crossing adds
+// Dx = dEx : incx and a y crossing Dy = dEy : incy (a negative increment
+// borrows 1 from the high word, which the constant carries back; B + inc never
+// leaves [0, 2^19), so each word gets exactly its own sum).
 template <bool BYTES>
 __device__ __forceinline__ void walk_groups(const StepParams &p, const uint32_t *s_bits,
                                             const uint8_t *s_cells, int &B, int &Eh, int incx,
                                             int incy, int dEx, int dEy, int n, int &k,
                                             uint32_t &flags, bool &act) {
+    uint64_t S = ((uint64_t)(uint32_t)Eh << 32) | (uint64_t)(uint32_t)B;
+    const uint64_t Dx = ((uint64_t)(uint32_t)dEx << 32) + (uint64_t)(int64_t)incx;
+    const uint64_t Dy = ((uint64_t)(uint32_t)dEy << 32) + (uint64_t)(int64_t)incy;
 #pragma unroll 1
     for (int gi = 0; gi < p.groups; ++gi) {
-        const bool x0 = Eh < 0;
-        const int B0 = B + (x0 ? incx : incy);
-        const int E1 = Eh + (x0 ? dEx : dEy);
-        const bool x1 = E1 < 0;
-        const int B1 = B0 + (x1 ? incx : incy);
-        const int E2 = E1 + (x1 ? dEx : dEy);
-        const bool x2 = E2 < 0;
-        const int B2 = B1 + (x2 ? incx : incy);
-        const int E3 = E2 + (x2 ? dEx : dEy);
-        const bool x3 = E3 < 0;
-        const int B3 = B2 + (x3 ? incx : incy);
-        const int E4 = E3 + (x3 ? dEx : dEy);
+        const uint64_t S0 = S + ((int64_t)S < 0 ? Dx : Dy);
+        const uint64_t S1 = S0 + ((int64_t)S0 < 0 ? Dx : Dy);
+        const uint64_t S2 = S1 + ((int64_t)S1 < 0 ? Dx : Dy);
+        const uint64_t S3 = S2 + ((int64_t)S2 < 0 ? Dx : Dy);
+        const int B0 = (int)(uint32_t)S0, B1 = (int)(uint32_t)S1;
+        const int B2 = (int)(uint32_t)S2, B3 = (int)(uint32_t)S3;
         uint32_t h;
-        if (BYTES) {  // one byte per cell: the cell index is the LDS address
-            h = (uint32_t)s_cells[B0] | ((uint32_t)s_cells[B1] << 1) |
-                ((uint32_t)s_cells[B2] << 2) | ((uint32_t)s_cells[B3] << 3);
+        if (BYTES) {
+            // one byte per cell at LDS address 0 (the kernel has no static
+            // LDS, which the host checks): the cell index is the address
+            typedef __attribute__((address_space(3))) const uint8_t lds_u8;
+            const lds_u8 *cells = reinterpret_cast<const lds_u8 *>(static_cast<uintptr_t>(0));
+            h = (uint32_t)cells[B0] | ((uint32_t)cells[B1] << 1) | ((uint32_t)cells[B2] << 2) |
+                ((uint32_t)cells[B3] << 3);
         } else {
             const uint32_t w0 = s_bits[B0 >> 5], w1 = s_bits[B1 >> 5];
             const uint32_t w2 = s_bits[B2 >> 5], w3 = s_bits[B3 >> 5];
@@ -1064,10 +1070,11 @@ __device__ __forceinline__ void walk_groups(const StepParams &p, const uint32_t 
             act = false;
             break;
         }
+        S = S3;
         B = B3;
-        Eh = E4;
         k += 4;
     }
+    Eh = (int)(S >> 32);
 }
 
 // Group walk: lanes take rays from s_misc[1]; a lane whose ray is done
@@ -1609,6 +1616,23 @@ int fused_resident_groups(int max_words, int m, int E, int T, int K, bool beams_
     NAVSIM_FUSED_SHAPES(NAVSIM_X)
 #undef NAVSIM_X
     return 0;
+}
+
+template <int E, int T>
+static int static_lds_et() {
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(fused_step_kernel<E, T>)) !=
+        hipSuccess)
+        return -1;
+    return (int)fa.sharedSizeBytes;
+}
+
+int fused_static_lds(int E, int T) {
+#define NAVSIM_X(e, t) \
+    if (E == e && T == t) return static_lds_et<e, t>();
+    NAVSIM_FUSED_SHAPES(NAVSIM_X)
+#undef NAVSIM_X
+    return -1;
 }
 
 bool fused_tile_envs_supported(int E) { return E == 1 || E == 2 || E == 4 || E == 8 || E == 16; }
