@@ -144,3 +144,21 @@ def test_map_profile_layout_matches_header(tmp_path):
                                            check=True).stdout.split()]
     assert vals[0] == C.sizeof(navsim.NavsimMapProfile)
     assert vals[1:] == [getattr(navsim.NavsimMapProfile, f).offset for f in fields]
+
+
+def test_tuning_layout_matches_header(tmp_path):
+    fields = [f for f, _ in navsim.NavsimTuning._fields_]
+    assert fields == ["tile_envs", "refill_at", "groups", "ray_slots", "walk", "persist", "threads"]
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "navsim.h"', "int main(void){",
+           'printf("%zu\\n", sizeof(navsim_tuning));']
+    src += [f'printf("%zu\\n", offsetof(navsim_tuning, {f}));' for f in fields]
+    src += ["return 0;}"]
+    c = tmp_path / "probe_tuning.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "probe_tuning"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    assert vals[0] == C.sizeof(navsim.NavsimTuning)
+    assert vals[1:] == [getattr(navsim.NavsimTuning, f).offset for f in fields]
+

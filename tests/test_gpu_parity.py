@@ -446,6 +446,15 @@ def test_api_errors_on_device():
     navsim.navsim_reset(h, None, obs)
     navsim.navsim_step(h, act, obs, r, u8, u8)
     torch.cuda.synchronize()
+    # launch-shape validation: each bad field alone; the handle keeps its shape
+    before = navsim.navsim_get_tuning(h)
+    base = dict(tile_envs=4, refill_at=48, groups=4, ray_slots=0, walk=0, persist=0, threads=256)
+    for bad in [dict(tile_envs=3), dict(refill_at=64), dict(groups=0), dict(ray_slots=100),
+                dict(walk=5), dict(persist=65), dict(threads=384)]:
+        with pytest.raises(navsim.NavsimError) as ei:
+            navsim.navsim_set_tuning(h, **dict(base, **bad))
+        assert ei.value.status == -1, bad
+    assert navsim.navsim_get_tuning(h) == before
     navsim.navsim_destroy(h)
 
 
