@@ -2,10 +2,14 @@
 // 2606.15846, section 2.2) for gfx950.
 //
 // Two mappings of the same step (step data path of eq. 7), identical results:
-//   fused_step_kernel  one workgroup per tile of envs sharing a map: the map's
-//                      padded bitmap staged in LDS, per-env work on 16-lane
-//                      groups, the tile's rays (new poses and reset poses)
-//                      walked by all lanes with refill, sector pooling in LDS.
+//   fused_step_kernel  one workgroup (256, 512 or 1024 threads) per tile of envs
+//                      sharing a map: the map's padded bitmap (and, for the
+//                      byte walks, a byte-per-cell copy) staged in LDS,
+//                      per-env work on 16-lane groups, the tile's rays (new
+//                      poses and reset poses) walked by all lanes from one
+//                      refilling pool, set up and pooled either in bulk passes
+//                      around the walk or by each lane as it claims and ends
+//                      a ray, sector pooling in LDS.
 //   plain_step_kernel  one thread per env, everything in sequence, bitmap read
 //                      from device memory (the comparison point).
 //
