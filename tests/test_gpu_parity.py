@@ -498,3 +498,40 @@ def test_launch_shape_does_not_change_results():
                 for k in oracle.STATE_KEYS:
                     assert np.array_equal(sa[k], sb[k]), (te, ra, gr, rs, wk, pe, th, k)
         sim.close()
+
+
+@pytest.mark.parametrize("wl", ["c2", "c4"])
+def test_pooled_obs_same_with_and_without_per_ray_outputs(wl):
+    # the step with and without the per-ray debug outputs (ranges, hits,
+    # visits) must produce the same observations, rewards, flags and state
+    say(f"{wl}: plain steps == steps with per-ray outputs (bitwise), walks 0, 3, 4")
+    w = configs.build_workload(wl)
+    N = w["cfg"]["num_envs"]
+    acts = torch.from_numpy(configs.uniform_actions(3, N, seed=17)).cuda()
+    for wk, te, th in [(0, 4, 256), (3, 4, 256), (4, 16, 1024)]:
+        sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0, profiles=w["profiles"])
+        try:
+            sim.set_tuning(te, 48, 8, walk=wk, threads=th)
+        except navsim.NavsimError:
+            assert wl == "c4" and wk == 4  # 512^2 maps: the byte copy does not fit
+            sim.close()
+            continue
+        sim.reset()
+        for t in range(3):
+            s0 = sim.get_state()
+            o, r, te_, tr, info = sim.step(acts[t])
+            got = [x.cpu().numpy().copy() for x in (o, r, te_, tr, info["final_obs"])]
+            s1 = sim.get_state()
+            sim.set_state(s0)
+            sim.step_debug(acts[t])
+            torch.cuda.synchronize()
+            want = [x.cpu().numpy().copy() for x in (sim.obs, sim.reward, sim.terminated,
+                                                      sim.truncated, sim.final_obs)]
+            done = (got[2] | got[3]).astype(bool)
+            for i, (a, b) in enumerate(zip(got, want)):
+                if i == 4:
+                    a, b = a[done], b[done]
+                assert np.array_equal(a, b), (wk, t, i)
+            s2 = sim.get_state()
+            assert all(np.array_equal(s1[k], s2[k]) for k in oracle.STATE_KEYS)
+        sim.close()
