@@ -25,9 +25,10 @@ DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4, "ray_slots": 0, "walk":
            "threads": 256}
 # walk = 1 (run walk) measured about 2x slower than the group walk on every
 # workload here, persistent workgroups 5-40 % slower; --full-space includes them
-SPACE = {"tile_envs": (1, 2, 4, 8, 16), "refill_at": (48, 56), "groups": (4, 8),
+SPACE = {"tile_envs": (1, 2, 4, 8, 16), "refill_at": (32, 40, 48), "groups": (8, 16),
          "ray_slots": (0, 1024), "walk": (0, 2, 3, 4), "persist": (0,), "threads": (256, 512, 1024)}
-FULL_SPACE = dict(SPACE, refill_at=(32, 48, 56), groups=(2, 4, 8), ray_slots=(0, 512, 1024, 2048),
+FULL_SPACE = dict(SPACE, refill_at=(24, 32, 40, 48, 56), groups=(2, 4, 8, 16, 32),
+                  ray_slots=(0, 512, 1024, 2048),
                   walk=(0, 1, 2, 3, 4), persist=(0, 2))
 FIELDS = tuple(DEFAULT)
 
