@@ -345,3 +345,32 @@ def test_march_scan_mode_step_pools_the_marched_beams():
             want.append(np.float32(rg))
         want = np.array(want).reshape(6, 10).min(axis=1)
         assert np.array_equal(out["obs"][e, :6], want), e
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_cells_walked_bound_the_range_from_below(seed):
+    # Within distance t a ray crosses at most t |dx| / s + 1 vertical and
+    # t |dy| / s + 1 horizontal grid lines, so the cell it enters after k
+    # steps of the traversal is at least (k - 2) s / (|dx| + |dy|) away:
+    # a relation between the oracle's ranges and visit counts (visits =
+    # k + 1) that neither computes from the other, every ray, grazing or not.
+    rng = np.random.default_rng(seed)
+    worst = math.inf
+    for _ in range(6):
+        H, W = int(rng.integers(8, 40)), int(rng.integers(8, 40))
+        s = float(np.float32(rng.choice([0.05, 0.1])))
+        occ = (rng.random((H, W)) < rng.uniform(0.02, 0.3)).astype(np.uint8)
+        M = _maps(occ, s)
+        for _ in range(300):
+            ox, oy = rng.uniform(0.0, W * s), rng.uniform(0.0, H * s)
+            a = rng.uniform(-math.pi, math.pi)
+            dx, dy = math.cos(a), math.sin(a)
+            rmax = float(rng.uniform(0.3, 1.2) * max(W, H) * s)
+            r = M.cast(0, ox, oy, dx, dy, rmax)
+            if r.hit == -1 or r.range == 0.0:
+                continue
+            k = r.visits - 1
+            bound = (k - 2) * s / (abs(dx) + abs(dy))
+            assert r.range >= bound - 1e-12, (ox, oy, a, k, r.range, bound)
+            worst = min(worst, r.range - bound)
+    assert worst < 2.5 * 0.1  # the bound is not vacuous: it comes within a few cells
