@@ -1576,14 +1576,18 @@ static hipError_t launch_fused_et(const StepParams &p, hipStream_t s) {
     const size_t lds = fused_lds_bytes(p.max_words, p.m, E, p.beams_lds ? p.K : 0,
                                        p.claim ? 0 : p.ray_cap, p.cell_bytes);
     if (lds > 65536u) {
-        // dynamic LDS beyond 64 KiB (gfx950 allows up to 160 KiB per workgroup)
-        static std::atomic<int> raised{65536};
-        if ((int)lds > raised.load()) {
-            const hipError_t e = hipFuncSetAttribute(
-                reinterpret_cast<const void *>(fused_step_kernel<E, T>),
-                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        // dynamic LDS beyond 64 KiB (gfx950 allows up to 160 KiB per workgroup),
+        // raised once per device and size
+        constexpr int kDevices = 64;
+        static std::atomic<int> raised[kDevices];
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if (dev < 0 || dev >= kDevices || (int)lds > raised[dev].load()) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(fused_step_kernel<E, T>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
-            raised.store((int)lds);
+            if (dev >= 0 && dev < kDevices) raised[dev].store((int)lds);
         }
     }
     unsigned grid = (unsigned)p.num_tiles;
