@@ -1349,14 +1349,16 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
         __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
-    if (tid == 0) {
-        int nj = 0;
-        for (int j = 0; j < E; ++j)
-            if (s_jobs[j].dst != 3) s_list[nj++] = j;
-        for (int j = 0; j < E; ++j)
-            if (s_misc[2 + j]) s_list[nj++] = E + j;
-        s_misc[0] = nj;
-        s_misc[1] = 0;
+    if (tid < 64) {
+        // active jobs in order (main jobs 0..E-1, then resets E..2E-1): lane q
+        // tests job q, a ballot and a prefix count give its list position
+        const bool on = tid < E ? s_jobs[tid].dst != 3 : (tid < 2 * E && s_misc[2 + tid - E] != 0);
+        const uint64_t bm = __ballot(on);
+        if (on) s_list[__popcll(bm & ((1ull << tid) - 1ull))] = tid;
+        if (tid == 0) {
+            s_misc[0] = __popcll(bm);
+            s_misc[1] = 0;
+        }
     }
     for (int q = tid; q < 2 * E * m; q += T) s_pool[q] = 0x7f800000u;  // +inf
     __syncthreads();
