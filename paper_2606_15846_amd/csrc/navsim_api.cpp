@@ -236,7 +236,12 @@ void apply_shape(navsim_s *h, const FusedShape &f) {
 
 // Envs grouped by map (stable in env order) into tiles of up to tile_envs envs,
 // one fused workgroup each.
-void build_tiles(const std::vector<int32_t> &env_map, int tile_envs, std::vector<int32_t> &perm,
+// Tiles are launched heaviest first (longest-processing-time order), by an
+// estimate of their scan work: envs x the map's beam count x the cells a ray
+// can cross (r_max / s, capped by the map's mean side); tiles of equal
+// weight keep their order, so a map's full tiles stay together.
+void build_tiles(const std::vector<int32_t> &env_map, int tile_envs,
+                 const std::vector<double> &map_weight, std::vector<int32_t> &perm,
                  std::vector<Tile> &tiles) {
     const int N = (int)env_map.size();
     perm.resize(N);
@@ -251,6 +256,9 @@ void build_tiles(const std::vector<int32_t> &env_map, int tile_envs, std::vector
         tiles.push_back(Tile{map, i, j - i, 0});
         i = j;
     }
+    std::stable_sort(tiles.begin(), tiles.end(), [&](const Tile &a, const Tile &b) {
+        return map_weight[a.map] * a.count > map_weight[b.map] * b.count;
+    });
 }
 
 navsim_status run(navsim_t h, const StepParams &p, int kernel, hipStream_t s) {
@@ -608,9 +616,14 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
         if (fs != NAVSIM_OK) return fs;
     }
     std::vector<int32_t> host_env_map(env_map, env_map + N);
+    std::vector<double> map_weight(num_maps);
+    for (int k = 0; k < num_maps; ++k)
+        map_weight[k] = (double)descs[k].K *
+                        std::min((double)cfg.max_range_m / (double)res_m[k],
+                                 0.5 * (double)(width[k] + height[k]));
     std::vector<int32_t> perm;
     std::vector<Tile> tiles;
-    build_tiles(host_env_map, h->tile_envs, perm, tiles);
+    build_tiles(host_env_map, h->tile_envs, map_weight, perm, tiles);
 
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
@@ -633,6 +646,7 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
     h->max_words = max_words;
     apply_shape(h, shape);
     h->host_env_map.swap(host_env_map);
+    h->host_map_weight.swap(map_weight);
     h->host_occ.assign(occ, occ + occ_off[num_maps]);
     h->host_occ_off = occ_off;
     h->host_w.assign(width, width + num_maps);
@@ -829,7 +843,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     if (h->loaded && t->tile_envs != h->tile_envs) {
         std::vector<int32_t> perm;
         std::vector<Tile> tiles;
-        build_tiles(h->host_env_map, t->tile_envs, perm, tiles);
+        build_tiles(h->host_env_map, t->tile_envs, h->host_map_weight, perm, tiles);
         DeviceGuard g(h->device);
         if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
         NS_HIP(hipDeviceSynchronize());

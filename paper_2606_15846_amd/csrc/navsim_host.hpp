@@ -73,6 +73,7 @@ struct navsim_s {
     int march_kmax = 0;
     double march_h = 0.03;
     std::vector<int32_t> host_env_map;  // kept to rebuild the tiles when tile_envs changes
+    std::vector<double> host_map_weight;  // per-map scan work estimate (tile launch order)
     // host copies of the loaded maps (reset proposals build their own tables)
     std::vector<uint8_t> host_occ;
     std::vector<int64_t> host_occ_off;
