@@ -181,6 +181,7 @@ def main():
     ap.add_argument("--walk", type=int, default=None)
     ap.add_argument("--persist", type=int, default=None)
     ap.add_argument("--threads", type=int, default=None)
+    ap.add_argument("--balance", type=int, default=None)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 device-to-device copies of 256 MiB (HBM counter scale)")
     args = ap.parse_args()
@@ -223,7 +224,8 @@ def main():
     # tuning.json) unless given on the command line; results do not depend on it
     from paper_2606_15846_amd import autotune
     tuning = autotune.best_for(autotune.workload_key(cfg, w["maps"], w["profiles"]))
-    for k in ("tile_envs", "refill_at", "groups", "ray_slots", "walk", "persist", "threads"):
+    for k in ("tile_envs", "refill_at", "groups", "ray_slots", "walk", "persist", "threads",
+              "balance"):
         if getattr(args, k) is not None:
             tuning[k] = getattr(args, k)
     sim.set_tuning(**tuning)

@@ -237,7 +237,8 @@ navsim_status navsim_set_scan(navsim_t h, int32_t mode, float step_m);
 /* Launch shape of the fused step.  Results never depend on it (bitwise); it
  * only moves work between lanes, wavefronts and workgroups. */
 typedef struct {
-    int32_t tile_envs;  /* envs per workgroup (they share one staged map): 1, 2, 4, 8, 16 */
+    int32_t tile_envs;  /* envs per workgroup (they share one staged map): 1, 2, 4, 8, 16, 32
+                           (at most this many with balance = 1)                            */
     int32_t refill_at;  /* a wavefront hands new rays to its idle lanes once at most this
                            many of its 64 lanes are still walking, 0..63                  */
     int32_t groups;     /* 4-cell groups a lane walks between refill checks, 1..64        */
@@ -261,12 +262,18 @@ typedef struct {
                            as stay resident, each taking c consecutive tiles at a time from
                            a device counter and keeping its staged map while the tiles'
                            map does not change                                             */
-    int32_t threads;    /* threads per workgroup, 256, 512 or 1024: the tile's envs share
-                           this many lanes (and one ray pool); automatic ray slots grow with
-                           it (the CU's LDS split between 1024 / threads workgroups)       */
+    int32_t threads;    /* threads per workgroup, 256, 512 or 1024 (at least 16 per env of
+                           a tile): the tile's envs share this many lanes (and one ray
+                           pool); automatic ray slots grow with it (the CU's LDS split
+                           between 1024 / threads workgroups)                              */
+    int32_t balance;    /* 0: tiles of tile_envs envs; 1: each map gets as many tiles as
+                           make every tile's estimated scan work (envs x beams x the mean
+                           cells a ray walks on that map, sampled on the host at load) about
+                           equal, at least as many tiles in all as workgroups run at once,
+                           at most tile_envs envs each.  Tiles always launch heaviest first */
 } navsim_tuning;
 
-/* Set the fused step's launch shape (defaults: 4, 48, 4, 0, 0, 0, 256).  Changing tile_envs
+/* Set the fused step's launch shape (defaults: 4, 48, 4, 0, 0, 0, 256, 0).  Changing tile_envs
  * after navsim_load_maps waits for the device and re-groups the envs; returns
  * NAVSIM_E_UNSUPPORTED if the larger tile would not fit LDS. */
 navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t);

@@ -22,14 +22,15 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_FILE = os.path.join(HERE, "tuning.json")
 DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4, "ray_slots": 0, "walk": 0, "persist": 0,
-           "threads": 256}
+           "threads": 256, "balance": 0}
 # walk = 1 (run walk) measured about 2x slower than the group walk on every
-# workload here, persistent workgroups 5-40 % slower; --full-space includes them
-SPACE = {"tile_envs": (1, 2, 4, 8, 16), "refill_at": (32, 40, 48), "groups": (8, 16),
-         "ray_slots": (0, 1024), "walk": (0, 2, 3, 4), "persist": (0,), "threads": (256, 512, 1024)}
+# workload here, persistent workgroups 5-40 % slower, the chunked bitmap walk
+# (walk 0) behind the byte and claim walks; --full-space includes them
+SPACE = {"tile_envs": (1, 2, 4, 8, 16, 32), "refill_at": (32, 40, 48), "groups": (8, 16),
+         "ray_slots": (0,), "walk": (2, 3, 4), "persist": (0,), "threads": (256, 512, 1024),
+         "balance": (0, 1)}
 FULL_SPACE = dict(SPACE, refill_at=(24, 32, 40, 48, 56), groups=(2, 4, 8, 16, 32),
-                  ray_slots=(0, 512, 1024, 2048),
-                  walk=(0, 1, 2, 3, 4), persist=(0, 2))
+                  ray_slots=(0, 512, 1024, 2048), walk=(0, 1, 2, 3, 4), persist=(0, 2))
 FIELDS = tuple(DEFAULT)
 
 

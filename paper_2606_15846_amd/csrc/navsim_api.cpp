@@ -236,25 +236,110 @@ void apply_shape(navsim_s *h, const FusedShape &f) {
 
 // Envs grouped by map (stable in env order) into tiles of up to tile_envs envs,
 // one fused workgroup each.
-// Tiles are launched heaviest first (longest-processing-time order), by an
-// estimate of their scan work: envs x the map's beam count x the cells a ray
-// can cross (r_max / s, capped by the map's mean side); tiles of equal
-// weight keep their order, so a map's full tiles stay together.
+// Scan work of one env on a map, for scheduling only: K times the mean
+// number of cells a ray walks, from a few rays cast on the host (up to 128
+// free cells, 16 directions each, first occupied or outside cell or r_max).
+double map_scan_work(const uint8_t *occ, int W, int H, double s, double rmax, int K,
+                     const int32_t *free_cells, int free_cnt) {
+    if (free_cnt <= 0) return (double)K;
+    const int samples = std::min(free_cnt, 128), stride = std::max(1, free_cnt / samples);
+    const double rc = rmax / s;
+    double cells = 0.0;
+    int rays = 0;
+    for (int q = 0; q < samples; ++q) {
+        const int c = free_cells[(int64_t)q * stride];
+        const double x0 = (c % W) + 0.5, y0 = (c / W) + 0.5;
+        for (int a = 0; a < 16; ++a) {
+            const double th = (a + 0.25) * (2.0 * M_PI / 16.0);
+            const double dx = cos(th), dy = sin(th);
+            int i = (int)x0, j = (int)y0, n = 0;
+            const int si = dx > 0 ? 1 : -1, sj = dy > 0 ? 1 : -1;
+            const double tdx = fabs(1.0 / dx), tdy = fabs(1.0 / dy);
+            double tx = (dx > 0 ? (i + 1 - x0) : (x0 - i)) * tdx;
+            double ty = (dy > 0 ? (j + 1 - y0) : (y0 - j)) * tdy;
+            for (;;) {
+                if (tx < ty) {
+                    if (tx > rc) break;
+                    i += si;
+                    tx += tdx;
+                } else {
+                    if (ty > rc) break;
+                    j += sj;
+                    ty += tdy;
+                }
+                ++n;
+                if (i < 0 || j < 0 || i >= W || j >= H || occ[(size_t)j * W + i]) break;
+            }
+            cells += n;
+            ++rays;
+        }
+    }
+    return (double)K * (1.0 + cells / rays);
+}
+
+// Envs grouped by map into tiles, launched heaviest first (longest-processing-
+// time order) by the tiles' estimated scan work (envs x the map's work per
+// env); tiles of equal weight keep their order, so a map's full tiles stay
+// together.  balance = 0: tiles of tile_envs envs (a map's last one smaller).
+// balance = 1: each map gets enough tiles that every tile's estimated work is
+// about equal, at least target_tiles in all (the workgroups that run at once),
+// at most tile_envs envs per tile; a map's envs split into near-equal tiles.
 void build_tiles(const std::vector<int32_t> &env_map, int tile_envs,
-                 const std::vector<double> &map_weight, std::vector<int32_t> &perm,
-                 std::vector<Tile> &tiles) {
+                 const std::vector<double> &map_weight, int balance, int target_tiles,
+                 std::vector<int32_t> &perm, std::vector<Tile> &tiles) {
     const int N = (int)env_map.size();
     perm.resize(N);
     for (int e = 0; e < N; ++e) perm[e] = e;
     std::stable_sort(perm.begin(), perm.end(),
                      [&](int32_t a, int32_t b) { return env_map[a] < env_map[b]; });
     tiles.clear();
+    // maps in use: [first, first + count) of perm
+    std::vector<int> mfirst, mcount, mid;
     for (int i = 0; i < N;) {
-        const int map = env_map[perm[i]];
         int j = i;
-        while (j < N && env_map[perm[j]] == map && j - i < tile_envs) ++j;
-        tiles.push_back(Tile{map, i, j - i, 0});
+        while (j < N && env_map[perm[j]] == env_map[perm[i]]) ++j;
+        mid.push_back(env_map[perm[i]]);
+        mfirst.push_back(i);
+        mcount.push_back(j - i);
         i = j;
+    }
+    const int nm = (int)mid.size();
+    std::vector<int> ntiles(nm);
+    int total = 0;
+    for (int q = 0; q < nm; ++q) {
+        ntiles[q] = (mcount[q] + tile_envs - 1) / tile_envs;
+        total += ntiles[q];
+    }
+    if (balance) {
+        // one more tile, each time, to the map whose tiles carry the most work
+        while (total < target_tiles) {
+            int best = -1;
+            double load = 0.0;
+            for (int q = 0; q < nm; ++q) {
+                if (ntiles[q] >= mcount[q]) continue;  // one env per tile already
+                const double l = map_weight[mid[q]] * (double)mcount[q] / ntiles[q];
+                if (l > load) {
+                    load = l;
+                    best = q;
+                }
+            }
+            if (best < 0) break;
+            ++ntiles[best];
+            ++total;
+        }
+    }
+    for (int q = 0; q < nm; ++q) {
+        const int n = mcount[q], T = ntiles[q];
+        if (balance) {
+            for (int t = 0, at = 0; t < T; ++t) {
+                const int c = n / T + (t < n % T ? 1 : 0);
+                tiles.push_back(Tile{mid[q], mfirst[q] + at, c, 0});
+                at += c;
+            }
+        } else {
+            for (int at = 0; at < n; at += tile_envs)
+                tiles.push_back(Tile{mid[q], mfirst[q] + at, std::min(tile_envs, n - at), 0});
+        }
     }
     std::stable_sort(tiles.begin(), tiles.end(), [&](const Tile &a, const Tile &b) {
         return map_weight[a.map] * a.count > map_weight[b.map] * b.count;
@@ -618,12 +703,14 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
     std::vector<int32_t> host_env_map(env_map, env_map + N);
     std::vector<double> map_weight(num_maps);
     for (int k = 0; k < num_maps; ++k)
-        map_weight[k] = (double)descs[k].K *
-                        std::min((double)cfg.max_range_m / (double)res_m[k],
-                                 0.5 * (double)(width[k] + height[k]));
+        map_weight[k] = used[k] ? map_scan_work(occ + occ_off[k], width[k], height[k],
+                                                (double)res_m[k], (double)cfg.max_range_m,
+                                                descs[k].K, free_cells.data() + descs[k].free_off,
+                                                descs[k].free_cnt)
+                                : 0.0;
     std::vector<int32_t> perm;
     std::vector<Tile> tiles;
-    build_tiles(host_env_map, h->tile_envs, map_weight, perm, tiles);
+    build_tiles(host_env_map, h->tile_envs, map_weight, h->balance, shape.resident, perm, tiles);
 
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
@@ -818,7 +905,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
     if (!t) return fail(NAVSIM_E_INVALID_ARG, "tuning is NULL");
     if (!fused_tile_envs_supported(t->tile_envs))
-        return fail(NAVSIM_E_INVALID_ARG, "tile_envs must be 1, 2, 4, 8 or 16");
+        return fail(NAVSIM_E_INVALID_ARG, "tile_envs must be 1, 2, 4, 8, 16 or 32");
     if (t->refill_at < 0 || t->refill_at > 63)
         return fail(NAVSIM_E_INVALID_ARG, "refill_at must be in 0..63");
     if (t->groups < 1 || t->groups > 64) return fail(NAVSIM_E_INVALID_ARG, "groups must be in 1..64");
@@ -829,6 +916,11 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
         return fail(NAVSIM_E_INVALID_ARG, "persist must be in 0..64");
     if (!fused_threads_supported(t->threads))
         return fail(NAVSIM_E_INVALID_ARG, "threads must be 256, 512 or 1024");
+    if (t->tile_envs * 16 > t->threads)
+        return fail(NAVSIM_E_INVALID_ARG, "tile_envs %d needs at least %d threads", t->tile_envs,
+                    t->tile_envs * 16);
+    if (t->balance != 0 && t->balance != 1)
+        return fail(NAVSIM_E_INVALID_ARG, "balance must be 0 or 1");
     {
         DeviceGuard g(h->device);
         drop_graph(h);
@@ -840,10 +932,11 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
                                              t->ray_slots, t->walk, h->scan_mode, shape);
         if (fs != NAVSIM_OK) return fs;
     }
-    if (h->loaded && t->tile_envs != h->tile_envs) {
+    if (h->loaded) {
         std::vector<int32_t> perm;
         std::vector<Tile> tiles;
-        build_tiles(h->host_env_map, t->tile_envs, h->host_map_weight, perm, tiles);
+        build_tiles(h->host_env_map, t->tile_envs, h->host_map_weight, t->balance, shape.resident,
+                    perm, tiles);
         DeviceGuard g(h->device);
         if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
         NS_HIP(hipDeviceSynchronize());
@@ -863,6 +956,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     h->walk_mode = t->walk;
     h->persist = t->persist;
     h->wg_threads = t->threads;
+    h->balance = t->balance;
     if (h->loaded) apply_shape(h, shape);
     return NAVSIM_OK;
 }
@@ -877,6 +971,7 @@ navsim_status navsim_get_tuning(navsim_t h, navsim_tuning *t) {
     t->walk = h->walk_mode;
     t->persist = h->persist;
     t->threads = h->wg_threads;
+    t->balance = h->balance;
     return NAVSIM_OK;
 }
 

@@ -64,6 +64,7 @@ struct navsim_s {
     bool beams_lds = true;
     int persist = 0;    // persistent workgroups: tiles per grab (0 = one workgroup per tile)
     int wg_threads = 256;  // fused step: threads per workgroup
+    int balance = 0;       // tiles sized per map by estimated scan work
     int cell_bytes = 0;    // walk 2, 4: LDS bytes of the byte-per-cell map copy
     int claim = 0;         // walk 3, 4 with the exact traversal: claim walk, no ray slots
     int lds_block = 65536, lds_cu = 65536;  // device LDS bytes per workgroup and per CU

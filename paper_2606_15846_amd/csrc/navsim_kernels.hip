@@ -1614,9 +1614,11 @@ static int resident_et(size_t lds) {
 }
 
 // Every supported (tile_envs, threads) pair.
+// (32-env tiles need 16 lanes per env in the motion phase: 512 threads or more)
 #define NAVSIM_FUSED_SHAPES(X)                                                                \
     X(1, 256) X(1, 512) X(1, 1024) X(2, 256) X(2, 512) X(2, 1024) X(4, 256) X(4, 512)        \
-    X(4, 1024) X(8, 256) X(8, 512) X(8, 1024) X(16, 256) X(16, 512) X(16, 1024)
+    X(4, 1024) X(8, 256) X(8, 512) X(8, 1024) X(16, 256) X(16, 512) X(16, 1024) X(32, 512)   \
+    X(32, 1024)
 
 int fused_resident_groups(int max_words, int m, int E, int T, int K, bool beams_lds, int ray_cap,
                           int cell_bytes) {
@@ -1645,7 +1647,9 @@ int fused_static_lds(int E, int T) {
     return -1;
 }
 
-bool fused_tile_envs_supported(int E) { return E == 1 || E == 2 || E == 4 || E == 8 || E == 16; }
+bool fused_tile_envs_supported(int E) {
+    return E == 1 || E == 2 || E == 4 || E == 8 || E == 16 || E == 32;
+}
 bool fused_threads_supported(int T) { return T == 256 || T == 512 || T == 1024; }
 
 // LDS walk slots per chunk: the rays of a full tile plus one reset pose

@@ -62,7 +62,7 @@ class NavsimMapProfile(C.Structure):
 class NavsimTuning(C.Structure):
     _fields_ = [("tile_envs", C.c_int32), ("refill_at", C.c_int32), ("groups", C.c_int32),
                 ("ray_slots", C.c_int32), ("walk", C.c_int32), ("persist", C.c_int32),
-                ("threads", C.c_int32)]
+                ("threads", C.c_int32), ("balance", C.c_int32)]
 
 
 class NavsimError(RuntimeError):
@@ -236,9 +236,9 @@ def navsim_rollout(h, steps: int, first_step: int, act, obs, reward, terminated,
 
 
 def navsim_set_tuning(h, tile_envs: int, refill_at: int, groups: int, ray_slots: int = 0,
-                      walk: int = 0, persist: int = 0, threads: int = 256):
+                      walk: int = 0, persist: int = 0, threads: int = 256, balance: int = 0):
     t = NavsimTuning(int(tile_envs), int(refill_at), int(groups), int(ray_slots), int(walk),
-                     int(persist), int(threads))
+                     int(persist), int(threads), int(balance))
     _check(load_library().navsim_set_tuning(h, C.byref(t)))
 
 
@@ -246,7 +246,8 @@ def navsim_get_tuning(h) -> dict:
     t = NavsimTuning()
     _check(load_library().navsim_get_tuning(h, C.byref(t)))
     return {"tile_envs": t.tile_envs, "refill_at": t.refill_at, "groups": t.groups,
-            "ray_slots": t.ray_slots, "walk": t.walk, "persist": t.persist, "threads": t.threads}
+            "ray_slots": t.ray_slots, "walk": t.walk, "persist": t.persist, "threads": t.threads,
+            "balance": t.balance}
 
 
 def navsim_get_state(h, num_envs: int, stream=None, device=None) -> dict:
@@ -374,8 +375,9 @@ class NavSim:
         _check(load_library().navsim_set_scan(self.h, int(mode), float(step_m)))
 
     def set_tuning(self, tile_envs: int, refill_at: int, groups: int, ray_slots: int = 0,
-                   walk: int = 0, persist: int = 0, threads: int = 256):
-        navsim_set_tuning(self.h, tile_envs, refill_at, groups, ray_slots, walk, persist, threads)
+                   walk: int = 0, persist: int = 0, threads: int = 256, balance: int = 0):
+        navsim_set_tuning(self.h, tile_envs, refill_at, groups, ray_slots, walk, persist, threads,
+                          balance)
 
     def get_tuning(self) -> dict:
         return navsim_get_tuning(self.h)

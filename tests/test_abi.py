@@ -148,7 +148,8 @@ def test_map_profile_layout_matches_header(tmp_path):
 
 def test_tuning_layout_matches_header(tmp_path):
     fields = [f for f, _ in navsim.NavsimTuning._fields_]
-    assert fields == ["tile_envs", "refill_at", "groups", "ray_slots", "walk", "persist", "threads"]
+    assert fields == ["tile_envs", "refill_at", "groups", "ray_slots", "walk", "persist", "threads",
+                      "balance"]
     src = ["#include <stdio.h>", "#include <stddef.h>", '#include "navsim.h"', "int main(void){",
            'printf("%zu\\n", sizeof(navsim_tuning));']
     src += [f'printf("%zu\\n", offsetof(navsim_tuning, {f}));' for f in fields]

@@ -135,12 +135,13 @@ def test_c4_full_size_launch_shapes_agree():
     w = configs.build_workload("c4")
     acts = torch.from_numpy(configs.uniform_actions(3, w["cfg"]["num_envs"], seed=5)).cuda()
     runs = []
-    for te, pe, th, wk in [(8, 0, 256, 0), (8, 4, 256, 0), (4, 1, 256, 0), (16, 16, 256, 0),
-                           (8, 0, 512, 0), (16, 0, 1024, 0), (4, 0, 1024, 0), (4, 0, 512, 3),
-                           (8, 2, 256, 3)]:
+    for te, pe, th, wk, bal in [(8, 0, 256, 0, 0), (8, 4, 256, 0, 0), (4, 1, 256, 0, 0),
+                                (16, 16, 256, 0, 0), (8, 0, 512, 0, 0), (16, 0, 1024, 0, 0),
+                                (4, 0, 1024, 0, 0), (4, 0, 512, 3, 0), (8, 2, 256, 3, 0),
+                                (16, 0, 512, 3, 1), (32, 0, 1024, 3, 1), (8, 3, 256, 3, 1)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0,
                      profiles=w["profiles"])
-        sim.set_tuning(te, 48, 8, walk=wk, persist=pe, threads=th)
+        sim.set_tuning(te, 48, 8, walk=wk, persist=pe, threads=th, balance=bal)
         outs = [sim.reset().cpu().numpy().copy()]
         for t in range(3):
             o, r, te_, tr, info = sim.step(acts[t])
@@ -450,7 +451,8 @@ def test_api_errors_on_device():
     before = navsim.navsim_get_tuning(h)
     base = dict(tile_envs=4, refill_at=48, groups=4, ray_slots=0, walk=0, persist=0, threads=256)
     for bad in [dict(tile_envs=3), dict(refill_at=64), dict(groups=0), dict(ray_slots=100),
-                dict(walk=5), dict(persist=65), dict(threads=384)]:
+                dict(walk=5), dict(persist=65), dict(threads=384), dict(tile_envs=32),
+                dict(balance=2)]:
         with pytest.raises(navsim.NavsimError) as ei:
             navsim.navsim_set_tuning(h, **dict(base, **bad))
         assert ei.value.status == -1, bad
@@ -478,11 +480,14 @@ def test_launch_shape_does_not_change_results():
             (8, 0, 1, 4096, 0, 0, 1024), (4, 56, 8, 0, 2, 0, 256), (1, 0, 1, 256, 2, 0, 256),
             (16, 48, 4, 0, 2, 0, 1024), (8, 63, 64, 0, 2, 3, 512), (2, 32, 2, 512, 2, 0, 256),
             (4, 56, 8, 0, 3, 0, 256), (1, 0, 1, 0, 3, 0, 256), (16, 48, 4, 0, 3, 2, 1024),
-            (8, 63, 64, 0, 4, 0, 512), (4, 56, 8, 0, 4, 0, 256), (2, 32, 2, 0, 4, 5, 256)]:
+            (8, 63, 64, 0, 4, 0, 512), (4, 56, 8, 0, 4, 0, 256), (2, 32, 2, 0, 4, 5, 256),
+            (32, 40, 8, 0, 4, 0, 512), (32, 32, 16, 0, 3, 0, 1024), (32, 48, 8, 0, 0, 3, 512)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
-        sim.set_tuning(te, ra, gr, rs, wk, pe, th)
+        bal = int(th == 1024 or te == 32)  # the larger workgroups also with balanced tiles
+        sim.set_tuning(te, ra, gr, rs, wk, pe, th, bal)
         assert sim.get_tuning() == {"tile_envs": te, "refill_at": ra, "groups": gr,
-                                    "ray_slots": rs, "walk": wk, "persist": pe, "threads": th}
+                                    "ray_slots": rs, "walk": wk, "persist": pe, "threads": th,
+                                    "balance": bal}
         sim.reset()
         outs = []
         for t in range(3):

@@ -114,7 +114,7 @@ def test_graph_recaptured_for_new_buffers_steps_and_tuning():
         if case == "threads":
             sim.set_tuning(16, 48, 4, threads=1024)
         if case == "claim":
-            sim.set_tuning(4, 56, 8, walk=4)
+            sim.set_tuning(4, 56, 8, walk=4, balance=1)
         if case == "first_step":
             sim.rollout(4, first_step=5, graph=True)
             torch.cuda.synchronize()
