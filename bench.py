@@ -148,10 +148,17 @@ def reset_proposal_gain(sim, w, args) -> dict:
         torch.cuda.synchronize()
         src = res["source"].cpu().numpy()
         ok = src >= 0
+        # difficulty: geodesic length (hops x cell size) against the requested bin
+        pc = w["proposer"]
+        width = (pc["d_hi_m"] - pc["d_lo_m"]) / nb
+        geo = res["hops"].cpu().numpy()[ok] * np.asarray(w["res"], np.float64)[mp[ok]]
+        lo = pc["d_lo_m"] + bins[ok] * width
         out[name] = {"valid_fraction": float(ok.mean()),
                      "checks_per_request": float(res["checks"].float().mean().item()),
                      "resets_per_s": float(ok.sum() / (e0.elapsed_time(e1) / 1e3)),
-                     "from_network": float(((src >= 0) & (src < M)).mean()) if M else 0.0}
+                     "from_network": float(((src >= 0) & (src < M)).mean()) if M else 0.0,
+                     "in_requested_bin": float(((geo >= lo) & (geo < lo + width)).mean()),
+                     "difficulty_error_m": float(np.abs(geo - (lo + width / 2)).mean())}
     out["gain_resets_per_s"] = out["learned"]["resets_per_s"] / out["rejection"]["resets_per_s"]
     rp.close()
     return out
