@@ -273,7 +273,7 @@ typedef struct {
                            at most tile_envs envs each.  Tiles always launch heaviest first */
 } navsim_tuning;
 
-/* Set the fused step's launch shape (defaults: 4, 48, 4, 0, 0, 0, 256, 0).  Changing tile_envs
+/* Set the fused step's launch shape (defaults: 8, 40, 8, 0, 3, 0, 256, 0).  Changing tile_envs
  * after navsim_load_maps waits for the device and re-groups the envs; returns
  * NAVSIM_E_UNSUPPORTED if the larger tile would not fit LDS. */
 navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t);

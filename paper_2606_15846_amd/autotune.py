@@ -21,7 +21,7 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_FILE = os.path.join(HERE, "tuning.json")
-DEFAULT = {"tile_envs": 4, "refill_at": 48, "groups": 4, "ray_slots": 0, "walk": 0, "persist": 0,
+DEFAULT = {"tile_envs": 8, "refill_at": 40, "groups": 8, "ray_slots": 0, "walk": 3, "persist": 0,
            "threads": 256, "balance": 0}
 # walk = 1 (run walk) measured about 2x slower than the group walk on every
 # workload here, persistent workgroups 5-40 % slower, the chunked bitmap walk

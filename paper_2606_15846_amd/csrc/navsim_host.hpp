@@ -60,7 +60,7 @@ struct navsim_s {
     int tile_envs = navsim::kDefaultTileEnvs, refill_at = navsim::kDefaultRefillAt, groups = navsim::kDefaultGroups;
     int ray_cap = 0;
     int ray_slots = 0;  // requested cap on ray_cap (0 = automatic)
-    int walk_mode = 0;  // fused walk: 0 cells in groups of 4, 1 runs, 2 groups of 4 on bytes
+    int walk_mode = navsim::kDefaultWalk;  // fused walk (see navsim_tuning.walk)
     bool beams_lds = true;
     int persist = 0;    // persistent workgroups: tiles per grab (0 = one workgroup per tile)
     int wg_threads = 256;  // fused step: threads per workgroup

@@ -18,9 +18,12 @@ namespace navsim {
 constexpr int kPad = 4;
 constexpr int kMaxMapWords = 12288;  // largest padded bitmap staged in LDS (48 KiB)
 constexpr int kMaxBeams = 4096;
-constexpr int kDefaultTileEnvs = 4;  // envs per fused workgroup (4, 8 or 16)
-constexpr int kDefaultRefillAt = 48;  // refill idle lanes once at most this many are busy
-constexpr int kDefaultGroups = 4;     // 4-cell groups walked between refill checks
+// Default launch shape of the fused step (a good choice on every workload
+// measured; the autotuner refines it per workload)
+constexpr int kDefaultTileEnvs = 8;   // envs per fused workgroup
+constexpr int kDefaultRefillAt = 40;  // refill idle lanes once at most this many are busy
+constexpr int kDefaultGroups = 8;     // 4-cell groups walked between refill checks
+constexpr int kDefaultWalk = 3;       // claim walk on the bitmap (any map size)
 
 struct MapDesc {
     int32_t w, h;

@@ -236,7 +236,7 @@ def navsim_rollout(h, steps: int, first_step: int, act, obs, reward, terminated,
 
 
 def navsim_set_tuning(h, tile_envs: int, refill_at: int, groups: int, ray_slots: int = 0,
-                      walk: int = 0, persist: int = 0, threads: int = 256, balance: int = 0):
+                      walk: int = 3, persist: int = 0, threads: int = 256, balance: int = 0):
     t = NavsimTuning(int(tile_envs), int(refill_at), int(groups), int(ray_slots), int(walk),
                      int(persist), int(threads), int(balance))
     _check(load_library().navsim_set_tuning(h, C.byref(t)))
@@ -375,7 +375,7 @@ class NavSim:
         _check(load_library().navsim_set_scan(self.h, int(mode), float(step_m)))
 
     def set_tuning(self, tile_envs: int, refill_at: int, groups: int, ray_slots: int = 0,
-                   walk: int = 0, persist: int = 0, threads: int = 256, balance: int = 0):
+                   walk: int = 3, persist: int = 0, threads: int = 256, balance: int = 0):
         navsim_set_tuning(self.h, tile_envs, refill_at, groups, ray_slots, walk, persist, threads,
                           balance)
 

@@ -75,10 +75,10 @@ def test_c2_plain_subset():
     sim.close()
 
 
-@pytest.mark.parametrize("walk", [1, 2, 3, 4])
+@pytest.mark.parametrize("walk", [0, 1, 2, 3, 4])
 def test_walk_variants_against_oracle(walk):
-    say(f"walk = {walk} (1 runs, 2 byte-per-cell map, 3 claim walk, 4 claim walk on bytes): "
-        f"c2 full size and c3 maps, fused, teacher-forced")
+    say(f"walk = {walk} (0 chunked groups, 1 runs, 2 byte-per-cell map, 3 claim walk, 4 claim "
+        f"walk on bytes): c2 full size and c3 maps, fused, teacher-forced")
     w = configs.build_workload("c2")
     sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
     sim.set_tuning(4, 48, 4, 0, walk)
