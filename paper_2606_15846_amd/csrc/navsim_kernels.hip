@@ -114,9 +114,11 @@ struct RectGeom {
     double c, sn, ex, ey, hs, pu, pw;
 };
 
-__device__ __forceinline__ RectGeom rect_geom(double th, double L, double B, double s) {
+__device__ __forceinline__ RectGeom rect_geom_cs(double c, double sn, double L, double B,
+                                                 double s) {
     RectGeom g;
-    sincos(th, &g.sn, &g.c);
+    g.c = c;
+    g.sn = sn;
     const double ac = fabs(g.c), as = fabs(g.sn);
     const double hl = 0.5 * L, hb = 0.5 * B;
     g.ex = hl * ac + hb * as;
@@ -125,6 +127,12 @@ __device__ __forceinline__ RectGeom rect_geom(double th, double L, double B, dou
     g.pu = hl + g.hs * (ac + as);
     g.pw = hb + g.hs * (as + ac);
     return g;
+}
+
+__device__ __forceinline__ RectGeom rect_geom(double th, double L, double B, double s) {
+    double sn, c;
+    sincos(th, &sn, &c);
+    return rect_geom_cs(c, sn, L, B, s);
 }
 
 __device__ __forceinline__ bool rect_cell(const RectGeom &g, double x, double y, int i, int j,
@@ -164,20 +172,35 @@ __device__ __forceinline__ CellRange cells_around(double x, double y, double ex,
 
 // Does any occupied candidate cell satisfy the exact predicate F(i, j)?  When
 // the window lies inside the stored rows, whole rows are tested with one mask
-// and F runs only on occupied cells; otherwise every cell is checked.
+// (four rows' masks read at a time, so their loads overlap) and F runs only on
+// occupied cells; otherwise every cell is checked.  The answer does not depend
+// on the order in which cells are tried.
 template <typename F>
 __device__ __forceinline__ bool any_filled_cell(const MapView &M, const CellRange &cr, F f) {
     const bool inside = cr.i0 >= -kPad && cr.j0 >= -kPad && cr.i0 + cr.nx <= M.w + kPad &&
                         cr.j0 + cr.ny <= M.h + kPad;
     if (inside) {
-        for (int dj = 0; dj < cr.ny; ++dj) {
-            const int r = cr.j0 + dj + kPad;
-            for (int c = 0; c < cr.nx; c += 32) {
-                uint32_t m = row_bits(M, r, cr.i0 + kPad + c, min(32, cr.nx - c));
-                while (m) {
-                    const int b = __ffs(m) - 1;
-                    m &= m - 1u;
-                    if (f(cr.i0 + c + b, cr.j0 + dj)) return true;
+        const int r0 = cr.j0 + kPad, last = cr.ny - 1;
+        for (int c = 0; c < cr.nx; c += 32) {
+            const int c0 = cr.i0 + kPad + c, len = min(32, cr.nx - c);
+            for (int dj = 0; dj < cr.ny; dj += 4) {
+                uint32_t mk[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    // rows past the window re-read its last row, then count as empty
+                    const uint32_t v = row_bits(M, r0 + min(dj + q, last), c0, len);
+                    mk[q] = dj + q <= last ? v : 0u;
+                }
+                if (!(mk[0] | mk[1] | mk[2] | mk[3])) continue;
+                // one copy of the exact test for the four rows
+#pragma unroll 1
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t m = q == 0 ? mk[0] : (q == 1 ? mk[1] : (q == 2 ? mk[2] : mk[3]));
+                    while (m) {
+                        const int b = __ffs(m) - 1;
+                        m &= m - 1u;
+                        if (f(cr.i0 + c + b, cr.j0 + dj + q)) return true;
+                    }
                 }
             }
         }
@@ -197,12 +220,20 @@ __device__ bool disc_hits(const MapView &M, double x, double y, double r) {
     return any_filled_cell(M, cr, [&](int i, int j) { return disc_cell(x, y, r2, i, j, s); });
 }
 
-__device__ bool footprint_hits(const MapView &M, const Robot &rb, double x, double y, double th) {
+__device__ bool footprint_hits_cs(const MapView &M, const Robot &rb, double x, double y,
+                                  double c, double sn) {
     if (rb.footprint == NAVSIM_DISC) return disc_hits(M, x, y, rb.radius);
-    const RectGeom g = rect_geom(th, rb.len, rb.wid, M.s);
+    const RectGeom g = rect_geom_cs(c, sn, rb.len, rb.wid, M.s);
     const CellRange cr = cells_around(x, y, g.ex, g.ey, M.s);
     const double s = M.s;
     return any_filled_cell(M, cr, [&](int i, int j) { return rect_cell(g, x, y, i, j, s); });
+}
+
+__device__ bool footprint_hits(const MapView &M, const Robot &rb, double x, double y, double th) {
+    if (rb.footprint == NAVSIM_DISC) return disc_hits(M, x, y, rb.radius);
+    double sn, c;
+    sincos(th, &sn, &c);
+    return footprint_hits_cs(M, rb, x, y, c, sn);
 }
 
 // ---------------------------------------------------------------------------
@@ -507,9 +538,8 @@ __device__ __forceinline__ ResetPose given_pose(const StepParams &p, int e) {
 
 // Store a reset: new state and the reset observation's scalar part (d, phi,
 // v = w = 0); c, sn receive the new heading's cosine and sine for its scan.
-__device__ void store_reset(const StepParams &p, int e, uint32_t ep, const ResetPose &r,
-                            double &c, double &sn) {
-    sincos((double)r.th, &sn, &c);
+__device__ void store_reset_cs(const StepParams &p, int e, uint32_t ep, const ResetPose &r,
+                               double c, double sn) {
     double d64;
     float d32, phi;
     goal_features((double)r.x, (double)r.y, c, sn, r.gx, r.gy, d64, d32, phi);
@@ -529,6 +559,12 @@ __device__ void store_reset(const StepParams &p, int e, uint32_t ep, const Reset
     p.st.t[e] = 0;
     p.st.ep[e] = ep + 1u;
     if (p.d_fb) p.d_fb[e] = (uint8_t)r.fb;
+}
+
+__device__ void store_reset(const StepParams &p, int e, uint32_t ep, const ResetPose &r,
+                            double &c, double &sn) {
+    sincos((double)r.th, &sn, &c);
+    store_reset_cs(p, e, ep, r, c, sn);
 }
 
 // ---------------------------------------------------------------------------
@@ -642,39 +678,79 @@ __device__ __forceinline__ bool group_any_filled(const MapView &M, const CellRan
 }
 
 __device__ bool group_footprint_hits(const MapView &M, const Robot &rb, double x, double y,
-                                     double th, int li) {
+                                     double c, double sn, int li) {
     if (rb.footprint == NAVSIM_DISC) {
         const double r = rb.radius, r2 = r * r, s = M.s;
         const CellRange cr = cells_around(x, y, r, r, s);
         return group_any_filled(M, cr, li, [&](int i, int j) { return disc_cell(x, y, r2, i, j, s); });
     }
-    const RectGeom g = rect_geom(th, rb.len, rb.wid, M.s);
+    const RectGeom g = rect_geom_cs(c, sn, rb.len, rb.wid, M.s);
     const CellRange cr = cells_around(x, y, g.ex, g.ey, M.s);
     const double s = M.s;
     return group_any_filled(M, cr, li, [&](int i, int j) { return rect_cell(g, x, y, i, j, s); });
 }
 
-// Reset draws of one env by its group: 16 attempts at a time, each lane
-// testing one whole candidate; the lowest successful attempt wins, which is
-// the first success of the sequential sampler.
+// Reset draws of one env by its group of 16 lanes.  A goal's clearance test
+// does not depend on the start pose (only its distance test does), so the
+// first pass tests start attempts 0..7 on lanes 0..7 and goal attempts 0..7 on
+// lanes 8..15 together; later passes test 16 attempts of one kind at a time.
+// The lowest successful attempt of each kind wins, which is the first success
+// of the sequential sampler.  c, sn receive the start heading's cosine and sine.
 __device__ ResetPose group_sample_reset(const StepParams &p, const MapView &M, const MapDesc &md,
-                                        int e, uint32_t ep, int li) {
+                                        int e, uint32_t ep, int li, double &c_out,
+                                        double &sn_out) {
+    constexpr int kHalf = kGroupLanes / 2;
     const double s = M.s, Ws = (double)md.w * s, Hs = (double)md.h * s;
     const Robot rb = robot_of(md);
     const int gbase = threadIdx.x & 48;
     ResetPose r{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0u};
+
+    // ---- first pass: starts 0..7 and goals 0..7 ----
+    const bool goal_lane = li >= kHalf;
+    const int a1 = goal_lane ? li - kHalf : li;
+    float fx = 0.0f, fy = 0.0f, ft = 0.0f;
+    double fc = 1.0, fs = 0.0;
+    bool clear = false;
+    if (a1 < p.tries) {
+        double u[4];
+        draw4(p, (uint32_t)e, ep, (uint32_t)a1, goal_lane ? 1u : 0u, u);
+        fx = (float)(u[0] * Ws);
+        fy = (float)(u[1] * Hs);
+        if (!goal_lane) {
+            ft = uniform_heading(u[2]);
+            sincos((double)ft, &fs, &fc);
+        }
+        bool hit;
+        if (!goal_lane && rb.footprint != NAVSIM_DISC)
+            hit = footprint_hits_cs(M, rb, (double)fx, (double)fy, fc, fs);
+        else
+            hit = disc_hits(M, (double)fx, (double)fy, goal_lane ? rb.rc : rb.radius);
+        clear = !hit;
+    }
+    const uint32_t first = group_ballot(clear);
     bool found = false;
-    for (int a0 = 0; a0 < p.tries; a0 += kGroupLanes) {
+    if (first & 0xFFu) {
+        const int src = gbase + __ffs(first & 0xFFu) - 1;
+        r.x = __shfl(fx, src);
+        r.y = __shfl(fy, src);
+        r.th = __shfl(ft, src);
+        c_out = __shfl(fc, src);
+        sn_out = __shfl(fs, src);
+        found = true;
+    }
+    for (int a0 = kHalf; a0 < p.tries && !found; a0 += kGroupLanes) {
         const int a = a0 + li;
         bool ok = false;
         float cx = 0.0f, cy = 0.0f, ct = 0.0f;
+        double cc = 1.0, cs = 0.0;
         if (a < p.tries) {
             double u[4];
             draw4(p, (uint32_t)e, ep, (uint32_t)a, 0u, u);
             cx = (float)(u[0] * Ws);
             cy = (float)(u[1] * Hs);
             ct = uniform_heading(u[2]);
-            ok = !footprint_hits(M, rb, (double)cx, (double)cy, (double)ct);
+            sincos((double)ct, &cs, &cc);
+            ok = !footprint_hits_cs(M, rb, (double)cx, (double)cy, cc, cs);
         }
         const uint32_t gm = group_ballot(ok);
         if (gm) {
@@ -682,8 +758,9 @@ __device__ ResetPose group_sample_reset(const StepParams &p, const MapView &M, c
             r.x = __shfl(cx, src);
             r.y = __shfl(cy, src);
             r.th = __shfl(ct, src);
+            c_out = __shfl(cc, src);
+            sn_out = __shfl(cs, src);
             found = true;
-            break;
         }
     }
     if (!found) {
@@ -691,10 +768,26 @@ __device__ ResetPose group_sample_reset(const StepParams &p, const MapView &M, c
         draw4(p, (uint32_t)e, ep, 0u, 2u, u);
         free_cell_centre(p, md, u[0], r.x, r.y);
         r.th = uniform_heading(u[2]);
+        sincos((double)r.th, &sn_out, &c_out);
         r.fb |= 1u;
     }
+
+    // ---- goals: the first pass's clear candidates, then 16 at a time ----
+    const double gmd = (double)p.gmd;
+    bool ok1 = false;
+    if (goal_lane && clear) {
+        const double ddx = (double)fx - (double)r.x, ddy = (double)fy - (double)r.y;
+        ok1 = sqrt(ddx * ddx + ddy * ddy) >= gmd;
+    }
+    const uint32_t gm1 = group_ballot(ok1) >> kHalf;
     found = false;
-    for (int b0 = 0; b0 < p.tries; b0 += kGroupLanes) {
+    if (gm1) {
+        const int src = gbase + kHalf + __ffs(gm1) - 1;
+        r.gx = __shfl(fx, src);
+        r.gy = __shfl(fy, src);
+        found = true;
+    }
+    for (int b0 = kHalf; b0 < p.tries && !found; b0 += kGroupLanes) {
         const int b = b0 + li;
         bool ok = false;
         float cx = 0.0f, cy = 0.0f;
@@ -705,7 +798,7 @@ __device__ ResetPose group_sample_reset(const StepParams &p, const MapView &M, c
             cy = (float)(u[1] * Hs);
             if (!disc_hits(M, (double)cx, (double)cy, rb.rc)) {
                 const double ddx = (double)cx - (double)r.x, ddy = (double)cy - (double)r.y;
-                ok = sqrt(ddx * ddx + ddy * ddy) >= (double)p.gmd;
+                ok = sqrt(ddx * ddx + ddy * ddy) >= gmd;
             }
         }
         const uint32_t gm = group_ballot(ok);
@@ -714,7 +807,6 @@ __device__ ResetPose group_sample_reset(const StepParams &p, const MapView &M, c
             r.gx = __shfl(cx, src);
             r.gy = __shfl(cy, src);
             found = true;
-            break;
         }
     }
     if (!found) {
@@ -1274,26 +1366,33 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
         // other workgroups' walks on the same SIMD
         __builtin_amdgcn_s_setprio(3);
         bool active = false, done = false;
+        uint32_t ep = 0u;
         if (grp < tile.count) {
             const int e = p.perm[tile.first + grp];
             active = true;
             if (p.mode == 1) {
                 done = !p.mask || p.mask[e];
                 if (li == 0) s_jobs[grp].dst = 3;
+                ep = p.st.ep[e];
             } else {
+                // every state load is issued before the first use: one memory
+                // round trip instead of one per dependent use
                 const float2 a = env_action(p, e);
+                const float x0 = p.st.x[e], y0 = p.st.y[e], th0 = p.st.th[e];
+                const float gx = p.st.gx[e], gy = p.st.gy[e], dprev = p.st.dprev[e];
+                const int t = p.st.t[e] + 1;
+                ep = p.st.ep[e];
                 if (p.act_out && li == 0)
                     *reinterpret_cast<float2 *>(p.act_out + 2 * (int64_t)e) = a;
-                const Motion mo = apply_action(p, a.x, a.y, p.st.x[e], p.st.y[e], p.st.th[e]);
+                const Motion mo = apply_action(p, a.x, a.y, x0, y0, th0);
                 const double x1 = (double)mo.x1, y1 = (double)mo.y1, th1 = (double)mo.th1;
-                const bool coll = group_footprint_hits(M, robot_of(md), x1, y1, th1, li);
                 double sn, c;
                 sincos(th1, &sn, &c);
+                const bool coll = group_footprint_hits(M, robot_of(md), x1, y1, c, sn, li);
                 double d64;
                 float d32, phi;
-                goal_features(x1, y1, c, sn, p.st.gx[e], p.st.gy[e], d64, d32, phi);
+                goal_features(x1, y1, c, sn, gx, gy, d64, d32, phi);
                 const bool goal = d64 < (double)p.goal_r;
-                const int t = p.st.t[e] + 1;
                 const bool term = goal || coll;
                 const bool trunc = (t >= p.horizon) && !term;
                 done = term || trunc;
@@ -1301,7 +1400,7 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
                     const float rew =
                         goal ? p.r_succ
                              : (coll ? p.r_coll
-                                     : (float)((double)p.c1 * ((double)p.st.dprev[e] - (double)d32)));
+                                     : (float)((double)p.c1 * ((double)dprev - (double)d32)));
                     p.reward[e] = rew;
                     p.term[e] = (uint8_t)term;
                     p.trunc[e] = (uint8_t)trunc;
@@ -1332,12 +1431,16 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
                 }
             }
             if (done) {
-                const uint32_t ep = p.st.ep[e];
-                const ResetPose r =
-                    p.pose ? given_pose(p, e) : group_sample_reset(p, M, md, e, ep, li);
+                double c = 1.0, sn = 0.0;
+                ResetPose r;
+                if (p.pose) {
+                    r = given_pose(p, e);
+                    sincos((double)r.th, &sn, &c);
+                } else {
+                    r = group_sample_reset(p, M, md, e, ep, li, c, sn);
+                }
                 if (li == 0) {
-                    double c, sn;
-                    store_reset(p, e, ep, r, c, sn);
+                    store_reset_cs(p, e, ep, r, c, sn);
                     make_tile_job(s_jobs[E + grp], M, r.x, r.y, c, sn, e, 0);
                 }
             }
