@@ -244,15 +244,47 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
     uint16_t *wl = act_lds + 32 * ld;  // this layer's weights
     float *s_act = reinterpret_cast<float *>(wl + a.wmax);  // [16][2] actions before noise
     const int row = a.m + 4;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    // A layer's weights and biases go to registers one layer ahead: layer
+    // l + 1's loads are in flight while layer l runs on the matrix cores.
+    // Weights: np kp / 8 <= 128 * 128 / 8 = 2048 vectors, at most 8 per
+    // thread; rows of kp bf16 stored with pitch kp + 8 (conflict-free fragment
+    // reads); thread t copies 16-byte column t % 16 of rows t / 16 + 16 i.
+    const int wc = threadIdx.x & 15, wr0 = threadIdx.x >> 4;
+    uint4 t8[8];
+    float bias[2];
+    auto load_layer = [&](int l) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.w + a.w_off[l]);
+        const int rv = a.kpad[l] / 8, np = a.npad[l];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int rw = wr0 + 16 * t;
+            t8[t] = (wc < rv && rw < np) ? src[rw * rv + wc] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        // this lane's biases, for its wavefront's column blocks (np <= 128)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int n0 = 16 * (wave + 4 * t);
+            bias[t] = n0 < np ? a.b[a.b_off[l] + n0 + fr] : 0.0f;
+        }
+    };
+    load_layer(0);
     // inputs: 16 rows x kpad[0] (<= 128) columns, 8 per thread, loads first
     {
         const int kp0 = a.kpad[0];
         const float beta = *a.beta;
         float v[8];
+        // every load in bounds (clamped row and column, N >= 1) and issued
+        // back to back; out-of-range entries are then replaced by 0
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int q = threadIdx.x + 256 * t, r = q >> 7, j = q & 127, e = row0 + r;
-            v[t] = (e < a.N && j < row) ? a.obs[(int64_t)e * row + j] : 0.0f;
+            v[t] = a.obs[(int64_t)min(e, a.N - 1) * row + min(j, row - 1)];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int q = threadIdx.x + 256 * t, r = q >> 7, j = q & 127, e = row0 + r;
+            if (!(e < a.N && j < row)) v[t] = 0.0f;
         }
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
@@ -262,36 +294,20 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
                     to_bf16_bits(j < a.m && row0 + r < a.N ? 1.0f / (v[t] - beta) : v[t]);
         }
     }
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
     for (int l = 0; l < a.layers; ++l) {
         const int kp = a.kpad[l], np = a.npad[l];
         {
-            // np kp / 8 <= 128 * 128 / 8 = 2048 vectors: at most 8 per thread, loads first
-            // rows of kp bf16 stored with pitch kp + 8 (conflict-free fragment reads);
-            // thread t copies 16-byte column t % 16 of rows t / 16 + 16 i
-            const uint4 *src = reinterpret_cast<const uint4 *>(a.w + a.w_off[l]);
             uint4 *dst = reinterpret_cast<uint4 *>(wl);
-            const int rv = kp / 8, c = threadIdx.x & 15, r0 = threadIdx.x >> 4;
-            uint4 t8[8];
+            const int rv = kp / 8;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                const int rw = r0 + 16 * t;
-                t8[t] = (c < rv && rw < np) ? src[rw * rv + c] : make_uint4(0u, 0u, 0u, 0u);
-            }
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int rw = r0 + 16 * t;
-                if (c < rv && rw < np) dst[rw * (rv + 1) + c] = t8[t];
+                const int rw = wr0 + 16 * t;
+                if (wc < rv && rw < np) dst[rw * (rv + 1) + wc] = t8[t];
             }
         }
-        // this lane's biases, for its wavefront's column blocks (np <= 128)
-        float bias[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int n0 = 16 * (wave + 4 * t);
-            bias[t] = n0 < np ? a.b[a.b_off[l] + n0 + fr] : 0.0f;
-        }
+        const float bias_l[2] = {bias[0], bias[1]};
         __syncthreads();  // inputs and weights in LDS
+        if (l + 1 < a.layers) load_layer(l + 1);
         const uint16_t *W = wl;
         const bool last = l + 1 == a.layers;
         bf16x8 av[4];  // the rows' input fragments, shared by every column block
@@ -315,7 +331,7 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int rr = (lane >> 4) * 4 + r;
-                float v = acc[r] + bias[t];
+                float v = acc[r] + bias_l[t];
                 if (!last) {
                     if (!(v > 0.0f)) v *= a.slope;
                     nxt_in[rr * ld + n] = to_bf16_bits(v);

@@ -325,6 +325,42 @@ def test_edge_configs(case, kname):
     sim.close()
 
 
+def _crowded_map():
+    # mostly occupied: three rooms hold ~22 % of the cells, and a disc of
+    # r 0.18 m fits around ~11 % of them
+    occ = np.ones((80, 100), np.uint8)
+    occ[8:30, 8:40] = 0
+    occ[48:72, 55:92] = 0
+    occ[30:42, 68:82] = 0
+    return occ
+
+
+@pytest.mark.parametrize("case", ["tries5", "tries12", "tries40", "rect20"])
+@pytest.mark.parametrize("kname", ["fused", "plain"])
+def test_crowded_map_reset_attempts(case, kname):
+    """Start and goal draws on a crowded map need many attempts: the first
+    success often comes after attempt 8 or 16 (the fused step's later passes)
+    or never (the free-cell fallback), with fewer attempts than one pass (5),
+    between one and two passes (12), many (40), and with a rectangle."""
+    say(f"crowded map, {case}, kernel={kname}")
+    occ = _crowded_map()
+    tries = {"tries5": 5, "tries12": 12, "tries40": 40, "rect20": 20}[case]
+    cfg = _small_cfg(num_envs=40, reset_max_tries=tries, goal_min_dist_m=1.0)
+    if case == "rect20":
+        cfg.update(footprint=1, length_m=0.5, width_m=0.3)
+    maps = [occ, occ[::-1].copy()]
+    env_map = (np.arange(cfg["num_envs"]) % 2).astype(np.int32)
+    _, fb = oracle.OracleSim(cfg, maps, [0.05, 0.05], env_map).reset(threads=16)
+    say(f"oracle reset: start fallbacks {int(((fb & 1) != 0).sum())}, "
+        f"goal fallbacks {int(((fb & 2) != 0).sum())} of {cfg['num_envs']}")
+    if tries <= 12:
+        assert (fb != 0).any()
+    sim, ref = make_pair(cfg, maps, [0.05, 0.05], env_map)
+    tot = run_teacher_forced(sim, ref, 20, KERNELS[kname], seed=9, label=f"crowded {case}/{kname}")
+    assert tot["resets"] > 0
+    sim.close()
+
+
 def test_pose_outside_map_and_inside_obstacle():
     say("poses outside the map / inside an obstacle")
     occ = np.zeros((40, 40), np.uint8)
