@@ -25,14 +25,19 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
-KERNEL_SRC = os.path.join(ROOT, "paper_2606_15846_amd", "csrc", "navsim_kernels.hip")
+# the fused step's source: the kernel file and the headers it includes
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2606_15846_amd", "csrc", f)
+               for f in ("navsim_kernels.hip", "navsim_internal.hpp", "philox.hpp")]
 PMC_FILE = os.path.join(ROOT, "profiles", "fused_step_c2_hbm_traffic.txt")
 SQ_FILE = os.path.join(ROOT, "profiles", "fused_step_c2_sq_counters.txt")
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9  # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (int32 ops/s)
 
 
 def kernel_source_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def profile_values(path: str):

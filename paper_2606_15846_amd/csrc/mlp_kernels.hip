@@ -310,23 +310,31 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
         if (l + 1 < a.layers) load_layer(l + 1);
         const uint16_t *W = wl;
         const bool last = l + 1 == a.layers;
-        bf16x8 av[4];  // the rows' input fragments, shared by every column block
+        // Every fragment is read before the first product, from positions
+        // clamped into this layer's K and N (always in bounds), so the reads
+        // share one LDS round trip; products past K are then skipped.
+        const int nkb = kp / 32;  // 1..4
+        bf16x8 av[4];             // the rows' input fragments, shared by every column block
+        bf16x8 bv[2][4];          // this wavefront's two column blocks
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb)
-            if (32 * kb < kp) av[kb] = *reinterpret_cast<const bf16x8 *>(&cur_in[fr * ld + 32 * kb + fk]);
+            av[kb] = *reinterpret_cast<const bf16x8 *>(&cur_in[fr * ld + 32 * min(kb, nkb - 1) + fk]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int n0 = min(16 * (wave + 4 * t), np - 16);
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb)
+                bv[t][kb] = *reinterpret_cast<const bf16x8 *>(W + (n0 + fr) * (kp + 8) +
+                                                              32 * min(kb, nkb - 1) + fk);
+        }
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const int n0 = 16 * (wave + 4 * t);
             if (n0 >= np) break;
             f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) {
-                if (32 * kb < kp) {
-                    const bf16x8 bv =
-                        *reinterpret_cast<const bf16x8 *>(W + (n0 + fr) * (kp + 8) + 32 * kb + fk);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[kb], bv, acc, 0, 0, 0);
-                }
-            }
+            for (int kb = 0; kb < 4; ++kb)
+                if (kb < nkb) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[kb], bv[t][kb], acc, 0, 0, 0);
             const int n = n0 + fr;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
