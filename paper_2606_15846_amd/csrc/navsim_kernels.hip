@@ -1535,18 +1535,20 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
     }
 }
 
-// One workgroup per tile (queue null), or persistent workgroups that take
-// `chunk` consecutive tiles at a time from a device counter; the last
-// workgroup to finish sets the counter back to zero for the next launch.
+// One workgroup per tile (Q false), or persistent workgroups (Q true) that
+// take `chunk` consecutive tiles at a time from a device counter; the last
+// workgroup to finish sets the counter back to zero for the next launch.  The
+// two are separate kernels: with the tile loop in the same kernel the
+// compiler hoisted the math library's polynomial coefficients out of it and
+// kept them in scratch memory, reloading one per step of every atan2.
 // Register budget: 128 VGPRs, so that 4 wavefronts share each SIMD and hide
 // one another's LDS latency in the walk (the compiler's own choice, ~200,
-// leaves 2).  The motion phase spills a few values to scratch memory; the
-// walk loop keeps everything in registers.
-template <int E, int T>
+// leaves 2); the walk loop keeps everything in registers.
+template <int E, int T, bool Q>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(kFusedWavesPerSimd)))
 void fused_step_kernel(StepParams p) {
     int staged = -1;
-    if (!p.queue) {
+    if constexpr (!Q) {
         fused_tile<E, T>(p, (int)blockIdx.x, staged);
         return;
     }
@@ -1676,8 +1678,8 @@ __global__ __launch_bounds__(64) void plain_step_kernel(StepParams p) {
 }
 
 // ---------------------------------------------------------------------------
-template <int E, int T>
-static hipError_t launch_fused_et(const StepParams &p, hipStream_t s) {
+template <int E, int T, bool Q>
+static hipError_t launch_fused_etq(const StepParams &p, hipStream_t s) {
     const size_t lds = fused_lds_bytes(p.max_words, p.m, E, p.beams_lds ? p.K : 0,
                                        p.claim ? 0 : p.ray_cap, p.cell_bytes);
     if (lds > 65536u) {
@@ -1689,7 +1691,7 @@ static hipError_t launch_fused_et(const StepParams &p, hipStream_t s) {
         hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
         if (dev < 0 || dev >= kDevices || (int)lds > raised[dev].load()) {
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(fused_step_kernel<E, T>),
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(fused_step_kernel<E, T, Q>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
             if (dev >= 0 && dev < kDevices) raised[dev].store((int)lds);
@@ -1701,14 +1703,20 @@ static hipError_t launch_fused_et(const StepParams &p, hipStream_t s) {
         const int chunks = (p.num_tiles + p.chunk - 1) / p.chunk;
         grid = (unsigned)std::max(1, std::min(chunks, p.resident));
     }
-    hipLaunchKernelGGL((fused_step_kernel<E, T>), dim3(grid), dim3(T), lds, s, p);
+    hipLaunchKernelGGL((fused_step_kernel<E, T, Q>), dim3(grid), dim3(T), lds, s, p);
     return hipGetLastError();
+}
+
+template <int E, int T>
+static hipError_t launch_fused_et(const StepParams &p, hipStream_t s) {
+    return p.queue ? launch_fused_etq<E, T, true>(p, s) : launch_fused_etq<E, T, false>(p, s);
 }
 
 template <int E, int T>
 static int resident_et(size_t lds) {
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_step_kernel<E, T>, T, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_step_kernel<E, T, false>, T,
+                                                     lds) !=
             hipSuccess ||
         hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -1735,11 +1743,13 @@ int fused_resident_groups(int max_words, int m, int E, int T, int K, bool beams_
 
 template <int E, int T>
 static int static_lds_et() {
-    hipFuncAttributes fa;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(fused_step_kernel<E, T>)) !=
-        hipSuccess)
+    hipFuncAttributes fa, fq;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(fused_step_kernel<E, T, false>)) !=
+            hipSuccess ||
+        hipFuncGetAttributes(&fq, reinterpret_cast<const void *>(fused_step_kernel<E, T, true>)) !=
+            hipSuccess)
         return -1;
-    return (int)fa.sharedSizeBytes;
+    return (int)std::max(fa.sharedSizeBytes, fq.sharedSizeBytes);
 }
 
 int fused_static_lds(int E, int T) {
