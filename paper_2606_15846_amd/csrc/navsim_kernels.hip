@@ -836,9 +836,12 @@ __device__ __forceinline__ uint4 pack_walk(const Walk &w, int max_n) {
 }
 
 // Range, hit and visits of a walked ray, folded into the sector pool.
-__device__ __forceinline__ void finish_ray(const StepParams &p, const MapView &M, const TileJob &j,
-                                           const double2 *s_beam, int job, int beam, uint2 res,
-                                           uint32_t *s_pool, int per, float inv_per, int E) {
+// Range of a finished ray (direction dx, dy) folded into its sector's pooled
+// minimum; per-ray outputs for main jobs when requested.
+__device__ __forceinline__ void finish_ray_dir(const StepParams &p, const MapView &M,
+                                               const TileJob &j, double dx, double dy, int job,
+                                               int beam, uint2 res, uint32_t *s_pool, int per,
+                                               float inv_per, int E) {
     float rg;
     int hit, vis;
     if (j.blocked) {
@@ -849,9 +852,6 @@ __device__ __forceinline__ void finish_ray(const StepParams &p, const MapView &M
         const int B = (int)(res.x & 0x7FFFFu), k = (int)(res.x >> 19);
         vis = k + 1;
         if (res.y & 1u) {
-            const double2 cs = s_beam[beam];
-            const double dx = j.c * cs.x - j.s * cs.y;
-            const double dy = j.s * cs.x + j.c * cs.y;
             walk_result(tile_origin(j, M.s), M.pitch, M.w, M.h, B, dx, dy, (double)p.rmax, rg,
                         hit);
         } else {
@@ -866,6 +866,19 @@ __device__ __forceinline__ void finish_ray(const StepParams &p, const MapView &M
         if (p.d_hits) p.d_hits[o] = hit;
         if (p.d_visits) p.d_visits[o] = vis;
     }
+}
+
+// The same with the direction recomputed from the job and the beam table.
+__device__ __forceinline__ void finish_ray(const StepParams &p, const MapView &M, const TileJob &j,
+                                           const double2 *s_beam, int job, int beam, uint2 res,
+                                           uint32_t *s_pool, int per, float inv_per, int E) {
+    double dx = 0.0, dy = 0.0;
+    if (!j.blocked && (res.y & 1u)) {
+        const double2 cs = s_beam[beam];
+        dx = j.c * cs.x - j.s * cs.y;
+        dy = j.s * cs.x + j.c * cs.y;
+    }
+    finish_ray_dir(p, M, j, dx, dy, job, beam, res, s_pool, per, inv_per, E);
 }
 
 // finish_ray for the fixed-step march: res.x = k | outcome << 28.
@@ -1244,13 +1257,14 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
     bool act = false, exhausted = false;
     int B = 0, Eh = 0, incx = 0, incy = 0, dEx = 0, dEy = 0, n = 0, k = 0;
     uint32_t flags = 0u;
+    double rdx = 0.0, rdy = 0.0;  // the claimed ray's direction, kept for its range
     for (;;) {
         uint64_t am = __ballot(act);
         if (!exhausted && __popcll(am) <= p.refill_at) {
             if (!act && g >= 0) {
-                finish_ray(p, M, s_jobs[job], s_beam, job, beam,
-                           make_uint2((uint32_t)B | ((uint32_t)k << 19), flags), s_pool, per,
-                           inv_per, E);
+                finish_ray_dir(p, M, s_jobs[job], rdx, rdy, job, beam,
+                               make_uint2((uint32_t)B | ((uint32_t)k << 19), flags), s_pool, per,
+                               inv_per, E);
                 g = -1;
             }
             const uint64_t idle = ~am;
@@ -1269,9 +1283,9 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
                 n = 0;
                 if (!j.blocked) {
                     const double2 cs = s_beam[beam];
-                    const double dx = j.c * cs.x - j.s * cs.y;
-                    const double dy = j.s * cs.x + j.c * cs.y;
-                    const Walk w = walk_setup(M.pitch, tile_origin(j, M.s), dx, dy, rmax_c);
+                    rdx = j.c * cs.x - j.s * cs.y;
+                    rdy = j.s * cs.x + j.c * cs.y;
+                    const Walk w = walk_setup(M.pitch, tile_origin(j, M.s), rdx, rdy, rmax_c);
                     B = w.B;
                     n = min(w.n, max_n);
                     Eh = w.Eh - w.thr;
@@ -1295,8 +1309,9 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
             walk_groups<BYTES>(p, s_bits, s_cells, B, Eh, incx, incy, dEx, dEy, n, k, flags, act);
     }
     if (g >= 0)
-        finish_ray(p, M, s_jobs[job], s_beam, job, beam,
-                   make_uint2((uint32_t)B | ((uint32_t)k << 19), flags), s_pool, per, inv_per, E);
+        finish_ray_dir(p, M, s_jobs[job], rdx, rdy, job, beam,
+                       make_uint2((uint32_t)B | ((uint32_t)k << 19), flags), s_pool, per, inv_per,
+                       E);
 }
 
 // LDS of the fused step, in order: the map's byte-per-cell copy [cell_bytes]
