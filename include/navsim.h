@@ -57,7 +57,7 @@ typedef enum {
     NAVSIM_E_NO_FREE_SPACE = -4,  /* a map used by some env has no collision-free cell */
     NAVSIM_E_OOM = -5,            /* device or host allocation failed               */
     NAVSIM_E_HIP = -6,            /* a HIP runtime call failed (message has details) */
-    NAVSIM_E_UNSUPPORTED = -7     /* valid but beyond this build's limits           */
+    NAVSIM_E_UNSUPPORTED = -7     /* valid but beyond this library's limits         */
 } navsim_status;
 
 enum { NAVSIM_DISC = 0, NAVSIM_RECT = 1 };
