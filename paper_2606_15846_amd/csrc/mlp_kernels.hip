@@ -234,7 +234,15 @@ __global__ void actor_noise_kernel(int N, float *act, float std, const uint32_t 
 // row's exploration noise pair (one Box-Muller transform), adds, clips and
 // stores both action components.  Same tiles, k order and rounding points as
 // the layer-by-layer GEMM path.
-__global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
+// Threads of the one-launch actor: 8 wavefronts, one 16-column block of a
+// layer (<= 128 wide) each, so that a wavefront's serial chain per layer is
+// one block's products and epilogue.
+constexpr int kActorThreads = 512;
+constexpr int kActorWaves = kActorThreads / 64;
+constexpr int kActorBlocks = 8 / kActorWaves;  // column blocks per wavefront
+constexpr int kActorPasses = 2048 / kActorThreads;  // 16 rows x 128 columns per pass set
+
+__global__ __launch_bounds__(kActorThreads) void actor_fused_kernel(ActorArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint16_t act_lds[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row0 = blockIdx.x * 16;
@@ -247,48 +255,49 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     // A layer's weights and biases go to registers one layer ahead: layer
     // l + 1's loads are in flight while layer l runs on the matrix cores.
-    // Weights: np kp / 8 <= 128 * 128 / 8 = 2048 vectors, at most 8 per
+    // Weights: np kp / 8 <= 128 * 128 / 8 = 2048 vectors, kActorPasses per
     // thread; rows of kp bf16 stored with pitch kp + 8 (conflict-free fragment
-    // reads); thread t copies 16-byte column t % 16 of rows t / 16 + 16 i.
+    // reads); thread t copies 16-byte column t % 16 of rows t / 16 + (T / 16) i.
     const int wc = threadIdx.x & 15, wr0 = threadIdx.x >> 4;
-    uint4 t8[8];
-    float bias[2];
+    constexpr int kRowStep = kActorThreads / 16;
+    uint4 t8[kActorPasses];
+    float bias[kActorBlocks];
     auto load_layer = [&](int l) {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.w + a.w_off[l]);
         const int rv = a.kpad[l] / 8, np = a.npad[l];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int rw = wr0 + 16 * t;
+        for (int t = 0; t < kActorPasses; ++t) {
+            const int rw = wr0 + kRowStep * t;
             t8[t] = (wc < rv && rw < np) ? src[rw * rv + wc] : make_uint4(0u, 0u, 0u, 0u);
         }
         // this lane's biases, for its wavefront's column blocks (np <= 128)
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int n0 = 16 * (wave + 4 * t);
+        for (int t = 0; t < kActorBlocks; ++t) {
+            const int n0 = 16 * (wave + kActorWaves * t);
             bias[t] = n0 < np ? a.b[a.b_off[l] + n0 + fr] : 0.0f;
         }
     };
     load_layer(0);
-    // inputs: 16 rows x kpad[0] (<= 128) columns, 8 per thread, loads first
+    // inputs: 16 rows x kpad[0] (<= 128) columns, kActorPasses per thread, loads first
     {
         const int kp0 = a.kpad[0];
         const float beta = *a.beta;
-        float v[8];
+        float v[kActorPasses];
         // every load in bounds (clamped row and column, N >= 1) and issued
         // back to back; out-of-range entries are then replaced by 0
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int q = threadIdx.x + 256 * t, r = q >> 7, j = q & 127, e = row0 + r;
+        for (int t = 0; t < kActorPasses; ++t) {
+            const int q = threadIdx.x + kActorThreads * t, r = q >> 7, j = q & 127, e = row0 + r;
             v[t] = a.obs[(int64_t)min(e, a.N - 1) * row + min(j, row - 1)];
         }
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int q = threadIdx.x + 256 * t, r = q >> 7, j = q & 127, e = row0 + r;
+        for (int t = 0; t < kActorPasses; ++t) {
+            const int q = threadIdx.x + kActorThreads * t, r = q >> 7, j = q & 127, e = row0 + r;
             if (!(e < a.N && j < row)) v[t] = 0.0f;
         }
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int q = threadIdx.x + 256 * t, r = q >> 7, j = q & 127;
+        for (int t = 0; t < kActorPasses; ++t) {
+            const int q = threadIdx.x + kActorThreads * t, r = q >> 7, j = q & 127;
             if (j < kp0)
                 cur_in[r * ld + j] =
                     to_bf16_bits(j < a.m && row0 + r < a.N ? 1.0f / (v[t] - beta) : v[t]);
@@ -300,12 +309,14 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
             uint4 *dst = reinterpret_cast<uint4 *>(wl);
             const int rv = kp / 8;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int rw = wr0 + 16 * t;
+            for (int t = 0; t < kActorPasses; ++t) {
+                const int rw = wr0 + kRowStep * t;
                 if (wc < rv && rw < np) dst[rw * (rv + 1) + wc] = t8[t];
             }
         }
-        const float bias_l[2] = {bias[0], bias[1]};
+        float bias_l[kActorBlocks];
+#pragma unroll
+        for (int t = 0; t < kActorBlocks; ++t) bias_l[t] = bias[t];
         __syncthreads();  // inputs and weights in LDS
         if (l + 1 < a.layers) load_layer(l + 1);
         const uint16_t *W = wl;
@@ -315,21 +326,21 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
         // share one LDS round trip; products past K are then skipped.
         const int nkb = kp / 32;  // 1..4
         bf16x8 av[4];             // the rows' input fragments, shared by every column block
-        bf16x8 bv[2][4];          // this wavefront's two column blocks
+        bf16x8 bv[kActorBlocks][4];  // this wavefront's column blocks
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb)
             av[kb] = *reinterpret_cast<const bf16x8 *>(&cur_in[fr * ld + 32 * min(kb, nkb - 1) + fk]);
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int n0 = min(16 * (wave + 4 * t), np - 16);
+        for (int t = 0; t < kActorBlocks; ++t) {
+            const int n0 = min(16 * (wave + kActorWaves * t), np - 16);
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb)
                 bv[t][kb] = *reinterpret_cast<const bf16x8 *>(W + (n0 + fr) * (kp + 8) +
                                                               32 * min(kb, nkb - 1) + fk);
         }
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int n0 = 16 * (wave + 4 * t);
+        for (int t = 0; t < kActorBlocks; ++t) {
+            const int n0 = 16 * (wave + kActorWaves * t);
             if (n0 >= np) break;
             f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -351,7 +362,7 @@ __global__ __launch_bounds__(256) void actor_fused_kernel(ActorArgs a) {
         if (!last) {
             // zero the padding columns [np, kpad[l + 1]) of the next input
             const int kn = a.kpad[l + 1], wpad = kn - np;
-            for (int q = threadIdx.x; q < 16 * wpad; q += 256) {
+            for (int q = threadIdx.x; q < 16 * wpad; q += kActorThreads) {
                 const int r = q / wpad;
                 nxt_in[r * ld + np + (q - r * wpad)] = 0;
             }
@@ -403,7 +414,8 @@ int actor_fused_wmax(int layers, const int *kpad, const int *npad) {
 hipError_t launch_actor_fused(const ActorArgs &a, hipStream_t s) {
     if (a.N <= 0) return hipSuccess;
     const size_t lds = actor_fused_lds_bytes(a.layers, a.kpad, a.npad, a.kmax);
-    hipLaunchKernelGGL(actor_fused_kernel, dim3((unsigned)((a.N + 15) / 16)), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(actor_fused_kernel, dim3((unsigned)((a.N + 15) / 16)), dim3(kActorThreads), lds,
+                       s, a);
     return hipGetLastError();
 }
 
