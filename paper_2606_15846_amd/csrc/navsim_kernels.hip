@@ -573,7 +573,8 @@ __device__ void store_reset(const StepParams &p, int e, uint32_t ep, const Reset
 //   1. stage the map's padded bitmap in LDS;
 //   2. motion: a group of 16 lanes per env (action, kinematics, collision with
 //      the footprint's candidate rows spread over the group, goal features,
-//      reward, flags; for envs that ended, 16 reset attempts at a time);
+//      reward, flags; for envs that ended, start and goal attempts on the
+//      group's lanes, 8 + 8 in the first pass, then 16 of one kind at a time);
 //   3. scan: the tile's pool of rays -- K per new pose and K per reset pose --
 //      is walked by all lanes; a lane that finishes takes the next ray from an
 //      LDS counter, refilled whenever at most refill_at lanes are busy, so the
