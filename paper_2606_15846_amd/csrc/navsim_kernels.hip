@@ -1168,15 +1168,31 @@ __device__ __forceinline__ void walk_groups(const StepParams &p, const uint32_t 
         // the r_max budget do not count
         const int rem = n - k;
         const int f = (int)__builtin_ctz(h | 16u);
-        if (f < rem && f < 4) {
-            B = f == 0 ? B0 : (f == 1 ? B1 : (f == 2 ? B2 : B3));
-            flags = 1u;
-            k += f + 1;
-            act = false;
-            break;
-        }
-        if (rem <= 4) {
-            k = n;
+        const bool hit = f < rem && f < 4;
+        if (BYTES) {
+            if (hit) {
+                B = f == 0 ? B0 : (f == 1 ? B1 : (f == 2 ? B2 : B3));
+                flags = 1u;
+                k += f + 1;
+                act = false;
+                break;
+            }
+            if (rem <= 4) {
+                k = n;
+                act = false;
+                break;
+            }
+        } else if (hit || rem <= 4) {
+            // one exit (a hit, or the budget ends in this group): fewer
+            // instructions per group in the bitmap walk (C4 641 -> 629 us); the
+            // byte walk measured faster with the two exits above (C5 747 vs 754)
+            if (hit) {
+                B = f == 0 ? B0 : (f == 1 ? B1 : (f == 2 ? B2 : B3));
+                flags = 1u;
+                k += f + 1;
+            } else {
+                k = n;
+            }
             act = false;
             break;
         }
