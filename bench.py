@@ -1,14 +1,22 @@
 """Throughput of the batched navigation step on one MI355X.
 
-Workload (default): 4096 envs over 16 seeded 128x128 maps at 0.05 m (rectangles
-and rasterised discs, ~15 % occupancy), disc robot r = 0.18 m, 360 beams over
-360 deg pooled to 30 sectors, r_max 6 m, dt 0.1 s, uniform random actions,
-auto-reset.  Inputs are resident in HBM before the timed region.
+Headline workload (default, the fused-batched configuration): 32768 envs over
+128 seeded maps whose sides are drawn from 96-512 cells at 0.05 m (rectangle +
+disc maps and rooms maps alternating), each map with its own beam count from
+{180, 360, 720, 1080} (pooled to 30 sectors) and its own footprint (disc
+r 0.18 m or 0.70 x 0.31 m rectangle), r_max 8 m, dt 0.05 s, uniform random
+actions with reverse, auto-reset, all envs in one launch per step.  A second
+leg times the 4096-env workload (16 maps 128x128, 360 beams, r_max 6 m).
+
+Before the warm-up an untimed burn-in of several episode horizons runs the
+envs into their steady mix of episode ages, so the timed steps hold the steady
+share of resets (auto-resets inside the step).  Inputs are resident in HBM
+before the timed region.
 
 One step = one navsim_step call over all envs = one launch of the fused step
-kernel (action -> pose -> collision -> reward/flags -> reset draws -> 360-beam
-scan of every new pose and every reset pose -> sector pooling -> observation
-rows).  Prints one JSON line.
+kernel (action -> pose -> collision -> reward/flags -> reset draws -> scan of
+every new pose and every reset pose -> sector pooling -> observation rows).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -24,13 +32,39 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
+NOMINAL_LDS_GBS = 256 * 128 * 2.4  # 256 CUs x 128 B/clk x 2.4 GHz = 78643 GB/s
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9  # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (int32 ops/s)
+SIMDS = 256 * 4
+XCDS = 8
+CLOCK_HZ = 2.4e9
 # the fused step's source: the kernel file and the headers it includes
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2606_15846_amd", "csrc", f)
                for f in ("navsim_kernels.hip", "navsim_internal.hpp", "philox.hpp")]
-PMC_FILE = os.path.join(ROOT, "profiles", "fused_step_c2_hbm_traffic.txt")
-SQ_FILE = os.path.join(ROOT, "profiles", "fused_step_c2_sq_counters.txt")
-VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9  # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (int32 ops/s)
+PROFILES = os.path.join(ROOT, "profiles")
+# the paper's own headline, for context only (another GPU, and the whole
+# training loop rather than the simulator step)
+PAPER_CONTEXT = {
+    "figure": "deployable navigation policy trained in under 20 s of wall-clock",
+    "hardware": "one RTX 5090 (host Ryzen 9 9950X)",
+    "what": "whole off-policy training loop (simulator + policy + learner), 1024 envs, "
+            "1080 beams; not a simulator-step throughput",
+    "source": "Abstract; section 3.4; table 2",
+}
+
+
+def plan_legs(steps: int, warmup: int, plain_steps: int, march_steps: int,
+              march_err_steps: int = 5) -> dict:
+    """Action rows and the [first, last) rows each leg reads.  Every leg
+    starts at the first timed row (the same saved state); the action array
+    holds as many rows as the longest leg needs."""
+    if steps < 1 or warmup < 0 or plain_steps < 0 or march_steps < 0 or march_err_steps < 0:
+        raise ValueError("steps must be >= 1 and the other counts >= 0")
+    legs = {"warmup": (0, warmup), "timed": (warmup, warmup + steps),
+            "replay": (warmup, warmup + steps), "plain": (warmup, warmup + plain_steps),
+            "march": (warmup, warmup + march_steps),
+            "march_error": (warmup, warmup + march_err_steps)}
+    rows = max(b for _, b in legs.values())
+    return {"rows": rows, "legs": legs}
 
 
 def kernel_source_hash() -> str:
@@ -55,21 +89,24 @@ def profile_values(path: str):
     return vals
 
 
-def hbm_traffic_from_profile():
+def hbm_traffic_from_profile(workload: str):
     """HBM bytes per launch from the committed counter summary (or None)."""
-    vals = profile_values(PMC_FILE)
+    vals = profile_values(os.path.join(PROFILES, f"fused_step_{workload}_hbm_traffic.txt"))
     try:
         return float(vals["hbm_bytes_per_launch"]) if vals else None
     except (KeyError, ValueError):
         return None
 
 
-def valu_from_profile(avg_launch_s: float, visits_per_launch: float):
-    """VALU issue of the same launches from the committed SQ counter summary:
-    wave instructions per launch, the share of the SIMDs' VALU issue they fill
-    over the live launch time (4 cycles per wave64 instruction), and lane
-    slots per cell visit; None when absent or stale."""
-    vals = profile_values(SQ_FILE)
+def sq_from_profile(workload: str, avg_launch_s: float, visits_per_launch: float):
+    """VALU issue and occupancy of the same launches from the committed SQ
+    counter summary: wave instructions per launch, the share of the SIMDs'
+    VALU issue they fill over the live launch time (4 cycles per wave64
+    instruction), lane slots per cell visit, LDS bank-conflict cycles per LDS
+    instruction, and resident wavefronts per SIMD (SQ_WAVE_CYCLES counts
+    wave-cycles in units of 4 clocks, summed over the chip, over the busy span
+    GRBM_GUI_ACTIVE / XCDs); None when absent or stale."""
+    vals = profile_values(os.path.join(PROFILES, f"fused_step_{workload}_sq_counters.txt"))
     if not vals:
         return None
     try:
@@ -77,31 +114,141 @@ def valu_from_profile(avg_launch_s: float, visits_per_launch: float):
     except (KeyError, ValueError):
         return None
     lane_ops = insts * 64.0
-    return {"wave_insts_per_launch": insts,
-            "issue_frac": lane_ops / (VALU_LANE_OPS_PEAK * avg_launch_s),
-            "lane_slots_per_visit": lane_ops / max(visits_per_launch, 1.0),
-            "peak_lane_ops_per_s": VALU_LANE_OPS_PEAK}
+    out = {"wave_insts_per_launch": insts,
+           "issue_frac": lane_ops / (VALU_LANE_OPS_PEAK * avg_launch_s),
+           "lane_slots_per_visit": lane_ops / max(visits_per_launch, 1.0),
+           "peak_lane_ops_per_s": VALU_LANE_OPS_PEAK}
+    for k in ("lds_bank_conflict_cycles_per_lds_inst", "waves_per_simd"):
+        if k in vals:
+            out[k] = float(vals[k])
+    return out
 
 
-def cpu_baseline(w, acts, rays_per_env_step: float, target_s: float = 10.0) -> dict:
+def measure_lds_peak(device: int) -> dict:
+    """Conflict-free 16-byte LDS reads over the whole chip (two workgroups of
+    1024 threads per CU, 64 KiB of LDS each): the measured LDS roof."""
+    from paper_2606_15846_amd.navsim import navsim_probe_lds_read
+    best = None
+    for threads, per_cu in ((1024, 2), (512, 2), (256, 2)):
+        ms, nb, _ = navsim_probe_lds_read(device, threads, 256 * per_cu * 8, 2048, 5)
+        gbs = nb / (ms / 1e3) / 1e9
+        row = {"threads": threads, "workgroups": 256 * per_cu * 8, "ms_per_launch": ms,
+               "bytes_per_launch": nb, "gb_per_s": gbs}
+        if best is None or gbs > best["gb_per_s"]:
+            best = row
+    best["bytes_per_clk_per_cu"] = best["gb_per_s"] * 1e9 / (256 * CLOCK_HZ)
+    return best
+
+
+def burn_in(sim, steps: int, seed: int):
+    """Untimed steps under device-drawn uniform actions (seeded), so that the
+    envs' episode ages reach their steady mix."""
+    import torch
+    g = torch.Generator(device=sim.device)
+    g.manual_seed(seed)
+    for _ in range(steps):
+        a = torch.rand((sim.N, 2), generator=g, device=sim.device) * 2.0 - 1.0
+        sim.step(a)
+    torch.cuda.synchronize(sim.device)
+
+
+def time_steps(sim, acts, first: int, count: int, plain: bool = False) -> float:
+    """Milliseconds for `count` back-to-back steps, one HIP event pair on the
+    stream the steps are launched on."""
+    import torch
+    stream = torch.cuda.current_stream(sim.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(sim.device)
+    e0.record(stream)
+    for t in range(count):
+        sim.step(acts[first + t], plain=plain)
+    e1.record(stream)
+    torch.cuda.synchronize(sim.device)
+    return e0.elapsed_time(e1)
+
+
+def replay_work(sim, acts, first: int, count: int, start_state, keep_first: bool):
+    """Replay the timed steps from their saved state with the per-ray outputs
+    on (results are bitwise those of the timed steps): cell visits, resets
+    (start / goal free-list fallbacks) and, optionally, the first step's
+    per-ray results and post-step state on the host."""
+    import torch
+    sim.set_state(start_state)
+    visits = torch.zeros((), dtype=torch.int64, device=sim.device)
+    resets = torch.zeros((), dtype=torch.int64, device=sim.device)
+    fb_start = torch.zeros((), dtype=torch.int64, device=sim.device)
+    fb_goal = torch.zeros((), dtype=torch.int64, device=sim.device)
+    first_step = None
+    for t in range(count):
+        dbg = sim.step_debug(acts[first + t])
+        visits += dbg["visits"].sum()
+        resets += dbg["reset"].sum()
+        fb = dbg["fallback"].to(torch.int64)
+        fb_start += (fb & 1).sum()
+        fb_goal += ((fb >> 1) & 1).sum()
+        if keep_first and t == 0:
+            first_step = {"ranges": dbg["ranges"].cpu().numpy(), "hits": dbg["hits"].cpu().numpy(),
+                          "collision": dbg["collision"].cpu().numpy(),
+                          "obs": sim.obs.cpu().numpy(), "reward": sim.reward.cpu().numpy(),
+                          "terminated": sim.terminated.cpu().numpy(),
+                          "truncated": sim.truncated.cpu().numpy(), "state": sim.get_state()}
+    torch.cuda.synchronize(sim.device)
+    return {"visits": int(visits.item()), "resets": int(resets.item()),
+            "fallback_start": int(fb_start.item()), "fallback_goal": int(fb_goal.item()),
+            "first_step": first_step}
+
+
+def live_beams(w, N, K):
+    """[N, K] mask of the beams each env casts (per-map beam counts)."""
+    if w["profiles"] is None:
+        return np.ones((N, K), bool)
+    kmap = np.array([q["num_beams"] for q in w["profiles"]])
+    kenv = kmap[np.asarray(w["env_map"])]
+    return np.arange(K)[None, :] < kenv[:, None]
+
+
+def cpu_baseline(w, acts_np, start_state, gpu_first, rays_per_env_step: float,
+                 target_s: float = 15.0) -> dict:
+    """The oracle on the machine's host cores, from the same steady state under
+    the same actions: its first step (with per-ray outputs) is compared with
+    the GPU's first timed step over every env -- a full-size parity sample
+    that also counts grazing rays -- then steps are timed for ~target_s."""
     import oracle
-    threads = min(len(os.sched_getaffinity(0)), 16)
+    threads = len(os.sched_getaffinity(0))
     ref = oracle.OracleSim(w["cfg"], w["maps"], w["res"], w["env_map"], profiles=w["profiles"])
-    ref.reset(threads=threads)
+    ref.set_state(start_state)
     N = ref.N
     t0 = time.perf_counter()
-    ref.step(acts[0], debug=False, threads=threads)
+    o = ref.step(acts_np[0], debug=True, threads=threads)
     one = time.perf_counter() - t0
-    steps = int(max(1, min(acts.shape[0] - 1, target_s / max(one, 1e-6))))
+    parity = None
+    if gpu_first is not None:
+        live = live_beams(w, N, ref.K)
+        graze = o["grazing"].astype(bool) & live
+        exact = live & ~graze
+        dr = np.abs(gpu_first["ranges"] - o["ranges"])[exact]
+        st_ok = all(np.array_equal(gpu_first["state"][k], ref.state[k]) for k in oracle.STATE_KEYS)
+        parity = {"envs": N, "rays": int(live.sum()), "grazing_rays": int(graze.sum()),
+                  "grazing_frac": float(graze.sum() / max(live.sum(), 1)),
+                  "hit_mismatch_nongrazing": int((gpu_first["hits"] != o["hits"])[exact].sum()),
+                  "max_range_err_nongrazing_m": float(dr.max()) if dr.size else 0.0,
+                  "collision_equal": bool(np.array_equal(gpu_first["collision"], o["collision"])),
+                  "flags_equal": bool(np.array_equal(gpu_first["terminated"], o["terminated"]) and
+                                      np.array_equal(gpu_first["truncated"], o["truncated"])),
+                  "max_reward_err": float(np.abs(gpu_first["reward"] - o["reward"]).max()),
+                  "post_step_state_bitwise": bool(st_ok)}
+    steps = int(max(1, min(200, target_s / max(one, 1e-6))))
     t0 = time.perf_counter()
     for t in range(1, 1 + steps):
-        ref.step(acts[t], debug=False, threads=threads)
+        ref.step(acts_np[t % acts_np.shape[0]], debug=False, threads=threads)
     dt = time.perf_counter() - t0
     rate = N * steps / dt
-    return {"value": rate, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+    return {"value": rate, "unit": "env-steps/s", "cores": threads,
+            "host_cpu_count": os.cpu_count(), "kind": "oracle",
             "rays_per_s": rate * rays_per_env_step,
-            "sample": f"{steps} steps x {N} envs of the same workload (scalar FP64 C oracle, "
-                      f"{threads} threads over env slices), {dt:.1f} s"}
+            "sample": f"{steps} steps x {N} envs of the same workload from the same steady state "
+                      f"(scalar FP64 C oracle, {threads} threads over env slices), {dt:.1f} s",
+            "parity_sample": parity}
 
 
 def reset_proposal_gain(sim, w, args) -> dict:
@@ -169,17 +316,210 @@ def reset_proposal_gain(sim, w, args) -> dict:
     return out
 
 
+def tuning_for(w, args) -> tuple[dict, bool]:
+    """The autotuned launch shape of the workload (paper_2606_15846_amd/
+    tuning.json) with command-line overrides; results do not depend on it.
+    Also whether it is the tuned shape (the one the committed counters cover)."""
+    from paper_2606_15846_amd import autotune
+    tuned = autotune.best_for(autotune.workload_key(w["cfg"], w["maps"], w["profiles"]))
+    tuning = dict(tuned)
+    for k in autotune.FIELDS:
+        if getattr(args, k, None) is not None:
+            tuning[k] = getattr(args, k)
+    return tuning, tuning == tuned
+
+
+def roofline(workload: str, visits: int, steps: int, ms_per_step: float, lds_peak, profiled):
+    lds_bytes_per_launch = 4.0 * visits / steps
+    # one launch per step, back to back: the timed region's time per step is
+    # the launch's duration plus the dispatch gap (the roofline's denominator)
+    avg_launch_s = ms_per_step / 1e3
+    achieved = lds_bytes_per_launch / avg_launch_s / 1e9
+    out = {"bound": "lds", "achieved": achieved, "peak": NOMINAL_LDS_GBS, "unit": "GB/s",
+           "frac": achieved / NOMINAL_LDS_GBS,
+           "traffic": hbm_traffic_from_profile(workload) if profiled else None,
+           "kernel": "fused_step_kernel", "avg_launch_us": avg_launch_s * 1e6,
+           "algorithmic_bytes_per_launch": lds_bytes_per_launch,
+           "bytes_per_unit": "4 B of bitmap word per grid-cell visit of the step's pre-reset scan",
+           "peak_nominal": NOMINAL_LDS_GBS,
+           "valu": sq_from_profile(workload, avg_launch_s, visits / steps) if profiled else None}
+    if lds_peak:
+        out["peak_measured"] = lds_peak["gb_per_s"]
+        out["frac_measured"] = achieved / lds_peak["gb_per_s"]
+    return out
+
+
+def run_fused_leg(name: str, args, steps: int, warmup: int, lds_peak, full: bool) -> dict:
+    """Build the workload, burn in, warm up, time `steps` fused steps and
+    count their work.  With full=True also the march, rollout, policy, plain,
+    proposal and CPU legs (the headline)."""
+    import torch
+    from paper_2606_15846_amd.navsim import NavSim
+    from workloads import configs
+
+    dev = torch.device("cuda", 0)
+    w = configs.build_workload(name)
+    cfg = w["cfg"]
+    N, K, m = cfg["num_envs"], cfg["num_beams"], cfg["num_sectors"]
+    live = live_beams(w, N, K)
+    rays_per_step = int(live.sum())
+    plan = plan_legs(steps, warmup, args.plain_steps if full and not args.no_plain else 0,
+                     min(steps, 200) if full and not args.no_march else 0,
+                     5 if full and not args.no_march else 0)
+    legs = plan["legs"]
+    acts_np = configs.uniform_actions(plan["rows"], N, seed=42)
+    acts = torch.from_numpy(acts_np).to(dev)
+    sim = NavSim(cfg, w["maps"], w["res"], w["env_map"], device=0, profiles=w["profiles"])
+    tuning, profiled = tuning_for(w, args) if full else tuning_for(w, argparse.Namespace())
+    sim.set_tuning(**tuning)
+    sim.reset()
+    t_burn = time.perf_counter()
+    burn_in(sim, args.burn_in, seed=4242)
+    t_burn = time.perf_counter() - t_burn
+    for t in range(*legs["warmup"]):
+        sim.step(acts[t])
+    torch.cuda.synchronize()
+    start_state = sim.get_state()
+    total_ms = time_steps(sim, acts, legs["timed"][0], steps)
+    ms_per_step = total_ms / steps
+    value = N * steps / (total_ms / 1e3)
+    work = replay_work(sim, acts, legs["replay"][0], steps, start_state,
+                       keep_first=full and not args.no_cpu)
+    out = {"workload": w["name"], "value": value, "unit": "env-steps/s", "steps": steps,
+           "warmup": warmup, "burn_in_steps": args.burn_in, "burn_in_s": t_burn,
+           "ms_per_step": ms_per_step, "rays_per_s": value * rays_per_step / N,
+           "beams_per_env_step": rays_per_step / N,
+           "reset_rate_per_step": work["resets"] / (N * steps),
+           "resets": work["resets"], "fallback_start": work["fallback_start"],
+           "fallback_goal": work["fallback_goal"],
+           "extra_rays_per_s": work["resets"] * (rays_per_step / N) / (total_ms / 1e3),
+           "cell_visits_per_env_step": work["visits"] / (N * steps),
+           "roofline": roofline(name, work["visits"], steps, ms_per_step, lds_peak, profiled),
+           "tuning": sim.get_tuning()}
+    if not full:
+        sim.close()
+        return out
+    stream = torch.cuda.current_stream(dev)
+
+    # the paper's fixed-step range query (0.03 m) on the same fused step
+    if not args.no_march:
+        a0, a1 = legs["march"]
+        sim.set_state(start_state)
+        sim.set_scan(1, args.march_step)
+        for t in range(a0, min(a1, a0 + 5)):
+            sim.step(acts[t])
+        sim.set_state(start_state)
+        mms = time_steps(sim, acts, a0, a1 - a0) / (a1 - a0)
+        # its error against the exact traversal: the same states and actions
+        # (poses, collisions and resets do not depend on the scan)
+        live_d = torch.from_numpy(live).to(dev)
+        e0_, e1_ = legs["march_error"]
+        stride = max(1, (5 * N * K) // 4_000_000)  # a bounded sample for the quantile
+        sim.set_state(start_state)
+        d_ray, d_sec = [], []
+        for t in range(e0_, e1_):
+            s0 = sim.get_state()
+            rm = sim.step_debug(acts[t])["ranges"].clone()
+            om = sim.obs[:, :m].clone()
+            sim.set_scan(0, 0.03)
+            sim.set_state(s0)
+            re = sim.step_debug(acts[t])["ranges"].clone()
+            oe = sim.obs[:, :m].clone()
+            d_ray.append((rm - re).abs()[live_d][::stride].cpu())
+            d_sec.append((om - oe).abs().flatten().cpu())
+            sim.set_scan(1, args.march_step)
+        sim.set_scan(0, 0.03)
+        d_ray, d_sec = torch.cat(d_ray).double(), torch.cat(d_sec).double()
+        cell = float(np.min(w["res"]))
+        out["march_scan"] = {
+            "value": N / (mms / 1e3), "unit": "env-steps/s", "ms_per_step": mms,
+            "steps": a1 - a0, "step_m": args.march_step, "traversal_speedup": mms / ms_per_step,
+            "error_vs_traversal": {
+                "rays": int(d_ray.numel()), "mean_abs_m": float(d_ray.mean()),
+                "p99_abs_m": float(d_ray.quantile(0.99)), "max_abs_m": float(d_ray.max()),
+                "rays_off_by_more_than_a_cell": float((d_ray > cell).double().mean()),
+                "sector_min_mean_abs_m": float(d_sec.mean()),
+                "sector_min_max_abs_m": float(d_sec.max())}}
+
+    # device rollouts: the same fused step under in-kernel actions, T steps
+    # captured once as a HIP graph and replayed
+    sim.set_state(start_state)
+    T = args.rollout_steps
+    bufs = sim.rollout_buffers(T, final_obs=True)
+    sim.rollout(T, first_step=0, buffers=bufs, graph=True)  # capture + warm
+    torch.cuda.synchronize()
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(1, steps // T)
+    r0.record(stream)
+    for r in range(reps):
+        sim.rollout(T, first_step=(r + 1) * T, buffers=bufs, graph=True)
+    r1.record(stream)
+    torch.cuda.synchronize()
+    rms = r0.elapsed_time(r1)
+    out["graph_rollout"] = {"value": N * T * reps / (rms / 1e3), "unit": "env-steps/s",
+                            "steps_per_rollout": T, "rollouts": reps,
+                            "ms_per_step": rms / (T * reps),
+                            "actions": "in-kernel Philox stream 4",
+                            "launch": "HIP graph of T fused steps"}
+    # the paper's actor in front of every step (graph of T actor + step launches)
+    if not args.no_policy:
+        from paper_2606_15846_amd.policy import Policy
+        pol = Policy(sim)
+        pol.init_params(seed=3, beta=-0.1)
+        sim.set_state(start_state)
+        obs0 = sim.obs.clone()
+        pol.rollout(T, 0, obs0, noise_std=0.1, buffers=bufs)  # capture + warm
+        torch.cuda.synchronize()
+        q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        q0.record(stream)
+        for r in range(reps):
+            pol.rollout(T, (r + 1) * T, obs0, noise_std=0.1, buffers=bufs)
+        q1.record(stream)
+        torch.cuda.synchronize()
+        qms = q0.elapsed_time(q1)
+        out["policy_rollout"] = {"value": N * T * reps / (qms / 1e3), "unit": "env-steps/s",
+                                 "ms_per_step": qms / (T * reps), "steps_per_rollout": T,
+                                 "actor": f"{pol.dims} leaky ReLU, tanh, bf16 matrix cores",
+                                 "launch": "HIP graph of T (actor + fused step)"}
+        pol.close()
+    del bufs
+
+    if not args.no_plain:
+        a0, a1 = legs["plain"]
+        sim.set_state(start_state)
+        pms = time_steps(sim, acts, a0, a1 - a0, plain=True)
+        prate = N * (a1 - a0) / (pms / 1e3)
+        out["plain"] = {"value": prate, "rays_per_s": prate * rays_per_step / N,
+                        "steps": a1 - a0, "ms_per_step": pms / (a1 - a0),
+                        "mapping": "one thread per env, beams in sequence, bitmap in HBM"}
+        out["speedup_vs_plain"] = value / prate
+    if w.get("proposer") and not args.no_proposal:
+        out["reset_proposal"] = reset_proposal_gain(sim, w, args)
+    sim.close()
+    if not args.no_cpu:
+        a0, a1 = legs["timed"]
+        out["cpu_baseline"] = cpu_baseline(w, acts_np[a0:], start_state, work["first_step"],
+                                           rays_per_step / N)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--secondary", default="c2",
+                    help="a second workload timed the same way ('' for none)")
+    ap.add_argument("--secondary-steps", type=int, default=1000)
+    ap.add_argument("--burn-in", type=int, default=1000,
+                    help="untimed steps before the warm-up (several 200-step horizons)")
     ap.add_argument("--plain-steps", type=int, default=50)
     ap.add_argument("--rollout-steps", type=int, default=64)
     ap.add_argument("--no-march", action="store_true")
     ap.add_argument("--no-proposal", action="store_true")
     ap.add_argument("--no-policy", action="store_true")
+    ap.add_argument("--no-lds-peak", action="store_true")
     ap.add_argument("--label-starts", type=int, default=131072)
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--proposal-requests", type=int, default=8192)
@@ -215,226 +555,57 @@ def main():
                           "copy_bytes_written_per_launch": b.numel() * 4, "launches": 5}))
         return
 
-    from paper_2606_15846_amd.navsim import NAVSIM_KERNEL_FUSED, NavSim
+    lds_peak = None if args.no_lds_peak else measure_lds_peak(0)
+    head = run_fused_leg(args.workload, args, args.steps, args.warmup, lds_peak, full=True)
+    second = None
+    if args.secondary and args.secondary != args.workload:
+        second = run_fused_leg(args.secondary, args, args.secondary_steps, args.warmup, lds_peak,
+                               full=False)
     from workloads import configs
-
-    dev = torch.device("cuda", 0)
     w = configs.build_workload(args.workload)
     cfg = w["cfg"]
-    N, K, m = cfg["num_envs"], cfg["num_beams"], cfg["num_sectors"]
-    # beams cast per step (per-map beam counts when the workload has profiles)
-    if w["profiles"] is None:
-        rays_per_step = N * K
-    else:
-        kmap = np.array([q["num_beams"] for q in w["profiles"]], dtype=np.int64)
-        rays_per_step = int(kmap[np.asarray(w["env_map"])].sum())
-    total = args.warmup + args.steps
-    acts_np = configs.uniform_actions(total, N, seed=42)
-    acts = torch.from_numpy(acts_np).to(dev)
-    sim = NavSim(cfg, w["maps"], w["res"], w["env_map"], device=0, profiles=w["profiles"])
-    # launch shape: the autotuned one for this workload (paper_2606_15846_amd/
-    # tuning.json) unless given on the command line; results do not depend on it
-    from paper_2606_15846_amd import autotune
-    tuning = autotune.best_for(autotune.workload_key(cfg, w["maps"], w["profiles"]))
-    tuned = dict(tuning)
-    for k in ("tile_envs", "refill_at", "groups", "ray_slots", "walk", "persist", "threads",
-              "balance"):
-        if getattr(args, k) is not None:
-            tuning[k] = getattr(args, k)
-    # the committed counter summaries cover the default workload in its tuned shape
-    profiled = args.workload == "c2" and tuning == tuned
-    sim.set_tuning(**tuning)
-    sim.reset()
-    for t in range(args.warmup):
-        sim.step(acts[t])
-    torch.cuda.synchronize()
-    start_state = sim.get_state()
-    stream = torch.cuda.current_stream(dev)
-    resets = torch.zeros((), dtype=torch.int64, device=dev)
-    # the timed steps: back to back, one event pair around all of them
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for t in range(args.steps):
-        sim.step(acts[args.warmup + t])
-    e1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
-    ms_per_step = total_ms / args.steps
-    value = N * args.steps / (total_ms / 1e3)
-
-    # algorithmic work of the timed steps: replay them with the per-ray visit
-    # counts switched on (same state, same actions, results are bitwise equal)
-    sim.set_state(start_state)
-    visits = 0
-    for t in range(args.steps):
-        dbg = sim.step_debug(acts[args.warmup + t], kernel=NAVSIM_KERNEL_FUSED)
-        visits += int(dbg["visits"].sum().item())
-        resets += dbg["reset"].sum()
-    reset_rate = float(resets.item()) / (N * args.steps)
-    lds_bytes_per_launch = 4.0 * visits / args.steps
-    # one launch per step, back to back: the timed region's time per step is
-    # the launch's duration plus the dispatch gap (the roofline's denominator)
-    avg_launch_s = ms_per_step / 1e3
-    achieved = lds_bytes_per_launch / avg_launch_s / 1e9
-    traffic = hbm_traffic_from_profile() if profiled else None
-    valu = valu_from_profile(avg_launch_s, visits / args.steps) if profiled else None
-
-    # the paper's fixed-step range query (0.03 m) on the same fused step
-    march = None
-    if not args.no_march:
-        sim.set_state(start_state)
-        sim.set_scan(1, args.march_step)
-        for t in range(5):
-            sim.step(acts[args.warmup + t])
-        sim.set_state(start_state)
-        torch.cuda.synchronize()
-        m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        msteps = min(args.steps, 200)
-        m0.record(stream)
-        for t in range(msteps):
-            sim.step(acts[args.warmup + t])
-        m1.record(stream)
-        torch.cuda.synchronize()
-        mms = m0.elapsed_time(m1) / msteps
-        # its error against the exact traversal: the same states and actions
-        # (poses, collisions and resets do not depend on the scan), 5 steps
-        if w["profiles"] is None:
-            live = torch.ones(N, K, dtype=torch.bool, device=dev)
-        else:  # beams past an env's own count are not cast
-            kenv = torch.tensor([q["num_beams"] for q in w["profiles"]], device=dev)[
-                torch.as_tensor(np.asarray(w["env_map"]), device=dev).long()]
-            live = torch.arange(K, device=dev)[None, :] < kenv[:, None]
-        stride = max(1, (5 * N * K) // 4_000_000)  # a bounded sample for the quantile
-        sim.set_state(start_state)
-        d_ray, d_sec = [], []
-        for t in range(5):
-            s0 = sim.get_state()
-            rm = sim.step_debug(acts[args.warmup + t])["ranges"].clone()
-            om = sim.obs[:, :m].clone()
-            sim.set_scan(0, 0.03)
-            sim.set_state(s0)
-            re = sim.step_debug(acts[args.warmup + t])["ranges"].clone()
-            oe = sim.obs[:, :m].clone()
-            d_ray.append((rm - re).abs()[live][::stride].cpu())
-            d_sec.append((om - oe).abs().flatten().cpu())
-            sim.set_scan(1, args.march_step)
-        sim.set_scan(0, 0.03)
-        d_ray, d_sec = torch.cat(d_ray).double(), torch.cat(d_sec).double()
-        cell = float(np.min(w["res"]))
-        march_err = {"rays": int(d_ray.numel()),
-                     "mean_abs_m": float(d_ray.mean()), "p99_abs_m": float(d_ray.quantile(0.99)),
-                     "max_abs_m": float(d_ray.max()),
-                     "rays_off_by_more_than_a_cell": float((d_ray > cell).double().mean()),
-                     "sector_min_mean_abs_m": float(d_sec.mean()),
-                     "sector_min_max_abs_m": float(d_sec.max())}
-        march = {"value": N / (mms / 1e3), "unit": "env-steps/s", "ms_per_step": mms,
-                 "steps": msteps, "step_m": args.march_step,
-                 "traversal_speedup": mms / ms_per_step, "error_vs_traversal": march_err}
-
-    # device rollouts: the same fused step under in-kernel actions, T steps
-    # captured once as a HIP graph and replayed
-    sim.set_state(start_state)
-    T = args.rollout_steps
-    bufs = sim.rollout_buffers(T, final_obs=True)
-    sim.rollout(T, first_step=0, buffers=bufs, graph=True)  # capture + warm
-    torch.cuda.synchronize()
-    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = max(1, args.steps // T)
-    r0.record(stream)
-    for r in range(reps):
-        sim.rollout(T, first_step=(r + 1) * T, buffers=bufs, graph=True)
-    r1.record(stream)
-    torch.cuda.synchronize()
-    rms = r0.elapsed_time(r1)
-    rollout = {"value": N * T * reps / (rms / 1e3), "unit": "env-steps/s",
-               "steps_per_rollout": T, "rollouts": reps, "ms_per_step": rms / (T * reps),
-               "actions": "in-kernel Philox stream 4", "launch": "HIP graph of T fused steps"}
-    # the paper's actor in front of every step (graph of T actor + step launches)
-    policy = None
-    if not args.no_policy:
-        from paper_2606_15846_amd.policy import Policy
-        pol = Policy(sim)
-        pol.init_params(seed=3, beta=-0.1)
-        sim.set_state(start_state)
-        obs0 = sim.obs.clone()
-        pol.rollout(T, 0, obs0, noise_std=0.1, buffers=bufs)  # capture + warm
-        torch.cuda.synchronize()
-        q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        q0.record(stream)
-        for r in range(reps):
-            pol.rollout(T, (r + 1) * T, obs0, noise_std=0.1, buffers=bufs)
-        q1.record(stream)
-        torch.cuda.synchronize()
-        qms = q0.elapsed_time(q1)
-        policy = {"value": N * T * reps / (qms / 1e3), "unit": "env-steps/s",
-                  "ms_per_step": qms / (T * reps), "steps_per_rollout": T,
-                  "actor": f"{pol.dims} leaky ReLU, tanh, bf16 matrix cores",
-                  "launch": "HIP graph of T (actor + fused step)"}
-        pol.close()
-    del bufs
-
-    plain = None
-    if not args.no_plain:
-        sim.set_state(start_state)
-        torch.cuda.synchronize()
-        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        p0.record(stream)
-        for t in range(args.plain_steps):
-            sim.step(acts[args.warmup + t], plain=True)
-        p1.record(stream)
-        torch.cuda.synchronize()
-        pms = p0.elapsed_time(p1)
-        prate = N * args.plain_steps / (pms / 1e3)
-        plain = {"value": prate, "rays_per_s": prate * rays_per_step / N, "steps": args.plain_steps,
-                 "ms_per_step": pms / args.plain_steps,
-                 "mapping": "one thread per env, beams in sequence, bitmap in HBM"}
-    sim_tuning = sim.get_tuning()
-    proposal = None
-    if w.get("proposer") and not args.no_proposal:
-        proposal = reset_proposal_gain(sim, w, args)
-    sim.close()
-
-    cpu = None if args.no_cpu else cpu_baseline(w, acts_np[args.warmup:], rays_per_step / N)
     out = {
         "metric": "env-steps/s + rays/s on 1 MI355X, fused-batched vs plain step; % LDS roofline",
-        "value": value,
+        "value": head["value"],
         "unit": "env-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32+f64",
         "data": "synthetic",
-        "config": {"workload": w["name"], "envs": N, "sectors": m, "maps": len(w["maps"]),
-                   "beams": K if w["profiles"] is None else "per map",
-                   "beams_per_env_step": rays_per_step / N,
+        "config": {"workload": head["workload"], "envs": cfg["num_envs"],
+                   "sectors": cfg["num_sectors"], "maps": len(w["maps"]),
+                   "beams": cfg["num_beams"] if w["profiles"] is None else "per map",
+                   "beams_per_env_step": head["beams_per_env_step"],
                    "map_cells": (f"{w['maps'][0].shape[1]}x{w['maps'][0].shape[0]}"
                                  if w["profiles"] is None else "per map"),
                    "res_m": w["res"][0], "max_range_m": cfg["max_range_m"],
                    "footprint": ("per map" if w["profiles"] is not None
-                                 else "disc" if cfg["footprint"] == 0 else "rect")},
-        "rays_per_s": value * rays_per_step / N,
-        "graph_rollout": rollout,
-        "policy_rollout": policy,
-        "march_scan": march,
-        "reset_proposal": proposal,
-        "plain": plain,
-        "speedup_vs_plain": (value / plain["value"]) if plain else None,
-        "tuning": sim_tuning,
-        "reset_rate_per_step": reset_rate,
-        "cell_visits_per_env_step": visits / (N * args.steps),
-        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": traffic,
-                     "kernel": "fused_step_kernel",
-                     "avg_launch_us": avg_launch_s * 1e6,
-                     "algorithmic_bytes_per_launch": lds_bytes_per_launch,
-                     "bytes_per_unit": "4 B of bitmap word per DDA cell visit of the step's pre-reset scan",
-                     "valu": valu},
-        "cpu_baseline": cpu,
+                                 else "disc" if cfg["footprint"] == 0 else "rect"),
+                   "launch": "one fused launch per step over all envs and maps"},
+        "rays_per_s": head["rays_per_s"],
+        "roofline": head["roofline"],
+        "cpu_baseline": head.get("cpu_baseline"),
+        "plain": head.get("plain"),
+        "speedup_vs_plain": head.get("speedup_vs_plain"),
+        "reset_rate_per_step": head["reset_rate_per_step"],
+        "resets": {"count": head["resets"], "fallback_start": head["fallback_start"],
+                   "fallback_goal": head["fallback_goal"],
+                   "extra_rays_per_s": head["extra_rays_per_s"]},
+        "burn_in_steps": head["burn_in_steps"],
+        "cell_visits_per_env_step": head["cell_visits_per_env_step"],
+        "graph_rollout": head.get("graph_rollout"),
+        "policy_rollout": head.get("policy_rollout"),
+        "march_scan": head.get("march_scan"),
+        "reset_proposal": head.get("reset_proposal"),
+        "tuning": head["tuning"],
+        "lds_peak_probe": lds_peak,
+        "secondary": second,
+        "paper_context": PAPER_CONTEXT,
     }
     print(json.dumps(out))
 

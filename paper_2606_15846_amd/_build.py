@@ -2,18 +2,21 @@
 
 Flags: -ffp-contract=off keeps the per-env double-precision arithmetic in its
 written order (no fused multiply-add); packed FP32 instructions are disabled.
+Each source is compiled to its own object in parallel, then linked.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnavsim.so")
 SOURCES = ["navsim_kernels.hip", "navsim_api.cpp", "mlp_kernels.hip", "reach_kernels.hip",
-           "reset_proposal.cpp", "policy.cpp"]
+           "reset_proposal.cpp", "policy.cpp", "lds_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
@@ -24,9 +27,22 @@ def hipcc_flags() -> list[str]:
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    cmd = [HIPCC, *hipcc_flags(), *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
 def build(verbose: bool = False) -> str:
-    cmd = [HIPCC, *hipcc_flags(), "-shared", "-o", LIB + ".tmp",
-           *[os.path.join(CSRC, s) for s in SOURCES]]
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = min(len(SOURCES), max(1, len(os.sched_getaffinity(0))))
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

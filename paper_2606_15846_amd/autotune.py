@@ -59,15 +59,23 @@ def best_for(key: str) -> dict:
     return best
 
 
-def save(key: str, best: dict, table: list, device_name: str, path: str = TUNING_FILE):
-    """Merge one workload's result into the JSON file at `path`."""
+def save(key: str, best: dict, table: list, device_name: str, path: str = TUNING_FILE,
+         table_path: str | None = None):
+    """Merge one workload's best shape into the JSON file at `path` (the
+    product keeps only the winner); the whole sweep goes to `table_path`."""
     allt = {}
     if os.path.exists(path):
         with open(path) as f:
             allt = json.load(f)
-    allt[key] = {"best": best, "device": device_name, "table": table}
+    ok = [r for r in table if "ms_per_step" in r]
+    allt[key] = {"best": best, "device": device_name,
+                 "ms_per_step": min(r["ms_per_step"] for r in ok), "candidates": len(table)}
     with open(path, "w") as f:
         json.dump(allt, f, indent=1, sort_keys=True)
+    if table_path:
+        os.makedirs(os.path.dirname(os.path.abspath(table_path)), exist_ok=True)
+        with open(table_path, "w") as f:
+            json.dump({"key": key, "device": device_name, "table": table}, f, indent=1)
 
 
 def time_steps(sim, acts, start_state, steps: int) -> float:
@@ -118,6 +126,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--out", default=TUNING_FILE, help="JSON file the result is merged into")
+    ap.add_argument("--table-out", default=None,
+                    help="JSON file for the whole sweep table (not kept in the product)")
     ap.add_argument("--full-space", action="store_true")
     args = ap.parse_args()
     w = configs.build_workload(args.workload)
@@ -131,7 +141,7 @@ def main():
     best, table = tune(sim, acts[20:], steps=args.steps, verbose=True,
                        space=FULL_SPACE if args.full_space else SPACE)
     key = workload_key(cfg, w["maps"], w["profiles"])
-    save(key, best, table, torch.cuda.get_device_name(0), args.out)
+    save(key, best, table, torch.cuda.get_device_name(0), args.out, args.table_out)
     print(json.dumps({"key": key, "best": best}))
     sim.close()
 

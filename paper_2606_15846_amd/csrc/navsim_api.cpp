@@ -617,6 +617,16 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
             return fail(NAVSIM_E_INVALID_ARG, "map %d: size %dx%d out of range", k, width[k],
                         height[k]);
         if (!finite_pos(res_m[k])) return fail(NAVSIM_E_INVALID_ARG, "map %d: res must be > 0", k);
+        {
+            const navsim_map_profile &q = prof[k];
+            const double rc = circumradius(q.footprint, q.radius_m, q.length_m, q.width_m);
+            const double win = floor(2.0 * rc / (double)res_m[k]) + 2.0;
+            if (win > (double)kMaxFootprintCells)
+                return fail(NAVSIM_E_UNSUPPORTED,
+                            "map %d: the footprint's candidate window, %.0f cells per side "
+                            "(circumscribed radius %.4f m at %.4f m cells), exceeds %d", k, win,
+                            rc, (double)res_m[k], kMaxFootprintCells);
+        }
         const int64_t wpr = (width[k] + 2 * kPad + 31) / 32;
         if (wpr * (int64_t)(height[k] + 2 * kPad) > kMaxMapWords)
             return fail(NAVSIM_E_UNSUPPORTED,

@@ -18,6 +18,11 @@ namespace navsim {
 constexpr int kPad = 4;
 constexpr int kMaxMapWords = 12288;  // largest padded bitmap staged in LDS (48 KiB)
 constexpr int kMaxBeams = 4096;
+// Largest footprint window, in cells per side: floor(2 rc / s) + 2 for the
+// circumscribed radius rc at cell size s bounds the candidate cells of the
+// disc, of every heading of the rectangle and of the goal disc.  Maps whose
+// profile exceeds it are rejected at load.
+constexpr int kMaxFootprintCells = 128;
 // Default launch shape of the fused step (a good choice on every workload
 // measured; the autotuner refines it per workload)
 constexpr int kDefaultTileEnvs = 8;   // envs per fused workgroup

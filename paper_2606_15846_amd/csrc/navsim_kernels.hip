@@ -165,8 +165,10 @@ __device__ __forceinline__ CellRange cells_around(double x, double y, double ex,
     r.j0 = clamp_cell(floor((y - ey) / s));
     const int i1 = clamp_cell(floor((x + ex) / s));
     const int j1 = clamp_cell(floor((y + ey) / s));
-    r.nx = min(max(i1 - r.i0 + 1, 0), 64);
-    r.ny = min(max(j1 - r.j0 + 1, 0), 64);
+    // at most floor(2 ex / s) + 2 <= kMaxFootprintCells + 1 for a finite pose
+    // (checked at load); the bound only stops runaway windows of garbage
+    r.nx = min(max(i1 - r.i0 + 1, 0), 2 * kMaxFootprintCells);
+    r.ny = min(max(j1 - r.j0 + 1, 0), 2 * kMaxFootprintCells);
     return r;
 }
 

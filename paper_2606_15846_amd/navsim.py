@@ -31,6 +31,7 @@ EXPORTS = ("navsim_create", "navsim_load_maps", "navsim_load_maps_ex", "navsim_r
            "navsim_set_tuning",
            "navsim_get_tuning",
            "navsim_get_state", "navsim_set_state", "navsim_destroy", "navsim_last_error")
+PROBE_EXPORTS = ("navsim_probe_lds_read",)  # include/navsim_probe.h
 STATE_KEYS = ("x", "y", "th", "v", "w", "gx", "gy", "dprev", "t", "ep")
 _STATE_DT = (np.float32,) * 8 + (np.int32, np.uint32)
 
@@ -99,11 +100,25 @@ def load_library(path: str = LIB_PATH):
     L.navsim_set_state.argtypes = [vp, vp, C.c_size_t, vp]
     L.navsim_destroy.argtypes = [vp]
     L.navsim_last_error.restype = C.c_char_p
-    for name in EXPORTS:
+    L.navsim_probe_lds_read.argtypes = [C.c_int, i32, i32, i32, i32, vp,
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    for name in EXPORTS + PROBE_EXPORTS:
         if name != "navsim_last_error":
             getattr(L, name).restype = C.c_int
     _LIB = L
     return L
+
+
+def navsim_probe_lds_read(hip_device: int, threads: int, blocks: int, iters: int,
+                          launches: int, want_words: bool = False):
+    """LDS read bandwidth (include/navsim_probe.h): returns (ms per launch,
+    bytes per launch, the stored words of the last launch or None)."""
+    out = np.zeros(blocks * threads, np.uint32) if want_words else None
+    ms, nb = C.c_double(), C.c_double()
+    _check(load_library().navsim_probe_lds_read(
+        int(hip_device), int(threads), int(blocks), int(iters), int(launches),
+        None if out is None else out.ctypes.data_as(C.c_void_p), C.byref(ms), C.byref(nb)))
+    return ms.value, nb.value, out
 
 
 def navsim_last_error() -> str:

@@ -28,11 +28,12 @@ def declared_functions():
 def test_library_exports_every_declared_function():
     lib = navsim.load_library()
     names = declared_functions()
-    assert len(names) == 33
+    assert len(names) == 34
     for n in names:
         assert hasattr(lib, n), n
     from paper_2606_15846_amd import policy, reset_proposal
-    assert sorted(navsim.EXPORTS + reset_proposal.EXPORTS + policy.EXPORTS) == names
+    assert sorted(navsim.EXPORTS + navsim.PROBE_EXPORTS + reset_proposal.EXPORTS +
+                  policy.EXPORTS) == names
 
 
 def test_struct_layout_matches_header(tmp_path):
@@ -128,6 +129,16 @@ def test_abi_version_and_null_arguments():
                                                None, None, None, 0, 1, None)),
                      ("navsim_policy_destroy", (None,))]:
         assert getattr(lib, fn)(*args) == -2, fn
+
+
+@pytest.mark.parametrize("args", [(0, 128, 1, 1, 1), (0, 256, 0, 1, 1), (0, 256, 1, 0, 1),
+                                  (0, 256, 1, 1, 0), (0, 256, 1, 1, 1001)])
+def test_lds_probe_validation_before_any_device_call(args):
+    lib = navsim.load_library()
+    ms, nb = C.c_double(), C.c_double()
+    assert lib.navsim_probe_lds_read(*args, None, C.byref(ms), C.byref(nb)) == -1
+    assert "navsim_probe_lds_read" in navsim.navsim_last_error()
+    assert lib.navsim_probe_lds_read(0, 256, 1, 1, 1, None, None, C.byref(nb)) == -1
 
 
 def test_map_profile_layout_matches_header(tmp_path):

@@ -576,3 +576,27 @@ def test_pooled_obs_same_with_and_without_per_ray_outputs(wl):
             s2 = sim.get_state()
             assert all(np.array_equal(s1[k], s2[k]) for k in oracle.STATE_KEYS)
         sim.close()
+
+
+@pytest.mark.parametrize("kname", ["fused", "plain"])
+def test_go2_rectangle_on_fine_grid(kname):
+    say(f"go2 preset (0.80 x 0.41 m rectangle, 1080 beams, r_max 20 m) on 1 cm rooms maps "
+        f"600^2: footprint window of 91 cells per side, kernel={kname}, 3 steps")
+    cfg = configs.go2(num_envs=256)
+    maps = [configs._maps.gen_rooms_map(7000 + k, w=600, h=600, res=0.01) for k in range(2)]
+    res = [0.01, 0.01]
+    env_map = configs.contiguous_env_map(256, 2)
+    sim, ref = make_pair(cfg, maps, res, env_map)
+    tot = run_teacher_forced(sim, ref, 3, KERNELS[kname], label=f"go2-1cm/{kname}")
+    assert tot["rays"] > 0
+    sim.close()
+
+
+def test_footprint_window_beyond_limit_is_rejected():
+    say("go2 rectangle on 5 mm cells: window of 181 cells, rejected at load")
+    cfg = configs.go2(num_envs=4)
+    maps = [configs._maps.gen_rooms_map(7000, w=400, h=400, res=0.005)]
+    with pytest.raises(navsim.NavsimError) as ei:
+        NavSim(cfg, maps, [0.005], np.zeros(4, np.int32), device=0)
+    assert ei.value.status == -7
+    assert "window" in str(ei.value)
