@@ -52,6 +52,11 @@ PAPER_CONTEXT = {
 }
 
 
+def log(msg: str) -> None:
+    """Progress of the legs on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def plan_legs(steps: int, warmup: int, plain_steps: int, march_steps: int,
               march_err_steps: int = 5) -> dict:
     """Action rows and the [first, last) rows each leg reads.  Every leg
@@ -373,6 +378,7 @@ def run_fused_leg(name: str, args, steps: int, warmup: int, lds_peak, full: bool
     tuning, profiled = tuning_for(w, args) if full else tuning_for(w, argparse.Namespace())
     sim.set_tuning(**tuning)
     sim.reset()
+    log(f"{name}: {N} envs built; burn-in of {args.burn_in} steps")
     t_burn = time.perf_counter()
     burn_in(sim, args.burn_in, seed=4242)
     t_burn = time.perf_counter() - t_burn
@@ -382,6 +388,7 @@ def run_fused_leg(name: str, args, steps: int, warmup: int, lds_peak, full: bool
     start_state = sim.get_state()
     total_ms = time_steps(sim, acts, legs["timed"][0], steps)
     ms_per_step = total_ms / steps
+    log(f"{name}: {steps} timed steps, {ms_per_step * 1e3:.1f} us per step")
     value = N * steps / (total_ms / 1e3)
     work = replay_work(sim, acts, legs["replay"][0], steps, start_state,
                        keep_first=full and not args.no_cpu)
@@ -403,6 +410,7 @@ def run_fused_leg(name: str, args, steps: int, warmup: int, lds_peak, full: bool
 
     # the paper's fixed-step range query (0.03 m) on the same fused step
     if not args.no_march:
+        log(f"{name}: fixed-step march leg")
         a0, a1 = legs["march"]
         sim.set_state(start_state)
         sim.set_scan(1, args.march_step)
@@ -443,6 +451,7 @@ def run_fused_leg(name: str, args, steps: int, warmup: int, lds_peak, full: bool
 
     # device rollouts: the same fused step under in-kernel actions, T steps
     # captured once as a HIP graph and replayed
+    log(f"{name}: graph rollout leg")
     sim.set_state(start_state)
     T = args.rollout_steps
     bufs = sim.rollout_buffers(T, final_obs=True)
@@ -463,6 +472,7 @@ def run_fused_leg(name: str, args, steps: int, warmup: int, lds_peak, full: bool
                             "launch": "HIP graph of T fused steps"}
     # the paper's actor in front of every step (graph of T actor + step launches)
     if not args.no_policy:
+        log(f"{name}: policy rollout leg")
         from paper_2606_15846_amd.policy import Policy
         pol = Policy(sim)
         pol.init_params(seed=3, beta=-0.1)
@@ -485,6 +495,7 @@ def run_fused_leg(name: str, args, steps: int, warmup: int, lds_peak, full: bool
     del bufs
 
     if not args.no_plain:
+        log(f"{name}: plain step leg")
         a0, a1 = legs["plain"]
         sim.set_state(start_state)
         pms = time_steps(sim, acts, a0, a1 - a0, plain=True)
@@ -494,9 +505,11 @@ def run_fused_leg(name: str, args, steps: int, warmup: int, lds_peak, full: bool
                         "mapping": "one thread per env, beams in sequence, bitmap in HBM"}
         out["speedup_vs_plain"] = value / prate
     if w.get("proposer") and not args.no_proposal:
+        log(f"{name}: reset proposal leg")
         out["reset_proposal"] = reset_proposal_gain(sim, w, args)
     sim.close()
     if not args.no_cpu:
+        log(f"{name}: oracle on the host cores")
         a0, a1 = legs["timed"]
         out["cpu_baseline"] = cpu_baseline(w, acts_np[a0:], start_state, work["first_step"],
                                            rays_per_step / N)
@@ -555,6 +568,7 @@ def main():
                           "copy_bytes_written_per_launch": b.numel() * 4, "launches": 5}))
         return
 
+    log("LDS read probe")
     lds_peak = None if args.no_lds_peak else measure_lds_peak(0)
     head = run_fused_leg(args.workload, args, args.steps, args.warmup, lds_peak, full=True)
     second = None
