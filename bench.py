@@ -547,6 +547,8 @@ def main():
     ap.add_argument("--persist", type=int, default=None)
     ap.add_argument("--threads", type=int, default=None)
     ap.add_argument("--balance", type=int, default=None)
+    ap.add_argument("--lds-probe-only", action="store_true",
+                    help="only run the LDS read probe and print its best shape (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 device-to-device copies of 256 MiB (HBM counter scale)")
     args = ap.parse_args()
@@ -570,6 +572,9 @@ def main():
 
     log("LDS read probe")
     lds_peak = None if args.no_lds_peak else measure_lds_peak(0)
+    if args.lds_probe_only:
+        print(json.dumps({"lds_peak_probe": lds_peak}))
+        return
     head = run_fused_leg(args.workload, args, args.steps, args.warmup, lds_peak, full=True)
     second = None
     if args.secondary and args.secondary != args.workload:
