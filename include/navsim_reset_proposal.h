@@ -102,6 +102,29 @@ navsim_status navsim_rp_propose(navsim_rp_t rp, int32_t n, const int32_t *map, c
                                 int32_t max_tries, float *pose, int32_t *hops, int32_t *source,
                                 int32_t *checks, float *y_out, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call, arguments, outputs and kernels as navsim_rp_propose, with every
+ * workspace it needs (the constant first-layer table, noise inputs, network
+ * outputs and two hidden activations) carved from one fixed 16 MiB array per
+ * device that the library's code object holds until the process ends; it
+ * calls no hipMalloc or hipFree.  Workspace bytes, each part rounded up to
+ * 256: maps x num_bins x hidden x 4 + R x (2 noise_dim + 4 + 20 + 4 hidden)
+ * with R = n x proposals (0 when proposals = 0: the rejection sampler alone
+ * uses none); e.g. 64 maps, 8 bins, hidden 256, noise 16: up to ~15,000
+ * draws per call.  Errors: as navsim_rp_propose, and INVALID_ARG when the
+ * workspace would exceed 16 MiB (nothing is launched).  Every call on a
+ * device shares that device's array and leaves its contents there (nothing in
+ * it needs to start at zero): calls that overlap on one device, on different
+ * streams or from different threads, race and must be serialised by the
+ * caller. */
+navsim_status navsim_rp_propose_noalloc(navsim_rp_t rp, int32_t n, const int32_t *map,
+                                        const int32_t *bin, const uint32_t *env,
+                                        const uint32_t *episode, int32_t proposals,
+                                        int32_t max_tries, float *pose, int32_t *hops,
+                                        int32_t *source, int32_t *checks, float *y_out,
+                                        void *hip_stream);
+
 /* Network on explicit inputs: x bfloat16 bits [n][d0] (d0 = 1024 + num_bins
  * + noise_dim), y float [n][5] (device). */
 navsim_status navsim_rp_forward(navsim_rp_t rp, int32_t n, const uint16_t *x, float *y,

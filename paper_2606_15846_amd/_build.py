@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnavsim.so")
 SOURCES = ["navsim_kernels.hip", "navsim_api.cpp", "mlp_kernels.hip", "reach_kernels.hip",
-           "reset_proposal.cpp", "policy.cpp", "lds_probe.hip"]
+           "reset_proposal.cpp", "policy.cpp", "lds_probe.hip", "rp_scratch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -15,6 +15,7 @@
 #include "navsim_host.hpp"
 #include "navsim_reset_proposal.h"
 #include "reach_internal.hpp"
+#include "rp_scratch.hpp"
 
 using namespace navsim;
 
@@ -87,6 +88,7 @@ struct navsim_rp_s {
     float *wloss = nullptr;        // loss weights [5]
     int64_t adam_t = 0;
     uint32_t train_step = 0;
+    void *scratch = nullptr;       // fixed per-device workspace (navsim_rp_propose_noalloc)
     // workspaces
     DevBuf ctable, colsum, x, hid[4], y, dyf, dyb, dh, dzf, dzb, lrows, zc, ridx, yc, hc[2],
         bmap, bbin, target, chosen, zp, rp_idx, yp;
@@ -128,10 +130,15 @@ void free_rp(navsim_rp_s *r) {
 
 int hidden_width(const navsim_rp_s *r) { return r->cfg.hidden; }
 
-// Refreshes ctable[(map, bin)] = W1[:, :1024 + nb] [pool | one-hot] + b1.
-navsim_status refresh_ctable(navsim_rp_s *r, hipStream_t s) {
+// Bytes of the constant first-layer table (one row per (map, bin)).
+size_t ctable_bytes(const navsim_rp_s *r) {
+    return (size_t)r->num_maps * r->cfg.num_bins * hidden_width(r) * sizeof(float);
+}
+
+// Writes ct[(map, bin)] = W1[:, :1024 + nb] [pool | one-hot] + b1 (float,
+// ctable_bytes(r) bytes).
+navsim_status refresh_ctable(navsim_rp_s *r, float *ct, hipStream_t s) {
     const int rows = r->num_maps * r->cfg.num_bins, Hd = hidden_width(r);
-    RP_BUF(r->ctable, (size_t)rows * Hd * sizeof(float));
     GemmArgs g;
     g.M = rows;
     g.N = Hd;
@@ -141,19 +148,20 @@ navsim_status refresh_ctable(navsim_rp_s *r, hipStream_t s) {
     g.B = r->pb + r->w_off[0];
     g.ldb = r->d0;
     g.bias = r->p + r->b_off[0];
-    g.Cf = r->ctable.as<float>();
+    g.Cf = ct;
     g.ldcf = Hd;
     RP_HIP(launch_gemm(g, s));
     return NAVSIM_OK;
 }
 
-// Network outputs for noise rows (constant part of layer 1 from ctable):
-// Z [R][nz] bf16, row_idx [R] -> Y [R][5] float.
+// Network outputs for noise rows (constant part of layer 1 from the table
+// ct): Z [R][nz] bf16, row_idx [R] -> Y [R][5] float; hidden activations in
+// hc0, hc1 (bf16, R x hidden each).
 navsim_status forward_noise(navsim_rp_s *r, int R, const uint16_t *Z, const int32_t *row_idx,
-                            float *Y, hipStream_t s) {
+                            float *Y, const float *ct, uint16_t *hc0, uint16_t *hc1,
+                            hipStream_t s) {
     const int Hd = hidden_width(r);
-    RP_BUF(r->hc[0], (size_t)R * Hd * 2);
-    RP_BUF(r->hc[1], (size_t)R * Hd * 2);
+    uint16_t *hc[2] = {hc0, hc1};
     const float slope = r->cfg.leaky_slope;
     GemmArgs g;
     g.M = R;
@@ -163,12 +171,12 @@ navsim_status forward_noise(navsim_rp_s *r, int R, const uint16_t *Z, const int3
     g.lda = r->cfg.noise_dim;
     g.B = r->pb + r->w_off[0] + kPoolCells + r->cfg.num_bins;
     g.ldb = r->d0;
-    g.bias_rows = r->ctable.as<float>();
+    g.bias_rows = ct;
     g.row_idx = row_idx;
     g.ldbr = Hd;
     g.act = 1;
     g.slope = slope;
-    g.Cb = r->hc[0].as<uint16_t>();
+    g.Cb = hc[0];
     g.ldcb = Hd;
     RP_HIP(launch_gemm(g, s));
     int cur = 0;
@@ -177,7 +185,7 @@ navsim_status forward_noise(navsim_rp_s *r, int R, const uint16_t *Z, const int3
         q.M = R;
         q.N = r->dims[l + 1];
         q.K = r->dims[l];
-        q.A = r->hc[cur].as<uint16_t>();
+        q.A = hc[cur];
         q.lda = r->dims[l];
         q.B = r->pb + r->w_off[l];
         q.ldb = r->dims[l];
@@ -185,7 +193,7 @@ navsim_status forward_noise(navsim_rp_s *r, int R, const uint16_t *Z, const int3
         if (l + 1 < r->L) {
             q.act = 1;
             q.slope = slope;
-            q.Cb = r->hc[1 - cur].as<uint16_t>();
+            q.Cb = hc[1 - cur];
             q.ldcb = q.N;
         } else {
             q.Cf = Y;
@@ -284,6 +292,91 @@ navsim_status adamw_step(navsim_rp_s *r, const float *grad, float lr, float wd, 
     r->adam_t += 1;
     RP_HIP(launch_adamw(r->nparams, r->p, r->pb, grad, r->m, r->v, r->decay, lr, 0.9f, 0.999f,
                         1e-8f, wd, r->adam_t, s));
+    return NAVSIM_OK;
+}
+
+// Arguments shared by the two proposal entry points.
+navsim_status check_propose(const navsim_rp_s *r, int32_t n, const int32_t *map,
+                            const int32_t *bin, const uint32_t *env, const uint32_t *episode,
+                            int32_t proposals, int32_t max_tries, const float *pose,
+                            const int32_t *hops, const int32_t *source, const int32_t *checks) {
+    if (!r) return fail(NAVSIM_E_BAD_HANDLE, "proposer is NULL");
+    if (n < 0 || proposals < 0 || proposals > 4096 || max_tries < 0)
+        return fail(NAVSIM_E_INVALID_ARG, "n >= 0, proposals in 0..4096, max_tries >= 0");
+    if ((int64_t)n * proposals > (1 << 24))
+        return fail(NAVSIM_E_INVALID_ARG, "n * proposals must be <= 2^24");
+    if (n > 0 && (!map || !bin || !env || !episode || !pose || !hops || !source || !checks))
+        return fail(NAVSIM_E_INVALID_ARG, "all arrays are required");
+    return NAVSIM_OK;
+}
+
+// Device buffers of one proposal call: the constant first-layer table, noise
+// inputs, their table rows, network outputs and two hidden activations.
+struct ProposeWork {
+    float *ct = nullptr;
+    uint16_t *z = nullptr;
+    int32_t *row_idx = nullptr;
+    float *y = nullptr;
+    uint16_t *hc0 = nullptr, *hc1 = nullptr;
+};
+
+constexpr size_t align_up(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Fixed-workspace bytes of a call with n requests x `proposals` draws (0
+// when proposals is 0: the rejection sampler alone uses no workspace).
+size_t noalloc_bytes(const navsim_rp_s *r, int32_t n, int32_t proposals) {
+    if (proposals <= 0 || n <= 0) return 0;
+    const size_t R = (size_t)n * (size_t)proposals, Hd = (size_t)hidden_width(r);
+    return align_up(ctable_bytes(r)) + align_up(R * r->cfg.noise_dim * 2) + align_up(R * 4) +
+           align_up(R * 5 * 4) + 2 * align_up(R * Hd * 2);
+}
+
+// Noise draws, network outputs, then the exact checks and the rejection
+// sampler behind them (w holds the buffers when proposals > 0).
+navsim_status propose_run(navsim_rp_s *r, int32_t n, const int32_t *map, const int32_t *bin,
+                          const uint32_t *env, const uint32_t *episode, int32_t proposals,
+                          int32_t max_tries, float *pose, int32_t *hops, int32_t *source,
+                          int32_t *checks, float *y_out, const ProposeWork &w, hipStream_t s) {
+    const float *y = nullptr;
+    if (proposals > 0) {
+        const int64_t R = (int64_t)n * proposals;
+        navsim_status st = refresh_ctable(r, w.ct, s);
+        if (st != NAVSIM_OK) return st;
+        NoiseArgs na;
+        na.n = n;
+        na.per = proposals;
+        na.nz = r->cfg.noise_dim;
+        na.nbins = r->cfg.num_bins;
+        na.num_maps = r->num_maps;
+        na.c0 = env;
+        na.c1 = episode;
+        na.c1_const = 0u;
+        na.stream = 8u;
+        na.map = map;
+        na.bin = bin;
+        na.z = w.z;
+        na.row_idx = w.row_idx;
+        RP_HIP(launch_noise(na, r->rp.key0, r->rp.key1, s));
+        if ((st = forward_noise(r, (int)R, na.z, na.row_idx, w.y, w.ct, w.hc0, w.hc1, s)) !=
+            NAVSIM_OK)
+            return st;
+        y = w.y;
+        if (y_out) RP_HIP(hipMemcpyAsync(y_out, y, (size_t)R * 5 * 4, hipMemcpyDeviceToDevice, s));
+    }
+    ProposeArgs pa;
+    pa.n = n;
+    pa.props = proposals;
+    pa.tries = max_tries;
+    pa.map = map;
+    pa.bin = bin;
+    pa.env = env;
+    pa.episode = episode;
+    pa.y = y;
+    pa.pose = pose;
+    pa.hops = hops;
+    pa.source = source;
+    pa.checks = checks;
+    RP_HIP(launch_propose(r->rp, pa, s));
     return NAVSIM_OK;
 }
 
@@ -453,6 +546,10 @@ navsim_status navsim_rp_create(navsim_t h, const navsim_rp_config *cfg, navsim_r
     rp.gmd = (double)h->cfg.goal_min_dist_m;
     rp.key0 = (uint32_t)(c.seed & 0xffffffffu);
     rp.key1 = (uint32_t)(c.seed >> 32);
+    // the fixed workspace's device address on this device (the device is current)
+    const hipError_t se = rp_scratch_address(r->device, &r->scratch);
+    if (se != hipSuccess)
+        return fail_out(fail(NAVSIM_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(se)));
     *out = r;
     return NAVSIM_OK;
 }
@@ -493,10 +590,12 @@ navsim_status navsim_rp_train(navsim_rp_t r, int32_t num_pairs, const int32_t *p
     RP_BUF(r->x, (size_t)batch * r->d0 * 2);
     RP_BUF(r->y, (size_t)batch * 5 * 4);
     RP_BUF(r->lrows, (size_t)batch * 4);
-    (void)Hd;
+    RP_BUF(r->ctable, ctable_bytes(r));
+    RP_BUF(r->hc[0], (size_t)R * Hd * 2);
+    RP_BUF(r->hc[1], (size_t)R * Hd * 2);
     for (int t = 0; t < steps; ++t) {
         const uint32_t step = r->train_step++;
-        navsim_status st = refresh_ctable(r, s);
+        navsim_status st = refresh_ctable(r, r->ctable.as<float>(), s);
         if (st != NAVSIM_OK) return st;
         BatchArgs ba;
         ba.batch = batch;
@@ -528,7 +627,8 @@ navsim_status navsim_rp_train(navsim_rp_t r, int32_t num_pairs, const int32_t *p
         na.z = r->zc.as<uint16_t>();
         na.row_idx = r->ridx.as<int32_t>();
         RP_HIP(launch_noise(na, r->rp.key0, r->rp.key1, s));
-        if ((st = forward_noise(r, R, na.z, na.row_idx, r->yc.as<float>(), s)) != NAVSIM_OK)
+        if ((st = forward_noise(r, R, na.z, na.row_idx, r->yc.as<float>(), r->ctable.as<float>(),
+                                r->hc[0].as<uint16_t>(), r->hc[1].as<uint16_t>(), s)) != NAVSIM_OK)
             return st;
         SelectArgs sa;
         sa.batch = batch;
@@ -563,58 +663,66 @@ navsim_status navsim_rp_propose(navsim_rp_t r, int32_t n, const int32_t *map, co
                                 const uint32_t *env, const uint32_t *episode, int32_t proposals,
                                 int32_t max_tries, float *pose, int32_t *hops, int32_t *source,
                                 int32_t *checks, float *y_out, void *stream) {
-    if (!r) return fail(NAVSIM_E_BAD_HANDLE, "proposer is NULL");
-    if (n < 0 || proposals < 0 || proposals > 4096 || max_tries < 0)
-        return fail(NAVSIM_E_INVALID_ARG, "n >= 0, proposals in 0..4096, max_tries >= 0");
-    if (n > 0 && (!map || !bin || !env || !episode || !pose || !hops || !source || !checks))
-        return fail(NAVSIM_E_INVALID_ARG, "all arrays are required");
-    if (n == 0) return NAVSIM_OK;
+    navsim_status st = check_propose(r, n, map, bin, env, episode, proposals, max_tries, pose,
+                                     hops, source, checks);
+    if (st != NAVSIM_OK || n == 0) return st;
     DeviceGuard dg(r->device);
-    const hipStream_t s = (hipStream_t)stream;
-    const float *y = nullptr;
+    ProposeWork w;
     if (proposals > 0) {
         const int64_t R = (int64_t)n * proposals;
-        if (R > (1 << 24)) return fail(NAVSIM_E_INVALID_ARG, "n * proposals must be <= 2^24");
+        const int Hd = hidden_width(r);
+        RP_BUF(r->ctable, ctable_bytes(r));
         RP_BUF(r->zp, (size_t)R * r->cfg.noise_dim * 2);
         RP_BUF(r->rp_idx, (size_t)R * 4);
         RP_BUF(r->yp, (size_t)R * 5 * 4);
-        navsim_status st = refresh_ctable(r, s);
-        if (st != NAVSIM_OK) return st;
-        NoiseArgs na;
-        na.n = n;
-        na.per = proposals;
-        na.nz = r->cfg.noise_dim;
-        na.nbins = r->cfg.num_bins;
-        na.num_maps = r->num_maps;
-        na.c0 = env;
-        na.c1 = episode;
-        na.c1_const = 0u;
-        na.stream = 8u;
-        na.map = map;
-        na.bin = bin;
-        na.z = r->zp.as<uint16_t>();
-        na.row_idx = r->rp_idx.as<int32_t>();
-        RP_HIP(launch_noise(na, r->rp.key0, r->rp.key1, s));
-        if ((st = forward_noise(r, (int)R, na.z, na.row_idx, r->yp.as<float>(), s)) != NAVSIM_OK)
-            return st;
-        y = r->yp.as<float>();
-        if (y_out) RP_HIP(hipMemcpyAsync(y_out, y, (size_t)R * 5 * 4, hipMemcpyDeviceToDevice, s));
+        RP_BUF(r->hc[0], (size_t)R * Hd * 2);
+        RP_BUF(r->hc[1], (size_t)R * Hd * 2);
+        w = ProposeWork{r->ctable.as<float>(), r->zp.as<uint16_t>(), r->rp_idx.as<int32_t>(),
+                        r->yp.as<float>(), r->hc[0].as<uint16_t>(), r->hc[1].as<uint16_t>()};
     }
-    ProposeArgs pa;
-    pa.n = n;
-    pa.props = proposals;
-    pa.tries = max_tries;
-    pa.map = map;
-    pa.bin = bin;
-    pa.env = env;
-    pa.episode = episode;
-    pa.y = y;
-    pa.pose = pose;
-    pa.hops = hops;
-    pa.source = source;
-    pa.checks = checks;
-    RP_HIP(launch_propose(r->rp, pa, s));
-    return NAVSIM_OK;
+    return propose_run(r, n, map, bin, env, episode, proposals, max_tries, pose, hops, source,
+                       checks, y_out, w, (hipStream_t)stream);
+}
+
+navsim_status navsim_rp_propose_noalloc(navsim_rp_t r, int32_t n, const int32_t *map,
+                                        const int32_t *bin, const uint32_t *env,
+                                        const uint32_t *episode, int32_t proposals,
+                                        int32_t max_tries, float *pose, int32_t *hops,
+                                        int32_t *source, int32_t *checks, float *y_out,
+                                        void *stream) {
+    navsim_status st = check_propose(r, n, map, bin, env, episode, proposals, max_tries, pose,
+                                     hops, source, checks);
+    if (st != NAVSIM_OK) return st;
+    if (!r->scratch) return fail(NAVSIM_E_STATE, "the proposer has no fixed workspace");
+    const size_t need = noalloc_bytes(r, n, proposals);
+    if (need > kRpScratchBytes)
+        return fail(NAVSIM_E_INVALID_ARG,
+                    "navsim_rp_propose_noalloc: %d requests x %d proposals need %zu workspace "
+                    "bytes, more than the fixed %zu (use fewer requests per call)",
+                    n, proposals, need, kRpScratchBytes);
+    if (n == 0) return NAVSIM_OK;
+    DeviceGuard dg(r->device);
+    ProposeWork w;
+    if (proposals > 0) {
+        // carve the fixed workspace in the order noalloc_bytes() counts it
+        const int64_t R = (int64_t)n * proposals;
+        const int Hd = hidden_width(r);
+        uint8_t *base = (uint8_t *)r->scratch;
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            uint8_t *q = base + off;
+            off += align_up(bytes);
+            return (void *)q;
+        };
+        w.ct = (float *)take(ctable_bytes(r));
+        w.z = (uint16_t *)take((size_t)R * r->cfg.noise_dim * 2);
+        w.row_idx = (int32_t *)take((size_t)R * 4);
+        w.y = (float *)take((size_t)R * 5 * 4);
+        w.hc0 = (uint16_t *)take((size_t)R * Hd * 2);
+        w.hc1 = (uint16_t *)take((size_t)R * Hd * 2);
+    }
+    return propose_run(r, n, map, bin, env, episode, proposals, max_tries, pose, hops, source,
+                       checks, y_out, w, (hipStream_t)stream);
 }
 
 navsim_status navsim_rp_forward(navsim_rp_t r, int32_t n, const uint16_t *x, float *y,

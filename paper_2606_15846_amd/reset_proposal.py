@@ -14,7 +14,8 @@ import torch
 from . import navsim as _ns
 
 EXPORTS = ("navsim_rp_create", "navsim_rp_label", "navsim_rp_train", "navsim_rp_propose",
-           "navsim_rp_forward", "navsim_rp_loss_grad", "navsim_rp_adamw", "navsim_rp_layout",
+           "navsim_rp_propose_noalloc", "navsim_rp_forward", "navsim_rp_loss_grad",
+           "navsim_rp_adamw", "navsim_rp_layout",
            "navsim_rp_get_params", "navsim_rp_set_params", "navsim_rp_destroy")
 
 
@@ -39,6 +40,7 @@ def _lib():
         L.navsim_rp_label.argtypes = [vp, i32, vp, u32, vp, vp, vp, vp]
         L.navsim_rp_train.argtypes = [vp, i32, vp, vp, vp, vp, i32, i32, i32, f32, f32, vp, vp]
         L.navsim_rp_propose.argtypes = [vp, i32, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.navsim_rp_propose_noalloc.argtypes = L.navsim_rp_propose.argtypes
         L.navsim_rp_forward.argtypes = [vp, i32, vp, vp, vp]
         L.navsim_rp_loss_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.navsim_rp_adamw.argtypes = [vp, vp, f32, f32, vp]
@@ -126,7 +128,9 @@ class ResetProposer:
             _ptr(loss, torch.float32, optional=True), self._stream()))
 
     def propose(self, map_ids, bins, env, episode, proposals: int, max_tries: int,
-                want_y: bool = False) -> dict:
+                want_y: bool = False, noalloc: bool = False) -> dict:
+        """noalloc: the entry point that takes its workspace from the fixed
+        per-device array (navsim_rp_propose_noalloc) instead of allocating."""
         dev = self.device
         m = torch.as_tensor(map_ids, dtype=torch.int32, device=dev).contiguous()
         b = torch.as_tensor(bins, dtype=torch.int32, device=dev).contiguous()
@@ -140,11 +144,12 @@ class ResetProposer:
                    checks=torch.empty(n, dtype=torch.int32, **z))
         if want_y and proposals > 0:
             out["y"] = torch.empty(n, proposals, 5, dtype=torch.float32, **z)
-        return self.propose_into(m, b, e, ep, proposals, max_tries, out)
+        return self.propose_into(m, b, e, ep, proposals, max_tries, out, noalloc=noalloc)
 
-    def propose_into(self, m, b, e, ep, proposals, max_tries, out):
+    def propose_into(self, m, b, e, ep, proposals, max_tries, out, noalloc: bool = False):
         n = m.numel()
-        _ns._check(_lib().navsim_rp_propose(
+        fn = _lib().navsim_rp_propose_noalloc if noalloc else _lib().navsim_rp_propose
+        _ns._check(fn(
             self.h, n, _ptr(m), _ptr(b), _ptr(e), _ptr(ep), int(proposals), int(max_tries),
             _ptr(out["pose"]), _ptr(out["hops"]), _ptr(out["source"]), _ptr(out["checks"]),
             _ptr(out.get("y"), optional=True), self._stream()))
