@@ -163,7 +163,11 @@ navsim_status navsim_reset_to(navsim_t h, const uint8_t *mask, const float *pose
  * stages the map's bitmap in LDS, steps each env on a group of 16 lanes
  * (ballots for collision and reset attempts), walks all of the tile's rays
  * (new poses and reset poses) with every lane, pools sectors in LDS and writes
- * the observation rows. */
+ * the observation rows.  With a reset proposer attached (navsim_rp_attach in
+ * navsim_reset_proposal.h), envs with a requested difficulty bin take their
+ * new pair from it instead: the fused launch defers their reset, the
+ * proposer's kernels pick and verify the pairs, and one masked reset launch
+ * applies them (all on hip_stream). */
 navsim_status navsim_step(navsim_t h, const float *act, float *obs, float *reward,
                           uint8_t *terminated, uint8_t *truncated, float *final_obs,
                           void *hip_stream);

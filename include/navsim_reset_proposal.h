@@ -125,6 +125,50 @@ navsim_status navsim_rp_propose_noalloc(navsim_rp_t rp, int32_t n, const int32_t
                                         int32_t *source, int32_t *checks, float *y_out,
                                         void *hip_stream);
 
+/* Learned resets inside the step (the sparse reset of section 2.2.3, with
+ * difficulty): after this call, every env e with bin[e] in 0..num_bins-1
+ * (host int32 [num_envs]; -1 = the free-space sampler as before) whose
+ * episode ends in navsim_step, or that navsim_reset resets, takes its new
+ * start/goal pair from this proposer, in the same call and on the same
+ * stream: the fused launch writes its flags, reward and final observation but
+ * leaves its reset for later; the first max_per_step such envs in env order
+ * become requests (env e, its map, bin[e], its episode counter), each tries
+ * `proposals` network draws and then max_tries rejection attempts exactly as
+ * navsim_rp_propose does (every pair passes the exact check: C-free start
+ * and goal, geodesic hop count in the bin, centre distance >= the goal
+ * minimum); a masked reset pass then sets every deferred env's state (v = w
+ * = 0, t = 0, episode counter + 1) and its reset observation in obs, from
+ * its pair, or from the free-space sampler (the pose navsim_step would have
+ * drawn) when its request found no valid pair or did not fit under
+ * max_per_step.  No allocation, host synchronisation or memset happens in
+ * the step.  navsim_step_plain and the rollout calls return UNSUPPORTED while
+ * a proposer is attached.  Calling it again replaces the bins (and the other
+ * settings); the handle's maps must be the ones the proposer was created
+ * for.  Errors: INVALID_ARG (a bin outside -1..num_bins-1, proposals outside
+ * 0..4096, max_tries < 0, max_per_step outside 1..num_envs,
+ * max_per_step x proposals > 2^24), STATE (another proposer is attached),
+ * OOM, HIP.  Synchronises the device. */
+navsim_status navsim_rp_attach(navsim_rp_t rp, const int32_t *bin, int32_t proposals,
+                               int32_t max_tries, int32_t max_per_step);
+
+/* Back to the free-space sampler for every env; frees the in-step buffers
+ * (synchronises the device).  navsim_rp_destroy detaches too. */
+navsim_status navsim_rp_detach(navsim_rp_t rp);
+
+/* Totals since attach (or the last clear), host int64 [8]: deferred resets,
+ * deferred resets past max_per_step, requests, pairs from the network, pairs
+ * from rejection attempts, requests with no valid pair, exact checks run,
+ * 0.  clear != 0 zeroes them.  STATE when not attached.  Synchronises. */
+navsim_status navsim_rp_attach_stats(navsim_rp_t rp, int64_t *out, int32_t clear);
+
+/* Per env, of the last step or reset: source (device int32 [num_envs]; for an
+ * env that deferred its reset: the draw that gave its pair as in
+ * navsim_rp_propose, or -1 for the free-space sampler; other rows keep older
+ * values) and hops (device int32 [num_envs], the pair's hop count where
+ * source >= 0).  Copies on hip_stream.  STATE when not attached. */
+navsim_status navsim_rp_attach_outputs(navsim_rp_t rp, int32_t *source, int32_t *hops,
+                                       void *hip_stream);
+
 /* Network on explicit inputs: x bfloat16 bits [n][d0] (d0 = 1024 + num_bins
  * + noise_dim), y float [n][5] (device). */
 navsim_status navsim_rp_forward(navsim_rp_t rp, int32_t n, const uint16_t *x, float *y,

@@ -121,6 +121,8 @@ def lib():
                             P(C.c_uint8), C.c_int64, C.c_int64]
     L.orc_step.argtypes = [P(OrcCfg), P(OrcMaps), P(OrcState), P(C.c_float), P(OrcOut),
                            C.c_int64, C.c_int64]
+    L.orc_step_defer.argtypes = [P(OrcCfg), P(OrcMaps), P(OrcState), P(C.c_float), P(OrcOut),
+                                 P(C.c_int32), C.c_int64, C.c_int64]
     _LIB = L
     return L
 
@@ -295,7 +297,9 @@ class OracleSim:
         with _cf.ThreadPoolExecutor(len(sl)) as ex:
             list(ex.map(fn, sl))
 
-    def step(self, act, debug: bool = True, threads: int = 1) -> dict:
+    def step(self, act, debug: bool = True, threads: int = 1, defer_bin=None) -> dict:
+        """One step of every env; with defer_bin [N] (int32), envs that end
+        with defer_bin[e] >= 0 are not reset (orc_step_defer)."""
         N, K, m = self.N, self.K, self.m
         act = np.ascontiguousarray(act, dtype=np.float32).reshape(N, 2)
         o = dict(obs=np.zeros((N, m + 4), np.float32), reward=np.zeros(N, np.float32),
@@ -315,9 +319,12 @@ class OracleSim:
                      _ptr(o["reset"], C.c_uint8), _ptr(o["fallback"], C.c_uint8))
         L = lib()
 
+        db = None if defer_bin is None else np.ascontiguousarray(defer_bin, dtype=np.int32)
+
         def run(sl):
-            L.orc_step(C.byref(self.cfg), C.byref(self.maps.struct), C.byref(self.st),
-                       _ptr(act, C.c_float), C.byref(out), sl[0], sl[1])
+            L.orc_step_defer(C.byref(self.cfg), C.byref(self.maps.struct), C.byref(self.st),
+                             _ptr(act, C.c_float), C.byref(out), _ptr(db, C.c_int32), sl[0],
+                             sl[1])
         self._run(run, threads)
         return o
 

@@ -565,9 +565,12 @@ void orc_reset(const orc_cfg *cfg, const orc_maps *M, orc_state *st, const uint8
     }
 }
 
-/* One step of envs [e0, e1), in the order of the step data path (eq. 7). */
-void orc_step(const orc_cfg *gcfg, const orc_maps *M, orc_state *st, const float *act,
-              const orc_out *out, int64_t e0, int64_t e1)
+/* One step of envs [e0, e1), in the order of the step data path (eq. 7).
+ * defer_bin (may be NULL): an env that ends with defer_bin[e] >= 0 is not
+ * reset here (its pair comes from the learned proposal, applied afterwards
+ * with orc_reset_to or, where no valid pair was found, orc_reset). */
+void orc_step_defer(const orc_cfg *gcfg, const orc_maps *M, orc_state *st, const float *act,
+                    const orc_out *out, const int32_t *defer_bin, int64_t e0, int64_t e1)
 {
     int K = gcfg->num_beams, m = gcfg->num_sectors; /* output strides: the largest K */
     double dt = (double)gcfg->dt_s;
@@ -639,7 +642,14 @@ void orc_step(const orc_cfg *gcfg, const orc_maps *M, orc_state *st, const float
         if (term || trunc) {
             if (out->final_obs)
                 memcpy(out->final_obs + e * (m + 4), obs_row, sizeof(float) * (size_t)(m + 4));
-            orc_reset_env(gcfg, M, st, e, out->obs, out->fallback);
+            if (!(defer_bin && defer_bin[e] >= 0))
+                orc_reset_env(gcfg, M, st, e, out->obs, out->fallback);
         }
     }
+}
+
+void orc_step(const orc_cfg *gcfg, const orc_maps *M, orc_state *st, const float *act,
+              const orc_out *out, int64_t e0, int64_t e1)
+{
+    orc_step_defer(gcfg, M, st, act, out, NULL, e0, e1);
 }

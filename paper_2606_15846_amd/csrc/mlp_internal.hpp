@@ -29,6 +29,10 @@ struct GemmArgs {
     int64_t ldcf = 0;
     uint16_t *Cb = nullptr;
     int64_t ldcb = 0;
+    // optional: rows = min(M, *m_dev * m_mul), read on the device (the grid
+    // still covers M rows; workgroups past the rows return at once)
+    const int32_t *m_dev = nullptr;
+    int m_mul = 1;
 };
 
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);

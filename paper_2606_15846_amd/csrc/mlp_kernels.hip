@@ -81,6 +81,13 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kLdsK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    int M = g.M;
+    if (g.m_dev) {
+        // rows known only on the device: the grid covers g.M, the rest exits
+        const int64_t md = (int64_t)*g.m_dev * g.m_mul;
+        M = md < (int64_t)M ? (int)(md > 0 ? md : 0) : M;
+        if (m0 >= M) return;
+    }
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const bool a_vec = (g.lda % 8 == 0) && (((uintptr_t)g.A & 15) == 0);
     const bool b_vec = (g.ldb % 8 == 0) && (((uintptr_t)g.B & 15) == 0);
@@ -91,7 +98,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     for (int k0 = 0; k0 < g.K; k0 += kBK) {
-        stage_tile<AK>(As, g.A, g.lda, g.M, g.K, m0, k0, a_vec, tid);
+        stage_tile<AK>(As, g.A, g.lda, M, g.K, m0, k0, a_vec, tid);
         stage_tile<BK>(Bs, g.B, g.ldb, g.N, g.K, n0, k0, b_vec, tid);
         __syncthreads();
         bf16x8 a[2], b[2];
@@ -116,7 +123,7 @@ __global__ __launch_bounds__(kGemmThreads) void gemm_kernel(GemmArgs g) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wm + 16 * i + (lane >> 4) * 4 + r;
-                if (m >= g.M) continue;
+                if (m >= M) continue;
                 float v = acc[i][j][r];
                 if (g.bias) v += g.bias[n];
                 if (g.bias_rows) v += g.bias_rows[(int64_t)g.row_idx[m] * g.ldbr + n];

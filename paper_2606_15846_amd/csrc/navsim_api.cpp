@@ -355,6 +355,22 @@ navsim_status run(navsim_t h, const StepParams &p, int kernel, hipStream_t s) {
     return NAVSIM_OK;
 }
 
+// After a fused launch that deferred resets: the attached proposer writes a
+// pair for every deferred env it serves, then one masked reset pass applies
+// them (the free-space sampler for the rest) and writes their reset rows.
+navsim_status finish_deferred(navsim_t h, float *obs, uint8_t *fallback, hipStream_t s) {
+    navsim_status st = h->hook.run(h->hook.ctx, s);
+    if (st != NAVSIM_OK) return st;
+    StepParams q = make_step_params(h);
+    q.mode = 1;
+    q.mask = h->hook.defer;
+    q.pose = h->hook.pose;
+    q.pose_src = h->hook.src;
+    q.obs = obs;
+    q.d_fb = fallback;
+    return run(h, q, NAVSIM_KERNEL_FUSED, s);
+}
+
 navsim_status step_common(navsim_t h, const float *act, float *obs, float *reward,
                           uint8_t *terminated, uint8_t *truncated, float *final_obs,
                           const navsim_debug *dbg, int32_t kernel, void *stream) {
@@ -382,7 +398,14 @@ navsim_status step_common(navsim_t h, const float *act, float *obs, float *rewar
         p.d_reset = dbg->reset;
         p.d_fb = dbg->fallback;
     }
-    return run(h, p, kernel, (hipStream_t)stream);
+    if (!h->hook.run) return run(h, p, kernel, (hipStream_t)stream);
+    if (kernel != NAVSIM_KERNEL_FUSED)
+        return fail(NAVSIM_E_UNSUPPORTED, "learned resets (navsim_rp_attach) run with the fused step only");
+    p.defer_bin = h->hook.bin;
+    p.defer_out = h->hook.defer;
+    navsim_status st = run(h, p, kernel, (hipStream_t)stream);
+    if (st != NAVSIM_OK) return st;
+    return finish_deferred(h, obs, dbg ? dbg->fallback : nullptr, (hipStream_t)stream);
 }
 
 // Every launch parameter (buffers, maps, settings) is part of a captured
@@ -772,7 +795,10 @@ navsim_status navsim_reset(navsim_t h, const uint8_t *mask, float *obs, void *hi
     p.mode = 1;
     p.mask = mask;
     p.obs = obs;
-    const navsim_status s = run(h, p, NAVSIM_KERNEL_FUSED, (hipStream_t)hip_stream);
+    p.defer_bin = h->hook.bin;
+    p.defer_out = h->hook.defer;
+    navsim_status s = run(h, p, NAVSIM_KERNEL_FUSED, (hipStream_t)hip_stream);
+    if (s == NAVSIM_OK && h->hook.run) s = finish_deferred(h, obs, nullptr, (hipStream_t)hip_stream);
     if (s == NAVSIM_OK) h->initialized = true;
     return s;
 }
@@ -853,6 +879,9 @@ navsim_status navsim_rollout(navsim_t h, int32_t steps, uint64_t first_step, flo
     if (kernel != NAVSIM_KERNEL_FUSED && kernel != NAVSIM_KERNEL_PLAIN)
         return fail(NAVSIM_E_INVALID_ARG, "unknown kernel %d", kernel);
     if (flags & ~NAVSIM_ROLLOUT_GRAPH) return fail(NAVSIM_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (h->hook.run)
+        return fail(NAVSIM_E_UNSUPPORTED,
+                    "rollouts use the in-kernel sampler: detach the reset proposer first");
     DeviceGuard g(h->device);
     if (g.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(g.err));
     StepParams p = make_step_params(h);

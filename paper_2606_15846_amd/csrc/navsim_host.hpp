@@ -90,6 +90,18 @@ struct navsim_s {
     hipGraphExec_t graph = nullptr;
     navsim::StepParams graph_params{};  // parameters of step 0 of the captured rollout
     int graph_steps = 0, graph_kernel = -1, graph_tile_envs = 0;
+    // learned resets inside the step (navsim_rp_attach): envs with a requested
+    // bin defer their reset in the fused launch, run() writes a verified pair
+    // for each (or leaves it to the free-space sampler), and a masked reset
+    // pass applies them
+    struct ResetHook {
+        const int32_t *bin = nullptr;  // device [N] requested bin per env, -1 none
+        uint8_t *defer = nullptr;      // device [N] the env deferred its reset in this call
+        const float *pose = nullptr;   // device [N][5] pairs written by run()
+        const int32_t *src = nullptr;  // device [N] >= 0 where run() wrote a pair
+        navsim_status (*run)(void *ctx, hipStream_t s) = nullptr;
+        void *ctx = nullptr;
+    } hook;
 };
 
 

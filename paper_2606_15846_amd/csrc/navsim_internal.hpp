@@ -93,6 +93,11 @@ struct StepParams {
     float *act_out;            // rollout: the drawn actions [N][2] (may be null)
     const uint8_t *mask;
     const float *pose;         // reset to given poses [N][5] (x, y, heading, goal x, goal y), or null
+    const int32_t *pose_src;   // with pose: env e takes row e only when pose_src[e] >= 0, else
+                               // the free-space sampler (null: every masked env takes its row)
+    const int32_t *defer_bin;  // envs whose episode ends with defer_bin[e] >= 0 are not reset
+                               // here (null: none); a later reset pass gives them their pair
+    uint8_t *defer_out;        // [N]: 1 where the env ended and deferred its reset, else 0
     float *obs, *reward, *final_obs;
     uint8_t *term, *trunc;
     // diagnostics (may be null)

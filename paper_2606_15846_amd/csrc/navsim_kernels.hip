@@ -1363,6 +1363,21 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
     uint4 *s_ray = reinterpret_cast<uint4 *>(s_beam + (p.beams_lds ? p.K : 0));  // [ray_cap]
     const int tid = threadIdx.x, lane = tid & 63;
     const Tile tile = p.tiles[tile_index];
+    if (p.mode == 1 && p.mask) {
+        // a masked reset pass: a tile with no masked env has nothing to do
+        // (its envs' rows stay untouched), so it skips the map staging too.
+        // The vote goes through a free word of the misc block (no static LDS:
+        // the byte walk needs its map copy at address 0)
+        int *s_vote = s_misc + 2 * E + 6;
+        if (tid == 0) *s_vote = 0;
+        __syncthreads();
+        if (tid < tile.count && p.mask[p.perm[tile.first + tid]]) *s_vote = 1;
+        __syncthreads();
+        if (*s_vote == 0) {
+            if (p.defer_out && tid < tile.count) p.defer_out[p.perm[tile.first + tid]] = 0;
+            return;
+        }
+    }
     const MapDesc md = p.maps[tile.map];
     const int K = md.K, m = p.m, per = K / m;
     const double2 *beams = p.beams + md.beam_off;  // this map's beam directions
@@ -1399,14 +1414,18 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
         // the rest of the workgroup waits for this: let it win issue slots from
         // other workgroups' walks on the same SIMD
         __builtin_amdgcn_s_setprio(3);
-        bool active = false, done = false;
+        bool active = false, done = false, defer = false;
         uint32_t ep = 0u;
         if (grp < tile.count) {
             const int e = p.perm[tile.first + grp];
             active = true;
             if (p.mode == 1) {
                 done = !p.mask || p.mask[e];
-                if (li == 0) s_jobs[grp].dst = 3;
+                defer = done && p.defer_bin && p.defer_bin[e] >= 0;
+                if (li == 0) {
+                    s_jobs[grp].dst = 3;
+                    if (p.defer_out) p.defer_out[e] = (uint8_t)defer;
+                }
                 ep = p.st.ep[e];
             } else {
                 // every state load is issued before the first use: one memory
@@ -1430,7 +1449,9 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
                 const bool term = goal || coll;
                 const bool trunc = (t >= p.horizon) && !term;
                 done = term || trunc;
+                defer = done && p.defer_bin && p.defer_bin[e] >= 0;
                 if (li == 0) {
+                    if (p.defer_out) p.defer_out[e] = (uint8_t)defer;
                     const float rew =
                         goal ? p.r_succ
                              : (coll ? p.r_coll
@@ -1464,10 +1485,10 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
                     }
                 }
             }
-            if (done) {
+            if (done && !defer) {
                 double c = 1.0, sn = 0.0;
                 ResetPose r;
-                if (p.pose) {
+                if (p.pose && (!p.pose_src || p.pose_src[e] >= 0)) {
                     r = given_pose(p, e);
                     sincos((double)r.th, &sn, &c);
                 } else {
@@ -1481,7 +1502,7 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
         }
         if (li == 0) {
             if (!active) s_jobs[grp].dst = 3;
-            s_misc[2 + grp] = (active && done) ? 1 : 0;
+            s_misc[2 + grp] = (active && done && !defer) ? 1 : 0;
         }
         __builtin_amdgcn_s_setprio(0);
     }
@@ -1705,7 +1726,9 @@ __global__ __launch_bounds__(64) void plain_step_kernel(StepParams p) {
     }
     if (!do_reset) return;
     const uint32_t ep = p.st.ep[e];
-    const ResetPose r = p.pose ? given_pose(p, e) : sample_reset(p, M, md, e, ep);
+    const ResetPose r = (p.pose && (!p.pose_src || p.pose_src[e] >= 0))
+                            ? given_pose(p, e)
+                            : sample_reset(p, M, md, e, ep);
     double c, sn;
     store_reset(p, e, ep, r, c, sn);
     observe_serial(p, M, md, (double)r.x, (double)r.y, c, sn, obs_row, -1);

@@ -287,6 +287,9 @@ navsim_status navsim_policy_rollout(navsim_t h, navsim_policy_t q, int32_t steps
     if (kernel != NAVSIM_KERNEL_FUSED && kernel != NAVSIM_KERNEL_PLAIN)
         return fail(NAVSIM_E_INVALID_ARG, "unknown kernel %d", kernel);
     if (flags & ~NAVSIM_ROLLOUT_GRAPH) return fail(NAVSIM_E_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (h->hook.run)
+        return fail(NAVSIM_E_UNSUPPORTED,
+                    "rollouts use the in-kernel sampler: detach the reset proposer first");
     if (!(noise_std >= 0.0f) || !isfinite(noise_std))
         return fail(NAVSIM_E_INVALID_ARG, "noise_std must be finite and >= 0");
     DeviceGuard dg(h->device);

@@ -47,6 +47,12 @@ struct ProposeArgs {
     const float *y;
     float *pose;
     int32_t *hops, *source, *checks;
+    // optional: requests = min(n, *n_dev) read on the device; outputs of
+    // request i at row slot[i] (else i); per-call totals added to stats
+    // {requests, from the network, from rejection, none valid, checks}
+    const int32_t *n_dev = nullptr;
+    const int32_t *slot = nullptr;
+    unsigned long long *stats = nullptr;
 };
 hipError_t launch_propose(const ReachParams &rp, const ProposeArgs &a, hipStream_t s);
 
@@ -62,8 +68,26 @@ struct NoiseArgs {
     const int32_t *map, *bin;
     uint16_t *z;
     int32_t *row_idx;
+    const int32_t *n_dev = nullptr;  // optional: requests = min(n, *n_dev) read on the device
 };
 hipError_t launch_noise(const NoiseArgs &a, uint32_t key0, uint32_t key1, hipStream_t s);
+
+// Requests of the envs that deferred their reset in a step: in env order,
+// env e with defer[e] != 0 and bin[e] >= 0 is request i (the first `cap`
+// only): env[i] = e, map[i] = env_map[e], bin[i] = bin[e], episode[i] =
+// ep[e]; src[e] = -1 for every such env (the proposal call then overwrites
+// the ones it serves); *n_out = min(count, cap); stats[0] += count,
+// stats[1] += count beyond cap.  One workgroup.
+struct CompactArgs {
+    int N, cap;
+    const uint8_t *defer;
+    const int32_t *bin, *env_map;
+    const uint32_t *ep;
+    uint32_t *env, *episode;
+    int32_t *map, *rbin, *src, *n_out;
+    unsigned long long *stats;
+};
+hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
 
 // Rows [pool(map) | one-hot(bin)] of every (map, bin), bfloat16, width
 // 1024 + nbins (the constant part of the first layer's input).

@@ -40,13 +40,20 @@ __device__ void stage_free(const ReachParams &rp, const ReachDesc &d, uint32_t *
 }
 
 // One search level: nx = (frontier moved by one step) & C-free & ~visited,
-// visited |= nx.  Returns the OR of this thread's nx words.
+// visited |= nx, over the words of rows r0..r1 and word columns c0..c1 only
+// (the caller's box holds every bit the level can set; nx, vis and fr are
+// zero outside it).  Returns the OR of this thread's nx words.
 __device__ uint32_t search_level(const ReachDesc &d, const uint32_t *fb, uint32_t *vis,
-                                 const uint32_t *fr, uint32_t *nx) {
+                                 const uint32_t *fr, uint32_t *nx, int r0, int r1, int c0,
+                                 int c1) {
     uint32_t any = 0;
-    const int wpr = d.wpr;
-    for (int w = threadIdx.x; w < d.words; w += blockDim.x) {
-        const int c = w % wpr, r = w / wpr;
+    const int wpr = d.wpr, nw = c1 - c0 + 1, total = (r1 - r0 + 1) * nw;
+    const float inv_nw = 1.0f / (float)nw;
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+        int rr = (int)((float)q * inv_nw);
+        if (rr * nw > q) --rr;
+        if ((rr + 1) * nw <= q) ++rr;
+        const int r = r0 + rr, c = c0 + (q - rr * nw), w = r * wpr + c;
         const uint32_t f = fr[w];
         uint32_t g = (f << 1) | (f >> 1);
         if (c > 0) g |= fr[w - 1] >> 31;
@@ -61,11 +68,31 @@ __device__ uint32_t search_level(const ReachDesc &d, const uint32_t *fb, uint32_
     return any;
 }
 
-// Clears vis and fr and seeds both with cell a (which must be C-free).
-__device__ void search_start(const ReachDesc &d, uint32_t *vis, uint32_t *fr, int a) {
-    for (int w = threadIdx.x; w < d.words; w += blockDim.x) {
-        vis[w] = 0u;
-        fr[w] = 0u;
+// Rows and word columns that level `level` (>= 1 moves from cell a) can reach.
+struct SearchBox {
+    int r0, r1, c0, c1;
+};
+
+__device__ __forceinline__ SearchBox level_box(const ReachDesc &d, int a, int level) {
+    const int i = a % d.W, j = a / d.W;
+    SearchBox b;
+    b.r0 = max(j - level, 0);
+    b.r1 = min(j + level, d.H - 1);
+    b.c0 = max(i - level, 0) >> 5;
+    b.c1 = min(i + level, d.W - 1) >> 5;
+    return b;
+}
+
+// Clears vis, fr and nx and seeds vis and fr with cell a (which must be C-free).
+__device__ void search_start(const ReachDesc &d, uint32_t *vis, uint32_t *fr, uint32_t *nx,
+                             int a) {
+    uint4 *v4 = reinterpret_cast<uint4 *>(vis), *f4 = reinterpret_cast<uint4 *>(fr),
+          *n4 = reinterpret_cast<uint4 *>(nx);
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (int w = threadIdx.x; w < (d.words + 3) / 4; w += blockDim.x) {
+        v4[w] = z;
+        f4[w] = z;
+        n4[w] = z;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -76,13 +103,18 @@ __device__ void search_start(const ReachDesc &d, uint32_t *vis, uint32_t *fr, in
 }
 
 // Hop count from C-free a to b within max_hops moves, else -1 (uniform
-// across the workgroup).
+// across the workgroup).  A 4-neighbour path is at least as long as the
+// Manhattan distance, so a farther b is rejected without a search, and level
+// L only touches the box of cells within L moves of a.
 __device__ int hops_to(const ReachDesc &d, const uint32_t *fb, uint32_t *vis, uint32_t *fr,
                        uint32_t *nx, int a, int b, int max_hops) {
     if (a == b) return 0;
-    search_start(d, vis, fr, a);
+    const int man = abs(a % d.W - b % d.W) + abs(a / d.W - b / d.W);
+    if (man > max_hops) return -1;
+    search_start(d, vis, fr, nx, a);
     for (int level = 0; level < max_hops; ++level) {
-        const uint32_t any = search_level(d, fb, vis, fr, nx);
+        const SearchBox bx = level_box(d, a, level + 1);
+        const uint32_t any = search_level(d, fb, vis, fr, nx, bx.r0, bx.r1, bx.c0, bx.c1);
         const int more = __syncthreads_or(any != 0u);
         if (cell_bit(nx, d, b)) return level + 1;
         if (!more) return -1;
@@ -167,7 +199,8 @@ __device__ __forceinline__ float cell_y(const ReachDesc &d, int c) {
 __global__ __launch_bounds__(kReachThreads) void label_kernel(ReachParams rp, const int32_t *map,
                                                               uint32_t first_sid, int32_t *start,
                                                               int32_t *goal, int32_t *hops) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ uint4 lds4[];  // 16-byte aligned: the searches clear it 16 bytes at a time
+    uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     __shared__ unsigned long long s_best[kReachMaxBins];
     const int i = blockIdx.x, tid = threadIdx.x;
     const int mk = map[i];
@@ -188,16 +221,25 @@ __global__ __launch_bounds__(kReachThreads) void label_kernel(ReachParams rp, co
     const int a = rp.free_cells[d.free_off + pick_of(c[0], d.free_cnt)];
     stage_free(rp, d, fb);
     if (tid < kReachMaxBins) s_best[tid] = ~0ull;
-    search_start(d, vis, fr, a);
+    search_start(d, vis, fr, nx, a);
     for (int level = 0; level < rp.max_hops; ++level) {
-        const uint32_t any = search_level(d, fb, vis, fr, nx);
+        const SearchBox bx = level_box(d, a, level + 1);
+        const uint32_t any = search_level(d, fb, vis, fr, nx, bx.r0, bx.r1, bx.c0, bx.c1);
         const int h = level + 1;
         const int k = rp.hop_bin[h];
         if (k >= 0 && any) {
+            // the words this thread wrote in search_level (same box, same
+            // order), so no barrier is needed before reading them
             unsigned long long best = ~0ull;
-            for (int w = tid; w < d.words; w += blockDim.x) {
-                uint32_t n = nx[w];
-                const int row = w / d.wpr, col0 = (w % d.wpr) * 32;
+            const int nw = bx.c1 - bx.c0 + 1, total = (bx.r1 - bx.r0 + 1) * nw;
+            const float inv_nw = 1.0f / (float)nw;
+            for (int qi = tid; qi < total; qi += blockDim.x) {
+                int rr = (int)((float)qi * inv_nw);
+                if (rr * nw > qi) --rr;
+                if ((rr + 1) * nw <= qi) ++rr;
+                const int row = bx.r0 + rr, wc = bx.c0 + (qi - rr * nw);
+                uint32_t n = nx[row * d.wpr + wc];
+                const int col0 = wc * 32;
                 while (n) {
                     const int bit = __ffs(n) - 1;
                     n &= n - 1u;
@@ -228,16 +270,23 @@ __global__ __launch_bounds__(kReachThreads) void label_kernel(ReachParams rp, co
 }
 
 __global__ __launch_bounds__(kReachThreads) void propose_kernel(ReachParams rp, ProposeArgs pa) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ uint4 lds4[];  // 16-byte aligned: the searches clear it 16 bytes at a time
+    uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     __shared__ int s_min;
     const int i = blockIdx.x, tid = threadIdx.x;
+    if (pa.n_dev && i >= *pa.n_dev) return;  // past the requests counted on the device
+    const int o = pa.slot ? pa.slot[i] : i;    // output row
     const int mk = pa.map[i], k = pa.bin[i];
     if (mk < 0 || mk >= rp.num_maps || k < 0 || k >= rp.nbins) {  // rejected request
-        if (tid < 5) pa.pose[(int64_t)i * 5 + tid] = 0.0f;
+        if (tid < 5) pa.pose[(int64_t)o * 5 + tid] = 0.0f;
         if (tid == 0) {
-            pa.hops[i] = -1;
-            pa.source[i] = -1;
-            pa.checks[i] = 0;
+            if (pa.hops) pa.hops[o] = -1;
+            pa.source[o] = -1;
+            if (pa.checks) pa.checks[o] = 0;
+            if (pa.stats) {
+                atomicAdd(&pa.stats[0], 1ull);
+                atomicAdd(&pa.stats[3], 1ull);
+            }
         }
         return;
     }
@@ -280,22 +329,69 @@ __global__ __launch_bounds__(kReachThreads) void propose_kernel(ReachParams rp, 
         }
     }
     if (tid == 0) {
-        float *p = pa.pose + (int64_t)i * 5;
+        float *p = pa.pose + (int64_t)o * 5;
         p[0] = ra >= 0 ? cell_x(d, ra) : 0.0f;
         p[1] = ra >= 0 ? cell_y(d, ra) : 0.0f;
         p[2] = th;
         p[3] = rb >= 0 ? cell_x(d, rb) : 0.0f;
         p[4] = rb >= 0 ? cell_y(d, rb) : 0.0f;
-        pa.hops[i] = rh;
-        pa.source[i] = src;
-        pa.checks[i] = checks;
+        if (pa.hops) pa.hops[o] = rh;
+        pa.source[o] = src;
+        if (pa.checks) pa.checks[o] = checks;
+        if (pa.stats) {
+            atomicAdd(&pa.stats[0], 1ull);
+            atomicAdd(&pa.stats[src < 0 ? 3 : (src < pa.props ? 1 : 2)], 1ull);
+            atomicAdd(&pa.stats[4], (unsigned long long)checks);
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void compact_kernel(CompactArgs a) {
+    __shared__ int s_wave[16];
+    __shared__ int s_base;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) s_base = 0;
+    __syncthreads();
+    for (int e0 = 0; e0 < a.N; e0 += 1024) {
+        const int e = e0 + tid;
+        const bool on = e < a.N && a.defer[e] != 0 && a.bin[e] >= 0;
+        const uint64_t bm = __ballot(on);
+        if (lane == 0) s_wave[wave] = __popcll(bm);
+        __syncthreads();
+        int before = s_base, total = 0;
+        for (int w = 0; w < 16; ++w) {
+            before += w < wave ? s_wave[w] : 0;
+            total += s_wave[w];
+        }
+        const int pos = before + __popcll(bm & ((1ull << lane) - 1ull));
+        if (on) {
+            a.src[e] = -1;
+            if (pos < a.cap) {
+                a.env[pos] = (uint32_t)e;
+                a.map[pos] = a.env_map[e];
+                a.rbin[pos] = a.bin[e];
+                a.episode[pos] = a.ep[e];
+            }
+        }
+        __syncthreads();
+        if (tid == 0) s_base += total;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int count = s_base;
+        *a.n_out = count < a.cap ? count : a.cap;
+        if (a.stats) {
+            atomicAdd(&a.stats[0], (unsigned long long)count);
+            atomicAdd(&a.stats[1], (unsigned long long)(count > a.cap ? count - a.cap : 0));
+        }
     }
 }
 
 __global__ void noise_kernel(NoiseArgs a, uint32_t key0, uint32_t key1) {
     const int nq = (a.nz + 3) / 4;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t rows = (int64_t)a.n * a.per;
+    const int n = a.n_dev ? min(a.n, *a.n_dev) : a.n;
+    const int64_t rows = (int64_t)n * a.per;
     if (idx >= rows * nq) return;
     const int64_t r = idx / nq;
     const int q = (int)(idx % nq);
@@ -413,6 +509,11 @@ hipError_t launch_propose(const ReachParams &rp, const ProposeArgs &a, hipStream
     if (a.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(propose_kernel, dim3((unsigned)a.n), dim3(kReachThreads), kSearchLds, s,
                        rp, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const CompactArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 

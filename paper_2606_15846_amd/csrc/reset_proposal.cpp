@@ -89,6 +89,23 @@ struct navsim_rp_s {
     int64_t adam_t = 0;
     uint32_t train_step = 0;
     void *scratch = nullptr;       // fixed per-device workspace (navsim_rp_propose_noalloc)
+    uint64_t param_version = 0;    // bumped whenever the parameters change
+    // learned resets inside the step (navsim_rp_attach): one device block
+    struct Attach {
+        bool on = false;
+        int props = 0, tries = 0, cap = 0;
+        void *block = nullptr;
+        int32_t *bin = nullptr, *src = nullptr, *hops = nullptr;  // [N]
+        uint8_t *defer = nullptr;                                 // [N]
+        float *pose = nullptr;                                    // [N][5]
+        uint32_t *r_env = nullptr, *r_ep = nullptr;               // [cap]
+        int32_t *r_map = nullptr, *r_bin = nullptr, *n_dev = nullptr;
+        unsigned long long *stats = nullptr;                      // [8]
+        float *ct = nullptr, *y = nullptr;
+        uint16_t *z = nullptr, *hc0 = nullptr, *hc1 = nullptr;
+        int32_t *ridx = nullptr;
+        uint64_t ct_version = ~0ull;
+    } at;
     // workspaces
     DevBuf ctable, colsum, x, hid[4], y, dyf, dyb, dh, dzf, dzb, lrows, zc, ridx, yc, hc[2],
         bmap, bbin, target, chosen, zp, rp_idx, yp;
@@ -159,7 +176,7 @@ navsim_status refresh_ctable(navsim_rp_s *r, float *ct, hipStream_t s) {
 // hc0, hc1 (bf16, R x hidden each).
 navsim_status forward_noise(navsim_rp_s *r, int R, const uint16_t *Z, const int32_t *row_idx,
                             float *Y, const float *ct, uint16_t *hc0, uint16_t *hc1,
-                            hipStream_t s) {
+                            hipStream_t s, const int32_t *m_dev = nullptr, int m_mul = 1) {
     const int Hd = hidden_width(r);
     uint16_t *hc[2] = {hc0, hc1};
     const float slope = r->cfg.leaky_slope;
@@ -178,6 +195,8 @@ navsim_status forward_noise(navsim_rp_s *r, int R, const uint16_t *Z, const int3
     g.slope = slope;
     g.Cb = hc[0];
     g.ldcb = Hd;
+    g.m_dev = m_dev;
+    g.m_mul = m_mul;
     RP_HIP(launch_gemm(g, s));
     int cur = 0;
     for (int l = 1; l < r->L; ++l) {
@@ -190,6 +209,8 @@ navsim_status forward_noise(navsim_rp_s *r, int R, const uint16_t *Z, const int3
         q.B = r->pb + r->w_off[l];
         q.ldb = r->dims[l];
         q.bias = r->p + r->b_off[l];
+        q.m_dev = m_dev;
+        q.m_mul = m_mul;
         if (l + 1 < r->L) {
             q.act = 1;
             q.slope = slope;
@@ -290,6 +311,7 @@ navsim_status backward_full(navsim_rp_s *r, int n, const uint16_t *X, const floa
 
 navsim_status adamw_step(navsim_rp_s *r, const float *grad, float lr, float wd, hipStream_t s) {
     r->adam_t += 1;
+    r->param_version += 1;
     RP_HIP(launch_adamw(r->nparams, r->p, r->pb, grad, r->m, r->v, r->decay, lr, 0.9f, 0.999f,
                         1e-8f, wd, r->adam_t, s));
     return NAVSIM_OK;
@@ -378,6 +400,87 @@ navsim_status propose_run(navsim_rp_s *r, int32_t n, const int32_t *map, const i
     pa.checks = checks;
     RP_HIP(launch_propose(r->rp, pa, s));
     return NAVSIM_OK;
+}
+
+// The in-step proposal pass (navsim_s::ResetHook::run): requests of the envs
+// that deferred their reset, noise draws and network outputs for them, then
+// the exact checks with the rejection sampler behind them; pairs go to the
+// envs' rows of the pose table.
+navsim_status rp_hook_run(void *ctx, hipStream_t s) {
+    navsim_rp_s *r = (navsim_rp_s *)ctx;
+    navsim_rp_s::Attach &A = r->at;
+    navsim_t h = r->h;
+    CompactArgs ca;
+    ca.N = h->cfg.num_envs;
+    ca.cap = A.cap;
+    ca.defer = A.defer;
+    ca.bin = A.bin;
+    ca.env_map = h->env_map;
+    ca.ep = h->st.ep;
+    ca.env = A.r_env;
+    ca.episode = A.r_ep;
+    ca.map = A.r_map;
+    ca.rbin = A.r_bin;
+    ca.src = A.src;
+    ca.n_out = A.n_dev;
+    ca.stats = A.stats;
+    RP_HIP(launch_compact(ca, s));
+    const float *y = nullptr;
+    if (A.props > 0) {
+        navsim_status st = NAVSIM_OK;
+        if (A.ct_version != r->param_version) {
+            if ((st = refresh_ctable(r, A.ct, s)) != NAVSIM_OK) return st;
+            A.ct_version = r->param_version;
+        }
+        NoiseArgs na;
+        na.n = A.cap;
+        na.per = A.props;
+        na.nz = r->cfg.noise_dim;
+        na.nbins = r->cfg.num_bins;
+        na.num_maps = r->num_maps;
+        na.c0 = A.r_env;
+        na.c1 = A.r_ep;
+        na.c1_const = 0u;
+        na.stream = 8u;
+        na.map = A.r_map;
+        na.bin = A.r_bin;
+        na.z = A.z;
+        na.row_idx = A.ridx;
+        na.n_dev = A.n_dev;
+        RP_HIP(launch_noise(na, r->rp.key0, r->rp.key1, s));
+        if ((st = forward_noise(r, A.cap * A.props, A.z, A.ridx, A.y, A.ct, A.hc0, A.hc1, s,
+                                A.n_dev, A.props)) != NAVSIM_OK)
+            return st;
+        y = A.y;
+    }
+    ProposeArgs pa;
+    pa.n = A.cap;
+    pa.props = A.props;
+    pa.tries = A.tries;
+    pa.map = A.r_map;
+    pa.bin = A.r_bin;
+    pa.env = A.r_env;
+    pa.episode = A.r_ep;
+    pa.y = y;
+    pa.pose = A.pose;
+    pa.hops = A.hops;
+    pa.source = A.src;
+    pa.checks = nullptr;
+    pa.n_dev = A.n_dev;
+    pa.slot = (const int32_t *)A.r_env;
+    pa.stats = A.stats + 2;
+    RP_HIP(launch_propose(r->rp, pa, s));
+    return NAVSIM_OK;
+}
+
+void detach_rp(navsim_rp_s *r) {
+    navsim_t h = r->h;
+    if (h && h->hook.ctx == r) h->hook = navsim_s::ResetHook{};
+    if (r->at.block) {
+        (void)hipDeviceSynchronize();  // steps in flight may still use the block
+        (void)hipFree(r->at.block);
+    }
+    r->at = navsim_rp_s::Attach{};
 }
 
 }  // namespace
@@ -795,6 +898,116 @@ navsim_status navsim_rp_set_params(navsim_rp_t r, const float *host, int64_t cou
     NS_HIP(hipMemcpy(r->p, host, (size_t)count * 4, hipMemcpyHostToDevice));
     NS_HIP(launch_to_bf16(count, r->p, r->pb, nullptr));
     NS_HIP(hipDeviceSynchronize());
+    r->param_version += 1;
+    return NAVSIM_OK;
+}
+
+navsim_status navsim_rp_attach(navsim_rp_t r, const int32_t *bin, int32_t proposals,
+                               int32_t max_tries, int32_t max_per_step) {
+    if (!r) return fail(NAVSIM_E_BAD_HANDLE, "proposer is NULL");
+    navsim_t h = r->h;
+    const int N = h->cfg.num_envs, nb = r->cfg.num_bins;
+    if (!bin) return fail(NAVSIM_E_INVALID_ARG, "bin (host int32 [num_envs]) is required");
+    if (proposals < 0 || proposals > 4096 || max_tries < 0 || max_per_step < 1 ||
+        max_per_step > N || (int64_t)max_per_step * proposals > (1 << 24))
+        return fail(NAVSIM_E_INVALID_ARG,
+                    "need proposals in 0..4096, max_tries >= 0, max_per_step in 1..num_envs and "
+                    "max_per_step * proposals <= 2^24");
+    for (int e = 0; e < N; ++e)
+        if (bin[e] < -1 || bin[e] >= nb)
+            return fail(NAVSIM_E_INVALID_ARG, "bin[%d] = %d is outside -1..%d", e, bin[e], nb - 1);
+    if (h->hook.run && h->hook.ctx != r)
+        return fail(NAVSIM_E_STATE, "another proposer is attached to this handle");
+    DeviceGuard dg(r->device);
+    if (dg.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(dg.err));
+    navsim_rp_s::Attach &A = r->at;
+    if (!(A.on && A.cap == max_per_step && A.props == proposals)) {
+        detach_rp(r);
+        const size_t R = (size_t)max_per_step * (size_t)proposals, Hd = (size_t)r->cfg.hidden;
+        const size_t parts[] = {(size_t)N * 4, (size_t)N * 4, (size_t)N * 4, (size_t)N,
+                                (size_t)N * 20, (size_t)max_per_step * 4, (size_t)max_per_step * 4,
+                                (size_t)max_per_step * 4, (size_t)max_per_step * 4, 256, 64,
+                                proposals ? ctable_bytes(r) : 0, R * 20,
+                                R * (size_t)r->cfg.noise_dim * 2, R * Hd * 2, R * Hd * 2, R * 4};
+        size_t total = 0;
+        for (size_t b : parts) total += align_up(b);
+        if (hipMalloc(&A.block, total) != hipSuccess) {
+            A.block = nullptr;
+            return fail(NAVSIM_E_OOM, "hipMalloc of %zu bytes for in-step proposals failed", total);
+        }
+        uint8_t *q = (uint8_t *)A.block;
+        void *ptrs[17];
+        for (int k = 0; k < 17; ++k) {
+            ptrs[k] = q;
+            q += align_up(parts[k]);
+        }
+        A.bin = (int32_t *)ptrs[0];
+        A.src = (int32_t *)ptrs[1];
+        A.hops = (int32_t *)ptrs[2];
+        A.defer = (uint8_t *)ptrs[3];
+        A.pose = (float *)ptrs[4];
+        A.r_env = (uint32_t *)ptrs[5];
+        A.r_ep = (uint32_t *)ptrs[6];
+        A.r_map = (int32_t *)ptrs[7];
+        A.r_bin = (int32_t *)ptrs[8];
+        A.n_dev = (int32_t *)ptrs[9];
+        A.stats = (unsigned long long *)ptrs[10];
+        A.ct = (float *)ptrs[11];
+        A.y = (float *)ptrs[12];
+        A.z = (uint16_t *)ptrs[13];
+        A.hc0 = (uint16_t *)ptrs[14];
+        A.hc1 = (uint16_t *)ptrs[15];
+        A.ridx = (int32_t *)ptrs[16];
+        A.cap = max_per_step;
+        A.props = proposals;
+        A.ct_version = ~0ull;
+        NS_HIP(hipMemset(A.block, 0, total));
+        NS_HIP(hipMemset(A.src, 0xff, (size_t)N * 4));
+        NS_HIP(hipMemset(A.hops, 0xff, (size_t)N * 4));
+    }
+    NS_HIP(hipDeviceSynchronize());  // steps in flight may read the old bins
+    NS_HIP(hipMemcpy(A.bin, bin, (size_t)N * 4, hipMemcpyHostToDevice));
+    A.tries = max_tries;
+    A.on = true;
+    h->hook.bin = A.bin;
+    h->hook.defer = A.defer;
+    h->hook.pose = A.pose;
+    h->hook.src = A.src;
+    h->hook.run = rp_hook_run;
+    h->hook.ctx = r;
+    return NAVSIM_OK;
+}
+
+navsim_status navsim_rp_detach(navsim_rp_t r) {
+    if (!r) return fail(NAVSIM_E_BAD_HANDLE, "proposer is NULL");
+    DeviceGuard dg(r->device);
+    detach_rp(r);
+    return NAVSIM_OK;
+}
+
+navsim_status navsim_rp_attach_stats(navsim_rp_t r, int64_t *out, int32_t clear) {
+    if (!r) return fail(NAVSIM_E_BAD_HANDLE, "proposer is NULL");
+    if (!out) return fail(NAVSIM_E_INVALID_ARG, "out (host int64 [8]) is required");
+    if (!r->at.on) return fail(NAVSIM_E_STATE, "the proposer is not attached");
+    DeviceGuard dg(r->device);
+    NS_HIP(hipDeviceSynchronize());
+    unsigned long long v[8];
+    NS_HIP(hipMemcpy(v, r->at.stats, sizeof v, hipMemcpyDeviceToHost));
+    for (int k = 0; k < 8; ++k) out[k] = (int64_t)v[k];
+    if (clear) NS_HIP(hipMemset(r->at.stats, 0, sizeof v));
+    return NAVSIM_OK;
+}
+
+navsim_status navsim_rp_attach_outputs(navsim_rp_t r, int32_t *source, int32_t *hops,
+                                       void *stream) {
+    if (!r) return fail(NAVSIM_E_BAD_HANDLE, "proposer is NULL");
+    if (!source || !hops) return fail(NAVSIM_E_INVALID_ARG, "source and hops are required");
+    if (!r->at.on) return fail(NAVSIM_E_STATE, "the proposer is not attached");
+    DeviceGuard dg(r->device);
+    const size_t bytes = (size_t)r->h->cfg.num_envs * 4;
+    const hipStream_t s = (hipStream_t)stream;
+    NS_HIP(hipMemcpyAsync(source, r->at.src, bytes, hipMemcpyDeviceToDevice, s));
+    NS_HIP(hipMemcpyAsync(hops, r->at.hops, bytes, hipMemcpyDeviceToDevice, s));
     return NAVSIM_OK;
 }
 
@@ -802,6 +1015,7 @@ navsim_status navsim_rp_destroy(navsim_rp_t r) {
     if (!r) return fail(NAVSIM_E_BAD_HANDLE, "proposer is NULL");
     {
         DeviceGuard dg(r->device);
+        detach_rp(r);
         (void)hipDeviceSynchronize();
         free_rp(r);
     }

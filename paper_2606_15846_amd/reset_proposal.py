@@ -16,7 +16,11 @@ from . import navsim as _ns
 EXPORTS = ("navsim_rp_create", "navsim_rp_label", "navsim_rp_train", "navsim_rp_propose",
            "navsim_rp_propose_noalloc", "navsim_rp_forward", "navsim_rp_loss_grad",
            "navsim_rp_adamw", "navsim_rp_layout",
-           "navsim_rp_get_params", "navsim_rp_set_params", "navsim_rp_destroy")
+           "navsim_rp_get_params", "navsim_rp_set_params", "navsim_rp_destroy",
+           "navsim_rp_attach", "navsim_rp_detach", "navsim_rp_attach_stats",
+           "navsim_rp_attach_outputs")
+STAT_NAMES = ("deferred", "over_cap", "requests", "from_network", "from_rejection", "no_pair",
+              "checks")
 
 
 class RPConfig(C.Structure):
@@ -48,6 +52,10 @@ def _lib():
         L.navsim_rp_get_params.argtypes = [vp, vp, i64]
         L.navsim_rp_set_params.argtypes = [vp, vp, i64]
         L.navsim_rp_destroy.argtypes = [vp]
+        L.navsim_rp_attach.argtypes = [vp, vp, i32, i32, i32]
+        L.navsim_rp_detach.argtypes = [vp]
+        L.navsim_rp_attach_stats.argtypes = [vp, vp, i32]
+        L.navsim_rp_attach_outputs.argtypes = [vp, vp, vp, vp]
         for n in EXPORTS:
             getattr(L, n).restype = C.c_int
         _DONE = True
@@ -154,6 +162,31 @@ class ResetProposer:
             _ptr(out["pose"]), _ptr(out["hops"]), _ptr(out["source"]), _ptr(out["checks"]),
             _ptr(out.get("y"), optional=True), self._stream()))
         return out
+
+    def attach(self, bins, proposals: int, max_tries: int, max_per_step: int):
+        """Learned resets inside NavSim.step / reset for envs with bins[e] >= 0
+        (navsim_rp_attach); bins: int [num_envs], -1 = free-space sampler."""
+        b = np.ascontiguousarray(np.asarray(bins, np.int32))
+        if b.shape != (self.sim.N,):
+            raise ValueError(f"bins must have shape ({self.sim.N},)")
+        _ns._check(_lib().navsim_rp_attach(self.h, b.ctypes.data, int(proposals),
+                                           int(max_tries), int(max_per_step)))
+
+    def detach(self):
+        _ns._check(_lib().navsim_rp_detach(self.h))
+
+    def attach_stats(self, clear: bool = False) -> dict:
+        out = np.zeros(8, np.int64)
+        _ns._check(_lib().navsim_rp_attach_stats(self.h, out.ctypes.data, int(bool(clear))))
+        return {k: int(v) for k, v in zip(STAT_NAMES, out)}
+
+    def attach_outputs(self) -> tuple[torch.Tensor, torch.Tensor]:
+        """(source, hops) per env of the last step or reset (device int32 [N])."""
+        z = dict(dtype=torch.int32, device=self.device)
+        src, hops = torch.empty(self.sim.N, **z), torch.empty(self.sim.N, **z)
+        _ns._check(_lib().navsim_rp_attach_outputs(self.h, _ptr(src), _ptr(hops),
+                                                   self._stream()))
+        return src, hops
 
     def forward(self, x_bits: torch.Tensor) -> torch.Tensor:
         n = x_bits.shape[0]

@@ -28,7 +28,7 @@ def declared_functions():
 def test_library_exports_every_declared_function():
     lib = navsim.load_library()
     names = declared_functions()
-    assert len(names) == 35
+    assert len(names) == 39
     for n in names:
         assert hasattr(lib, n), n
     from paper_2606_15846_amd import policy, reset_proposal

@@ -251,3 +251,40 @@ def test_fallback_when_free_space_is_tiny():
     assert np.all(fb & 2)
     assert np.any(fb & 1)
     _check_reset_rows(sim, obs, fb, range(16))
+
+
+def test_deferred_reset_then_masked_reset_equals_the_plain_step():
+    # an env whose reset is deferred keeps its post-step state and counters;
+    # resetting exactly the deferred envs afterwards draws the same poses
+    # (the draw depends only on env, episode and attempt), so the two-part
+    # step equals the plain one, and envs without a bin are reset as usual
+    w = configs.build_workload("c2", num_envs=48)
+    a = oracle.OracleSim(w["cfg"], w["maps"], w["res"], w["env_map"])
+    b = oracle.OracleSim(w["cfg"], w["maps"], w["res"], w["env_map"])
+    a.reset()
+    st = a.get_state()
+    st["t"][::3] = 199  # a third of the envs truncate in the next step
+    a.set_state(st)
+    b.set_state(st)
+    bins = np.where(np.arange(48) % 2 == 0, np.arange(48) % 8, -1).astype(np.int32)
+    act = configs.uniform_actions(1, 48, seed=9)[0]
+    oa = a.step(act)
+    ob = b.step(act, defer_bin=bins)
+    for k in ("terminated", "truncated", "reward", "collision", "reset", "final_obs"):
+        assert np.array_equal(oa[k], ob[k]), k
+    done = ob["reset"].astype(bool)
+    deferred = done & (bins >= 0)
+    assert deferred.sum() >= 4 and (done & (bins < 0)).sum() >= 4
+    after = b.get_state()
+    # deferred envs: the post-step pose, episode counter unchanged
+    assert np.array_equal(after["ep"][deferred], st["ep"][deferred])
+    assert np.all(after["t"][deferred] == st["t"][deferred] + 1)
+    # every other env: the plain step's state and observation
+    keep = ~deferred
+    for k in oracle.STATE_KEYS:
+        assert np.array_equal(after[k][keep], a.state[k][keep]), k
+    assert np.array_equal(ob["obs"][keep], oa["obs"][keep])
+    obs2, _ = b.reset(deferred.astype(np.uint8))
+    for k in oracle.STATE_KEYS:
+        assert np.array_equal(b.state[k], a.state[k]), k
+    assert np.array_equal(obs2[deferred], oa["obs"][deferred])
