@@ -8,6 +8,12 @@ r 0.18 m or 0.70 x 0.31 m rectangle), r_max 8 m, dt 0.05 s, uniform random
 actions with reverse, auto-reset, all envs in one launch per step.  A second
 leg times the 4096-env workload (16 maps 128x128, 360 beams, r_max 6 m).
 
+A third leg runs the learned reset proposal on its own workload (65,536
+envs on 64 rooms maps 256x256, 8 difficulty bins): labelling, training, the
+network against the rejection sampler on the same requests, and the step
+with the proposer attached, so that every sparse reset takes a verified pair
+at the env's requested difficulty, timed against the same step without it.
+
 Before the warm-up an untimed burn-in of several episode horizons runs the
 envs into their steady mix of episode ages, so the timed steps hold the steady
 share of resets (auto-resets inside the step).  Inputs are resident in HBM
@@ -256,7 +262,7 @@ def cpu_baseline(w, acts_np, start_state, gpu_first, rays_per_env_step: float,
             "parity_sample": parity}
 
 
-def reset_proposal_gain(sim, w, args) -> dict:
+def reset_proposal_gain(sim, w, args, keep_proposer: bool = False) -> dict:
     """Learned reset proposal against the plain rejection sampler on the
     workload's maps: label pairs with the GPU search, train the network, then
     answer the same requests (uniform over the bins) both ways and time them.
@@ -317,7 +323,76 @@ def reset_proposal_gain(sim, w, args) -> dict:
                      "in_requested_bin": float(((geo >= lo) & (geo < lo + width)).mean()),
                      "difficulty_error_m": float(np.abs(geo - (lo + width / 2)).mean())}
     out["gain_resets_per_s"] = out["learned"]["resets_per_s"] / out["rejection"]["resets_per_s"]
+    if keep_proposer:
+        out["_proposer"] = rp
+    else:
+        rp.close()
+    return out
+
+
+def learned_reset_leg(args) -> dict:
+    """The learned reset proposal on its own workload (65,536 envs, 64 rooms
+    maps 256x256, 8 difficulty bins over 1-12 m): label pairs, train the
+    network, compare it with the rejection sampler on the same requests, then
+    attach it to the step (every env asks for bin env mod 8) and time steps
+    whose sparse resets take verified pairs from it, against the same step
+    with the free-space sampler."""
+    import torch
+    from paper_2606_15846_amd.navsim import NavSim
+    from workloads import configs
+
+    w = configs.build_workload(args.proposal_workload)
+    cfg = w["cfg"]
+    N = cfg["num_envs"]
+    sim = NavSim(cfg, w["maps"], w["res"], w["env_map"], device=0)
+    tuning, _ = tuning_for(w, argparse.Namespace())
+    sim.set_tuning(**tuning)
+    sim.reset()
+    log(f"learned resets: {N} envs built; burn-in of {args.burn_in} steps")
+    burn_in(sim, args.burn_in, seed=77)
+    g = torch.Generator(device=sim.device)
+    g.manual_seed(78)
+
+    def timed(k):
+        acts = [torch.rand((N, 2), generator=g, device=sim.device) * 2.0 - 1.0 for _ in range(k)]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for a in acts:
+            sim.step(a)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    steps = args.proposal_steps
+    plain_ms = timed(steps)
+    out = {"workload": w["name"], "steps": steps,
+           "free_space_step": {"ms_per_step": plain_ms, "env_steps_per_s": N / (plain_ms / 1e3)}}
+    log("learned resets: labelling and training")
+    out["offline"] = reset_proposal_gain(sim, w, args, keep_proposer=True)
+    rp = out["offline"].pop("_proposer")
+    P, T, cap = 32, 400, min(N, 2048)
+    rp.attach((np.arange(N) % rp.nb).astype(np.int32), proposals=P, max_tries=T,
+              max_per_step=cap)
+    timed(20)  # warm: the first resets of the attached proposer
+    rp.attach_stats(clear=True)
+    log("learned resets: attached steps")
+    ms = timed(steps)
+    st = rp.attach_stats()
+    out["in_step"] = {
+        "ms_per_step": ms, "env_steps_per_s": N / (ms / 1e3),
+        "proposals": P, "max_tries": T, "max_per_step": cap,
+        "bins": "env mod 8 (every env asks for a bin)",
+        "resets_per_step": st["deferred"] / steps,
+        "learned_resets_per_s": st["requests"] / (ms * steps / 1e3),
+        "from_network": st["from_network"] / max(st["requests"], 1),
+        "from_rejection": st["from_rejection"] / max(st["requests"], 1),
+        "no_valid_pair": st["no_pair"] / max(st["requests"], 1),
+        "over_cap": st["over_cap"] / max(st["deferred"], 1),
+        "exact_checks_per_reset": st["checks"] / max(st["requests"], 1),
+        "step_time_vs_free_space": ms / plain_ms}
     rp.close()
+    sim.close()
     return out
 
 
@@ -504,9 +579,6 @@ def run_fused_leg(name: str, args, steps: int, warmup: int, lds_peak, full: bool
                         "steps": a1 - a0, "ms_per_step": pms / (a1 - a0),
                         "mapping": "one thread per env, beams in sequence, bitmap in HBM"}
         out["speedup_vs_plain"] = value / prate
-    if w.get("proposer") and not args.no_proposal:
-        log(f"{name}: reset proposal leg")
-        out["reset_proposal"] = reset_proposal_gain(sim, w, args)
     sim.close()
     if not args.no_cpu:
         log(f"{name}: oracle on the host cores")
@@ -536,6 +608,9 @@ def main():
     ap.add_argument("--label-starts", type=int, default=131072)
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--proposal-requests", type=int, default=8192)
+    ap.add_argument("--proposal-workload", default="c5",
+                    help="workload of the learned reset leg (needs a proposer config)")
+    ap.add_argument("--proposal-steps", type=int, default=50)
     ap.add_argument("--march-step", type=float, default=0.03)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -576,6 +651,9 @@ def main():
         print(json.dumps({"lds_peak_probe": lds_peak}))
         return
     head = run_fused_leg(args.workload, args, args.steps, args.warmup, lds_peak, full=True)
+    learned = None
+    if not args.no_proposal:
+        learned = learned_reset_leg(args)
     second = None
     if args.secondary and args.secondary != args.workload:
         second = run_fused_leg(args.secondary, args, args.secondary_steps, args.warmup, lds_peak,
@@ -620,7 +698,7 @@ def main():
         "graph_rollout": head.get("graph_rollout"),
         "policy_rollout": head.get("policy_rollout"),
         "march_scan": head.get("march_scan"),
-        "reset_proposal": head.get("reset_proposal"),
+        "learned_reset": learned,
         "tuning": head["tuning"],
         "lds_peak_probe": lds_peak,
         "secondary": second,

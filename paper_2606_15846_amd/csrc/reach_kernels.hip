@@ -269,6 +269,212 @@ __global__ __launch_bounds__(kReachThreads) void label_kernel(ReachParams rp, co
     if (tid == 0) start[i] = a;
 }
 
+// ---------------------------------------------------------------------------
+// Searches in one wavefront's registers, for maps whose rows take WPR words
+// with WPR dividing 32 (W <= 32, 64, ..., 1024 cells): lane l holds words
+// [32 l, 32 l + 32) of the row-major C-free bitset, i.e. 32 / WPR whole rows,
+// so a row's left and right carries stay in the lane and only the rows above
+// the lane's first and below its last come from lanes l - 1 and l + 1
+// (cross-lane moves).  No LDS and no workgroup barrier per level: the four
+// wavefronts of a workgroup check four candidates at once.
+
+// Word j (uniform) of a lane's 32 registers, without dynamic register indexing.
+__device__ __forceinline__ uint32_t pick_word(const uint32_t v[32], int j) {
+    uint32_t out = 0u;
+#pragma unroll
+    for (int q = 0; q < 32; ++q)
+        if (q == j) out = v[q];
+    return out;
+}
+
+// Hop count from a to b (both C-free, a != b) within max_hops moves, else -1
+// (uniform across the wavefront); the same levels as hops_to.
+template <int WPR>
+__device__ int wave_hops(const uint32_t cf[32], const ReachDesc &d, int a, int b, int max_hops,
+                         int lane) {
+    const int wa = (a / d.W) * WPR + ((a % d.W) >> 5);
+    const int wb = (b / d.W) * WPR + ((b % d.W) >> 5);
+    const int la = wa >> 5, ja = wa & 31, lb = wb >> 5, jb = wb & 31;
+    const uint32_t ba = 1u << ((a % d.W) & 31), bb = (b % d.W) & 31;
+    uint32_t fr[32], vis[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const uint32_t seed = (lane == la && j == ja) ? ba : 0u;
+        fr[j] = seed;
+        vis[j] = seed;
+    }
+    for (int level = 1; level <= max_hops; ++level) {
+        uint32_t up[WPR], dn[WPR];
+#pragma unroll
+        for (int k = 0; k < WPR; ++k) {
+            // rows above the lane's first: the last row of lane - 1; below its
+            // last: the first row of lane + 1 (none past the ends)
+            const uint32_t u = __shfl_up(fr[32 - WPR + k], 1);
+            const uint32_t w = __shfl_down(fr[k], 1);
+            up[k] = lane > 0 ? u : 0u;
+            dn[k] = lane < 63 ? w : 0u;
+        }
+        uint32_t any = 0u, nx[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const uint32_t f = fr[j];
+            uint32_t g = (f << 1) | (f >> 1);
+            if (j % WPR != 0) g |= fr[j - 1] >> 31;
+            if (j % WPR != WPR - 1) g |= fr[j + 1] << 31;
+            g |= j >= WPR ? fr[j >= WPR ? j - WPR : 0] : up[j < WPR ? j : 0];
+            g |= j + WPR < 32 ? fr[j + WPR < 32 ? j + WPR : 0] : dn[j + WPR >= 32 ? j + WPR - 32 : 0];
+            nx[j] = g & cf[j] & ~vis[j];
+            any |= nx[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            vis[j] |= nx[j];
+            fr[j] = nx[j];
+        }
+        const uint32_t gw = __shfl(pick_word(nx, jb), lb);
+        if ((gw >> bb) & 1u) return level;
+        if (__ballot(any != 0u) == 0ull) return -1;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ bool lds_cell(const uint32_t *fb, const ReachDesc &d, int c) {
+    return (fb[(c / d.W) * d.wpr + ((c % d.W) >> 5)] >> ((c % d.W) & 31)) & 1u;
+}
+
+// Nearest C-free cell to c (least |di| + |dj|, then least index; -1 if none),
+// by one wavefront: the cells of ring r split over the lanes, a ballot and a
+// lane minimum.
+__device__ int wave_snap(const ReachDesc &d, const uint32_t *fb, int c, int lane) {
+    if (lds_cell(fb, d, c)) return c;
+    const int i0 = c % d.W, j0 = c / d.W;
+    for (int r = 1; r <= d.W + d.H; ++r) {
+        int best = INT_MAX;
+        for (int q = lane; q < 4 * r; q += 64) {
+            const int side = q / r, t = q % r;
+            const int di = side == 0 ? r - t : (side == 1 ? -t : (side == 2 ? t - r : t));
+            const int dj = side == 0 ? t : (side == 1 ? r - t : (side == 2 ? -t : t - r));
+            const int i = i0 + di, j = j0 + dj;
+            if (i >= 0 && i < d.W && j >= 0 && j < d.H && lds_cell(fb, d, j * d.W + i))
+                best = min(best, j * d.W + i);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o));
+        if (best != INT_MAX) return best;
+    }
+    return -1;
+}
+
+// The exact check of (a, b) for bin k by one wavefront (see check_pair).
+template <int WPR>
+__device__ int wave_check(const ReachParams &rp, const ReachDesc &d, const uint32_t *fb,
+                          const uint32_t cf[32], int a, int b, int k, int lane) {
+    if (a < 0 || b < 0 || !lds_cell(fb, d, a) || !lds_cell(fb, d, b)) return -1;
+    if (centre_dist(d, a, b) < rp.gmd) return -1;
+    const int hi = rp.bin_hi[k];
+    int h;
+    if (a == b) {
+        h = 0;
+    } else {
+        const int man = abs(a % d.W - b % d.W) + abs(a / d.W - b / d.W);
+        h = man > hi ? -1 : wave_hops<WPR>(cf, d, a, b, hi, lane);
+    }
+    return (h >= 0 && rp.hop_bin[h] == k) ? h : -1;
+}
+
+// Candidate c of request i: network draw c < props (decoded, snapped), else
+// rejection attempt c - props.  Returns the pair and the heading.
+__device__ void candidate(const ReachParams &rp, const ProposeArgs &pa, const ReachDesc &d,
+                          const uint32_t *fb, int i, int c, int lane, int &a, int &b,
+                          float &th) {
+    if (c < pa.props) {
+        const float *y = pa.y + ((int64_t)i * pa.props + c) * 5;
+        const int a0 = decode_axis(y[1], d.H) * d.W + decode_axis(y[0], d.W);
+        const int b0 = decode_axis(y[4], d.H) * d.W + decode_axis(y[3], d.W);
+        a = wave_snap(d, fb, a0, lane);
+        b = wave_snap(d, fb, b0, lane);
+        th = decode_heading(y[2]);
+    } else {
+        uint32_t q[4] = {pa.env[i], pa.episode[i], (uint32_t)(c - pa.props), 7u};
+        philox4x32_10(q, rp.key0, rp.key1);
+        a = rp.free_cells[d.free_off + pick_of(q[0], d.free_cnt)];
+        b = rp.free_cells[d.free_off + pick_of(q[1], d.free_cnt)];
+        th = (float)((((double)q[2] + 0.5) / kTwo32) * (2.0 * kPiR) - kPiR);
+    }
+}
+
+// Proposals with one candidate per wavefront: candidates 4 r .. 4 r + 3 are
+// checked together and the lowest valid one wins, the result of checking
+// them in order; `checks` counts as the sequential search does.
+template <int WPR>
+__device__ void propose_waves(const ReachParams &rp, const ProposeArgs &pa, const ReachDesc &d,
+                              const uint32_t *fb, int i, int o, int k) {
+    __shared__ int s_ok[4], s_a[4], s_b[4], s_h[4];
+    __shared__ float s_th[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t cf[32];
+    const int base = lane * 32;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) cf[j] = base + j < d.words ? fb[base + j] : 0u;
+    const int total = pa.props + (d.free_cnt > 0 ? pa.tries : 0);
+    int win = -1, la = -1, lb = -1, lh = -1;
+    float lth = 0.0f;
+    for (int c0 = 0; c0 < total && win < 0; c0 += 4) {
+        const int c = c0 + wave;
+        int a = -1, b = -1, h = -1;
+        float th = 0.0f;
+        if (c < total) {
+            candidate(rp, pa, d, fb, i, c, lane, a, b, th);
+            h = wave_check<WPR>(rp, d, fb, cf, a, b, k, lane);
+        }
+        if (lane == 0) {
+            s_ok[wave] = (c < total && h >= 0) ? c : INT_MAX;
+            s_a[wave] = a;
+            s_b[wave] = b;
+            s_h[wave] = h;
+            s_th[wave] = th;
+        }
+        __syncthreads();
+        int best = INT_MAX, bw = -1;
+        for (int w = 0; w < 4; ++w)
+            if (s_ok[w] < best) {
+                best = s_ok[w];
+                bw = w;
+            }
+        if (bw >= 0) {
+            win = best;
+            la = s_a[bw];
+            lb = s_b[bw];
+            lh = s_h[bw];
+            lth = s_th[bw];
+        } else if (total - 1 >= c0 && total - 1 < c0 + 4 && total - 1 >= pa.props) {
+            // none valid: the last rejection attempt's pair stands
+            const int w = total - 1 - c0;
+            la = s_a[w];
+            lb = s_b[w];
+            lth = s_th[w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float *p = pa.pose + (int64_t)o * 5;
+        p[0] = la >= 0 ? cell_x(d, la) : 0.0f;
+        p[1] = la >= 0 ? cell_y(d, la) : 0.0f;
+        p[2] = lth;
+        p[3] = lb >= 0 ? cell_x(d, lb) : 0.0f;
+        p[4] = lb >= 0 ? cell_y(d, lb) : 0.0f;
+        const int checks = win >= 0 ? win + 1 : total;
+        if (pa.hops) pa.hops[o] = win >= 0 ? lh : -1;
+        pa.source[o] = win;
+        if (pa.checks) pa.checks[o] = checks;
+        if (pa.stats) {
+            atomicAdd(&pa.stats[0], 1ull);
+            atomicAdd(&pa.stats[win < 0 ? 3 : (win < pa.props ? 1 : 2)], 1ull);
+            atomicAdd(&pa.stats[4], (unsigned long long)checks);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kReachThreads) void propose_kernel(ReachParams rp, ProposeArgs pa) {
     extern __shared__ uint4 lds4[];  // 16-byte aligned: the searches clear it 16 bytes at a time
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
@@ -295,6 +501,16 @@ __global__ __launch_bounds__(kReachThreads) void propose_kernel(ReachParams rp, 
              *nx = fr + kReachMaxWords;
     stage_free(rp, d, fb);
     __syncthreads();
+    if (blockDim.x == 256 && d.wpr * d.H <= kReachMaxWords && 32 % d.wpr == 0) {
+        switch (d.wpr) {  // rows of 1, 2, 4, ..., 32 words: searches in registers
+            case 1: propose_waves<1>(rp, pa, d, fb, i, o, k); return;
+            case 2: propose_waves<2>(rp, pa, d, fb, i, o, k); return;
+            case 4: propose_waves<4>(rp, pa, d, fb, i, o, k); return;
+            case 8: propose_waves<8>(rp, pa, d, fb, i, o, k); return;
+            case 16: propose_waves<16>(rp, pa, d, fb, i, o, k); return;
+            default: propose_waves<32>(rp, pa, d, fb, i, o, k); return;
+        }
+    }
     int checks = 0, src = -1, ra = -1, rb = -1, rh = -1;
     float th = 0.0f;
     for (int j = 0; j < pa.props && src < 0; ++j) {
