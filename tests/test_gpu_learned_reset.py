@@ -122,11 +122,12 @@ def test_learned_resets_inside_the_step_against_oracle():
     acts = configs.uniform_actions(6, N, seed=17)
     tot = dict(deferred=0, network=0, rejection=0, free=0)
     for step in range(6):
-        st = sim.get_state()
+        # the oracle's own state (bitwise the GPU's: compare_step asserts it)
+        st = ref.get_state()
         if step % 2 == 0:
             st["t"][(np.arange(N) + step) % 3 == 0] = 199  # a third truncate now
             sim.set_state(st)
-        ref.set_state(st)
+            ref.set_state(st)
         g, gst = parity.gpu_step(sim, acts[step], kernel=0)
         r = ref.step(acts[step], threads=8, defer_bin=bins)
         deferred = r["reset"].astype(bool) & (bins >= 0)
@@ -154,8 +155,10 @@ def test_learned_resets_in_masked_reset_and_detach():
     bins = (np.arange(N) % 8).astype(np.int32)
     rp.attach(bins, proposals=PROPS, max_tries=TRIES, max_per_step=CAP)
     mask = (np.arange(N) % 3 == 1).astype(np.uint8)
-    pre = sim.get_state()
-    ref.set_state(pre)
+    pre = ref.get_state()
+    g0 = sim.get_state()
+    for k in oracle.STATE_KEYS:
+        assert np.array_equal(g0[k], pre[k]), k
     obs = sim.reset(torch.from_numpy(mask).to(sim.device)).cpu().numpy()
     torch.cuda.synchronize()
     r = {"obs": np.zeros((N, sim.m + 4), np.float32), "fallback": np.zeros(N, np.uint8)}
@@ -180,8 +183,6 @@ def test_learned_resets_in_masked_reset_and_detach():
     with pytest.raises(NavsimError, match="detach"):
         sim.rollout(4, first_step=0, buffers=sim.rollout_buffers(4), graph=False)
     rp.detach()
-    st = sim.get_state()
-    ref.set_state(st)
     g, gst = parity.gpu_step(sim, act.cpu().numpy(), kernel=0)
     r = ref.step(act.cpu().numpy(), threads=8)
     parity.compare_step(g, r, gst, ref, label="after detach")
