@@ -332,10 +332,16 @@ __device__ __forceinline__ void walk_result(const RayOrigin &o, int pitch, int W
                                             int &hit) {
     const int row = small_div(B, pitch, __builtin_amdgcn_rcpf((float)pitch)), col = B - row * pitch;
     const int ix = col - kPad, iy = row - kPad;
-    const double ninf = -__builtin_huge_val();
-    const double tx = dx != 0.0 ? (((double)(dx > 0.0 ? ix : ix + 1)) * o.s - o.x) / dx : ninf;
-    const double ty = dy != 0.0 ? (((double)(dy > 0.0 ? iy : iy + 1)) * o.s - o.y) / dy : ninf;
-    double t = tx > ty ? tx : ty;
+    // t_x = X / dx and t_y = Y / dy (a zero component gives -inf); the later
+    // one is picked without dividing, t_x > t_y iff X sgn(dx) |dy| > Y sgn(dy)
+    // |dx| (both sides scaled by |dx| |dy| > 0), and only it is divided.  The
+    // products can misorder the two only when they agree to ~1 ulp, i.e. for a
+    // ray through a grid corner, and the value is then the same either way
+    const double X = ((double)(dx > 0.0 ? ix : ix + 1)) * o.s - o.x;
+    const double Y = ((double)(dy > 0.0 ? iy : iy + 1)) * o.s - o.y;
+    const bool use_x =
+        dy == 0.0 || (dx != 0.0 && (dx > 0.0 ? X : -X) * fabs(dy) > (dy > 0.0 ? Y : -Y) * fabs(dx));
+    double t = use_x ? X / dx : Y / dy;
     t = t > 0.0 ? t : 0.0;  // also maps -0 and NaN to +0
     t = t < rmax ? t : rmax;
     range = (float)t;
@@ -1205,6 +1211,57 @@ __device__ __forceinline__ void walk_groups(const StepParams &p, const uint32_t 
     Eh = (int)(S >> 32);
 }
 
+// Up to `groups` groups of 4 cells of one lane's walk, for the claim walk:
+// the state is S = Eh : B alone (an x crossing adds Dx = dEx : incx, a y
+// crossing Dy = dEy : incy, see walk_groups) and the cells left in the r_max
+// budget, rem.  One exit test per group: a cell of the group is occupied, or
+// the budget ends in it; then the first occupied cell within the budget is
+// the hit (Bh, flags = 1, rem reduced by the cells walked up to it), else
+// the budget is used up (rem = 0); act turns false.
+template <bool BYTES>
+__device__ __forceinline__ void walk_run(const StepParams &p, const uint32_t *s_bits,
+                                         uint64_t &S, uint64_t Dx, uint64_t Dy, int &rem,
+                                         uint32_t &flags, bool &act, int &Bh) {
+#pragma unroll 1
+    for (int gi = 0; gi < p.groups; ++gi) {
+        // the sign of S is the sign of its high word
+        const uint64_t S0 = S + ((int)(uint32_t)(S >> 32) < 0 ? Dx : Dy);
+        const uint64_t S1 = S0 + ((int)(uint32_t)(S0 >> 32) < 0 ? Dx : Dy);
+        const uint64_t S2 = S1 + ((int)(uint32_t)(S1 >> 32) < 0 ? Dx : Dy);
+        const uint64_t S3 = S2 + ((int)(uint32_t)(S2 >> 32) < 0 ? Dx : Dy);
+        const int B0 = (int)(uint32_t)S0, B1 = (int)(uint32_t)S1;
+        const int B2 = (int)(uint32_t)S2, B3 = (int)(uint32_t)S3;
+        uint32_t h;
+        if (BYTES) {
+            typedef __attribute__((address_space(3))) const uint8_t lds_u8;
+            const lds_u8 *cells = reinterpret_cast<const lds_u8 *>(static_cast<uintptr_t>(0));
+            h = (uint32_t)cells[B0] | ((uint32_t)cells[B1] << 1) | ((uint32_t)cells[B2] << 2) |
+                ((uint32_t)cells[B3] << 3);
+        } else {
+            const uint32_t w0 = s_bits[B0 >> 5], w1 = s_bits[B1 >> 5];
+            const uint32_t w2 = s_bits[B2 >> 5], w3 = s_bits[B3 >> 5];
+            h = __builtin_amdgcn_ubfe(w0, (uint32_t)B0, 1u) |
+                (__builtin_amdgcn_ubfe(w1, (uint32_t)B1, 1u) << 1) |
+                (__builtin_amdgcn_ubfe(w2, (uint32_t)B2, 1u) << 2) |
+                (__builtin_amdgcn_ubfe(w3, (uint32_t)B3, 1u) << 3);
+        }
+        if (h != 0u || rem <= 4) {
+            const int f = (int)__builtin_ctz(h | 16u);
+            if (f < rem) {
+                Bh = f == 0 ? B0 : (f == 1 ? B1 : (f == 2 ? B2 : B3));
+                flags = 1u;
+                rem -= f + 1;
+            } else {
+                rem = 0;
+            }
+            act = false;
+            break;
+        }
+        S = S3;
+        rem -= 4;
+    }
+}
+
 // Group walk: lanes take rays from s_misc[1]; a lane whose ray is done
 // writes its result back and takes a new one once at most refill_at lanes of
 // its wavefront are still walking.  Cells are read from the bitmap, or (BYTES)
@@ -1274,7 +1331,8 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
                                            double rmax_c, int max_n, int E, int lane) {
     int g = -1, job = 0, beam = 0;
     bool act = false, exhausted = false;
-    int B = 0, Eh = 0, incx = 0, incy = 0, dEx = 0, dEy = 0, n = 0, k = 0;
+    uint64_t S = 0, Dx = 0, Dy = 0;  // walk state and the two crossing steps (see walk_run)
+    int n = 0, rem = 0, Bh = 0;
     uint32_t flags = 0u;
     double rdx = 0.0, rdy = 0.0;  // the claimed ray's direction, kept for its range
     for (;;) {
@@ -1282,8 +1340,8 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
         if (!exhausted && __popcll(am) <= p.refill_at) {
             if (!act && g >= 0) {
                 finish_ray_dir(p, M, s_jobs[job], rdx, rdy, job, beam,
-                               make_uint2((uint32_t)B | ((uint32_t)k << 19), flags), s_pool, per,
-                               inv_per, E);
+                               make_uint2((uint32_t)Bh | ((uint32_t)(n - rem) << 19), flags),
+                               s_pool, per, inv_per, E);
                 g = -1;
             }
             const uint64_t idle = ~am;
@@ -1298,22 +1356,18 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
                 beam = g - jl * K;
                 job = s_list[jl];
                 const TileJob &j = s_jobs[job];
-                B = 0;
                 n = 0;
                 if (!j.blocked) {
                     const double2 cs = s_beam[beam];
                     rdx = j.c * cs.x - j.s * cs.y;
                     rdy = j.s * cs.x + j.c * cs.y;
                     const Walk w = walk_setup(M.pitch, tile_origin(j, M.s), rdx, rdy, rmax_c);
-                    B = w.B;
                     n = min(w.n, max_n);
-                    Eh = w.Eh - w.thr;
-                    dEx = w.dEx;
-                    dEy = w.dEy;
-                    incx = w.incx;
-                    incy = w.incy;
+                    S = ((uint64_t)(uint32_t)(w.Eh - w.thr) << 32) | (uint64_t)(uint32_t)w.B;
+                    Dx = ((uint64_t)(uint32_t)w.dEx << 32) + (uint64_t)(int64_t)w.incx;
+                    Dy = ((uint64_t)(uint32_t)w.dEy << 32) + (uint64_t)(int64_t)w.incy;
                 }
-                k = 0;
+                rem = n;
                 flags = 0u;
                 act = n > 0;
             }
@@ -1324,13 +1378,12 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
             if (exhausted) break;
             continue;
         }
-        if (act)
-            walk_groups<BYTES>(p, s_bits, s_cells, B, Eh, incx, incy, dEx, dEy, n, k, flags, act);
+        if (act) walk_run<BYTES>(p, s_bits, S, Dx, Dy, rem, flags, act, Bh);
     }
     if (g >= 0)
         finish_ray_dir(p, M, s_jobs[job], rdx, rdy, job, beam,
-                       make_uint2((uint32_t)B | ((uint32_t)k << 19), flags), s_pool, per, inv_per,
-                       E);
+                       make_uint2((uint32_t)Bh | ((uint32_t)(n - rem) << 19), flags), s_pool, per,
+                       inv_per, E);
 }
 
 // LDS of the fused step, in order: the map's byte-per-cell copy [cell_bytes]
