@@ -341,7 +341,10 @@ __device__ __forceinline__ void walk_result(const RayOrigin &o, int pitch, int W
     const double Y = ((double)(dy > 0.0 ? iy : iy + 1)) * o.s - o.y;
     const bool use_x =
         dy == 0.0 || (dx != 0.0 && (dx > 0.0 ? X : -X) * fabs(dy) > (dy > 0.0 ? Y : -Y) * fabs(dx));
-    double t = use_x ? X / dx : Y / dy;
+    // select first, then divide: one division per lane even when the lanes
+    // of a wavefront pick different axes
+    const double num = use_x ? X : Y, den = use_x ? dx : dy;
+    double t = num / den;
     t = t > 0.0 ? t : 0.0;  // also maps -0 and NaN to +0
     t = t < rmax ? t : rmax;
     range = (float)t;
