@@ -287,8 +287,8 @@ def reset_proposal_gain(sim, w, args, keep_proposer: bool = False) -> dict:
                  goal=lab["goal"][keep].contiguous())
     loss = torch.zeros(args.train_steps, device=sim.device)
     t0 = time.perf_counter()
-    rp.train(pairs, steps=args.train_steps, batch=1024, samples=16, lr=1e-3, weight_decay=1e-4,
-             loss=loss)
+    rp.train(pairs, steps=args.train_steps, batch=1024, samples=args.train_samples, lr=1e-3,
+             weight_decay=1e-4, loss=loss)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     lv = loss.cpu().numpy() / 1024
@@ -299,7 +299,7 @@ def reset_proposal_gain(sim, w, args, keep_proposer: bool = False) -> dict:
     env = np.arange(n)
     ep = rng.integers(0, 1 << 20, n)
     out = {"pairs": int(pairs["map"].numel()), "label_s": t_label, "train_steps": args.train_steps,
-           "train_s": t_train, "loss_first_50": float(lv[:50].mean()),
+           "train_samples": args.train_samples, "train_s": t_train, "loss_first_50": float(lv[:50].mean()),
            "loss_last_50": float(lv[-50:].mean()), "requests": n}
     for name, M, tries in (("learned", 32, 400), ("rejection", 0, 432)):
         rp.propose(mp, bins, env, ep, proposals=M, max_tries=tries)
@@ -371,7 +371,9 @@ def learned_reset_leg(args) -> dict:
     log("learned resets: labelling and training")
     out["offline"] = reset_proposal_gain(sim, w, args, keep_proposer=True)
     rp = out["offline"].pop("_proposer")
-    P, T, cap = 32, 400, min(N, 2048)
+    # in the step: 32 network draws, then at most 64 rejection attempts (a
+    # request past that takes the free-space pose), at most 2,048 per step
+    P, T, cap = 32, 64, min(N, 2048)
     rp.attach((np.arange(N) % rp.nb).astype(np.int32), proposals=P, max_tries=T,
               max_per_step=cap)
     timed(20)  # warm: the first resets of the attached proposer
@@ -607,6 +609,8 @@ def main():
     ap.add_argument("--no-lds-peak", action="store_true")
     ap.add_argument("--label-starts", type=int, default=131072)
     ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--train-samples", type=int, default=128,
+                    help="noise draws per target in training (the closest one is fitted)")
     ap.add_argument("--proposal-requests", type=int, default=8192)
     ap.add_argument("--proposal-workload", default="c5",
                     help="workload of the learned reset leg (needs a proposer config)")
