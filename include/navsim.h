@@ -299,7 +299,8 @@ navsim_status navsim_get_state(navsim_t h, void *host_soa, size_t bytes, void *h
 navsim_status navsim_set_state(navsim_t h, const void *host_soa, size_t bytes, void *hip_stream);
 
 /* Free all device and host memory of the handle.  Using h afterwards, or
- * destroying it twice, is undefined. */
+ * destroying it twice, is undefined.  Errors: STATE while reset proposers
+ * created on h (navsim_rp_create) are alive: destroy them first. */
 navsim_status navsim_destroy(navsim_t h);
 
 /* Message for the last failed call on this thread ("" if none). */

@@ -59,8 +59,10 @@ typedef struct {
 
 /* Proposer for the maps currently loaded in h (it keeps its own tables; load
  * new maps = create a new proposer).  Weights: uniform in +-1/sqrt(fan_in),
- * biases 0.  Errors: INVALID_ARG (config), STATE (no maps), UNSUPPORTED (a
- * map outside the size limits above), OOM, HIP. */
+ * biases 0.  h must outlive the proposer (navsim_destroy(h) fails with STATE
+ * while a proposer created on it is alive).  Errors: INVALID_ARG (config),
+ * STATE (no maps), UNSUPPORTED (a map outside the size limits above), OOM,
+ * HIP. */
 navsim_status navsim_rp_create(navsim_t h, const navsim_rp_config *cfg, navsim_rp_t *out);
 
 /* Labelled pairs (device arrays): row i draws start id first_sid + i on map

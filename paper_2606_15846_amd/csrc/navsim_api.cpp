@@ -1016,6 +1016,9 @@ navsim_status navsim_get_tuning(navsim_t h, navsim_tuning *t) {
 
 navsim_status navsim_destroy(navsim_t h) {
     if (!h) return fail(NAVSIM_E_BAD_HANDLE, "handle is NULL");
+    if (h->proposers > 0)
+        return fail(NAVSIM_E_STATE, "%d reset proposer(s) still use this handle: destroy them first",
+                    h->proposers);
     {
         DeviceGuard g(h->device);
         free_device(h);

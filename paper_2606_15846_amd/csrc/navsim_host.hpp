@@ -102,6 +102,7 @@ struct navsim_s {
         navsim_status (*run)(void *ctx, hipStream_t s) = nullptr;
         void *ctx = nullptr;
     } hook;
+    int proposers = 0;  // live navsim_rp handles created on this handle
 };
 
 

@@ -653,6 +653,7 @@ navsim_status navsim_rp_create(navsim_t h, const navsim_rp_config *cfg, navsim_r
     const hipError_t se = rp_scratch_address(r->device, &r->scratch);
     if (se != hipSuccess)
         return fail_out(fail(NAVSIM_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(se)));
+    h->proposers++;
     *out = r;
     return NAVSIM_OK;
 }
@@ -1019,6 +1020,7 @@ navsim_status navsim_rp_destroy(navsim_rp_t r) {
         (void)hipDeviceSynchronize();
         free_rp(r);
     }
+    if (r->h && r->h->proposers > 0) r->h->proposers--;
     delete r;
     return NAVSIM_OK;
 }

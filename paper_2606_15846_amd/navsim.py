@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -299,6 +300,7 @@ class NavSim:
         self.cfg = dict(cfg)
         self.N, self.K, self.m = int(cfg["num_envs"]), int(cfg["num_beams"]), int(cfg["num_sectors"])
         self.h = None
+        self._proposers = weakref.WeakSet()  # reset proposers built on this handle
         self.h = navsim_create(cfg, self.device.index or 0)
         try:
             navsim_load_maps_ex(self.h, maps, res, env_map, profiles)
@@ -314,6 +316,9 @@ class NavSim:
         self.truncated = torch.zeros(self.N, dtype=torch.uint8, **z)
 
     def close(self):
+        # proposers hold the handle: the library refuses to free it before them
+        for rp in list(getattr(self, "_proposers", ())):
+            rp.close()
         h, self.h = getattr(self, "h", None), None
         if h is not None:
             navsim_destroy(h)

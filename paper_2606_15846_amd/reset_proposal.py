@@ -88,6 +88,7 @@ class ResetProposer:
         h = C.c_void_p()
         _ns._check(_lib().navsim_rp_create(sim.h, C.byref(rc), C.byref(h)))
         self.h = h
+        sim._proposers.add(self)
         self.nb = int(c["num_bins"])
         L = C.c_int32()
         cnt = C.c_int64()

@@ -362,3 +362,19 @@ def test_reset_to_proposed_poses_matches_oracle():
     assert d.max() <= 1e-4, d.max()
     rp.close()
     sim.close()
+
+
+def test_handle_outlives_its_proposers():
+    """navsim_destroy refuses (STATE) while a proposer built on the handle is
+    alive; NavSim.close() closes its proposers first."""
+    from paper_2606_15846_amd import navsim as ns
+    w = configs.build_workload("c5", num_envs=16)
+    sim = NavSim(w["cfg"], w["maps"][:2], w["res"][:2], (np.arange(16) % 2).astype(np.int32),
+                 device=0)
+    rp = ResetProposer(sim, **w["proposer"])
+    with pytest.raises(ns.NavsimError, match="destroy them first"):
+        ns.navsim_destroy(sim.h)
+    rp.attach(np.zeros(16, np.int32), proposals=4, max_tries=4, max_per_step=4)
+    sim.close()
+    assert rp.h is None and sim.h is None
+    rp.close()  # a second close is a no-op
