@@ -179,22 +179,31 @@ int choose_ray_cap(int max_words, const navsim_config &c, int tile_envs, int thr
     return cap;
 }
 
+// LDS words of the staged bitmaps: the largest bitmap, and for the run walk on
+// the bitmap and its transpose (walk 5, exact traversal) the largest
+// transposed one after it.
+int staged_words(int max_words, int max_words_t, int walk, int scan_mode) {
+    return max_words + ((scan_mode == NAVSIM_SCAN_TRAVERSAL && walk == 5) ? max_words_t : 0);
+}
+
 // LDS layout of the fused step for one launch shape and scan mode.  The claim
-// walk (walk 3, 4; exact traversal only) keeps no ray slots; the chunked
+// walks (walk 3, 4, 5; exact traversal only) keep no ray slots; the chunked
 // walks (and the march) use ray_cap slots.  walk 2 and 4 stage the map's
-// byte-per-cell copy.  Fails with UNSUPPORTED when nothing fits.
+// byte-per-cell copy, walk 5 the transposed bitmap.  Fails with UNSUPPORTED
+// when nothing fits.
 struct FusedShape {
     int ray_cap = 0, cell_bytes = 0, claim = 0, resident = 0;
     bool beams_lds = true;
 };
 
-navsim_status fused_shape(const navsim_s *h, int max_words, int tile_envs, int threads, int slots,
-                          int walk, int scan_mode, FusedShape &out) {
+navsim_status fused_shape(const navsim_s *h, int max_words_row, int max_words_t, int tile_envs,
+                          int threads, int slots, int walk, int scan_mode, FusedShape &out) {
     const navsim_config &c = h->cfg;
     const int m = c.num_sectors, K = c.num_beams;
+    const int max_words = staged_words(max_words_row, max_words_t, walk, scan_mode);
     out.claim = scan_mode == NAVSIM_SCAN_TRAVERSAL && walk >= 3;
     out.cell_bytes =
-        (scan_mode == NAVSIM_SCAN_TRAVERSAL && (walk == 2 || walk == 4)) ? max_words * 32 : 0;
+        (scan_mode == NAVSIM_SCAN_TRAVERSAL && (walk == 2 || walk == 4)) ? max_words_row * 32 : 0;
     if (out.cell_bytes && fused_static_lds(tile_envs, threads) != 0)
         return fail(NAVSIM_E_UNSUPPORTED,
                     "the byte walk needs a fused kernel without static LDS (tile_envs %d, "
@@ -506,7 +515,8 @@ StepParams navsim::make_step_params(const navsim_s *h) {
     p.tiles = h->tiles;
     p.num_tiles = h->num_tiles;
     p.num_maps = h->num_maps;
-    p.max_words = h->max_words;
+    p.max_words = staged_words(h->max_words, h->max_words_t, h->walk_mode, h->scan_mode);
+    p.tbits_off = p.max_words > h->max_words ? h->max_words : 0;
     p.refill_at = h->refill_at;
     p.groups = h->groups;
     p.ray_cap = h->ray_cap;
@@ -674,7 +684,7 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
     std::map<int, int32_t> beam_off;
     std::vector<uint32_t> bits;
     std::vector<int32_t> free_cells;
-    int max_words = 4;
+    int max_words = 4, max_words_t = 4;
     for (int k = 0; k < num_maps; ++k) {
         const int W = width[k], H = height[k];
         const uint8_t *m = occ + occ_off[k];
@@ -712,6 +722,23 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
             }
         }
         max_words = std::max(max_words, d.words);
+        // transposed copy: line c = ix + kPad holds the padded column, bit r =
+        // iy + kPad; the same ring of occupied cells
+        d.wpr_t = (H + 2 * kPad + 31) / 32;
+        d.words_t = ((d.wpr_t * (W + 2 * kPad)) + 3) & ~3;
+        d.word_off_t = (int64_t)bits.size();
+        bits.resize(bits.size() + d.words_t, 0xffffffffu);
+        uint32_t *bt = bits.data() + d.word_off_t;
+        for (int ix = 0; ix < W; ++ix) {
+            uint32_t *line = bt + (size_t)(ix + kPad) * d.wpr_t;
+            for (int wd = 0; wd < d.wpr_t; ++wd) line[wd] = 0u;
+            for (int r = 0; r < d.wpr_t * 32; ++r) {
+                const int iy = r - kPad;
+                const bool filled = iy < 0 || iy >= H || m[(size_t)iy * W + ix] != 0;
+                if (filled) line[r >> 5] |= 1u << (r & 31);
+            }
+        }
+        max_words_t = std::max(max_words_t, d.words_t);
         d.free_off = (int64_t)free_cells.size();
         const double s = (double)res_m[k];
         for (int iy = 0; iy < H; ++iy)
@@ -729,7 +756,7 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
     FusedShape shape;
     {
         DeviceGuard g(h->device);
-        const navsim_status fs = fused_shape(h, max_words, h->tile_envs, h->wg_threads,
+        const navsim_status fs = fused_shape(h, max_words, max_words_t, h->tile_envs, h->wg_threads,
                                              h->ray_slots, h->walk_mode, h->scan_mode, shape);
         if (fs != NAVSIM_OK) return fs;
     }
@@ -764,6 +791,7 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
     h->num_maps = num_maps;
     h->num_tiles = (int)tiles.size();
     h->max_words = max_words;
+    h->max_words_t = max_words_t;
     apply_shape(h, shape);
     h->host_env_map.swap(host_env_map);
     h->host_map_weight.swap(map_weight);
@@ -925,7 +953,7 @@ navsim_status navsim_set_scan(navsim_t h, int32_t mode, float step_m) {
     FusedShape shape;
     if (h->loaded) {
         DeviceGuard g(h->device);
-        const navsim_status fs = fused_shape(h, h->max_words, h->tile_envs, h->wg_threads,
+        const navsim_status fs = fused_shape(h, h->max_words, h->max_words_t, h->tile_envs, h->wg_threads,
                                              h->ray_slots, h->walk_mode, mode, shape);
         if (fs != NAVSIM_OK) return fs;
     }
@@ -950,7 +978,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     if (t->groups < 1 || t->groups > 64) return fail(NAVSIM_E_INVALID_ARG, "groups must be in 1..64");
     if (t->ray_slots < 0 || (t->ray_slots > 0 && t->ray_slots < 256))
         return fail(NAVSIM_E_INVALID_ARG, "ray_slots must be 0 or >= 256");
-    if (t->walk < 0 || t->walk > 4) return fail(NAVSIM_E_INVALID_ARG, "walk must be in 0..4");
+    if (t->walk < 0 || t->walk > 5) return fail(NAVSIM_E_INVALID_ARG, "walk must be in 0..5");
     if (t->persist < 0 || t->persist > 64)
         return fail(NAVSIM_E_INVALID_ARG, "persist must be in 0..64");
     if (!fused_threads_supported(t->threads))
@@ -967,7 +995,7 @@ navsim_status navsim_set_tuning(navsim_t h, const navsim_tuning *t) {
     FusedShape shape;
     if (h->loaded) {
         DeviceGuard g(h->device);
-        const navsim_status fs = fused_shape(h, h->max_words, t->tile_envs, t->threads,
+        const navsim_status fs = fused_shape(h, h->max_words, h->max_words_t, t->tile_envs, t->threads,
                                              t->ray_slots, t->walk, h->scan_mode, shape);
         if (fs != NAVSIM_OK) return fs;
     }

@@ -57,6 +57,7 @@ struct navsim_s {
     int32_t *perm = nullptr;
     navsim::Tile *tiles = nullptr;
     int num_maps = 0, num_tiles = 0, max_words = 0;
+    int max_words_t = 0;  // largest transposed bitmap (staged beside the bitmap by walk 5)
     int tile_envs = navsim::kDefaultTileEnvs, refill_at = navsim::kDefaultRefillAt, groups = navsim::kDefaultGroups;
     int ray_cap = 0;
     int ray_slots = 0;  // requested cap on ray_cap (0 = automatic)

@@ -44,6 +44,11 @@ struct MapDesc {
     int32_t footprint;  // NAVSIM_DISC / NAVSIM_RECT
     float radius, len, wid;
     double rc;          // circumradius of the footprint
+    // the same bitmap transposed (line c = padded column, bit r = padded row;
+    // kPad occupied ring, every bit at r >= H + kPad set), for walk 5
+    int32_t wpr_t;       // words per padded column
+    int32_t words_t;     // padded words, rounded up to a multiple of 4
+    int64_t word_off_t;  // start in the bit pool (multiple of 4 words)
 };
 
 // A group of up to tile_envs envs that share one map (one fused workgroup).
@@ -62,7 +67,8 @@ struct StepParams {
     int32_t N, K, m, horizon, tries, mode;  // K: largest beam count; mode 0 step, 1 reset
     int32_t refill_at, groups;  // fused walk: refill threshold, 4-cell groups per check
     int32_t walk_mode;          // fused walk: 0 groups of 4 cells, 1 runs, 2 groups on bytes,
-                                // 3 claim walk (setup and finish per claimed ray), 4 on bytes
+                                // 3 claim walk (setup and finish per claimed ray), 4 on bytes,
+                                // 5 claim walk over runs on the bitmap and its transpose
     int32_t cell_bytes;         // walk 2, 4: LDS bytes of the byte-per-cell map copy (else 0)
     int32_t claim;              // claim walk in use (walk 3, 4 with the exact traversal)
     int32_t *queue;             // persistent workgroups: {next tile, finished groups}, or null
@@ -85,7 +91,8 @@ struct StepParams {
     const double2 *beams;  // (cos, sin) of each beam's angle to the heading
     const int32_t *perm;   // env ids grouped by map
     const Tile *tiles;
-    int32_t num_tiles, num_maps, max_words;
+    int32_t num_tiles, num_maps, max_words;  // max_words: LDS words of the staged bitmaps
+    int32_t tbits_off;  // walk 5: LDS word offset of the staged transposed bitmap (else 0)
     // inputs / outputs
     const float *act;          // normalised actions [N][2], or null in a rollout
     const uint32_t *step_ctr;  // rollout: device {lo, hi} of the first step index

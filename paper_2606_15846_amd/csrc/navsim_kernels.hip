@@ -1389,10 +1389,184 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
                        inv_per, E);
 }
 
+// Run walk on the bitmap and its transpose (walk 5).  Between two steps along
+// its minor axis a ray moves along its major axis only, so its cells come in
+// runs on one line of the map: a row of the bitmap for an x-major ray
+// (DX >= DY), a row of the transposed bitmap (a column of the map) for a
+// y-major one.  With e the decision variable of the integer walk turned so
+// that a major step is taken iff e < 0 (x-major: e = E' as in walk_setup;
+// y-major: e = -1 - E'), a major step adds a (the minor quantised component)
+// and a minor step subtracts b (the major one).  Once e is in [0, a] (after
+// the run that leaves the origin, which takes one division), every later run
+// is a minor step and r = q + [e < M1] major steps with q = floor((b - 1) / a)
+// and M1 = (b - 1) mod a + 1, after which e <- e - M1 + [e < M1] a stays in
+// [0, a): runs of any length without dividing.  Up to 31 cells of a run are
+// tested at once from two bitmap words (a funnel shift and a bit-field
+// extract), so that lanes walking x- and y-major rays run the same
+// instructions.  The cells, and therefore every result, are the other walks'.
+constexpr int kLongRun = 1 << 14;  // run length of an axis-parallel ray (past any budget)
+
+// Per-ray constants of the run walk.  Positions are bit indices into the
+// staged line bitmap of the ray's major axis, plus `off`: the copy's start,
+// and -31 when walking toward lower positions, so that a position is the
+// first bit of the 32-cell window that holds the cell.
+struct RunRay {
+    int q1;         // q + 1: cells of a run without the extra major step
+    int M1;         // e < M1 adds the extra major step
+    int up, dn;     // e's change over a run: a - M1 with the extra step, -M1 without
+    int dmin;       // a minor step relative to a major one
+    int sm;         // 0 walking toward higher positions (a major step is +1), -1 toward lower
+    int off;
+};
+
+// Up to `groups` windows of one lane's run walk.  State: X (the window
+// position of the next cell along the major axis), e, pend (cells left in the
+// current run, its minor step included) and rem (cells left in the r_max
+// budget).  A window holds L = min(pend, rem, 31) cells; when one of them is
+// occupied the first in walk order is the hit (Xh = its window position,
+// flags = 1, rem reduced by the cells walked up to it), and when the budget
+// ends in the window without a hit rem = 0; act turns false then.
+__device__ __forceinline__ void run_windows(const StepParams &p, const uint32_t *s_bits,
+                                            const RunRay &c, int &X, int &e, int &pend, int &rem,
+                                            uint32_t &flags, bool &act, int &Xh) {
+    uint32_t t = 0u;
+    int Q = 0, L = 0;
+    // one exit condition inside the loop (fewer lane masks to keep); the walk's
+    // end is worked out after it from the last window
+#pragma unroll 1
+    for (int gi = 0; gi < p.groups; ++gi) {
+        const bool newl = pend == 0;
+        const bool extra = e < c.M1;
+        pend = newl ? c.q1 + (int)extra : pend;
+        e = newl ? e + (extra ? c.up : c.dn) : e;
+        Q = X + (newl ? c.dmin : 0);
+        L = min(min(pend, rem), 31);
+        const int wq = Q >> 5;
+        const uint32_t v = __builtin_amdgcn_alignbit(s_bits[wq + 1], s_bits[wq], (uint32_t)Q);
+        // the window's cells: bits 0 .. L-1 walking up, 32-L .. 31 walking down
+        t = __builtin_amdgcn_ubfe(v, (uint32_t)((32 - L) & c.sm), (uint32_t)L);
+        // past the window (taken back below when the walk ends in it)
+        X = Q + ((L ^ c.sm) - c.sm);
+        pend -= L;
+        rem -= L;
+        if (t != 0u || rem <= 0) break;
+    }
+    if (t != 0u) {
+        // walking up: the lowest set bit; walking down: the highest
+        const int f = c.sm ? L - 32 + (int)__builtin_clz(t) : (int)__builtin_ctz(t);
+        Xh = Q + ((f ^ c.sm) - c.sm);
+        flags = 1u;
+        rem += L - f - 1;
+        act = false;
+    } else if (rem <= 0) {
+        rem = 0;
+        act = false;
+    }
+}
+
+// The claim walk (see claim_walk) over runs: each claimed ray is set up for
+// run_windows, and a hit found in the transposed bitmap is turned back into
+// the bitmap's cell index for walk_result.
+__device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapView &M,
+                                               const uint32_t *s_bits, int pitch_t,
+                                               const TileJob *s_jobs, const int *s_list,
+                                               const double2 *s_beam, uint32_t *s_pool,
+                                               int *s_misc, int R, int K, float inv_K, int per,
+                                               float inv_per, double rmax_c, int max_n, int E,
+                                               int lane) {
+    const float inv_pitch_t = __builtin_amdgcn_rcpf((float)pitch_t);
+    int g = -1, job = 0, beam = 0;
+    bool act = false, exhausted = false, xmaj = true;
+    RunRay c{};
+    int X = 0, e = 0, pend = 0, n = 0, rem = 0, Xh = 0;
+    uint32_t flags = 0u;
+    double rdx = 0.0, rdy = 0.0;  // the claimed ray's direction, kept for its range
+    auto finish = [&]() {
+        // the hit's line position (0 without a hit: the field shares its word
+        // with the visit count)
+        int Bh = flags ? Xh - c.off : 0;
+        if (flags && !xmaj) {
+            const int col = small_div(Bh, pitch_t, inv_pitch_t);
+            Bh = (Bh - col * pitch_t) * M.pitch + col;
+        }
+        finish_ray_dir(p, M, s_jobs[job], rdx, rdy, job, beam,
+                       make_uint2((uint32_t)Bh | ((uint32_t)(n - rem) << 19), flags), s_pool, per,
+                       inv_per, E);
+    };
+    for (;;) {
+        uint64_t am = __ballot(act);
+        if (!exhausted && __popcll(am) <= p.refill_at) {
+            if (!act && g >= 0) {
+                finish();
+                g = -1;
+            }
+            const uint64_t idle = ~am;
+            const int nidle = 64 - __popcll(am);
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
+            base = __shfl(base, 0);
+            const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
+            if (!act && my < R) {
+                g = my;
+                const int jl = small_div(g, K, inv_K);
+                beam = g - jl * K;
+                job = s_list[jl];
+                const TileJob &j = s_jobs[job];
+                n = 0;
+                if (!j.blocked) {
+                    const double2 cs = s_beam[beam];
+                    rdx = j.c * cs.x - j.s * cs.y;
+                    rdy = j.s * cs.x + j.c * cs.y;
+                    const Walk w = walk_setup(M.pitch, tile_origin(j, M.s), rdx, rdy, rmax_c);
+                    n = min(w.n, max_n);
+                    const int Ep = w.Eh - w.thr;  // x step iff Ep < 0
+                    const int DX = -w.dEy, DY = w.dEx;
+                    xmaj = DX >= DY;
+                    const int a = xmaj ? DY : DX, b = xmaj ? DX : DY;
+                    e = xmaj ? Ep : -1 - Ep;
+                    // the run leaving the origin: ceil(-e / a) major steps
+                    pend = 0;
+                    if (e < 0) {
+                        if (a > 0) {
+                            pend = (int)(((uint32_t)(-e) + (uint32_t)(a - 1)) / (uint32_t)a);
+                            e += pend * a;
+                        } else {
+                            pend = kLongRun;
+                        }
+                    }
+                    const int q = a > 0 ? (int)((uint32_t)(b - 1) / (uint32_t)a) : kLongRun;
+                    c.q1 = q + 1;
+                    c.M1 = a > 0 ? b - q * a : 0;
+                    c.up = a - c.M1;
+                    c.dn = -c.M1;
+                    const bool down = xmaj ? w.incx < 0 : w.incy < 0;
+                    const int smaj = down ? -1 : 1;
+                    const int smin = xmaj ? w.incy : (w.incx > 0 ? pitch_t : -pitch_t);
+                    c.sm = down ? -1 : 0;
+                    c.dmin = smin - smaj;
+                    c.off = (down ? -31 : 0) + (xmaj ? 0 : 32 * p.tbits_off);
+                    X = (xmaj ? w.B : (j.i0 + kPad) * pitch_t + (j.j0 + kPad)) + smaj + c.off;
+                }
+                rem = n;
+                flags = 0u;
+                act = n > 0;
+            }
+            exhausted = base + nidle >= R;
+            am = __ballot(act);
+        }
+        if (am == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+        if (act) run_windows(p, s_bits, c, X, e, pend, rem, flags, act, Xh);
+    }
+    if (g >= 0) finish();
+}
+
 // LDS of the fused step, in order: the map's byte-per-cell copy [cell_bytes]
 // (byte walk only: at address 0, so that a cell index is its LDS address),
-// bitmap [max_words], jobs [2E] (main,
-// reset), pooled minima [2E][m] (+ padding), active job list [2E], misc
+// bitmap [max_words] (walk 5: the bitmap, then its transpose from word
+// tbits_off), jobs [2E] (main, reset), pooled minima [2E][m] (+ padding), active job list [2E], misc
 // [2E + 8] ([0] active jobs, [1] next ray, [2, 2 + E) done flags, [2E + 7]
 // next tile of a persistent workgroup), beams [K] when staged, ray slots
 // [ray_cap] (none for the claim walk).
@@ -1441,6 +1615,11 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
         const uint4 *g = reinterpret_cast<const uint4 *>(p.bits + md.word_off);
         uint4 *b4 = reinterpret_cast<uint4 *>(s_bits);
         for (int q = tid; q < md.words / 4; q += T) b4[q] = g[q];
+        if (p.tbits_off) {
+            const uint4 *gt = reinterpret_cast<const uint4 *>(p.bits + md.word_off_t);
+            uint4 *t4 = reinterpret_cast<uint4 *>(s_bits + p.tbits_off);
+            for (int q = tid; q < md.words_t / 4; q += T) t4[q] = gt[q];
+        }
         if (p.cell_bytes) {
             // byte copy: bit b of word q becomes byte 32 q + b (0 or 1); a
             // nibble times 0x00204081 moves its bit i to bit 8 i
@@ -1585,7 +1764,10 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
     const int max_n = M.w + M.h + 2 * kPad;  // a walk meets the padding ring before this
     if (p.claim) {
         // s_misc[1] (next ray) and the pool were cleared before the last barrier
-        if (p.cell_bytes)
+        if (p.tbits_off)
+            claim_run_walk(p, M, s_bits, md.wpr_t * 32, s_jobs, s_list, s_beam, s_pool, s_misc, R,
+                           K, inv_K, per, inv_per, rmax_c, max_n, E, lane);
+        else if (p.cell_bytes)
             claim_walk<true>(p, M, s_bits, s_cells, s_jobs, s_list, s_beam, s_pool, s_misc, R, K,
                              inv_K, per, inv_per, rmax_c, max_n, E, lane);
         else

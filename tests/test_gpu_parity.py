@@ -76,10 +76,11 @@ def test_c2_plain_subset():
     sim.close()
 
 
-@pytest.mark.parametrize("walk", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("walk", [0, 1, 2, 3, 4, 5])
 def test_walk_variants_against_oracle(walk):
     say(f"walk = {walk} (0 chunked groups, 1 runs, 2 byte-per-cell map, 3 claim walk, 4 claim "
-        f"walk on bytes): c2 full size and c3 maps, fused, teacher-forced")
+        f"walk on bytes, 5 claim walk over runs on the bitmap and its transpose): c2 full size "
+        f"and c3 maps, fused, teacher-forced")
     w = configs.build_workload("c2")
     sim, ref = make_pair(w["cfg"], w["maps"], w["res"], w["env_map"])
     sim.set_tuning(4, 48, 4, 0, walk)
@@ -91,6 +92,70 @@ def test_walk_variants_against_oracle(walk):
     sim.set_tuning(4 if big else 2, 40, 8, 0, walk, threads=1024 if big else 256)
     run_teacher_forced(sim, ref, 3, NAVSIM_KERNEL_FUSED, label=f"c3/walk{walk}")
     sim.close()
+
+
+def test_run_walk_on_grid_lines_corners_and_axis_rays():
+    """Origins exactly on grid lines and corners (1/16 m cells: the coordinates
+    are exact in float), heading 0 with 360 beams over the full circle (the
+    axis-parallel and 45-degree rays among them), 8 m range (runs far longer
+    than one 31-cell window): the run walk on the bitmap and its transpose
+    (walk 5) gives bitwise the hits, visits and ranges of the claim walks on
+    the bitmap (3) and on bytes (4), of the chunked run walk (1) and of the
+    plain kernel's cell-by-cell walk; non-grazing rays against the oracle."""
+    say("run walk: 512 envs on grid corners and lines of a 1/16 m map, axis and 45-degree "
+        "rays, walks 5 / 3 / 4 / 1 / plain")
+    from workloads import maps as gm
+    res = 0.0625
+    occ = gm.gen_rect_disc_map(23, w=200, h=180, res=res)
+    N = 512
+    cfg = configs.make_config(num_envs=N, num_beams=360, num_sectors=36, fov_rad=2 * math.pi,
+                              max_range_m=8.0, dt_s=0.1, footprint=0, radius_m=0.1,
+                              v_min=0.0, v_max=0.5, w_min=-1.0, w_max=1.0)
+    env_map = np.zeros(N, np.int32)
+    rng = np.random.default_rng(7)
+    free = np.argwhere(occ == 0)
+    pick = free[rng.choice(len(free), N, replace=False)]
+    offs = np.array([(0, 0), (0.5, 0), (0, 0.5), (0.5, 0.5), (0.25, 0), (0, 0.75)])
+    o = offs[np.arange(N) % len(offs)]
+    x = ((pick[:, 1] + o[:, 0]) * res).astype(np.float32)
+    y = ((pick[:, 0] + o[:, 1]) * res).astype(np.float32)
+    assert np.array_equal(x.astype(np.float64) / res % 0.25, np.zeros(N))  # on the grid
+    th = np.where(np.arange(N) % 4 == 3, np.float32(0.4), np.float32(0.0)).astype(np.float32)
+    acts = np.tile(np.array([-1.0, 0.0], np.float32), (N, 1))  # v = 0, w = 0: pose kept
+    runs = []
+    for kernel, walk, te, thr in [(NAVSIM_KERNEL_FUSED, 5, 8, 256),
+                                  (NAVSIM_KERNEL_FUSED, 5, 32, 1024),
+                                  (NAVSIM_KERNEL_FUSED, 3, 8, 256),
+                                  (NAVSIM_KERNEL_FUSED, 4, 16, 1024),
+                                  (NAVSIM_KERNEL_FUSED, 1, 4, 256),
+                                  (NAVSIM_KERNEL_PLAIN, 0, 4, 256)]:
+        sim, ref = make_pair(cfg, [occ], [res], env_map)
+        sim.set_tuning(te, 40, 8, 0, walk, threads=thr)
+        sim.reset()
+        torch.cuda.synchronize()
+        st = sim.get_state()
+        st["x"][:] = x
+        st["y"][:] = y
+        st["th"][:] = th
+        st["t"][:] = 0
+        sim.set_state(st)
+        g, gst = gpu_step(sim, acts, kernel)
+        kept = ~g["reset"].astype(bool)
+        assert np.array_equal(gst["x"][kept], x[kept]) and np.array_equal(gst["th"][kept], th[kept])
+        if walk == 5 and te == 8:
+            ref.set_state(st)
+            r = ref.step(acts, threads=16)
+            rep = compare_step(g, r, gst, ref, label="run walk on the grid")
+            say(f"grazing rays {rep['grazing']} of {N * 360}; longest walk "
+                f"{int(g['visits'].max())} cells")
+            assert int(g["visits"].max()) > 64
+        runs.append(g)
+        sim.close()
+    ended = runs[0]["reset"].astype(bool)
+    for i, other in enumerate(runs[1:]):
+        for k in ("ranges", "hits", "visits", "obs", "reward", "terminated", "reset"):
+            assert np.array_equal(runs[0][k], other[k]), (i + 1, k)
+        assert np.array_equal(runs[0]["final_obs"][ended], other["final_obs"][ended]), i + 1
 
 
 def test_c3_full_size_fused():
@@ -139,7 +204,9 @@ def test_c4_full_size_launch_shapes_agree():
     for te, pe, th, wk, bal in [(8, 0, 256, 0, 0), (8, 4, 256, 0, 0), (4, 1, 256, 0, 0),
                                 (16, 16, 256, 0, 0), (8, 0, 512, 0, 0), (16, 0, 1024, 0, 0),
                                 (4, 0, 1024, 0, 0), (4, 0, 512, 3, 0), (8, 2, 256, 3, 0),
-                                (16, 0, 512, 3, 1), (32, 0, 1024, 3, 1), (8, 3, 256, 3, 1)]:
+                                (16, 0, 512, 3, 1), (32, 0, 1024, 3, 1), (8, 3, 256, 3, 1),
+                                (16, 0, 512, 5, 1), (8, 0, 256, 5, 1), (8, 3, 256, 5, 0),
+                                (32, 0, 1024, 5, 1)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0,
                      profiles=w["profiles"])
         sim.set_tuning(te, 48, 8, walk=wk, persist=pe, threads=th, balance=bal)
@@ -198,16 +265,12 @@ def test_mixed_profiles_launch_shapes_agree():
     cfg, occ, res, env_map, prof = _mixed_small(num_envs=150)
     acts = configs.uniform_actions(5, cfg["num_envs"], seed=33)
     runs = []
-    for kernel, te, pe, th in [(NAVSIM_KERNEL_PLAIN, 4, 0, 256), (NAVSIM_KERNEL_FUSED, 4, 0, 256),
-                               (NAVSIM_KERNEL_FUSED, 8, 0, 256), (NAVSIM_KERNEL_FUSED, 16, 0, 256),
-                               (NAVSIM_KERNEL_FUSED, 4, 3, 256), (NAVSIM_KERNEL_FUSED, 2, 16, 256),
-                               (NAVSIM_KERNEL_FUSED, 8, 0, 512), (NAVSIM_KERNEL_FUSED, 16, 0, 1024),
-                               (NAVSIM_KERNEL_FUSED, 4, 0, -256), (NAVSIM_KERNEL_FUSED, 8, 2, -1024),
-                               (NAVSIM_KERNEL_FUSED, 4, 0, 3256), (NAVSIM_KERNEL_FUSED, 16, 0, 41024)]:
-        # th < 0: the byte-per-cell walk with |th| threads; th = 3xxx / 4xxxx: claim
-        # walk (bitmap / bytes) with xxx threads
-        walk, thr = (2, -th) if th < 0 else ((3, th - 3000) if 3000 < th < 4000 else
-                                             ((4, th - 40000) if th > 40000 else (0, th)))
+    F = NAVSIM_KERNEL_FUSED
+    for kernel, te, pe, thr, walk in [
+            (NAVSIM_KERNEL_PLAIN, 4, 0, 256, 0), (F, 4, 0, 256, 0), (F, 8, 0, 256, 0),
+            (F, 16, 0, 256, 0), (F, 4, 3, 256, 0), (F, 2, 16, 256, 0), (F, 8, 0, 512, 0),
+            (F, 16, 0, 1024, 0), (F, 4, 0, 256, 2), (F, 8, 2, 1024, 2), (F, 4, 0, 256, 3),
+            (F, 16, 0, 1024, 4), (F, 4, 0, 256, 5), (F, 16, 2, 1024, 5), (F, 1, 0, 256, 5)]:
         sim = NavSim(cfg, occ, res, env_map, device=0, profiles=prof)
         sim.set_tuning(te, 48, 4, walk=walk, persist=pe, threads=thr)
         sim.reset()
@@ -271,10 +334,11 @@ def test_march_mixed_profiles_and_launch_shapes():
     run_teacher_forced(sim, ref, 6, NAVSIM_KERNEL_FUSED, seed=4, label="march-mixed")
     acts = configs.uniform_actions(3, 60, seed=8)
     runs = []
-    # walk 4 (claim walk on bytes) applies to the exact traversal only: the
-    # march keeps its chunked path under it
+    # walks 4 and 5 (claim walks) apply to the exact traversal only: the march
+    # keeps its chunked path under them
     for kernel, te, wk in [(NAVSIM_KERNEL_PLAIN, 4, 0), (NAVSIM_KERNEL_FUSED, 4, 0),
-                           (NAVSIM_KERNEL_FUSED, 16, 0), (NAVSIM_KERNEL_FUSED, 4, 4)]:
+                           (NAVSIM_KERNEL_FUSED, 16, 0), (NAVSIM_KERNEL_FUSED, 4, 4),
+                           (NAVSIM_KERNEL_FUSED, 4, 5)]:
         s2 = NavSim(cfg, occ, res, env_map, device=0, profiles=prof)
         s2.set_scan(navsim.NAVSIM_SCAN_MARCH, 0.05)
         s2.set_tuning(te, 40, 2, walk=wk)
@@ -488,7 +552,7 @@ def test_api_errors_on_device():
     before = navsim.navsim_get_tuning(h)
     base = dict(tile_envs=4, refill_at=48, groups=4, ray_slots=0, walk=0, persist=0, threads=256)
     for bad in [dict(tile_envs=3), dict(refill_at=64), dict(groups=0), dict(ray_slots=100),
-                dict(walk=5), dict(persist=65), dict(threads=384), dict(tile_envs=32),
+                dict(walk=6), dict(persist=65), dict(threads=384), dict(tile_envs=32),
                 dict(balance=2)]:
         with pytest.raises(navsim.NavsimError) as ei:
             navsim.navsim_set_tuning(h, **dict(base, **bad))
@@ -518,7 +582,9 @@ def test_launch_shape_does_not_change_results():
             (16, 48, 4, 0, 2, 0, 1024), (8, 63, 64, 0, 2, 3, 512), (2, 32, 2, 512, 2, 0, 256),
             (4, 56, 8, 0, 3, 0, 256), (1, 0, 1, 0, 3, 0, 256), (16, 48, 4, 0, 3, 2, 1024),
             (8, 63, 64, 0, 4, 0, 512), (4, 56, 8, 0, 4, 0, 256), (2, 32, 2, 0, 4, 5, 256),
-            (32, 40, 8, 0, 4, 0, 512), (32, 32, 16, 0, 3, 0, 1024), (32, 48, 8, 0, 0, 3, 512)]:
+            (32, 40, 8, 0, 4, 0, 512), (32, 32, 16, 0, 3, 0, 1024), (32, 48, 8, 0, 0, 3, 512),
+            (4, 56, 8, 0, 5, 0, 256), (1, 0, 1, 0, 5, 0, 256), (16, 48, 4, 0, 5, 2, 1024),
+            (8, 63, 64, 0, 5, 0, 512), (32, 40, 8, 0, 5, 0, 512), (2, 32, 2, 0, 5, 5, 256)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0)
         bal = int(th == 1024 or te == 32)  # the larger workgroups also with balanced tiles
         sim.set_tuning(te, ra, gr, rs, wk, pe, th, bal)
@@ -546,11 +612,11 @@ def test_launch_shape_does_not_change_results():
 def test_pooled_obs_same_with_and_without_per_ray_outputs(wl):
     # the step with and without the per-ray debug outputs (ranges, hits,
     # visits) must produce the same observations, rewards, flags and state
-    say(f"{wl}: plain steps == steps with per-ray outputs (bitwise), walks 0, 3, 4")
+    say(f"{wl}: plain steps == steps with per-ray outputs (bitwise), walks 0, 3, 4, 5")
     w = configs.build_workload(wl)
     N = w["cfg"]["num_envs"]
     acts = torch.from_numpy(configs.uniform_actions(3, N, seed=17)).cuda()
-    for wk, te, th in [(0, 4, 256), (3, 4, 256), (4, 16, 1024)]:
+    for wk, te, th in [(0, 4, 256), (3, 4, 256), (4, 16, 1024), (5, 16, 512)]:
         sim = NavSim(w["cfg"], w["maps"], w["res"], w["env_map"], device=0, profiles=w["profiles"])
         try:
             sim.set_tuning(te, 48, 8, walk=wk, threads=th)
