@@ -202,6 +202,10 @@ navsim_status fused_shape(const navsim_s *h, int max_words_row, int max_words_t,
     const int m = c.num_sectors, K = c.num_beams;
     const int max_words = staged_words(max_words_row, max_words_t, walk, scan_mode);
     out.claim = scan_mode == NAVSIM_SCAN_TRAVERSAL && walk >= 3;
+    // the run walk packs a hit's position in the transposed bitmap in 19 bits
+    if (max_words > max_words_row && (int64_t)max_words_t * 32 >= (1 << 19))
+        return fail(NAVSIM_E_UNSUPPORTED, "walk 5: a transposed bitmap of %d words is too large",
+                    max_words_t);
     out.cell_bytes =
         (scan_mode == NAVSIM_SCAN_TRAVERSAL && (walk == 2 || walk == 4)) ? max_words_row * 32 : 0;
     if (out.cell_bytes && fused_static_lds(tile_envs, threads) != 0)

@@ -64,10 +64,11 @@ struct MapView {
     const uint32_t *bits;
     int w, h, wpr, pitch;
     double s;
+    int pitch_t;  // bits per line of the transposed bitmap
 };
 
 __device__ __forceinline__ MapView map_view(const uint32_t *bits, const MapDesc &md) {
-    return MapView{bits, md.w, md.h, md.wpr, md.wpr * 32, (double)md.res};
+    return MapView{bits, md.w, md.h, md.wpr, md.wpr * 32, (double)md.res, md.wpr_t * 32};
 }
 
 __device__ __forceinline__ bool cell_filled(const MapView &M, int i, int j) {
@@ -280,6 +281,15 @@ __device__ __forceinline__ RayOrigin ray_origin(const MapView &M, double x, doub
     return o;
 }
 
+// r_max in cells for walk_setup, capped at kMaxWalkCells: a walk meets the
+// padding ring within W + H + 2 kPad <= 8191 cells, so any budget beyond
+// that is cut to the same walk, and the cap keeps the end point's cell index
+// within int range.
+constexpr double kMaxWalkCells = 16384.0;
+__device__ __forceinline__ double walk_cells(double rmax, double s) {
+    return fmin(rmax / s, kMaxWalkCells);
+}
+
 // Integer walk state of one ray.  With g = distance to the next grid line in
 // the direction of travel (2^-32 cells) and D = quantised |direction|,
 // E = gx DY - gy DX compares the two next crossing distances; an x crossing
@@ -302,8 +312,10 @@ __device__ __forceinline__ Walk walk_setup(int pitch, const RayOrigin &o, double
     Walk w;
     w.Eh = (int)(E >> 32);
     w.thr = ((uint32_t)(uint64_t)E == 0u) ? 1 : 0;
-    const double exc = fmin(fmax(o.xc + rmax_c * dx, -1048576.0), 1048576.0);
-    const double eyc = fmin(fmax(o.yc + rmax_c * dy, -1048576.0), 1048576.0);
+    // rmax_c is at most kMaxWalkCells (see walk_cells) and the origin lies in
+    // the map, so the end point converts to int without clamping
+    const double exc = o.xc + rmax_c * dx;
+    const double eyc = o.yc + rmax_c * dy;
     w.n = abs((int)floor(exc) - o.i0) + abs((int)floor(eyc) - o.j0);
     w.B = (o.j0 + kPad) * pitch + (o.i0 + kPad);
     w.incx = px ? 1 : -1;
@@ -313,14 +325,26 @@ __device__ __forceinline__ Walk walk_setup(int pitch, const RayOrigin &o, double
     return w;
 }
 
-// q = floor(a / b) for 0 <= a < 2^24, b >= 1 and a / b < 2^20, given inv_b
-// within a few float ulps of 1 / b: the float estimate is then within one of
-// the quotient, and the two tests fix it.
-__device__ __forceinline__ int small_div(int a, int b, float inv_b) {
+// q = floor(a / b) and r = a - q b for 0 <= a < 2^24, 1 <= b < 2^23 and
+// a / b < 2^20, given inv_b within a few float ulps of 1 / b: the float
+// estimate is then within one of the quotient, which the remainder (one
+// full-rate 24-bit product) fixes.
+__device__ __forceinline__ int small_divmod(int a, int b, float inv_b, int &r) {
     int q = (int)((float)a * inv_b);
-    if (q * b > a) --q;
-    if ((q + 1) * b <= a) ++q;
+    r = a - __mul24(q, b);
+    if (r < 0) {
+        --q;
+        r += b;
+    } else if (r >= b) {
+        ++q;
+        r -= b;
+    }
     return q;
+}
+
+__device__ __forceinline__ int small_div(int a, int b, float inv_b) {
+    int r;
+    return small_divmod(a, b, inv_b, r);
 }
 
 // Range and hit id of a walk that stopped in cell B.  The ray enters a cell
@@ -329,8 +353,12 @@ __device__ __forceinline__ int small_div(int a, int b, float inv_b) {
 // or parallel to the ray, gives -inf); recomputed once in double.
 __device__ __forceinline__ void walk_result(const RayOrigin &o, int pitch, int W, int H, int B,
                                             double dx, double dy, double rmax, float &range,
-                                            int &hit) {
-    const int row = small_div(B, pitch, __builtin_amdgcn_rcpf((float)pitch)), col = B - row * pitch;
+                                            int &hit, bool transposed = false) {
+    // B: bit index of the cell in the bitmap (line = padded row, lines of
+    // `pitch` bits), or in the transposed one (line = padded column)
+    int pos;
+    const int line = small_divmod(B, pitch, __builtin_amdgcn_rcpf((float)pitch), pos);
+    const int row = transposed ? pos : line, col = transposed ? line : pos;
     const int ix = col - kPad, iy = row - kPad;
     // t_x = X / dx and t_y = Y / dy (a zero component gives -inf); the later
     // one is picked without dividing, t_x > t_y iff X sgn(dx) |dy| > Y sgn(dy)
@@ -342,12 +370,14 @@ __device__ __forceinline__ void walk_result(const RayOrigin &o, int pitch, int W
     const bool use_x =
         dy == 0.0 || (dx != 0.0 && (dx > 0.0 ? X : -X) * fabs(dy) > (dy > 0.0 ? Y : -Y) * fabs(dx));
     // select first, then divide: one division per lane even when the lanes
-    // of a wavefront pick different axes
+    // of a wavefront pick different axes.  The quotient in single precision
+    // (relative error about 2^-22: ~2 um at 8 m); its operands stay double,
+    // since cancellation in X and Y is absolute, not relative
     const double num = use_x ? X : Y, den = use_x ? dx : dy;
-    double t = num / den;
-    t = t > 0.0 ? t : 0.0;  // also maps -0 and NaN to +0
-    t = t < rmax ? t : rmax;
-    range = (float)t;
+    float t = (float)num * __builtin_amdgcn_rcpf((float)den);
+    t = t > 0.0f ? t : 0.0f;  // also maps -0 and NaN to +0
+    const float rm = (float)rmax;
+    range = t < rm ? t : rm;
     hit = ((unsigned)ix < (unsigned)W && (unsigned)iy < (unsigned)H) ? iy * W + ix : -2;
 }
 
@@ -597,6 +627,7 @@ struct TileJob {
     double c, s, x, y, xc, yc;
     int64_t OX, OY;
     int i0, j0, blocked, block_hit, env, dst;  // dst 0 obs row, 1 final_obs row, 2 none
+    int B0, P0;  // the origin cell's bit index in the bitmap and in its transpose
 };
 
 // Register budget of the fused step: 4 wavefronts per SIMD (16 per CU).
@@ -631,6 +662,8 @@ __device__ __forceinline__ void make_tile_job(TileJob &j, const MapView &M, floa
     j.block_hit = o.block_hit;
     j.env = env;
     j.dst = dst;
+    j.B0 = (o.j0 + kPad) * M.pitch + (o.i0 + kPad);
+    j.P0 = (o.i0 + kPad) * M.pitch_t + (o.j0 + kPad);
 }
 
 __device__ __forceinline__ RayOrigin tile_origin(const TileJob &j, double s) {
@@ -847,7 +880,6 @@ __device__ __forceinline__ uint4 pack_walk(const Walk &w, int max_n) {
     return r;
 }
 
-// Range, hit and visits of a walked ray, folded into the sector pool.
 // Range of a finished ray (direction dx, dy) folded into its sector's pooled
 // minimum; per-ray outputs for main jobs when requested.
 __device__ __forceinline__ void finish_ray_dir(const StepParams &p, const MapView &M,
@@ -864,14 +896,16 @@ __device__ __forceinline__ void finish_ray_dir(const StepParams &p, const MapVie
         const int B = (int)(res.x & 0x7FFFFu), k = (int)(res.x >> 19);
         vis = k + 1;
         if (res.y & 1u) {
-            walk_result(tile_origin(j, M.s), M.pitch, M.w, M.h, B, dx, dy, (double)p.rmax, rg,
-                        hit);
+            // bit 1: B indexes the transposed bitmap (run walk, y-major ray)
+            const bool tr = (res.y & 2u) != 0u;
+            walk_result(tile_origin(j, M.s), tr ? M.pitch_t : M.pitch, M.w, M.h, B, dx, dy,
+                        (double)p.rmax, rg, hit, tr);
         } else {
             rg = p.rmax;
             hit = -1;
         }
     }
-    atomicMin(&s_pool[job * p.m + small_div(beam, per, inv_per)], __float_as_uint(rg));
+    atomicMin(&s_pool[__mul24(job, p.m) + small_div(beam, per, inv_per)], __float_as_uint(rg));
     if (job < E) {
         const int64_t o = (int64_t)j.env * p.K + beam;
         if (p.d_ranges) p.d_ranges[o] = rg;
@@ -904,7 +938,7 @@ __device__ __forceinline__ void finish_march(const StepParams &p, const MapView 
     float rg;
     int hit, vis;
     march_result(p, M, j.x, j.y, dx, dy, (int)(res & 0x0FFFFFFFu), (int)(res >> 28), rg, hit, vis);
-    atomicMin(&s_pool[job * p.m + small_div(beam, per, inv_per)], __float_as_uint(rg));
+    atomicMin(&s_pool[__mul24(job, p.m) + small_div(beam, per, inv_per)], __float_as_uint(rg));
     if (job < E) {
         const int64_t o = (int64_t)j.env * p.K + beam;
         if (p.d_ranges) p.d_ranges[o] = rg;
@@ -1087,7 +1121,9 @@ __device__ __forceinline__ void march_walk(const StepParams &p, const MapView &M
             base = __shfl(base, 0);
             const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
             if (!act && my < Rc) {
-                const int g = c0 + my, jl = small_div(g, K, inv_K), beam = g - jl * K;
+                const int g = c0 + my;
+                int beam;
+                const int jl = small_divmod(g, K, inv_K, beam);
                 const TileJob &j = s_jobs[s_list[jl]];
                 const double2 cs = s_beam[beam];
                 dx = j.c * cs.x - j.s * cs.y;
@@ -1355,8 +1391,7 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
             const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
             if (!act && my < R) {
                 g = my;
-                const int jl = small_div(g, K, inv_K);
-                beam = g - jl * K;
+                const int jl = small_divmod(g, K, inv_K, beam);
                 job = s_list[jl];
                 const TileJob &j = s_jobs[job];
                 n = 0;
@@ -1405,6 +1440,23 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
 // extract), so that lanes walking x- and y-major rays run the same
 // instructions.  The cells, and therefore every result, are the other walks'.
 constexpr int kLongRun = 1 << 14;  // run length of an axis-parallel ray (past any budget)
+
+// floor(x / a) for 0 <= x <= 2^31 and 1 <= a <= 2^30 when that is below
+// 12000, else some value >= 8192: a run that long outlasts any walk's budget
+// (at most 8191 cells), so its exact length never matters.  inv_a is the
+// float reciprocal of a; the float estimate is then within one of the
+// quotient, and the two tests (q a < 2^32 for such q) fix it.
+__device__ __forceinline__ int run_quot(uint32_t x, uint32_t a, float inv_a) {
+    const float qf = (float)x * inv_a;
+    if (!(qf < 12000.0f)) return kLongRun;
+    int q = (int)qf;
+    const uint32_t qa = (uint32_t)q * a;
+    if (qa > x)
+        --q;
+    else if (x - qa >= a)
+        ++q;
+    return q;
+}
 
 // Per-ray constants of the run walk.  Positions are bit indices into the
 // staged line bitmap of the ray's major axis, plus `off`: the copy's start,
@@ -1468,13 +1520,13 @@ __device__ __forceinline__ void run_windows(const StepParams &p, const uint32_t 
 // run_windows, and a hit found in the transposed bitmap is turned back into
 // the bitmap's cell index for walk_result.
 __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapView &M,
-                                               const uint32_t *s_bits, int pitch_t,
+                                               const uint32_t *s_bits,
                                                const TileJob *s_jobs, const int *s_list,
                                                const double2 *s_beam, uint32_t *s_pool,
                                                int *s_misc, int R, int K, float inv_K, int per,
                                                float inv_per, double rmax_c, int max_n, int E,
                                                int lane) {
-    const float inv_pitch_t = __builtin_amdgcn_rcpf((float)pitch_t);
+    const int pitch_t = M.pitch_t;
     int g = -1, job = 0, beam = 0;
     bool act = false, exhausted = false, xmaj = true;
     RunRay c{};
@@ -1483,15 +1535,12 @@ __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapVie
     double rdx = 0.0, rdy = 0.0;  // the claimed ray's direction, kept for its range
     auto finish = [&]() {
         // the hit's line position (0 without a hit: the field shares its word
-        // with the visit count)
-        int Bh = flags ? Xh - c.off : 0;
-        if (flags && !xmaj) {
-            const int col = small_div(Bh, pitch_t, inv_pitch_t);
-            Bh = (Bh - col * pitch_t) * M.pitch + col;
-        }
+        // with the visit count); flag bit 1 marks a position in the transpose
+        const int Bh = flags ? Xh - c.off : 0;
         finish_ray_dir(p, M, s_jobs[job], rdx, rdy, job, beam,
-                       make_uint2((uint32_t)Bh | ((uint32_t)(n - rem) << 19), flags), s_pool, per,
-                       inv_per, E);
+                       make_uint2((uint32_t)Bh | ((uint32_t)(n - rem) << 19),
+                                  flags | (flags && !xmaj ? 2u : 0u)),
+                       s_pool, per, inv_per, E);
     };
     for (;;) {
         uint64_t am = __ballot(act);
@@ -1508,8 +1557,7 @@ __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapVie
             const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
             if (!act && my < R) {
                 g = my;
-                const int jl = small_div(g, K, inv_K);
-                beam = g - jl * K;
+                const int jl = small_divmod(g, K, inv_K, beam);
                 job = s_list[jl];
                 const TileJob &j = s_jobs[job];
                 n = 0;
@@ -1524,19 +1572,22 @@ __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapVie
                     xmaj = DX >= DY;
                     const int a = xmaj ? DY : DX, b = xmaj ? DX : DY;
                     e = xmaj ? Ep : -1 - Ep;
-                    // the run leaving the origin: ceil(-e / a) major steps
+                    // the run leaving the origin: ceil(-e / a) major steps; then
+                    // q = floor((b - 1) / a) (a = 0: an axis-parallel ray, one run)
+                    const float inv_a = __builtin_amdgcn_rcpf((float)a);
                     pend = 0;
-                    if (e < 0) {
-                        if (a > 0) {
-                            pend = (int)(((uint32_t)(-e) + (uint32_t)(a - 1)) / (uint32_t)a);
-                            e += pend * a;
-                        } else {
-                            pend = kLongRun;
+                    int q = kLongRun;
+                    if (a > 0) {
+                        if (e < 0) {
+                            pend = run_quot((uint32_t)(-e) + (uint32_t)(a - 1), (uint32_t)a, inv_a);
+                            e = (int)((uint32_t)e + (uint32_t)pend * (uint32_t)a);
                         }
+                        q = run_quot((uint32_t)(b - 1), (uint32_t)a, inv_a);
+                    } else if (e < 0) {
+                        pend = kLongRun;
                     }
-                    const int q = a > 0 ? (int)((uint32_t)(b - 1) / (uint32_t)a) : kLongRun;
                     c.q1 = q + 1;
-                    c.M1 = a > 0 ? b - q * a : 0;
+                    c.M1 = a > 0 ? (int)((uint32_t)b - (uint32_t)q * (uint32_t)a) : 0;
                     c.up = a - c.M1;
                     c.dn = -c.M1;
                     const bool down = xmaj ? w.incx < 0 : w.incy < 0;
@@ -1545,7 +1596,7 @@ __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapVie
                     c.sm = down ? -1 : 0;
                     c.dmin = smin - smaj;
                     c.off = (down ? -31 : 0) + (xmaj ? 0 : 32 * p.tbits_off);
-                    X = (xmaj ? w.B : (j.i0 + kPad) * pitch_t + (j.j0 + kPad)) + smaj + c.off;
+                    X = (xmaj ? j.B0 : j.P0) + smaj + c.off;
                 }
                 rem = n;
                 flags = 0u;
@@ -1760,12 +1811,12 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
     const int nj = s_misc[0];
     const int R = nj * K;
     const float inv_K = 1.0f / (float)K, inv_per = 1.0f / (float)per;
-    const double rmax_c = (double)p.rmax / M.s;
+    const double rmax_c = walk_cells((double)p.rmax, M.s);
     const int max_n = M.w + M.h + 2 * kPad;  // a walk meets the padding ring before this
     if (p.claim) {
         // s_misc[1] (next ray) and the pool were cleared before the last barrier
         if (p.tbits_off)
-            claim_run_walk(p, M, s_bits, md.wpr_t * 32, s_jobs, s_list, s_beam, s_pool, s_misc, R,
+            claim_run_walk(p, M, s_bits, s_jobs, s_list, s_beam, s_pool, s_misc, R,
                            K, inv_K, per, inv_per, rmax_c, max_n, E, lane);
         else if (p.cell_bytes)
             claim_walk<true>(p, M, s_bits, s_cells, s_jobs, s_list, s_beam, s_pool, s_misc, R, K,
@@ -1779,7 +1830,9 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
         const int Rc = min(p.ray_cap, R - c0);
         // (1) every ray's walk start, all lanes busy (the march needs none)
         for (int r = tid; r < Rc && p.scan_mode != 1; r += T) {
-            const int g = c0 + r, jl = small_div(g, K, inv_K), beam = g - jl * K;
+            const int g = c0 + r;
+            int beam;
+            const int jl = small_divmod(g, K, inv_K, beam);
             const TileJob &j = s_jobs[s_list[jl]];
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (!j.blocked) {
@@ -1807,7 +1860,9 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
         __syncthreads();
         // (3) ranges, hits, pooling, all lanes busy
         for (int q = tid; q < Rc; q += T) {
-            const int g = c0 + q, jl = small_div(g, K, inv_K), beam = g - jl * K;
+            const int g = c0 + q;
+            int beam;
+            const int jl = small_divmod(g, K, inv_K, beam);
             const int job = s_list[jl];
             const uint4 v = s_ray[q];
             if (p.scan_mode == 1)
@@ -1873,7 +1928,7 @@ void fused_step_kernel(StepParams p) {
 __device__ void observe_serial(const StepParams &p, const MapView &M, const MapDesc &md, double x,
                                double y, double c, double sn, float *obs_row, int64_t dbg_row) {
     const RayOrigin o = ray_origin(M, x, y);
-    const double rmax = (double)p.rmax, rmax_c = rmax / M.s;
+    const double rmax = (double)p.rmax, rmax_c = walk_cells(rmax, M.s);
     const double2 *beams = p.beams + md.beam_off;
     const int per = md.K / p.m;
     for (int j = 0; j < p.m; ++j) {
