@@ -23,14 +23,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_FILE = os.path.join(HERE, "tuning.json")
 DEFAULT = {"tile_envs": 8, "refill_at": 40, "groups": 8, "ray_slots": 0, "walk": 3, "persist": 0,
            "threads": 256, "balance": 0}
-# walk = 1 (run walk) measured about 2x slower than the group walk on every
-# workload here, persistent workgroups 5-40 % slower, the chunked bitmap walk
-# (walk 0) behind the byte and claim walks; --full-space includes them
-SPACE = {"tile_envs": (1, 2, 4, 8, 16, 32), "refill_at": (32, 40, 48), "groups": (8, 16),
-         "ray_slots": (0,), "walk": (2, 3, 4), "persist": (0,), "threads": (256, 512, 1024),
+# walk = 1 (chunked run walk) measured about 2x slower than the group walk on
+# every workload here, persistent workgroups 5-40 % slower, the chunked bitmap
+# walk (walk 0) behind the byte and claim walks; --full-space includes them
+SPACE = {"tile_envs": (1, 2, 4, 8, 16, 32), "refill_at": (24, 32, 40, 48), "groups": (8, 16),
+         "ray_slots": (0,), "walk": (2, 3, 4, 5), "persist": (0,), "threads": (256, 512, 1024),
          "balance": (0, 1)}
-FULL_SPACE = dict(SPACE, refill_at=(24, 32, 40, 48, 56), groups=(2, 4, 8, 16, 32),
-                  ray_slots=(0, 512, 1024, 2048), walk=(0, 1, 2, 3, 4), persist=(0, 2))
+FULL_SPACE = dict(SPACE, refill_at=(16, 24, 32, 40, 48, 56), groups=(2, 4, 8, 16, 32),
+                  ray_slots=(0, 512, 1024, 2048), walk=(0, 1, 2, 3, 4, 5), persist=(0, 2))
 FIELDS = tuple(DEFAULT)
 
 
@@ -129,16 +129,21 @@ def main():
     ap.add_argument("--table-out", default=None,
                     help="JSON file for the whole sweep table (not kept in the product)")
     ap.add_argument("--full-space", action="store_true")
+    ap.add_argument("--burn-in", type=int, default=250,
+                    help="steps run before timing, past the episode horizon, so that the timed "
+                         "steps hold the steady mix of resets")
     args = ap.parse_args()
     w = configs.build_workload(args.workload)
     cfg = w["cfg"]
     dev = torch.device("cuda", 0)
     sim = NavSim(cfg, w["maps"], w["res"], w["env_map"], device=0, profiles=w["profiles"])
     sim.reset()
-    acts = torch.from_numpy(configs.uniform_actions(args.steps + 20, cfg["num_envs"], seed=7)).to(dev)
-    for t in range(20):
-        sim.step(acts[t])
-    best, table = tune(sim, acts[20:], steps=args.steps, verbose=True,
+    N = cfg["num_envs"]
+    acts = torch.from_numpy(configs.uniform_actions(args.steps, N, seed=7)).to(dev)
+    burn = torch.from_numpy(configs.uniform_actions(min(args.burn_in, 64), N, seed=8)).to(dev)
+    for t in range(args.burn_in):
+        sim.step(burn[t % burn.shape[0]])
+    best, table = tune(sim, acts, steps=args.steps, verbose=True,
                        space=FULL_SPACE if args.full_space else SPACE)
     key = workload_key(cfg, w["maps"], w["profiles"])
     save(key, best, table, torch.cuda.get_device_name(0), args.out, args.table_out)
