@@ -378,7 +378,7 @@ __device__ __forceinline__ void walk_result(const RayOrigin &o, int pitch, int W
     t = t > 0.0f ? t : 0.0f;  // also maps -0 and NaN to +0
     const float rm = (float)rmax;
     range = t < rm ? t : rm;
-    hit = ((unsigned)ix < (unsigned)W && (unsigned)iy < (unsigned)H) ? iy * W + ix : -2;
+    hit = ((unsigned)ix < (unsigned)W && (unsigned)iy < (unsigned)H) ? __mul24(iy, W) + ix : -2;
 }
 
 // Sequential walk of one ray (plain kernel).
@@ -666,6 +666,13 @@ __device__ __forceinline__ void make_tile_job(TileJob &j, const MapView &M, floa
     j.P0 = (o.i0 + kPad) * M.pitch_t + (o.j0 + kPad);
 }
 
+// s_jobs[job], its offset as a full-rate 24-bit product (a TileJob's size is
+// not a power of two)
+__device__ __forceinline__ const TileJob &job_ref(const TileJob *s_jobs, int job) {
+    return *reinterpret_cast<const TileJob *>(reinterpret_cast<const char *>(s_jobs) +
+                                              __mul24(job, (int)sizeof(TileJob)));
+}
+
 __device__ __forceinline__ RayOrigin tile_origin(const TileJob &j, double s) {
     RayOrigin o;
     o.x = j.x;
@@ -906,7 +913,7 @@ __device__ __forceinline__ void finish_ray_dir(const StepParams &p, const MapVie
         }
     }
     atomicMin(&s_pool[__mul24(job, p.m) + small_div(beam, per, inv_per)], __float_as_uint(rg));
-    if (job < E) {
+    if (job < E && (p.d_ranges || p.d_hits || p.d_visits)) {
         const int64_t o = (int64_t)j.env * p.K + beam;
         if (p.d_ranges) p.d_ranges[o] = rg;
         if (p.d_hits) p.d_hits[o] = hit;
@@ -939,7 +946,7 @@ __device__ __forceinline__ void finish_march(const StepParams &p, const MapView 
     int hit, vis;
     march_result(p, M, j.x, j.y, dx, dy, (int)(res & 0x0FFFFFFFu), (int)(res >> 28), rg, hit, vis);
     atomicMin(&s_pool[__mul24(job, p.m) + small_div(beam, per, inv_per)], __float_as_uint(rg));
-    if (job < E) {
+    if (job < E && (p.d_ranges || p.d_hits || p.d_visits)) {
         const int64_t o = (int64_t)j.env * p.K + beam;
         if (p.d_ranges) p.d_ranges[o] = rg;
         if (p.d_hits) p.d_hits[o] = hit;
@@ -1378,7 +1385,7 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
         uint64_t am = __ballot(act);
         if (!exhausted && __popcll(am) <= p.refill_at) {
             if (!act && g >= 0) {
-                finish_ray_dir(p, M, s_jobs[job], rdx, rdy, job, beam,
+                finish_ray_dir(p, M, job_ref(s_jobs, job), rdx, rdy, job, beam,
                                make_uint2((uint32_t)Bh | ((uint32_t)(n - rem) << 19), flags),
                                s_pool, per, inv_per, E);
                 g = -1;
@@ -1393,7 +1400,7 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
                 g = my;
                 const int jl = small_divmod(g, K, inv_K, beam);
                 job = s_list[jl];
-                const TileJob &j = s_jobs[job];
+                const TileJob &j = job_ref(s_jobs, job);
                 n = 0;
                 if (!j.blocked) {
                     const double2 cs = s_beam[beam];
@@ -1419,7 +1426,7 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
         if (act) walk_run<BYTES>(p, s_bits, S, Dx, Dy, rem, flags, act, Bh);
     }
     if (g >= 0)
-        finish_ray_dir(p, M, s_jobs[job], rdx, rdy, job, beam,
+        finish_ray_dir(p, M, job_ref(s_jobs, job), rdx, rdy, job, beam,
                        make_uint2((uint32_t)Bh | ((uint32_t)(n - rem) << 19), flags), s_pool, per,
                        inv_per, E);
 }
@@ -1446,15 +1453,19 @@ constexpr int kLongRun = 1 << 14;  // run length of an axis-parallel ray (past a
 // (at most 8191 cells), so its exact length never matters.  inv_a is the
 // float reciprocal of a; the float estimate is then within one of the
 // quotient, and the two tests (q a < 2^32 for such q) fix it.
-__device__ __forceinline__ int run_quot(uint32_t x, uint32_t a, float inv_a) {
+// r = x - q a (the remainder when q is exact; anything otherwise).
+__device__ __forceinline__ int run_quot(uint32_t x, uint32_t a, float inv_a, uint32_t &r) {
     const float qf = (float)x * inv_a;
     if (!(qf < 12000.0f)) return kLongRun;
     int q = (int)qf;
-    const uint32_t qa = (uint32_t)q * a;
-    if (qa > x)
+    r = x - (uint32_t)q * a;
+    if ((int32_t)r < 0) {  // |r| < 2 a <= 2^31: the sign bit tells
         --q;
-    else if (x - qa >= a)
+        r += a;
+    } else if (r >= a) {
         ++q;
+        r -= a;
+    }
     return q;
 }
 
@@ -1537,7 +1548,7 @@ __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapVie
         // the hit's line position (0 without a hit: the field shares its word
         // with the visit count); flag bit 1 marks a position in the transpose
         const int Bh = flags ? Xh - c.off : 0;
-        finish_ray_dir(p, M, s_jobs[job], rdx, rdy, job, beam,
+        finish_ray_dir(p, M, job_ref(s_jobs, job), rdx, rdy, job, beam,
                        make_uint2((uint32_t)Bh | ((uint32_t)(n - rem) << 19),
                                   flags | (flags && !xmaj ? 2u : 0u)),
                        s_pool, per, inv_per, E);
@@ -1559,7 +1570,7 @@ __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapVie
                 g = my;
                 const int jl = small_divmod(g, K, inv_K, beam);
                 job = s_list[jl];
-                const TileJob &j = s_jobs[job];
+                const TileJob &j = job_ref(s_jobs, job);
                 n = 0;
                 if (!j.blocked) {
                     const double2 cs = s_beam[beam];
@@ -1574,20 +1585,24 @@ __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapVie
                     e = xmaj ? Ep : -1 - Ep;
                     // the run leaving the origin: ceil(-e / a) major steps; then
                     // q = floor((b - 1) / a) (a = 0: an axis-parallel ray, one run)
+                    // (remainders instead of products: e + pend a = a - 1 - r0 and
+                    // M1 = b - q a = r1 + 1)
                     const float inv_a = __builtin_amdgcn_rcpf((float)a);
                     pend = 0;
                     int q = kLongRun;
+                    uint32_t r0 = 0u, r1 = 0u;
                     if (a > 0) {
                         if (e < 0) {
-                            pend = run_quot((uint32_t)(-e) + (uint32_t)(a - 1), (uint32_t)a, inv_a);
-                            e = (int)((uint32_t)e + (uint32_t)pend * (uint32_t)a);
+                            pend = run_quot((uint32_t)(-e) + (uint32_t)(a - 1), (uint32_t)a, inv_a,
+                                            r0);
+                            e = a - 1 - (int)r0;
                         }
-                        q = run_quot((uint32_t)(b - 1), (uint32_t)a, inv_a);
+                        q = run_quot((uint32_t)(b - 1), (uint32_t)a, inv_a, r1);
                     } else if (e < 0) {
                         pend = kLongRun;
                     }
                     c.q1 = q + 1;
-                    c.M1 = a > 0 ? (int)((uint32_t)b - (uint32_t)q * (uint32_t)a) : 0;
+                    c.M1 = a > 0 ? (int)r1 + 1 : 0;
                     c.up = a - c.M1;
                     c.dn = -c.M1;
                     const bool down = xmaj ? w.incx < 0 : w.incy < 0;
