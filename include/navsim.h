@@ -262,9 +262,13 @@ typedef struct {
                            bitmap (32x its LDS; no address arithmetic or bit extraction per
                            cell); 3: as 0, but each lane sets up the rays it claims and
                            pools each ray when done (no LDS ray slots, no chunks; ray_slots
-                           is ignored); 4: as 3 on the byte copy.  3 and 4 apply to the
-                           exact traversal; the fixed-step march keeps its chunked walk.
-                           Same cells, same results                                       */
+                           is ignored); 4: as 3 on the byte copy; 5: as 3, testing up to
+                           31 cells of a run between minor-axis steps at once, x-major rays
+                           in the bitmap and y-major rays in its transpose staged beside it
+                           (2x the bitmap's LDS; UNSUPPORTED for a transposed bitmap of
+                           16384 words or more).  3, 4 and 5 apply to the exact traversal;
+                           the fixed-step march keeps its chunked walk.  Same cells, same
+                           results                                                        */
     int32_t persist;    /* 0: one workgroup per tile; c in 1..64: only as many workgroups
                            as stay resident, each taking c consecutive tiles at a time from
                            a device counter and keeping its staged map while the tiles'
