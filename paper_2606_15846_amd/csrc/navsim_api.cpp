@@ -290,6 +290,59 @@ double map_scan_work(const uint8_t *occ, int W, int H, double s, double rmax, in
     return (double)K * (1.0 + cells / rays);
 }
 
+// Launch order for the XCDs' own L2 caches.  The dispatcher hands workgroup i
+// to XCD i mod kXcds, so the tiles at positions x, x + kXcds, x + 2 kXcds, ...
+// all run on XCD x; placing a map's tiles there lets that XCD's L2 fetch the
+// map's bitmaps from HBM once instead of every XCD fetching them.  Maps go to
+// XCDs in descending total work, each to the least-loaded XCD with room for
+// all of its tiles (each XCD takes exactly its share of positions; a map is
+// split only when no XCD has room), and each XCD runs its own tiles heaviest
+// first.  Results do not depend on the order; small launches (fewer than two
+// tiles per XCD, or fewer maps than XCDs) keep the plain heaviest-first order.
+void order_tiles_by_xcd(std::vector<Tile> &tiles, const std::vector<double> &map_weight) {
+    const int T = (int)tiles.size();
+    std::vector<int> maps;  // in first-seen order of the heaviest-first list
+    std::vector<double> work(map_weight.size(), 0.0);
+    std::vector<int> ntile(map_weight.size(), 0);
+    for (const Tile &t : tiles) {
+        if (ntile[t.map]++ == 0) maps.push_back(t.map);
+        work[t.map] += map_weight[t.map] * t.count;
+    }
+    if (T < 2 * kXcds || (int)maps.size() < kXcds) return;
+    std::stable_sort(maps.begin(), maps.end(),
+                     [&](int a, int b) { return work[a] > work[b]; });
+    std::vector<int> room(kXcds), xcd_of(map_weight.size(), -1);
+    std::vector<double> load(kXcds, 0.0);
+    for (int x = 0; x < kXcds; ++x) room[x] = T / kXcds + (x < T % kXcds ? 1 : 0);
+    std::vector<std::vector<Tile>> per(kXcds);
+    std::vector<std::vector<Tile>> by_map(map_weight.size());
+    for (const Tile &t : tiles) by_map[t.map].push_back(t);  // heaviest first within a map
+    for (const int m : maps) {
+        std::vector<Tile> &mt = by_map[m];
+        size_t next = 0;
+        while (next < mt.size()) {
+            const int need = (int)(mt.size() - next);
+            int best = -1;
+            for (int x = 0; x < kXcds; ++x)  // least loaded with room for the rest
+                if (room[x] >= need && (best < 0 || load[x] < load[best])) best = x;
+            if (best < 0)  // none: the XCD with the most room takes what fits
+                for (int x = 0; x < kXcds; ++x)
+                    if (room[x] > 0 && (best < 0 || room[x] > room[best])) best = x;
+            const int take = std::min(need, room[best]);
+            for (int k = 0; k < take; ++k, ++next) {
+                per[best].push_back(mt[next]);
+                load[best] += map_weight[m] * mt[next].count;
+            }
+            room[best] -= take;
+        }
+    }
+    for (int x = 0; x < kXcds; ++x)
+        std::stable_sort(per[x].begin(), per[x].end(), [&](const Tile &a, const Tile &b) {
+            return map_weight[a.map] * a.count > map_weight[b.map] * b.count;
+        });
+    for (int i = 0; i < T; ++i) tiles[i] = per[i % kXcds][i / kXcds];
+}
+
 // Envs grouped by map into tiles, launched heaviest first (longest-processing-
 // time order) by the tiles' estimated scan work (envs x the map's work per
 // env); tiles of equal weight keep their order, so a map's full tiles stay
@@ -357,6 +410,7 @@ void build_tiles(const std::vector<int32_t> &env_map, int tile_envs,
     std::stable_sort(tiles.begin(), tiles.end(), [&](const Tile &a, const Tile &b) {
         return map_weight[a.map] * a.count > map_weight[b.map] * b.count;
     });
+    order_tiles_by_xcd(tiles, map_weight);
 }
 
 navsim_status run(navsim_t h, const StepParams &p, int kernel, hipStream_t s) {

@@ -118,6 +118,7 @@ int fused_ray_cap(int max_words, int m, int tile_envs, int K, bool beams_lds, in
                   int cell_bytes);
 // Wavefronts per CU that the fused step's register budget allows (4 per SIMD).
 constexpr int kFusedWavesPerCu = 16;
+constexpr int kXcds = 8;  // gfx950: 8 XCDs of 32 CUs, each with its own L2
 // Workgroups of the fused step that fit on the current device at once (0 on error).
 int fused_resident_groups(int max_words, int m, int tile_envs, int threads, int K, bool beams_lds,
                           int ray_cap, int cell_bytes);
