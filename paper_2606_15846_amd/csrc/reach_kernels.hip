@@ -279,61 +279,69 @@ __global__ __launch_bounds__(kReachThreads) void label_kernel(ReachParams rp, co
 // wavefronts of a workgroup check four candidates at once.
 
 // Word j (uniform) of a lane's 32 registers, without dynamic register indexing.
-__device__ __forceinline__ uint32_t pick_word(const uint32_t v[32], int j) {
-    uint32_t out = 0u;
+// One breadth-first level of wave_hops: the next frontier nx from fr; a cell
+// joins it iff a 4-neighbour is in fr and it is still in un (C-free, not
+// reached yet), and then leaves un.  Returns whether any lane's nx is
+// non-empty.  A word's horizontal neighbours come from two funnel shifts with
+// the adjacent words of its row.
+template <int WPR>
+__device__ __forceinline__ bool wave_level(const uint32_t fr[32], uint32_t nx[32], uint32_t un[32],
+                                           int lane) {
+    uint32_t up[WPR], dn[WPR];
 #pragma unroll
-    for (int q = 0; q < 32; ++q)
-        if (q == j) out = v[q];
-    return out;
+    for (int k = 0; k < WPR; ++k) {
+        // rows above the lane's first: the last row of lane - 1; below its
+        // last: the first row of lane + 1 (none past the ends)
+        const uint32_t u = __shfl_up(fr[32 - WPR + k], 1);
+        const uint32_t w = __shfl_down(fr[k], 1);
+        up[k] = lane > 0 ? u : 0u;
+        dn[k] = lane < 63 ? w : 0u;
+    }
+    uint32_t any = 0u;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const uint32_t prev = j % WPR != 0 ? fr[j % WPR != 0 ? j - 1 : 0] : 0u;
+        const uint32_t next = j % WPR != WPR - 1 ? fr[j % WPR != WPR - 1 ? j + 1 : 0] : 0u;
+        const uint32_t h = __builtin_amdgcn_alignbit(fr[j], prev, 31u) |
+                           __builtin_amdgcn_alignbit(next, fr[j], 1u);
+        const uint32_t v = (j >= WPR ? fr[j >= WPR ? j - WPR : 0] : up[j < WPR ? j : 0]) |
+                           (j + WPR < 32 ? fr[j + WPR < 32 ? j + WPR : 0]
+                                         : dn[j + WPR >= 32 ? j + WPR - 32 : 0]);
+        nx[j] = (h | v) & un[j];
+        un[j] ^= nx[j];
+        any |= nx[j];
+    }
+    return __ballot(any != 0u) != 0ull;
 }
 
 // Hop count from a to b (both C-free, a != b) within max_hops moves, else -1
-// (uniform across the wavefront); the same levels as hops_to.
+// (uniform across the wavefront); the same levels as hops_to.  Per lane: 32
+// words of rows of WPR words; two frontier buffers used in turn (two levels
+// per loop pass, so no frontier is copied).
 template <int WPR>
 __device__ int wave_hops(const uint32_t cf[32], const ReachDesc &d, int a, int b, int max_hops,
                          int lane) {
     const int wa = (a / d.W) * WPR + ((a % d.W) >> 5);
     const int wb = (b / d.W) * WPR + ((b % d.W) >> 5);
-    const int la = wa >> 5, ja = wa & 31, lb = wb >> 5, jb = wb & 31;
+    const int la = wa >> 5, ja = wa & 31, lb = wb >> 5;
+    // b's register index is the same on every lane: read it with one relative
+    // move rather than a select over all 32 words
+    const int jb = __builtin_amdgcn_readfirstlane(wb & 31);
     const uint32_t ba = 1u << ((a % d.W) & 31), bb = (b % d.W) & 31;
-    uint32_t fr[32], vis[32];
+    uint32_t f0[32], f1[32], un[32];
 #pragma unroll
     for (int j = 0; j < 32; ++j) {
         const uint32_t seed = (lane == la && j == ja) ? ba : 0u;
-        fr[j] = seed;
-        vis[j] = seed;
+        f0[j] = seed;
+        un[j] = cf[j] & ~seed;
     }
-    for (int level = 1; level <= max_hops; ++level) {
-        uint32_t up[WPR], dn[WPR];
-#pragma unroll
-        for (int k = 0; k < WPR; ++k) {
-            // rows above the lane's first: the last row of lane - 1; below its
-            // last: the first row of lane + 1 (none past the ends)
-            const uint32_t u = __shfl_up(fr[32 - WPR + k], 1);
-            const uint32_t w = __shfl_down(fr[k], 1);
-            up[k] = lane > 0 ? u : 0u;
-            dn[k] = lane < 63 ? w : 0u;
-        }
-        uint32_t any = 0u, nx[32];
-#pragma unroll
-        for (int j = 0; j < 32; ++j) {
-            const uint32_t f = fr[j];
-            uint32_t g = (f << 1) | (f >> 1);
-            if (j % WPR != 0) g |= fr[j - 1] >> 31;
-            if (j % WPR != WPR - 1) g |= fr[j + 1] << 31;
-            g |= j >= WPR ? fr[j >= WPR ? j - WPR : 0] : up[j < WPR ? j : 0];
-            g |= j + WPR < 32 ? fr[j + WPR < 32 ? j + WPR : 0] : dn[j + WPR >= 32 ? j + WPR - 32 : 0];
-            nx[j] = g & cf[j] & ~vis[j];
-            any |= nx[j];
-        }
-#pragma unroll
-        for (int j = 0; j < 32; ++j) {
-            vis[j] |= nx[j];
-            fr[j] = nx[j];
-        }
-        const uint32_t gw = __shfl(pick_word(nx, jb), lb);
-        if ((gw >> bb) & 1u) return level;
-        if (__ballot(any != 0u) == 0ull) return -1;
+    for (int level = 1; level <= max_hops; level += 2) {
+        bool more = wave_level<WPR>(f0, f1, un, lane);
+        if ((__shfl(f1[jb], lb) >> bb) & 1u) return level;
+        if (!more || level + 1 > max_hops) return -1;
+        more = wave_level<WPR>(f1, f0, un, lane);
+        if ((__shfl(f0[jb], lb) >> bb) & 1u) return level + 1;
+        if (!more) return -1;
     }
     return -1;
 }
