@@ -319,28 +319,31 @@ __device__ __forceinline__ bool wave_level(const uint32_t fr[32], uint32_t nx[32
 // words of rows of WPR words; two frontier buffers used in turn (two levels
 // per loop pass, so no frontier is copied).
 template <int WPR>
-__device__ int wave_hops(const uint32_t cf[32], const ReachDesc &d, int a, int b, int max_hops,
+__device__ int wave_hops(const uint32_t *fb, const ReachDesc &d, int a, int b, int max_hops,
                          int lane) {
     const int wa = (a / d.W) * WPR + ((a % d.W) >> 5);
     const int wb = (b / d.W) * WPR + ((b % d.W) >> 5);
     const int la = wa >> 5, ja = wa & 31, lb = wb >> 5;
-    // b's register index is the same on every lane: read it with one relative
-    // move rather than a select over all 32 words
+    // b is reached when its bit leaves un; its register index is the same on
+    // every lane (one relative register move)
     const int jb = __builtin_amdgcn_readfirstlane(wb & 31);
     const uint32_t ba = 1u << ((a % d.W) & 31), bb = (b % d.W) & 31;
+    // the C-free words come from the staged map in LDS (lane l holds words
+    // 32 l .. 32 l + 31), read once per search rather than kept in registers
     uint32_t f0[32], f1[32], un[32];
+    const int base = lane * 32;
 #pragma unroll
     for (int j = 0; j < 32; ++j) {
         const uint32_t seed = (lane == la && j == ja) ? ba : 0u;
         f0[j] = seed;
-        un[j] = cf[j] & ~seed;
+        un[j] = (base + j < d.words ? fb[base + j] : 0u) & ~seed;
     }
     for (int level = 1; level <= max_hops; level += 2) {
         bool more = wave_level<WPR>(f0, f1, un, lane);
-        if ((__shfl(f1[jb], lb) >> bb) & 1u) return level;
+        if (!((__shfl(un[jb], lb) >> bb) & 1u)) return level;
         if (!more || level + 1 > max_hops) return -1;
         more = wave_level<WPR>(f1, f0, un, lane);
-        if ((__shfl(f0[jb], lb) >> bb) & 1u) return level + 1;
+        if (!((__shfl(un[jb], lb) >> bb) & 1u)) return level + 1;
         if (!more) return -1;
     }
     return -1;
@@ -376,7 +379,7 @@ __device__ int wave_snap(const ReachDesc &d, const uint32_t *fb, int c, int lane
 // The exact check of (a, b) for bin k by one wavefront (see check_pair).
 template <int WPR>
 __device__ int wave_check(const ReachParams &rp, const ReachDesc &d, const uint32_t *fb,
-                          const uint32_t cf[32], int a, int b, int k, int lane) {
+                          int a, int b, int k, int lane) {
     if (a < 0 || b < 0 || !lds_cell(fb, d, a) || !lds_cell(fb, d, b)) return -1;
     if (centre_dist(d, a, b) < rp.gmd) return -1;
     const int hi = rp.bin_hi[k];
@@ -385,7 +388,7 @@ __device__ int wave_check(const ReachParams &rp, const ReachDesc &d, const uint3
         h = 0;
     } else {
         const int man = abs(a % d.W - b % d.W) + abs(a / d.W - b / d.W);
-        h = man > hi ? -1 : wave_hops<WPR>(cf, d, a, b, hi, lane);
+        h = man > hi ? -1 : wave_hops<WPR>(fb, d, a, b, hi, lane);
     }
     return (h >= 0 && rp.hop_bin[h] == k) ? h : -1;
 }
@@ -420,10 +423,6 @@ __device__ void propose_waves(const ReachParams &rp, const ProposeArgs &pa, cons
     __shared__ int s_ok[4], s_a[4], s_b[4], s_h[4];
     __shared__ float s_th[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t cf[32];
-    const int base = lane * 32;
-#pragma unroll
-    for (int j = 0; j < 32; ++j) cf[j] = base + j < d.words ? fb[base + j] : 0u;
     const int total = pa.props + (d.free_cnt > 0 ? pa.tries : 0);
     int win = -1, la = -1, lb = -1, lh = -1;
     float lth = 0.0f;
@@ -433,7 +432,7 @@ __device__ void propose_waves(const ReachParams &rp, const ProposeArgs &pa, cons
         float th = 0.0f;
         if (c < total) {
             candidate(rp, pa, d, fb, i, c, lane, a, b, th);
-            h = wave_check<WPR>(rp, d, fb, cf, a, b, k, lane);
+            h = wave_check<WPR>(rp, d, fb, a, b, k, lane);
         }
         if (lane == 0) {
             s_ok[wave] = (c < total && h >= 0) ? c : INT_MAX;
