@@ -291,12 +291,14 @@ __device__ __forceinline__ bool wave_level(const uint32_t fr[32], uint32_t nx[32
 #pragma unroll
     for (int k = 0; k < WPR; ++k) {
         // rows above the lane's first: the last row of lane - 1; below its
-        // last: the first row of lane + 1 (none past the ends)
-        const uint32_t u = __shfl_up(fr[32 - WPR + k], 1);
-        const uint32_t w = __shfl_down(fr[k], 1);
-        up[k] = lane > 0 ? u : 0u;
-        dn[k] = lane < 63 ? w : 0u;
+        // last: the first row of lane + 1; none past the ends.  DPP wavefront
+        // shifts by one lane (wave_shr:1, wave_shl:1), the lane past an end
+        // reading 0: one full-rate move each, no LDS permute and no select
+        up[k] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)fr[32 - WPR + k], 0x138, 0xf, 0xf,
+                                                      true);
+        dn[k] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)fr[k], 0x130, 0xf, 0xf, true);
     }
+    (void)lane;
     uint32_t any = 0u;
 #pragma unroll
     for (int j = 0; j < 32; ++j) {
