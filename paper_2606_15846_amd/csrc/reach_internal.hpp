@@ -10,6 +10,9 @@ namespace navsim {
 constexpr int kReachMaxWords = 2048;  // C-free bitset words per map (e.g. 256 x 256 cells)
 constexpr int kReachMaxBins = 16;
 constexpr int kReachThreads = 256;
+// propose_kernel: one candidate check per wavefront, 8 at a time for launches
+// of at most this many requests, else 4
+constexpr int kProposeWideMax = 2048;
 constexpr int kPoolCells = 1024;      // 32 x 32 pooled occupancy
 
 // One map's C-free bitset: row j, column i is bit i & 31 of word

@@ -416,19 +416,20 @@ __device__ void candidate(const ReachParams &rp, const ProposeArgs &pa, const Re
     }
 }
 
-// Proposals with one candidate per wavefront: candidates 4 r .. 4 r + 3 are
-// checked together and the lowest valid one wins, the result of checking
-// them in order; `checks` counts as the sequential search does.
-template <int WPR>
+// Proposals with one candidate per wavefront: candidates W r .. W r + W - 1
+// (W wavefronts) are checked together and the lowest valid one wins, the
+// result of checking them in order; `checks` counts as the sequential search
+// does.
+template <int WPR, int W>
 __device__ void propose_waves(const ReachParams &rp, const ProposeArgs &pa, const ReachDesc &d,
                               const uint32_t *fb, int i, int o, int k) {
-    __shared__ int s_ok[4], s_a[4], s_b[4], s_h[4];
-    __shared__ float s_th[4];
+    __shared__ int s_ok[W], s_a[W], s_b[W], s_h[W];
+    __shared__ float s_th[W];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int total = pa.props + (d.free_cnt > 0 ? pa.tries : 0);
     int win = -1, la = -1, lb = -1, lh = -1;
     float lth = 0.0f;
-    for (int c0 = 0; c0 < total && win < 0; c0 += 4) {
+    for (int c0 = 0; c0 < total && win < 0; c0 += W) {
         const int c = c0 + wave;
         int a = -1, b = -1, h = -1;
         float th = 0.0f;
@@ -445,7 +446,7 @@ __device__ void propose_waves(const ReachParams &rp, const ProposeArgs &pa, cons
         }
         __syncthreads();
         int best = INT_MAX, bw = -1;
-        for (int w = 0; w < 4; ++w)
+        for (int w = 0; w < W; ++w)
             if (s_ok[w] < best) {
                 best = s_ok[w];
                 bw = w;
@@ -456,7 +457,7 @@ __device__ void propose_waves(const ReachParams &rp, const ProposeArgs &pa, cons
             lb = s_b[bw];
             lh = s_h[bw];
             lth = s_th[bw];
-        } else if (total - 1 >= c0 && total - 1 < c0 + 4 && total - 1 >= pa.props) {
+        } else if (total - 1 >= c0 && total - 1 < c0 + W && total - 1 >= pa.props) {
             // none valid: the last rejection attempt's pair stands
             const int w = total - 1 - c0;
             la = s_a[w];
@@ -484,7 +485,9 @@ __device__ void propose_waves(const ReachParams &rp, const ProposeArgs &pa, cons
     }
 }
 
-__global__ __launch_bounds__(kReachThreads) void propose_kernel(ReachParams rp, ProposeArgs pa) {
+// One workgroup of W wavefronts per request.
+template <int W>
+__global__ __launch_bounds__(64 * W) void propose_kernel(ReachParams rp, ProposeArgs pa) {
     extern __shared__ uint4 lds4[];  // 16-byte aligned: the searches clear it 16 bytes at a time
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     __shared__ int s_min;
@@ -510,14 +513,14 @@ __global__ __launch_bounds__(kReachThreads) void propose_kernel(ReachParams rp, 
              *nx = fr + kReachMaxWords;
     stage_free(rp, d, fb);
     __syncthreads();
-    if (blockDim.x == 256 && d.wpr * d.H <= kReachMaxWords && 32 % d.wpr == 0) {
+    if (d.wpr * d.H <= kReachMaxWords && 32 % d.wpr == 0) {
         switch (d.wpr) {  // rows of 1, 2, 4, ..., 32 words: searches in registers
-            case 1: propose_waves<1>(rp, pa, d, fb, i, o, k); return;
-            case 2: propose_waves<2>(rp, pa, d, fb, i, o, k); return;
-            case 4: propose_waves<4>(rp, pa, d, fb, i, o, k); return;
-            case 8: propose_waves<8>(rp, pa, d, fb, i, o, k); return;
-            case 16: propose_waves<16>(rp, pa, d, fb, i, o, k); return;
-            default: propose_waves<32>(rp, pa, d, fb, i, o, k); return;
+            case 1: propose_waves<1, W>(rp, pa, d, fb, i, o, k); return;
+            case 2: propose_waves<2, W>(rp, pa, d, fb, i, o, k); return;
+            case 4: propose_waves<4, W>(rp, pa, d, fb, i, o, k); return;
+            case 8: propose_waves<8, W>(rp, pa, d, fb, i, o, k); return;
+            case 16: propose_waves<16, W>(rp, pa, d, fb, i, o, k); return;
+            default: propose_waves<32, W>(rp, pa, d, fb, i, o, k); return;
         }
     }
     int checks = 0, src = -1, ra = -1, rb = -1, rh = -1;
@@ -732,8 +735,13 @@ hipError_t launch_label(const ReachParams &rp, int n, const int32_t *map, uint32
 
 hipError_t launch_propose(const ReachParams &rp, const ProposeArgs &a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(propose_kernel, dim3((unsigned)a.n), dim3(kReachThreads), kSearchLds, s,
-                       rp, a);
+    // few requests (a step's resets): 8 candidates at a time shortens the
+    // slowest requests, which set the launch's time; many (a batch): 4, fewer
+    // checks past the first valid candidate
+    if (a.n <= kProposeWideMax)
+        hipLaunchKernelGGL(propose_kernel<8>, dim3((unsigned)a.n), dim3(512), kSearchLds, s, rp, a);
+    else
+        hipLaunchKernelGGL(propose_kernel<4>, dim3((unsigned)a.n), dim3(256), kSearchLds, s, rp, a);
     return hipGetLastError();
 }
 

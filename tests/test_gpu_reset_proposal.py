@@ -378,3 +378,31 @@ def test_handle_outlives_its_proposers():
     sim.close()
     assert rp.h is None and sim.h is None
     rp.close()  # a second close is a no-op
+
+
+def test_wide_and_narrow_candidate_rounds_agree():
+    """A launch of more than 2048 requests checks 4 candidates of a request
+    at a time, a smaller one 8: the same requests give bitwise the same pairs,
+    sources, hop counts and check counts either way (the lowest valid
+    candidate wins, and checks count as in a sequential search)."""
+    say("2100 requests in one launch (4 candidates at a time) == two launches of 1050 (8)")
+    sim, rp, ref, reach, _ = setup()
+    n = 2100
+    rng = np.random.default_rng(11)
+    mp = rng.integers(0, 4, n).astype(np.int32)
+    bins = rng.integers(0, rp.nb, n).astype(np.int32)
+    env = np.arange(n, dtype=np.uint32)
+    ep = (np.arange(n) * 7 % 13).astype(np.uint32)
+    whole = rp.propose(mp, bins, env, ep, proposals=8, max_tries=24)
+    h = n // 2
+    parts = [rp.propose(mp[s], bins[s], env[s], ep[s], proposals=8, max_tries=24)
+             for s in (slice(0, h), slice(h, n))]
+    torch.cuda.synchronize()
+    for k in ("pose", "hops", "source", "checks"):
+        a = whole[k].cpu().numpy()
+        b = np.concatenate([p[k].cpu().numpy() for p in parts])
+        assert np.array_equal(a, b), k
+    src = whole["source"].cpu().numpy()
+    assert (src >= 0).mean() > 0.5 and (src >= 8).any()  # network draws and rejection both used
+    rp.close()
+    sim.close()
