@@ -575,24 +575,52 @@ __global__ __launch_bounds__(64 * W) void propose_kernel(ReachParams rp, Propose
 }
 
 __global__ __launch_bounds__(1024) void compact_kernel(CompactArgs a) {
+    // each thread takes 16 consecutive envs per pass (one 16-byte load of
+    // their flags; bins read only for the flagged ones), and a workgroup
+    // prefix sum of the per-thread counts places them in env order
     __shared__ int s_wave[16];
     __shared__ int s_base;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) s_base = 0;
     __syncthreads();
-    for (int e0 = 0; e0 < a.N; e0 += 1024) {
-        const int e = e0 + tid;
-        const bool on = e < a.N && a.defer[e] != 0 && a.bin[e] >= 0;
-        const uint64_t bm = __ballot(on);
-        if (lane == 0) s_wave[wave] = __popcll(bm);
+    const bool vec = (reinterpret_cast<uintptr_t>(a.defer) & 15u) == 0u;
+    for (int e0 = 0; e0 < a.N; e0 += 1024 * 16) {
+        const int eb = e0 + tid * 16;
+        uint32_t m = 0u;  // bit i: env eb + i asks for a pair
+        if (vec && eb + 16 <= a.N) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(a.defer + eb);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if ((w[q] >> (8 * b)) & 0xffu) m |= 1u << (4 * q + b);
+        } else {
+            for (int i = 0; i < 16; ++i)
+                if (eb + i < a.N && a.defer[eb + i] != 0) m |= 1u << i;
+        }
+        for (uint32_t r = m; r != 0u; r &= r - 1u) {
+            const int i = (int)__builtin_ctz(r);
+            if (a.bin[eb + i] < 0) m &= ~(1u << i);
+        }
+        const int cnt = __popc(m);
+        int inc = cnt;  // inclusive prefix sum over the wavefront
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(inc, o);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) s_wave[wave] = inc;
         __syncthreads();
         int before = s_base, total = 0;
         for (int w = 0; w < 16; ++w) {
-            before += w < wave ? s_wave[w] : 0;
-            total += s_wave[w];
+            const int c = s_wave[w];
+            before += w < wave ? c : 0;
+            total += c;
         }
-        const int pos = before + __popcll(bm & ((1ull << lane) - 1ull));
-        if (on) {
+        int pos = before + inc - cnt;
+        for (uint32_t r = m; r != 0u; r &= r - 1u, ++pos) {
+            const int e = eb + (int)__builtin_ctz(r);
             a.src[e] = -1;
             if (pos < a.cap) {
                 a.env[pos] = (uint32_t)e;

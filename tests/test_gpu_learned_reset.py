@@ -36,10 +36,10 @@ def say(*a):
     sys.stdout.flush()
 
 
-def setup():
-    w = configs.build_workload("c5", num_envs=N)
+def setup(n=N):
+    w = configs.build_workload("c5", num_envs=n)
     maps, res = w["maps"][:NMAPS], w["res"][:NMAPS]
-    env_map = (np.arange(N) % NMAPS).astype(np.int32)
+    env_map = (np.arange(n) % NMAPS).astype(np.int32)
     cfg = w["cfg"]
     sim = NavSim(cfg, maps, res, env_map, device=0)
     pcfg = dict(w["proposer"], seed=0xABCD)
@@ -74,12 +74,13 @@ def apply_deferred(sim, rp, ref, reach, ref_out, deferred, bins, pre_ep, label):
     fallback rows of the deferred envs are replaced by the oracle's."""
     src, hops = (t.cpu().numpy() for t in rp.attach_outputs())
     st = sim.get_state()
+    n = sim.N
     order = np.nonzero(deferred)[0]
     assert np.all(src[order[CAP:]] == -1), f"{label}: envs past the cap got pairs"
-    prop = np.zeros(N, bool)
+    prop = np.zeros(n, bool)
     prop[order] = src[order] >= 0
     free = deferred & ~prop
-    pose = np.zeros((N, 5), np.float32)
+    pose = np.zeros((n, 5), np.float32)
     n_net = n_rej = 0
     for e in np.nonzero(prop)[0]:
         R = reach[e % NMAPS]
@@ -147,21 +148,22 @@ def test_learned_resets_inside_the_step_against_oracle():
     sim.close()
 
 
-def test_learned_resets_in_masked_reset_and_detach():
-    sim, rp, ref, reach = setup()
+@pytest.mark.parametrize("n", [N, 200])  # 200: envs past the last 16-env block of the compaction
+def test_learned_resets_in_masked_reset_and_detach(n):
+    sim, rp, ref, reach = setup(n)
     sim.reset()
     ref.reset(threads=8)
     torch.cuda.synchronize()
-    bins = (np.arange(N) % 8).astype(np.int32)
+    bins = (np.arange(n) % 8).astype(np.int32)
     rp.attach(bins, proposals=PROPS, max_tries=TRIES, max_per_step=CAP)
-    mask = (np.arange(N) % 3 == 1).astype(np.uint8)
+    mask = (np.arange(n) % 3 == 1).astype(np.uint8)
     pre = ref.get_state()
     g0 = sim.get_state()
     for k in oracle.STATE_KEYS:
         assert np.array_equal(g0[k], pre[k]), k
     obs = sim.reset(torch.from_numpy(mask).to(sim.device)).cpu().numpy()
     torch.cuda.synchronize()
-    r = {"obs": np.zeros((N, sim.m + 4), np.float32), "fallback": np.zeros(N, np.uint8)}
+    r = {"obs": np.zeros((n, sim.m + 4), np.float32), "fallback": np.zeros(n, np.uint8)}
     c = apply_deferred(sim, rp, ref, reach, r, mask.astype(bool), bins, pre["ep"], "reset")
     say(f"masked reset: {c}")
     gst = sim.get_state()
@@ -177,7 +179,7 @@ def test_learned_resets_in_masked_reset_and_detach():
         assert np.abs(obs[e, m:] - r["obs"][e, m:]).max() <= parity.SCALAR_TOL
     # while attached, the plain step and rollouts refuse; after detach the
     # step is the plain free-space one again
-    act = torch.from_numpy(configs.uniform_actions(1, N, seed=3)[0]).to(sim.device)
+    act = torch.from_numpy(configs.uniform_actions(1, n, seed=3)[0]).to(sim.device)
     with pytest.raises(NavsimError, match="fused step only"):
         sim.step(act, plain=True)
     with pytest.raises(NavsimError, match="detach"):
