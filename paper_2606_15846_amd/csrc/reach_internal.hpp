@@ -13,6 +13,9 @@ constexpr int kReachThreads = 256;
 // propose_kernel: one candidate check per wavefront, 8 at a time for launches
 // of at most this many requests, else 4
 constexpr int kProposeWideMax = 2048;
+// in-step proposals: rounds a request's own workgroup checks before its other
+// rounds go to the tail launch, all at once
+constexpr int kProposeHeadRounds = 2;
 constexpr int kPoolCells = 1024;      // 32 x 32 pooled occupancy
 
 // One map's C-free bitset: row j, column i is bit i & 31 of word
@@ -56,8 +59,22 @@ struct ProposeArgs {
     const int32_t *n_dev = nullptr;
     const int32_t *slot = nullptr;
     unsigned long long *stats = nullptr;
+    // optional two-phase search: a request with no valid candidate in its
+    // first head_rounds rounds (0: no limit) is appended to pend (count
+    // *n_pend, best[p] = INT_MAX) instead of written; the tail launch checks
+    // its remaining rounds all at once (round slots in tail) and the final
+    // launch writes it
+    int head_rounds = 0;
+    int32_t *pend = nullptr, *n_pend = nullptr, *best = nullptr;
+    int4 *tail = nullptr;
 };
+// Candidates checked together per request (one per wavefront).
+int propose_width(int n);
 hipError_t launch_propose(const ReachParams &rp, const ProposeArgs &a, hipStream_t s);
+// The rounds head_rounds .. head_rounds + tail_rounds - 1 of the pending
+// requests (a.n = the most there can be), then their outputs.
+hipError_t launch_propose_tail(const ReachParams &rp, const ProposeArgs &a, int tail_rounds,
+                               hipStream_t s);
 
 // Noise inputs: row r = i * per + j of z (bfloat16, nz columns) draws
 // Philox(c0[i], c1[i] or c1_const, (j << 8) | q, stream) words for
@@ -89,6 +106,7 @@ struct CompactArgs {
     uint32_t *env, *episode;
     int32_t *map, *rbin, *src, *n_out;
     unsigned long long *stats;
+    int32_t *n_pend = nullptr;  // cleared here for the proposal launches that follow
 };
 hipError_t launch_compact(const CompactArgs &a, hipStream_t s);
 

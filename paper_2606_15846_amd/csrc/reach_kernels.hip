@@ -420,69 +420,99 @@ __device__ void candidate(const ReachParams &rp, const ProposeArgs &pa, const Re
 // (W wavefronts) are checked together and the lowest valid one wins, the
 // result of checking them in order; `checks` counts as the sequential search
 // does.
+// Outputs of request i (row o): pair (a, b) and heading th, the winning
+// candidate win (-1: none valid), its hop count h; checks as the sequential
+// search counts them.
+__device__ void write_request(const ProposeArgs &pa, const ReachDesc &d, int o, int win, int la,
+                              int lb, int lh, float lth, int total) {
+    float *p = pa.pose + (int64_t)o * 5;
+    p[0] = la >= 0 ? cell_x(d, la) : 0.0f;
+    p[1] = la >= 0 ? cell_y(d, la) : 0.0f;
+    p[2] = lth;
+    p[3] = lb >= 0 ? cell_x(d, lb) : 0.0f;
+    p[4] = lb >= 0 ? cell_y(d, lb) : 0.0f;
+    const int checks = win >= 0 ? win + 1 : total;
+    if (pa.hops) pa.hops[o] = win >= 0 ? lh : -1;
+    pa.source[o] = win;
+    if (pa.checks) pa.checks[o] = checks;
+    if (pa.stats) {
+        atomicAdd(&pa.stats[0], 1ull);
+        atomicAdd(&pa.stats[win < 0 ? 3 : (win < pa.props ? 1 : 2)], 1ull);
+        atomicAdd(&pa.stats[4], (unsigned long long)checks);
+    }
+}
+
+// W candidates c0 .. c0 + W - 1 of request i, one per wavefront; returns the
+// lowest valid one (-1: none), with its pair, hop count and heading in the
+// *_out arguments (every thread); with none valid and the request's last
+// candidate (a rejection attempt) in this round, that attempt's pair and
+// heading go there instead (the pair that stands when nothing is valid).
 template <int WPR, int W>
-__device__ void propose_waves(const ReachParams &rp, const ProposeArgs &pa, const ReachDesc &d,
-                              const uint32_t *fb, int i, int o, int k) {
+__device__ int check_round(const ReachParams &rp, const ProposeArgs &pa, const ReachDesc &d,
+                           const uint32_t *fb, int i, int k, int c0, int total, int &a_out,
+                           int &b_out, int &h_out, float &th_out) {
     __shared__ int s_ok[W], s_a[W], s_b[W], s_h[W];
     __shared__ float s_th[W];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = c0 + wave;
+    int a = -1, b = -1, h = -1;
+    float th = 0.0f;
+    if (c < total) {
+        candidate(rp, pa, d, fb, i, c, lane, a, b, th);
+        h = wave_check<WPR>(rp, d, fb, a, b, k, lane);
+    }
+    if (lane == 0) {
+        s_ok[wave] = (c < total && h >= 0) ? c : INT_MAX;
+        s_a[wave] = a;
+        s_b[wave] = b;
+        s_h[wave] = h;
+        s_th[wave] = th;
+    }
+    __syncthreads();
+    int best = INT_MAX, bw = -1;
+    for (int w = 0; w < W; ++w)
+        if (s_ok[w] < best) {
+            best = s_ok[w];
+            bw = w;
+        }
+    int win = -1;
+    if (bw >= 0) {
+        win = best;
+        a_out = s_a[bw];
+        b_out = s_b[bw];
+        h_out = s_h[bw];
+        th_out = s_th[bw];
+    } else if (total - 1 >= c0 && total - 1 < c0 + W && total - 1 >= pa.props) {
+        // none valid: the last rejection attempt's pair stands
+        const int w = total - 1 - c0;
+        a_out = s_a[w];
+        b_out = s_b[w];
+        th_out = s_th[w];
+    }
+    __syncthreads();
+    return win;
+}
+
+template <int WPR, int W>
+__device__ void propose_waves(const ReachParams &rp, const ProposeArgs &pa, const ReachDesc &d,
+                              const uint32_t *fb, int i, int o, int k) {
     const int total = pa.props + (d.free_cnt > 0 ? pa.tries : 0);
     int win = -1, la = -1, lb = -1, lh = -1;
     float lth = 0.0f;
-    for (int c0 = 0; c0 < total && win < 0; c0 += W) {
-        const int c = c0 + wave;
-        int a = -1, b = -1, h = -1;
-        float th = 0.0f;
-        if (c < total) {
-            candidate(rp, pa, d, fb, i, c, lane, a, b, th);
-            h = wave_check<WPR>(rp, d, fb, a, b, k, lane);
-        }
-        if (lane == 0) {
-            s_ok[wave] = (c < total && h >= 0) ? c : INT_MAX;
-            s_a[wave] = a;
-            s_b[wave] = b;
-            s_h[wave] = h;
-            s_th[wave] = th;
-        }
-        __syncthreads();
-        int best = INT_MAX, bw = -1;
-        for (int w = 0; w < W; ++w)
-            if (s_ok[w] < best) {
-                best = s_ok[w];
-                bw = w;
+    int c0 = 0;
+    for (int round = 0; c0 < total && win < 0; c0 += W, ++round) {
+        if (pa.head_rounds > 0 && round == pa.head_rounds) {
+            // the rest of this request's rounds go to the tail launch
+            if (threadIdx.x == 0) {
+                const int p = atomicAdd(pa.n_pend, 1);
+                pa.pend[p] = i;
+                pa.best[p] = INT_MAX;
             }
-        if (bw >= 0) {
-            win = best;
-            la = s_a[bw];
-            lb = s_b[bw];
-            lh = s_h[bw];
-            lth = s_th[bw];
-        } else if (total - 1 >= c0 && total - 1 < c0 + W && total - 1 >= pa.props) {
-            // none valid: the last rejection attempt's pair stands
-            const int w = total - 1 - c0;
-            la = s_a[w];
-            lb = s_b[w];
-            lth = s_th[w];
+            return;
         }
-        __syncthreads();
+        win = check_round<WPR, W>(rp, pa, d, fb, i, k, c0, total, la, lb, lh, lth);
     }
-    if (threadIdx.x == 0) {
-        float *p = pa.pose + (int64_t)o * 5;
-        p[0] = la >= 0 ? cell_x(d, la) : 0.0f;
-        p[1] = la >= 0 ? cell_y(d, la) : 0.0f;
-        p[2] = lth;
-        p[3] = lb >= 0 ? cell_x(d, lb) : 0.0f;
-        p[4] = lb >= 0 ? cell_y(d, lb) : 0.0f;
-        const int checks = win >= 0 ? win + 1 : total;
-        if (pa.hops) pa.hops[o] = win >= 0 ? lh : -1;
-        pa.source[o] = win;
-        if (pa.checks) pa.checks[o] = checks;
-        if (pa.stats) {
-            atomicAdd(&pa.stats[0], 1ull);
-            atomicAdd(&pa.stats[win < 0 ? 3 : (win < pa.props ? 1 : 2)], 1ull);
-            atomicAdd(&pa.stats[4], (unsigned long long)checks);
-        }
-    }
+    if (threadIdx.x == 0) write_request(pa, d, o, win, la, lb, lh, lth, total);
 }
 
 // One workgroup of W wavefronts per request.
@@ -581,7 +611,10 @@ __global__ __launch_bounds__(1024) void compact_kernel(CompactArgs a) {
     __shared__ int s_wave[16];
     __shared__ int s_base;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) s_base = 0;
+    if (tid == 0) {
+        s_base = 0;
+        if (a.n_pend) *a.n_pend = 0;
+    }
     __syncthreads();
     const bool vec = (reinterpret_cast<uintptr_t>(a.defer) & 15u) == 0u;
     for (int e0 = 0; e0 < a.N; e0 += 1024 * 16) {
@@ -761,12 +794,109 @@ hipError_t launch_label(const ReachParams &rp, int n, const int32_t *map, uint32
     return hipGetLastError();
 }
 
+// Tail rounds: every (pending request, round) is one work item, taken by the
+// workgroups of a fixed grid in round-major order (all requests' first tail
+// round, then their second, ...), so a request's rounds run at once on
+// different workgroups.  A round's lowest valid candidate goes to its slot and
+// into the request's best index (atomic minimum); a round that starts above a
+// valid candidate already found is skipped (it cannot win).  Requests reach
+// the pending list only from the register search, so the same path serves.
+template <int W>
+__global__ __launch_bounds__(64 * W) void propose_tail_kernel(ReachParams rp, ProposeArgs pa,
+                                                              int tail_rounds) {
+    extern __shared__ uint4 lds4[];
+    uint32_t *fb = reinterpret_cast<uint32_t *>(lds4);
+    const int np = *pa.n_pend;
+    const int items = np * tail_rounds;
+    for (int g = blockIdx.x; g < items; g += gridDim.x) {
+        const int p = g % np, r = g / np;
+        const int i = pa.pend[p];
+        const int mk = pa.map[i], k = pa.bin[i];
+        const ReachDesc d = rp.maps[mk];
+        const int total = pa.props + (d.free_cnt > 0 ? pa.tries : 0);
+        const int c0 = (pa.head_rounds + r) * W;
+        // uniform across the workgroup: one read of best, then a barrier
+        // before any thread moves on
+        __shared__ int s_skip;
+        if (threadIdx.x == 0) s_skip = c0 >= total || __atomic_load_n(&pa.best[p], __ATOMIC_RELAXED) < c0;
+        __syncthreads();
+        const bool skip = s_skip != 0;
+        __syncthreads();
+        if (skip) continue;
+        stage_free(rp, d, fb);
+        __syncthreads();
+        int a = -1, b = -1, h = -1, win = -1;
+        float th = 0.0f;
+        switch (d.wpr) {
+            case 1: win = check_round<1, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th); break;
+            case 2: win = check_round<2, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th); break;
+            case 4: win = check_round<4, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th); break;
+            case 8: win = check_round<8, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th); break;
+            case 16: win = check_round<16, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th); break;
+            default: win = check_round<32, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th); break;
+        }
+        if (threadIdx.x == 0 && win >= 0) {
+            pa.tail[(int64_t)p * tail_rounds + r] = make_int4(a, b, h, __float_as_int(th));
+            atomicMin(&pa.best[p], win);
+        }
+        __syncthreads();  // the map in LDS is restaged by the next item
+    }
+}
+
+// Outputs of the pending requests: the lowest valid candidate any tail round
+// found, else the last rejection attempt's pair (as the sequential search).
+__global__ void propose_final_kernel(ReachParams rp, ProposeArgs pa, int tail_rounds, int W) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= *pa.n_pend) return;
+    const int i = pa.pend[p], o = pa.slot ? pa.slot[i] : i;
+    const ReachDesc d = rp.maps[pa.map[i]];
+    const int total = pa.props + (d.free_cnt > 0 ? pa.tries : 0);
+    const int win = pa.best[p] == INT_MAX ? -1 : pa.best[p];
+    int la = -1, lb = -1, lh = -1;
+    float lth = 0.0f;
+    if (win >= 0) {
+        const int4 q = pa.tail[(int64_t)p * tail_rounds + win / W - pa.head_rounds];
+        la = q.x;
+        lb = q.y;
+        lh = q.z;
+        lth = __int_as_float(q.w);
+    } else if (total - 1 >= pa.props) {
+        uint32_t q[4] = {pa.env[i], pa.episode[i], (uint32_t)(total - 1 - pa.props), 7u};
+        philox4x32_10(q, rp.key0, rp.key1);
+        la = rp.free_cells[d.free_off + pick_of(q[0], d.free_cnt)];
+        lb = rp.free_cells[d.free_off + pick_of(q[1], d.free_cnt)];
+        lth = (float)((((double)q[2] + 0.5) / kTwo32) * (2.0 * kPiR) - kPiR);
+    }
+    write_request(pa, d, o, win, la, lb, lh, lth, total);
+}
+
+int propose_width(int n) { return n <= kProposeWideMax ? 8 : 4; }
+
+hipError_t launch_propose_tail(const ReachParams &rp, const ProposeArgs &a, int tail_rounds,
+                               hipStream_t s) {
+    if (a.n <= 0 || tail_rounds <= 0) return hipSuccess;
+    // a fixed grid: the pending count is only known on the device
+    const unsigned g = (unsigned)std::min<int64_t>((int64_t)a.n * tail_rounds, 1024);
+    const int W = propose_width(a.n);
+    if (W == 8)
+        hipLaunchKernelGGL(propose_tail_kernel<8>, dim3(g), dim3(512), kSearchLds, s, rp, a,
+                           tail_rounds);
+    else
+        hipLaunchKernelGGL(propose_tail_kernel<4>, dim3(g), dim3(256), kSearchLds, s, rp, a,
+                           tail_rounds);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(propose_final_kernel, dim3(nblocks(a.n, 256)), dim3(256), 0, s, rp, a,
+                       tail_rounds, W);
+    return hipGetLastError();
+}
+
 hipError_t launch_propose(const ReachParams &rp, const ProposeArgs &a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
     // few requests (a step's resets): 8 candidates at a time shortens the
     // slowest requests, which set the launch's time; many (a batch): 4, fewer
     // checks past the first valid candidate
-    if (a.n <= kProposeWideMax)
+    if (propose_width(a.n) == 8)
         hipLaunchKernelGGL(propose_kernel<8>, dim3((unsigned)a.n), dim3(512), kSearchLds, s, rp, a);
     else
         hipLaunchKernelGGL(propose_kernel<4>, dim3((unsigned)a.n), dim3(256), kSearchLds, s, rp, a);

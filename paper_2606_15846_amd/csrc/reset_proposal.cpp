@@ -104,6 +104,9 @@ struct navsim_rp_s {
         float *ct = nullptr, *y = nullptr;
         uint16_t *z = nullptr, *hc0 = nullptr, *hc1 = nullptr;
         int32_t *ridx = nullptr;
+        int32_t *pend = nullptr, *best = nullptr;  // [cap] requests left to the tail launch
+        int4 *tail = nullptr;                      // [cap][tail_rounds] round slots
+        int tail_rounds = 0;                       // rounds after the head rounds
         uint64_t ct_version = ~0ull;
     } at;
     // workspaces
@@ -424,6 +427,7 @@ navsim_status rp_hook_run(void *ctx, hipStream_t s) {
     ca.src = A.src;
     ca.n_out = A.n_dev;
     ca.stats = A.stats;
+    ca.n_pend = A.n_dev + 1;  // the pending count shares the counters' block
     RP_HIP(launch_compact(ca, s));
     const float *y = nullptr;
     if (A.props > 0) {
@@ -469,7 +473,21 @@ navsim_status rp_hook_run(void *ctx, hipStream_t s) {
     pa.n_dev = A.n_dev;
     pa.slot = (const int32_t *)A.r_env;
     pa.stats = A.stats + 2;
+    // the few requests with no valid candidate in their head rounds set the
+    // launch's time when their rounds run one after another: their remaining
+    // rounds go to one tail launch, one workgroup per round
+    const int tail_rounds =
+        std::max(0, (int)(((int64_t)A.props + A.tries + propose_width(A.cap) - 1) /
+                          propose_width(A.cap)) - kProposeHeadRounds);
+    if (tail_rounds > 0) {
+        pa.head_rounds = kProposeHeadRounds;
+        pa.pend = A.pend;
+        pa.n_pend = A.n_dev + 1;
+        pa.best = A.best;
+        pa.tail = A.tail;
+    }
     RP_HIP(launch_propose(r->rp, pa, s));
+    if (tail_rounds > 0) RP_HIP(launch_propose_tail(r->rp, pa, tail_rounds, s));
     return NAVSIM_OK;
 }
 
@@ -922,14 +940,23 @@ navsim_status navsim_rp_attach(navsim_rp_t r, const int32_t *bin, int32_t propos
     DeviceGuard dg(r->device);
     if (dg.err != hipSuccess) return fail(NAVSIM_E_HIP, "hipSetDevice: %s", hipGetErrorString(dg.err));
     navsim_rp_s::Attach &A = r->at;
-    if (!(A.on && A.cap == max_per_step && A.props == proposals)) {
+    // rounds of candidates after the head rounds (one tail workgroup each)
+    const int W = propose_width(max_per_step);
+    const int64_t rounds = ((int64_t)proposals + max_tries + W - 1) / W;
+    const int tail_rounds = (int)std::max<int64_t>(0, rounds - kProposeHeadRounds);
+    if ((int64_t)max_per_step * tail_rounds > (1 << 24))
+        return fail(NAVSIM_E_INVALID_ARG, "max_per_step * candidate rounds must be at most 2^24");
+    if (!(A.on && A.cap == max_per_step && A.props == proposals && A.tail_rounds >= tail_rounds)) {
         detach_rp(r);
         const size_t R = (size_t)max_per_step * (size_t)proposals, Hd = (size_t)r->cfg.hidden;
         const size_t parts[] = {(size_t)N * 4, (size_t)N * 4, (size_t)N * 4, (size_t)N,
                                 (size_t)N * 20, (size_t)max_per_step * 4, (size_t)max_per_step * 4,
                                 (size_t)max_per_step * 4, (size_t)max_per_step * 4, 256, 64,
                                 proposals ? ctable_bytes(r) : 0, R * 20,
-                                R * (size_t)r->cfg.noise_dim * 2, R * Hd * 2, R * Hd * 2, R * 4};
+                                R * (size_t)r->cfg.noise_dim * 2, R * Hd * 2, R * Hd * 2, R * 4,
+                                (size_t)max_per_step * 4, (size_t)max_per_step * 4,
+                                (size_t)max_per_step * (size_t)tail_rounds * 16};
+        constexpr int kParts = (int)(sizeof parts / sizeof parts[0]);
         size_t total = 0;
         for (size_t b : parts) total += align_up(b);
         if (hipMalloc(&A.block, total) != hipSuccess) {
@@ -937,11 +964,15 @@ navsim_status navsim_rp_attach(navsim_rp_t r, const int32_t *bin, int32_t propos
             return fail(NAVSIM_E_OOM, "hipMalloc of %zu bytes for in-step proposals failed", total);
         }
         uint8_t *q = (uint8_t *)A.block;
-        void *ptrs[17];
-        for (int k = 0; k < 17; ++k) {
+        void *ptrs[kParts];
+        for (int k = 0; k < kParts; ++k) {
             ptrs[k] = q;
             q += align_up(parts[k]);
         }
+        A.pend = (int32_t *)ptrs[17];
+        A.best = (int32_t *)ptrs[18];
+        A.tail = (int4 *)ptrs[19];
+        A.tail_rounds = tail_rounds;
         A.bin = (int32_t *)ptrs[0];
         A.src = (int32_t *)ptrs[1];
         A.hops = (int32_t *)ptrs[2];
