@@ -15,7 +15,7 @@ constexpr int kReachThreads = 256;
 constexpr int kProposeWideMax = 2048;
 // in-step proposals: rounds a request's own workgroup checks before its other
 // rounds go to the tail launch, all at once
-constexpr int kProposeHeadRounds = 2;
+constexpr int kProposeHeadRounds = 1;
 constexpr int kPoolCells = 1024;      // 32 x 32 pooled occupancy
 
 // One map's C-free bitset: row j, column i is bit i & 31 of word
