@@ -322,7 +322,7 @@ __device__ __forceinline__ bool wave_level(const uint32_t fr[32], uint32_t nx[32
 // per loop pass, so no frontier is copied).
 template <int WPR>
 __device__ int wave_hops(const uint32_t *fb, const ReachDesc &d, int a, int b, int max_hops,
-                         int lane) {
+                         int lane, int c, const int *s_won) {
     const int wa = (a / d.W) * WPR + ((a % d.W) >> 5);
     const int wb = (b / d.W) * WPR + ((b % d.W) >> 5);
     const int la = wa >> 5, ja = wa & 31, lb = wb >> 5;
@@ -341,6 +341,9 @@ __device__ int wave_hops(const uint32_t *fb, const ReachDesc &d, int a, int b, i
         un[j] = (base + j < d.words ? fb[base + j] : 0u) & ~seed;
     }
     for (int level = 1; level <= max_hops; level += 2) {
+        // a lower candidate of the round already passed: this one cannot win
+        // (looked at every 8 levels)
+        if (s_won && (level & 7) == 1 && __atomic_load_n(s_won, __ATOMIC_RELAXED) < c) return -1;
         bool more = wave_level<WPR>(f0, f1, un, lane);
         if (!((__shfl(un[jb], lb) >> bb) & 1u)) return level;
         if (!more || level + 1 > max_hops) return -1;
@@ -381,7 +384,7 @@ __device__ int wave_snap(const ReachDesc &d, const uint32_t *fb, int c, int lane
 // The exact check of (a, b) for bin k by one wavefront (see check_pair).
 template <int WPR>
 __device__ int wave_check(const ReachParams &rp, const ReachDesc &d, const uint32_t *fb,
-                          int a, int b, int k, int lane) {
+                          int a, int b, int k, int lane, int c = 0, const int *s_won = nullptr) {
     if (a < 0 || b < 0 || !lds_cell(fb, d, a) || !lds_cell(fb, d, b)) return -1;
     if (centre_dist(d, a, b) < rp.gmd) return -1;
     const int hi = rp.bin_hi[k];
@@ -390,7 +393,7 @@ __device__ int wave_check(const ReachParams &rp, const ReachDesc &d, const uint3
         h = 0;
     } else {
         const int man = abs(a % d.W - b % d.W) + abs(a / d.W - b / d.W);
-        h = man > hi ? -1 : wave_hops<WPR>(fb, d, a, b, hi, lane);
+        h = man > hi ? -1 : wave_hops<WPR>(fb, d, a, b, hi, lane, c, s_won);
     }
     return (h >= 0 && rp.hop_bin[h] == k) ? h : -1;
 }
@@ -453,13 +456,19 @@ __device__ int check_round(const ReachParams &rp, const ProposeArgs &pa, const R
                            int &b_out, int &h_out, float &th_out) {
     __shared__ int s_ok[W], s_a[W], s_b[W], s_h[W];
     __shared__ float s_th[W];
+    __shared__ int s_won;  // lowest candidate of the round found valid so far
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = c0 + wave;
+    if (threadIdx.x == 0) s_won = INT_MAX;
+    __syncthreads();
     int a = -1, b = -1, h = -1;
     float th = 0.0f;
     if (c < total) {
         candidate(rp, pa, d, fb, i, c, lane, a, b, th);
-        h = wave_check<WPR>(rp, d, fb, a, b, k, lane);
+        // searches of higher candidates stop once a lower one has passed
+        // (they cannot win); the winner and the check counts are unchanged
+        h = wave_check<WPR>(rp, d, fb, a, b, k, lane, c, &s_won);
+        if (h >= 0 && lane == 0) atomicMin(&s_won, c);
     }
     if (lane == 0) {
         s_ok[wave] = (c < total && h >= 0) ? c : INT_MAX;
