@@ -322,7 +322,7 @@ __device__ __forceinline__ bool wave_level(const uint32_t fr[32], uint32_t nx[32
 // per loop pass, so no frontier is copied).
 template <int WPR>
 __device__ int wave_hops(const uint32_t *fb, const ReachDesc &d, int a, int b, int max_hops,
-                         int lane, int c, const int *s_won) {
+                         int lane, int c, const int *s_won, const int *g_won) {
     const int wa = (a / d.W) * WPR + ((a % d.W) >> 5);
     const int wb = (b / d.W) * WPR + ((b % d.W) >> 5);
     const int la = wa >> 5, ja = wa & 31, lb = wb >> 5;
@@ -341,9 +341,13 @@ __device__ int wave_hops(const uint32_t *fb, const ReachDesc &d, int a, int b, i
         un[j] = (base + j < d.words ? fb[base + j] : 0u) & ~seed;
     }
     for (int level = 1; level <= max_hops; level += 2) {
-        // a lower candidate of the round already passed: this one cannot win
-        // (looked at every 8 levels)
-        if (s_won && (level & 7) == 1 && __atomic_load_n(s_won, __ATOMIC_RELAXED) < c) return -1;
+        // a lower candidate of the round (s_won, LDS) or of the request (g_won,
+        // device memory: other workgroups' rounds) already passed: this one
+        // cannot win (looked at every 8 levels)
+        if ((level & 7) == 1) {
+            if (s_won && __atomic_load_n(s_won, __ATOMIC_RELAXED) < c) return -1;
+            if (g_won && __atomic_load_n(g_won, __ATOMIC_RELAXED) < c) return -1;
+        }
         bool more = wave_level<WPR>(f0, f1, un, lane);
         if (!((__shfl(un[jb], lb) >> bb) & 1u)) return level;
         if (!more || level + 1 > max_hops) return -1;
@@ -384,7 +388,8 @@ __device__ int wave_snap(const ReachDesc &d, const uint32_t *fb, int c, int lane
 // The exact check of (a, b) for bin k by one wavefront (see check_pair).
 template <int WPR>
 __device__ int wave_check(const ReachParams &rp, const ReachDesc &d, const uint32_t *fb,
-                          int a, int b, int k, int lane, int c = 0, const int *s_won = nullptr) {
+                          int a, int b, int k, int lane, int c = 0, const int *s_won = nullptr,
+                          const int *g_won = nullptr) {
     if (a < 0 || b < 0 || !lds_cell(fb, d, a) || !lds_cell(fb, d, b)) return -1;
     if (centre_dist(d, a, b) < rp.gmd) return -1;
     const int hi = rp.bin_hi[k];
@@ -393,7 +398,7 @@ __device__ int wave_check(const ReachParams &rp, const ReachDesc &d, const uint3
         h = 0;
     } else {
         const int man = abs(a % d.W - b % d.W) + abs(a / d.W - b / d.W);
-        h = man > hi ? -1 : wave_hops<WPR>(fb, d, a, b, hi, lane, c, s_won);
+        h = man > hi ? -1 : wave_hops<WPR>(fb, d, a, b, hi, lane, c, s_won, g_won);
     }
     return (h >= 0 && rp.hop_bin[h] == k) ? h : -1;
 }
@@ -453,7 +458,7 @@ __device__ void write_request(const ProposeArgs &pa, const ReachDesc &d, int o, 
 template <int WPR, int W>
 __device__ int check_round(const ReachParams &rp, const ProposeArgs &pa, const ReachDesc &d,
                            const uint32_t *fb, int i, int k, int c0, int total, int &a_out,
-                           int &b_out, int &h_out, float &th_out) {
+                           int &b_out, int &h_out, float &th_out, const int *g_won = nullptr) {
     __shared__ int s_ok[W], s_a[W], s_b[W], s_h[W];
     __shared__ float s_th[W];
     __shared__ int s_won;  // lowest candidate of the round found valid so far
@@ -467,7 +472,7 @@ __device__ int check_round(const ReachParams &rp, const ProposeArgs &pa, const R
         candidate(rp, pa, d, fb, i, c, lane, a, b, th);
         // searches of higher candidates stop once a lower one has passed
         // (they cannot win); the winner and the check counts are unchanged
-        h = wave_check<WPR>(rp, d, fb, a, b, k, lane, c, &s_won);
+        h = wave_check<WPR>(rp, d, fb, a, b, k, lane, c, &s_won, g_won);
         if (h >= 0 && lane == 0) atomicMin(&s_won, c);
     }
     if (lane == 0) {
@@ -836,13 +841,14 @@ __global__ __launch_bounds__(64 * W) void propose_tail_kernel(ReachParams rp, Pr
         __syncthreads();
         int a = -1, b = -1, h = -1, win = -1;
         float th = 0.0f;
+        const int *gw = &pa.best[p];
         switch (d.wpr) {
-            case 1: win = check_round<1, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th); break;
-            case 2: win = check_round<2, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th); break;
-            case 4: win = check_round<4, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th); break;
-            case 8: win = check_round<8, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th); break;
-            case 16: win = check_round<16, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th); break;
-            default: win = check_round<32, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th); break;
+            case 1: win = check_round<1, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th, gw); break;
+            case 2: win = check_round<2, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th, gw); break;
+            case 4: win = check_round<4, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th, gw); break;
+            case 8: win = check_round<8, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th, gw); break;
+            case 16: win = check_round<16, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th, gw); break;
+            default: win = check_round<32, W>(rp, pa, d, fb, i, k, c0, total, a, b, h, th, gw); break;
         }
         if (threadIdx.x == 0 && win >= 0) {
             pa.tail[(int64_t)p * tail_rounds + r] = make_int4(a, b, h, __float_as_int(th));
