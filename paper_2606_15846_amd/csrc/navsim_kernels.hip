@@ -306,9 +306,12 @@ __device__ __forceinline__ Walk walk_setup(int pitch, const RayOrigin &o, double
     const uint32_t DY = (uint32_t)rint(fabs(dy) * kTwoPow30);
     const bool px = dx > 0.0, py = dy > 0.0;
     const uint32_t fx = (uint32_t)(uint64_t)o.OX, fy = (uint32_t)(uint64_t)o.OY;
-    const uint64_t gx = px ? (4294967296ull - fx) : (uint64_t)fx;
-    const uint64_t gy = py ? (4294967296ull - fy) : (uint64_t)fy;
-    const int64_t E = (int64_t)(gx * (uint64_t)DY) - (int64_t)(gy * (uint64_t)DX);
+    // g = 2^32 - f or f: 33 bits (2^32 when f = 0 going up), taken as its low
+    // word times D plus D 2^32 for that one case
+    const uint32_t gxl = px ? 0u - fx : fx, gyl = py ? 0u - fy : fy;
+    const uint64_t Px = (uint64_t)gxl * DY + ((px && fx == 0u) ? (uint64_t)DY << 32 : 0ull);
+    const uint64_t Py = (uint64_t)gyl * DX + ((py && fy == 0u) ? (uint64_t)DX << 32 : 0ull);
+    const int64_t E = (int64_t)(Px - Py);
     Walk w;
     w.Eh = (int)(E >> 32);
     w.thr = ((uint32_t)(uint64_t)E == 0u) ? 1 : 0;
@@ -367,8 +370,8 @@ __device__ __forceinline__ void walk_result(const RayOrigin &o, int pitch, int W
     // ray through a grid corner, and the value is then the same either way
     const double X = ((double)(dx > 0.0 ? ix : ix + 1)) * o.s - o.x;
     const double Y = ((double)(dy > 0.0 ? iy : iy + 1)) * o.s - o.y;
-    const bool use_x =
-        dy == 0.0 || (dx != 0.0 && (dx > 0.0 ? X : -X) * fabs(dy) > (dy > 0.0 ? Y : -Y) * fabs(dx));
+    const bool later_x = (dx > 0.0 ? X : -X) * fabs(dy) > (dy > 0.0 ? Y : -Y) * fabs(dx);
+    const bool use_x = (dy == 0.0) | ((dx != 0.0) & later_x);
     // select first, then divide: one division per lane even when the lanes
     // of a wavefront pick different axes.  The quotient in single precision
     // (relative error about 2^-22: ~2 um at 8 m); its operands stay double,
@@ -1003,8 +1006,10 @@ __device__ __forceinline__ void run_walk(const StepParams &p, const MapView &M,
             const int nidle = 64 - __popcll(am);
             int base = 0;
             if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
-            base = __shfl(base, 0);
-            const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
+            // every lane is active here, so the first active one is lane 0
+            base = __builtin_amdgcn_readfirstlane(base);
+            const int my = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, (uint32_t)base));
             if (!act && my < Rc) {
                 const uint4 v = s_ray[my];
                 r = my;
@@ -1125,8 +1130,10 @@ __device__ __forceinline__ void march_walk(const StepParams &p, const MapView &M
             const int nidle = 64 - __popcll(am);
             int base = 0;
             if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
-            base = __shfl(base, 0);
-            const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
+            // every lane is active here, so the first active one is lane 0
+            base = __builtin_amdgcn_readfirstlane(base);
+            const int my = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, (uint32_t)base));
             if (!act && my < Rc) {
                 const int g = c0 + my;
                 int beam;
@@ -1333,8 +1340,10 @@ __device__ __forceinline__ void group_walk(const StepParams &p, const MapView &M
             const int nidle = 64 - __popcll(am);
             int base = 0;
             if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
-            base = __shfl(base, 0);
-            const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
+            // every lane is active here, so the first active one is lane 0
+            base = __builtin_amdgcn_readfirstlane(base);
+            const int my = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, (uint32_t)base));
             if (!act && my < Rc) {
                 const uint4 v = s_ray[my];
                 r = my;
@@ -1394,8 +1403,10 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
             const int nidle = 64 - __popcll(am);
             int base = 0;
             if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
-            base = __shfl(base, 0);
-            const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
+            // every lane is active here, so the first active one is lane 0
+            base = __builtin_amdgcn_readfirstlane(base);
+            const int my = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, (uint32_t)base));
             if (!act && my < R) {
                 g = my;
                 const int jl = small_divmod(g, K, inv_K, beam);
@@ -1564,8 +1575,10 @@ __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapVie
             const int nidle = 64 - __popcll(am);
             int base = 0;
             if (lane == 0) base = atomicAdd(&s_misc[1], nidle);
-            base = __shfl(base, 0);
-            const int my = base + __popcll(idle & ((1ull << lane) - 1ull));
+            // every lane is active here, so the first active one is lane 0
+            base = __builtin_amdgcn_readfirstlane(base);
+            const int my = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, (uint32_t)base));
             if (!act && my < R) {
                 g = my;
                 const int jl = small_divmod(g, K, inv_K, beam);
