@@ -692,6 +692,18 @@ __device__ __forceinline__ RayOrigin tile_origin(const TileJob &j, double s) {
     return o;
 }
 
+// Claim walks start on the main jobs' rays while the tile's reset poses are
+// still being drawn; a reset job (index E + group) is published through the
+// flag s_misc[2 + job] once its pose and walk origin are in s_jobs.  Reset
+// rays come last in claim order, so the wait below is almost never taken; it
+// ends because every listed reset job is drawn by its own group (bounded
+// loops) before that group's wavefront enters the walk.
+__device__ __forceinline__ void wait_job_ready(const int *s_misc, int job, int E) {
+    if (job < E) return;
+    while (__hip_atomic_load(s_misc + 2 + job, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+        __builtin_amdgcn_s_sleep(1);
+}
+
 // The 16 ballot bits of this lane's group of 16.
 __device__ __forceinline__ uint32_t group_ballot(bool pred) {
     const uint64_t b = __ballot(pred);
@@ -1411,6 +1423,7 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
                 g = my;
                 const int jl = small_divmod(g, K, inv_K, beam);
                 job = s_list[jl];
+                wait_job_ready(s_misc, job, E);
                 const TileJob &j = job_ref(s_jobs, job);
                 n = 0;
                 if (!j.blocked) {
@@ -1583,6 +1596,7 @@ __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapVie
                 g = my;
                 const int jl = small_divmod(g, K, inv_K, beam);
                 job = s_list[jl];
+                wait_job_ready(s_misc, job, E);
                 const TileJob &j = job_ref(s_jobs, job);
                 n = 0;
                 if (!j.blocked) {
@@ -1646,8 +1660,9 @@ __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapVie
 // (byte walk only: at address 0, so that a cell index is its LDS address),
 // bitmap [max_words] (walk 5: the bitmap, then its transpose from word
 // tbits_off), jobs [2E] (main, reset), pooled minima [2E][m] (+ padding), active job list [2E], misc
-// [2E + 8] ([0] active jobs, [1] next ray, [2, 2 + E) done flags, [2E + 7]
-// next tile of a persistent workgroup), beams [K] when staged, ray slots
+// [2E + 8] ([0] active jobs, [1] next ray, [2, 2 + E) done flags, [2 + E, 2 + 2E)
+// reset jobs published, [2E + 6] tile vote, [2E + 7] next tile of a
+// persistent workgroup), beams [K] when staged, ray slots
 // [ray_cap] (none for the claim walk).
 template <int E>
 __device__ __forceinline__ int *fused_list(const StepParams &p) {
@@ -1724,6 +1739,9 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
 
     // ---- motion: one group of 16 lanes per env ----
     const int grp = tid >> 4, li = tid & 15;
+    bool later_reset = false;  // this group draws its env's reset pose after the job list
+    int reset_env = 0;
+    uint32_t reset_ep = 0u;
     if (grp < E) {
         // the rest of the workgroup waits for this: let it win issue slots from
         // other workgroups' walks on the same SIMD
@@ -1800,18 +1818,9 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
                 }
             }
             if (done && !defer) {
-                double c = 1.0, sn = 0.0;
-                ResetPose r;
-                if (p.pose && (!p.pose_src || p.pose_src[e] >= 0)) {
-                    r = given_pose(p, e);
-                    sincos((double)r.th, &sn, &c);
-                } else {
-                    r = group_sample_reset(p, M, md, e, ep, li, c, sn);
-                }
-                if (li == 0) {
-                    store_reset_cs(p, e, ep, r, c, sn);
-                    make_tile_job(s_jobs[E + grp], M, r.x, r.y, c, sn, e, 0);
-                }
+                later_reset = true;
+                reset_env = e;
+                reset_ep = ep;
             }
         }
         if (li == 0) {
@@ -1827,6 +1836,7 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
         const bool on = tid < E ? s_jobs[tid].dst != 3 : (tid < 2 * E && s_misc[2 + tid - E] != 0);
         const uint64_t bm = __ballot(on);
         if (on) s_list[__popcll(bm & ((1ull << tid) - 1ull))] = tid;
+        if (tid < E) s_misc[2 + E + tid] = 0;  // reset jobs not yet published
         if (tid == 0) {
             s_misc[0] = __popcll(bm);
             s_misc[1] = 0;
@@ -1834,6 +1844,27 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
     }
     for (int q = tid; q < 2 * E * m; q += T) s_pool[q] = 0x7f800000u;  // +inf
     __syncthreads();
+    if (later_reset) {
+        // a done env's reset pose, drawn by its group of 16 lanes; in the claim
+        // walks the other wavefronts start walking meanwhile (see wait_job_ready)
+        __builtin_amdgcn_s_setprio(3);
+        double c = 1.0, sn = 0.0;
+        ResetPose r;
+        if (p.pose && (!p.pose_src || p.pose_src[reset_env] >= 0)) {
+            r = given_pose(p, reset_env);
+            sincos((double)r.th, &sn, &c);
+        } else {
+            r = group_sample_reset(p, M, md, reset_env, reset_ep, li, c, sn);
+        }
+        if (li == 0) {
+            store_reset_cs(p, reset_env, reset_ep, r, c, sn);
+            make_tile_job(s_jobs[E + grp], M, r.x, r.y, c, sn, reset_env, 0);
+            __hip_atomic_store(s_misc + 2 + E + grp, 1, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __builtin_amdgcn_s_setprio(0);
+    }
+    if (!p.claim) __syncthreads();  // the chunked walks set up every ray at once
 
     // ---- scan, in chunks of at most ray_cap rays ----
     const int nj = s_misc[0];
