@@ -1705,6 +1705,28 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
     const MapDesc md = p.maps[tile.map];
     const int K = md.K, m = p.m, per = K / m;
     const double2 *beams = p.beams + md.beam_off;  // this map's beam directions
+    // the motion's inputs (one group of 16 lanes per env), loaded before the
+    // map is staged so that the two memory latencies overlap
+    const int grp = tid >> 4, li = tid & 15;
+    const bool mover = grp < E && grp < tile.count;
+    int me = 0, mt = 0;
+    uint32_t mep = 0u;
+    float2 ma = make_float2(0.0f, 0.0f);
+    float mx = 0.0f, my = 0.0f, mth = 0.0f, mgx = 0.0f, mgy = 0.0f, mdprev = 0.0f;
+    if (mover) {
+        me = p.perm[tile.first + grp];
+        mep = p.st.ep[me];
+        if (p.mode != 1) {
+            ma = env_action(p, me);
+            mx = p.st.x[me];
+            my = p.st.y[me];
+            mth = p.st.th[me];
+            mgx = p.st.gx[me];
+            mgy = p.st.gy[me];
+            mdprev = p.st.dprev[me];
+            mt = p.st.t[me] + 1;
+        }
+    }
     if (tile.map != staged_map) {  // a persistent workgroup keeps its map between tiles
         const uint4 *g = reinterpret_cast<const uint4 *>(p.bits + md.word_off);
         uint4 *b4 = reinterpret_cast<uint4 *>(s_bits);
@@ -1738,7 +1760,6 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
     const bool want_debug = p.d_ranges || p.d_hits || p.d_visits;
 
     // ---- motion: one group of 16 lanes per env ----
-    const int grp = tid >> 4, li = tid & 15;
     bool later_reset = false;  // this group draws its env's reset pose after the job list
     int reset_env = 0;
     uint32_t reset_ep = 0u;
@@ -1748,9 +1769,10 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
         __builtin_amdgcn_s_setprio(3);
         bool active = false, done = false, defer = false;
         uint32_t ep = 0u;
-        if (grp < tile.count) {
-            const int e = p.perm[tile.first + grp];
+        if (mover) {
+            const int e = me;
             active = true;
+            ep = mep;
             if (p.mode == 1) {
                 done = !p.mask || p.mask[e];
                 defer = done && p.defer_bin && p.defer_bin[e] >= 0;
@@ -1758,15 +1780,11 @@ __device__ __forceinline__ void fused_tile(const StepParams &p, int tile_index, 
                     s_jobs[grp].dst = 3;
                     if (p.defer_out) p.defer_out[e] = (uint8_t)defer;
                 }
-                ep = p.st.ep[e];
             } else {
-                // every state load is issued before the first use: one memory
-                // round trip instead of one per dependent use
-                const float2 a = env_action(p, e);
-                const float x0 = p.st.x[e], y0 = p.st.y[e], th0 = p.st.th[e];
-                const float gx = p.st.gx[e], gy = p.st.gy[e], dprev = p.st.dprev[e];
-                const int t = p.st.t[e] + 1;
-                ep = p.st.ep[e];
+                const float2 a = ma;
+                const float x0 = mx, y0 = my, th0 = mth;
+                const float gx = mgx, gy = mgy, dprev = mdprev;
+                const int t = mt;
                 if (p.act_out && li == 0)
                     *reinterpret_cast<float2 *>(p.act_out + 2 * (int64_t)e) = a;
                 const Motion mo = apply_action(p, a.x, a.y, x0, y0, th0);
