@@ -64,11 +64,15 @@ struct MapView {
     const uint32_t *bits;
     int w, h, wpr, pitch;
     double s;
-    int pitch_t;  // bits per line of the transposed bitmap
+    int pitch_t;                 // bits per line of the transposed bitmap
+    float inv_pitch, inv_pitch_t;  // float reciprocals of the two (for small_divmod)
 };
 
 __device__ __forceinline__ MapView map_view(const uint32_t *bits, const MapDesc &md) {
-    return MapView{bits, md.w, md.h, md.wpr, md.wpr * 32, (double)md.res, md.wpr_t * 32};
+    const int pitch = md.wpr * 32, pitch_t = md.wpr_t * 32;
+    return MapView{bits,   md.w, md.h, md.wpr, pitch, (double)md.res, pitch_t,
+                   __builtin_amdgcn_rcpf((float)pitch),
+                   __builtin_amdgcn_rcpf((float)(pitch_t > 0 ? pitch_t : 1))};
 }
 
 __device__ __forceinline__ bool cell_filled(const MapView &M, int i, int j) {
@@ -354,13 +358,13 @@ __device__ __forceinline__ int small_div(int a, int b, float inv_b) {
 // when it has crossed both the cell's x line and its y line facing it, so the
 // range is the later of the two crossing distances (a line behind the origin,
 // or parallel to the ray, gives -inf); recomputed once in double.
-__device__ __forceinline__ void walk_result(const RayOrigin &o, int pitch, int W, int H, int B,
-                                            double dx, double dy, double rmax, float &range,
-                                            int &hit, bool transposed = false) {
+__device__ __forceinline__ void walk_result(const RayOrigin &o, int pitch, float inv_pitch, int W,
+                                            int H, int B, double dx, double dy, double rmax,
+                                            float &range, int &hit, bool transposed = false) {
     // B: bit index of the cell in the bitmap (line = padded row, lines of
     // `pitch` bits), or in the transposed one (line = padded column)
     int pos;
-    const int line = small_divmod(B, pitch, __builtin_amdgcn_rcpf((float)pitch), pos);
+    const int line = small_divmod(B, pitch, inv_pitch, pos);
     const int row = transposed ? pos : line, col = transposed ? line : pos;
     const int ix = col - kPad, iy = row - kPad;
     // t_x = X / dx and t_y = Y / dy (a zero component gives -inf); the later
@@ -403,7 +407,7 @@ __device__ __forceinline__ void cast_ray(const MapView &M, const RayOrigin &o, d
     }
     visits = k + 1;
     if (found) {
-        walk_result(o, M.pitch, M.w, M.h, w.B, dx, dy, rmax, range, hit);
+        walk_result(o, M.pitch, M.inv_pitch, M.w, M.h, w.B, dx, dy, rmax, range, hit);
     } else {
         range = (float)rmax;
         hit = -1;
@@ -920,7 +924,8 @@ __device__ __forceinline__ void finish_ray_dir(const StepParams &p, const MapVie
         if (res.y & 1u) {
             // bit 1: B indexes the transposed bitmap (run walk, y-major ray)
             const bool tr = (res.y & 2u) != 0u;
-            walk_result(tile_origin(j, M.s), tr ? M.pitch_t : M.pitch, M.w, M.h, B, dx, dy,
+            walk_result(tile_origin(j, M.s), tr ? M.pitch_t : M.pitch,
+                        tr ? M.inv_pitch_t : M.inv_pitch, M.w, M.h, B, dx, dy,
                         (double)p.rmax, rg, hit, tr);
         } else {
             rg = p.rmax;
@@ -1473,24 +1478,22 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
 constexpr int kLongRun = 1 << 14;  // run length of an axis-parallel ray (past any budget)
 
 // floor(x / a) for 0 <= x <= 2^31 and 1 <= a <= 2^30 when that is below
-// 12000, else some value >= 8192: a run that long outlasts any walk's budget
-// (at most 8191 cells), so its exact length never matters.  inv_a is the
-// float reciprocal of a; the float estimate is then within one of the
-// quotient, and the two tests (q a < 2^32 for such q) fix it.
-// r = x - q a (the remainder when q is exact; anything otherwise).
+// 12000, else kLongRun: a run that long outlasts any walk's budget (at most
+// 8191 cells), so its exact length never matters.  a = 0 (inv_a infinite)
+// also gives kLongRun.  inv_a is the float reciprocal of a; the float
+// estimate is then within one of the quotient, and the two tests (q a < 2^32
+// for such q) fix it.  r = x - q a when the quotient is returned (anything
+// with kLongRun).  No branches: every lane of a refill takes the same path.
 __device__ __forceinline__ int run_quot(uint32_t x, uint32_t a, float inv_a, uint32_t &r) {
     const float qf = (float)x * inv_a;
-    if (!(qf < 12000.0f)) return kLongRun;
-    int q = (int)qf;
-    r = x - (uint32_t)q * a;
-    if ((int32_t)r < 0) {  // |r| < 2 a <= 2^31: the sign bit tells
-        --q;
-        r += a;
-    } else if (r >= a) {
-        ++q;
-        r -= a;
-    }
-    return q;
+    const bool longr = !(qf < 12000.0f);
+    const int q0 = (int)(longr ? 0.0f : qf);
+    const uint32_t r0 = x - (uint32_t)q0 * a;
+    const bool neg = (int32_t)r0 < 0;  // |r0| < 2 a <= 2^31: the sign bit tells
+    const bool over = !neg && r0 >= a;
+    r = neg ? r0 + a : (over ? r0 - a : r0);
+    const int q = q0 + (over ? 1 : 0) - (neg ? 1 : 0);
+    return longr ? kLongRun : q;
 }
 
 // Per-ray constants of the run walk.  Positions are bit indices into the
@@ -1614,22 +1617,18 @@ __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapVie
                     // q = floor((b - 1) / a) (a = 0: an axis-parallel ray, one run)
                     // (remainders instead of products: e + pend a = a - 1 - r0 and
                     // M1 = b - q a = r1 + 1)
+                    // (a = 0, an axis-parallel ray: both quotients are kLongRun, one
+                    // run, and e, M1 never matter; with e >= 0 the first step is the
+                    // minor one and the first quotient is not used)
                     const float inv_a = __builtin_amdgcn_rcpf((float)a);
-                    pend = 0;
-                    int q = kLongRun;
                     uint32_t r0 = 0u, r1 = 0u;
-                    if (a > 0) {
-                        if (e < 0) {
-                            pend = run_quot((uint32_t)(-e) + (uint32_t)(a - 1), (uint32_t)a, inv_a,
+                    const int p0 = run_quot((uint32_t)(-e) + (uint32_t)(a - 1), (uint32_t)a, inv_a,
                                             r0);
-                            e = a - 1 - (int)r0;
-                        }
-                        q = run_quot((uint32_t)(b - 1), (uint32_t)a, inv_a, r1);
-                    } else if (e < 0) {
-                        pend = kLongRun;
-                    }
+                    const int q = run_quot((uint32_t)(b - 1), (uint32_t)a, inv_a, r1);
+                    pend = e < 0 ? p0 : 0;
+                    e = e < 0 ? a - 1 - (int)r0 : e;
                     c.q1 = q + 1;
-                    c.M1 = a > 0 ? (int)r1 + 1 : 0;
+                    c.M1 = (int)r1 + 1;
                     c.up = a - c.M1;
                     c.dn = -c.M1;
                     const bool down = xmaj ? w.incx < 0 : w.incy < 0;
