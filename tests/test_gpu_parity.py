@@ -471,6 +471,22 @@ def test_fused_equals_plain_bitwise():
     b.close()
 
 
+@pytest.mark.parametrize("walk", [3, 4, 5])
+def test_every_env_resets_every_step(walk):
+    """Horizon 1: every env ends and is reset in every step, so a tile's
+    reset jobs (drawn while the claim walk already runs on the main jobs, the
+    final observations here) are as many as its envs and rays of unpublished
+    reset jobs are claimed; teacher-forced against the oracle."""
+    say(f"horizon 1, walk {walk}: every env resets every step, 32-env tiles, c2 maps, 512 envs")
+    w = configs.build_workload("c2", num_envs=512)
+    cfg = dict(w["cfg"], horizon=1)
+    sim, ref = make_pair(cfg, w["maps"], w["res"], w["env_map"])
+    sim.set_tuning(32, 40, 16, 0, walk, threads=1024 if walk == 4 else 512)
+    tot = run_teacher_forced(sim, ref, 3, NAVSIM_KERNEL_FUSED, label=f"horizon1/walk{walk}")
+    assert tot["resets"] == 3 * 512
+    sim.close()
+
+
 def test_determinism_and_checkpoint():
     say("determinism + checkpoint/resume, c2 maps, 256 envs")
     w = configs.build_workload("c2", num_envs=256)
