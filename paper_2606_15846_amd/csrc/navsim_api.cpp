@@ -3,12 +3,14 @@
 // and documented in include/navsim.h.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdlib.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <map>
+#include <set>
 #include <new>
 #include <string>
 #include <vector>
@@ -299,6 +301,28 @@ double map_scan_work(const uint8_t *occ, int W, int H, double s, double rmax, in
 // split only when no XCD has room), and each XCD runs its own tiles heaviest
 // first.  Results do not depend on the order; small launches (fewer than two
 // tiles per XCD, or fewer maps than XCDs) keep the plain heaviest-first order.
+// Multiply-shift constants of a map's two small divisions (MapDesc), checked
+// over the whole operand range once per distinct divisor.
+int ceil_log2(uint32_t x) {
+    int s = 0;
+    while ((1u << s) < x) ++s;
+    return s;
+}
+
+void magic_for(uint32_t d, int bits, uint32_t &magic, int32_t &shift) {
+    shift = bits + ceil_log2(d);
+    magic = (uint32_t)(((1ull << shift) + d - 1) / d);
+    static std::set<std::pair<uint32_t, int>> checked;
+    if (checked.insert({d, bits}).second)
+        for (uint64_t x = 0; x < (1ull << bits); ++x)
+            if ((uint32_t)((x * magic) >> shift) != (uint32_t)(x / d)) abort();
+}
+
+void set_quotient_magic(MapDesc &d, int sectors) {
+    magic_for((uint32_t)d.K, 18, d.k_magic, d.k_shift);
+    magic_for((uint32_t)(d.K / sectors), 12, d.per_magic, d.per_shift);
+}
+
 void order_tiles_by_xcd(std::vector<Tile> &tiles, const std::vector<double> &map_weight) {
     const int T = (int)tiles.size();
     std::vector<int> maps;  // in first-seen order of the heaviest-first list
@@ -759,6 +783,7 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
         d.len = prof[k].length_m;
         d.wid = prof[k].width_m;
         d.rc = circumradius(d.footprint, d.radius, d.len, d.wid);
+        set_quotient_magic(d, cfg.num_sectors);
         auto it = beam_off.find(d.K);
         if (it == beam_off.end()) {
             it = beam_off.emplace(d.K, (int32_t)beams.size()).first;

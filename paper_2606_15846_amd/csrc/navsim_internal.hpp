@@ -49,6 +49,12 @@ struct MapDesc {
     int32_t wpr_t;       // words per padded column
     int32_t words_t;     // padded words, rounded up to a multiple of 4
     int64_t word_off_t;  // start in the bit pool (multiple of 4 words)
+    // exact quotients by multiply and shift: floor(x / K) = x k_magic >> k_shift
+    // for x < 2^18 (a claim index), floor(b / per) = b per_magic >> per_shift
+    // for b < 2^12 (a beam; per = K / sectors), with magic = ceil(2^shift / d)
+    // and shift = 18 (12) + ceil(log2 d), so that x d <= 2^shift
+    uint32_t k_magic, per_magic;
+    int32_t k_shift, per_shift;
 };
 
 // A group of up to tile_envs envs that share one map (one fused workgroup).

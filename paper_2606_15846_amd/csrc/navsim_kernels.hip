@@ -66,13 +66,18 @@ struct MapView {
     double s;
     int pitch_t;                 // bits per line of the transposed bitmap
     float inv_pitch, inv_pitch_t;  // float reciprocals of the two (for small_divmod)
+    uint32_t k_magic, per_magic;   // quotients by K and by beams per sector (MapDesc)
+    int k_shift, per_shift;
 };
 
 __device__ __forceinline__ MapView map_view(const uint32_t *bits, const MapDesc &md) {
     const int pitch = md.wpr * 32, pitch_t = md.wpr_t * 32;
-    return MapView{bits,   md.w, md.h, md.wpr, pitch, (double)md.res, pitch_t,
-                   __builtin_amdgcn_rcpf((float)pitch),
-                   __builtin_amdgcn_rcpf((float)(pitch_t > 0 ? pitch_t : 1))};
+    return MapView{bits,         md.w,         md.h,
+                   md.wpr,       pitch,        (double)md.res,
+                   pitch_t,      __builtin_amdgcn_rcpf((float)pitch),
+                   __builtin_amdgcn_rcpf((float)(pitch_t > 0 ? pitch_t : 1)),
+                   md.k_magic,   md.per_magic, md.k_shift,
+                   md.per_shift};
 }
 
 __device__ __forceinline__ bool cell_filled(const MapView &M, int i, int j) {
@@ -352,6 +357,31 @@ __device__ __forceinline__ int small_divmod(int a, int b, float inv_b, int &r) {
 __device__ __forceinline__ int small_div(int a, int b, float inv_b) {
     int r;
     return small_divmod(a, b, inv_b, r);
+}
+
+// Sector of a beam: floor(beam / per) by one 24-bit product and a shift (the
+// map's constants make it exact for every beam < 2^12).
+__device__ __forceinline__ int beam_sector(const MapView &M, int beam) {
+    return (int)(__umul24((uint32_t)beam, M.per_magic) >> M.per_shift);
+}
+
+// Job list entry and beam of claimed ray g = base + (lane's rank < 64), with
+// base the same on every lane: one exact multiply-shift quotient of the
+// uniform base (scalar), then at most one wrap per lane when K >= 64; smaller
+// beam counts take the per-lane quotient.
+__device__ __forceinline__ int claim_decode(const MapView &M, int base, int g, int K, float inv_K,
+                                            int &beam) {
+    if (K < 64) return small_divmod(g, K, inv_K, beam);
+    // the constants are uniform: scalar registers, so that the product and
+    // j0 K are scalar arithmetic
+    const uint32_t km = __builtin_amdgcn_readfirstlane(M.k_magic);
+    const uint32_t ks = __builtin_amdgcn_readfirstlane((uint32_t)M.k_shift);
+    const int Ku = __builtin_amdgcn_readfirstlane(K);
+    const int j0 = (int)(((uint64_t)(uint32_t)base * km) >> ks);
+    beam = g - j0 * Ku;
+    const bool wrap = beam >= Ku;
+    beam -= wrap ? Ku : 0;
+    return j0 + (wrap ? 1 : 0);
 }
 
 // Range and hit id of a walk that stopped in cell B.  The ray enters a cell
@@ -932,7 +962,7 @@ __device__ __forceinline__ void finish_ray_dir(const StepParams &p, const MapVie
             hit = -1;
         }
     }
-    atomicMin(&s_pool[__mul24(job, p.m) + small_div(beam, per, inv_per)], __float_as_uint(rg));
+    atomicMin(&s_pool[__mul24(job, p.m) + beam_sector(M, beam)], __float_as_uint(rg));
     if (job < E && (p.d_ranges || p.d_hits || p.d_visits)) {
         const int64_t o = (int64_t)j.env * p.K + beam;
         if (p.d_ranges) p.d_ranges[o] = rg;
@@ -965,7 +995,7 @@ __device__ __forceinline__ void finish_march(const StepParams &p, const MapView 
     float rg;
     int hit, vis;
     march_result(p, M, j.x, j.y, dx, dy, (int)(res & 0x0FFFFFFFu), (int)(res >> 28), rg, hit, vis);
-    atomicMin(&s_pool[__mul24(job, p.m) + small_div(beam, per, inv_per)], __float_as_uint(rg));
+    atomicMin(&s_pool[__mul24(job, p.m) + beam_sector(M, beam)], __float_as_uint(rg));
     if (job < E && (p.d_ranges || p.d_hits || p.d_visits)) {
         const int64_t o = (int64_t)j.env * p.K + beam;
         if (p.d_ranges) p.d_ranges[o] = rg;
@@ -1426,7 +1456,7 @@ __device__ __forceinline__ void claim_walk(const StepParams &p, const MapView &M
                 (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, (uint32_t)base));
             if (!act && my < R) {
                 g = my;
-                const int jl = small_divmod(g, K, inv_K, beam);
+                const int jl = claim_decode(M, base, g, K, inv_K, beam);
                 job = s_list[jl];
                 wait_job_ready(s_misc, job, E);
                 const TileJob &j = job_ref(s_jobs, job);
@@ -1597,7 +1627,7 @@ __device__ __forceinline__ void claim_run_walk(const StepParams &p, const MapVie
                 (uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, (uint32_t)base));
             if (!act && my < R) {
                 g = my;
-                const int jl = small_divmod(g, K, inv_K, beam);
+                const int jl = claim_decode(M, base, g, K, inv_K, beam);
                 job = s_list[jl];
                 wait_job_ready(s_misc, job, E);
                 const TileJob &j = job_ref(s_jobs, job);
