@@ -3,13 +3,13 @@
 // and documented in include/navsim.h.
 #include <hip/hip_runtime.h>
 #include <math.h>
-#include <stdlib.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <set>
 #include <new>
 #include <string>
@@ -309,18 +309,22 @@ int ceil_log2(uint32_t x) {
     return s;
 }
 
-void magic_for(uint32_t d, int bits, uint32_t &magic, int32_t &shift) {
+bool magic_for(uint32_t d, int bits, uint32_t &magic, int32_t &shift) {
     shift = bits + ceil_log2(d);
     magic = (uint32_t)(((1ull << shift) + d - 1) / d);
-    static std::set<std::pair<uint32_t, int>> checked;
-    if (checked.insert({d, bits}).second)
-        for (uint64_t x = 0; x < (1ull << bits); ++x)
-            if ((uint32_t)((x * magic) >> shift) != (uint32_t)(x / d)) abort();
+    static std::mutex mu;
+    static std::set<std::pair<uint32_t, int>> checked;  // divisors already verified
+    std::lock_guard<std::mutex> lock(mu);
+    if (checked.count({d, bits})) return true;
+    for (uint64_t x = 0; x < (1ull << bits); ++x)
+        if ((uint32_t)((x * magic) >> shift) != (uint32_t)(x / d)) return false;
+    checked.insert({d, bits});
+    return true;
 }
 
-void set_quotient_magic(MapDesc &d, int sectors) {
-    magic_for((uint32_t)d.K, 18, d.k_magic, d.k_shift);
-    magic_for((uint32_t)(d.K / sectors), 12, d.per_magic, d.per_shift);
+bool set_quotient_magic(MapDesc &d, int sectors) {
+    return magic_for((uint32_t)d.K, 18, d.k_magic, d.k_shift) &&
+           magic_for((uint32_t)(d.K / sectors), 12, d.per_magic, d.per_shift);
 }
 
 void order_tiles_by_xcd(std::vector<Tile> &tiles, const std::vector<double> &map_weight) {
@@ -783,7 +787,9 @@ navsim_status navsim_load_maps_ex(navsim_t h, int32_t num_maps, const int32_t *w
         d.len = prof[k].length_m;
         d.wid = prof[k].width_m;
         d.rc = circumradius(d.footprint, d.radius, d.len, d.wid);
-        set_quotient_magic(d, cfg.num_sectors);
+        if (!set_quotient_magic(d, cfg.num_sectors))
+            return fail(NAVSIM_E_UNSUPPORTED, "map %d: no exact quotient constants for %d beams", k,
+                        d.K);
         auto it = beam_off.find(d.K);
         if (it == beam_off.end()) {
             it = beam_off.emplace(d.K, (int32_t)beams.size()).first;
