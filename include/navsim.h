@@ -109,7 +109,10 @@ navsim_status navsim_create(const navsim_config *cfg, int hip_device, navsim_t *
  * circumscribed disc fits (the reset sampler could not succeed);
  * NAVSIM_E_UNSUPPORTED if a map's footprint window, floor(2 rc / res) + 2 cells
  * per side for the circumscribed radius rc, exceeds 128 cells (for example the
- * 0.80 x 0.41 m rectangle fits down to 0.0071 m cells: 91 cells at 0.01 m). */
+ * 0.80 x 0.41 m rectangle fits down to 0.0071 m cells: 91 cells at 0.01 m);
+ * NAVSIM_E_UNSUPPORTED also guards the step's exact multiply-shift quotients
+ * by a map's beam count and beams per sector, which are checked here over
+ * their whole operand range (they hold for every beam count up to the limit). */
 navsim_status navsim_load_maps(navsim_t h, int32_t num_maps, const int32_t *width,
                                const int32_t *height, const float *res_m, const uint8_t *occ,
                                const int32_t *env_map);
