@@ -365,7 +365,7 @@ def _small_cfg(**kw):
 
 
 @pytest.mark.parametrize("case", ["ragged", "many_sectors", "fov270", "rect_noborder",
-                                  "single_env", "long_range"])
+                                  "single_env", "long_range", "max_beams"])
 @pytest.mark.parametrize("kname", ["fused", "plain"])
 def test_edge_configs(case, kname):
     say(f"edge config {case}, kernel={kname}")
@@ -383,6 +383,10 @@ def test_edge_configs(case, kname):
         cfg.update(num_envs=1)
     elif case == "long_range":
         cfg.update(max_range_m=50.0, num_beams=64, num_sectors=8)
+    elif case == "max_beams":
+        # the largest beam count: the claim index and the beam's sector come
+        # from multiply-shift quotients whose exact range ends here
+        cfg.update(num_beams=4096, num_sectors=64)
     maps = [occ, occ[::-1].copy()]
     env_map = (np.arange(cfg["num_envs"]) % 2).astype(np.int32)
     sim, ref = make_pair(cfg, maps, [0.05, 0.05], env_map)
