@@ -251,9 +251,17 @@ void apply_shape(navsim_s *h, const FusedShape &f) {
 
 // Envs grouped by map (stable in env order) into tiles of up to tile_envs envs,
 // one fused workgroup each.
-// Scan work of one env on a map, for scheduling only: K times the mean
-// number of cells a ray walks, from a few rays cast on the host (up to 128
-// free cells, 16 directions each, first occupied or outside cell or r_max).
+// A ray's fixed cost in units of one cell visit: claiming it, setting up its
+// walk, its range and pooling (~360 VALU lane-slots per ray against ~10 per
+// visited cell in the C4 counters, ~35 visits), plus its partial last window
+// and the lanes that idle as rays end.  C4's step time is flat for 50 to 250
+// and 1 % slower with the bare cell count.
+constexpr double kRayCostCells = 64.0;
+
+// Scan work of one env on a map, for scheduling only: K times (the mean
+// number of cells a ray walks + a ray's fixed cost), from a few rays cast on
+// the host (up to 128 free cells, 16 directions each, first occupied or
+// outside cell or r_max).
 double map_scan_work(const uint8_t *occ, int W, int H, double s, double rmax, int K,
                      const int32_t *free_cells, int free_cnt) {
     if (free_cnt <= 0) return (double)K;
@@ -289,7 +297,7 @@ double map_scan_work(const uint8_t *occ, int W, int H, double s, double rmax, in
             ++rays;
         }
     }
-    return (double)K * (1.0 + cells / rays);
+    return (double)K * (kRayCostCells + cells / rays);
 }
 
 // Launch order for the XCDs' own L2 caches.  The dispatcher hands workgroup i
